@@ -1,0 +1,28 @@
+"""CPU oracle for Feynman-path sampling on the p-bit Boltzmann machine.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call, link
+or execute anything in this package: only the tests, the smoke check and the
+CPU-baseline leg of the benchmark use it.  It shares no code with the HIP
+path (no kernels, headers, helpers, tables or pre/post-processing); the two
+meet only through the seeded circuit generators in `workloads/`.
+
+Everything here is plain and slow on purpose, in FP64, each function citing
+the passage of the paper it follows:
+
+  exact.py      statevector of Eq. (U), brute-force Feynman-path sum of
+                Eq. (path), the magnitude circuit and Z of Eq. (weightedS)
+  compile.py    gate energies Eq. (UE) as magnitude / phase-bin tables,
+                the Appendix's exact elimination of zero entries (copy / XOR
+                / NOT), free p-bits, cones, real-energy factors, colouring
+  chain.c       Philox4x32-10 and the Gibbs chain of Fig. 2 steps 1-3,
+  chain.py      replayed chain by chain (plain C, loaded through ctypes)
+  estimator.py  Eqs. (U343), (U23), (U26), (U30): amplitudes, sigma, TV
+  ancestral.py  an independent exact sampler of p_C (layer-by-layer)
+  made.py       FP64 MADE forward / backward / Adam (the learned proposal)
+
+Pins that tie each part to the paper rather than to itself live in
+tests/test_oracle_*.py.  Parity unpinned: none of the functions above is
+unpinned except `chain.philox` whose known-answer vectors are checked only
+against an independent host build of rocRAND's Philox4x32-10 engine when
+hipcc is present (see tests/test_oracle_philox.py).
+"""

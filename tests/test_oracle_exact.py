@@ -1,0 +1,266 @@
+"""Pins of the oracle's exact layer (statevector, path sum, compile) to the
+paper and to mathematics other than the oracle itself."""
+import cmath
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import circuit as oc
+from oracle import compile as ocomp
+from oracle import estimator as oest
+from oracle import exact
+from workloads import circuits as wc
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _circ(c):
+    return oc.from_dict(c)
+
+
+def small_random(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 4))
+    d = int(rng.integers(1, 5 if n < 3 else 4))
+    return _circ(wc.random_clifford_t(n, d, seed, K=3))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_statevector_equals_path_sum_and_dense(seed):
+    """Eq. (U) as a matrix product and Eq. (path) as an explicit sum over
+    every Feynman path are the same number (exact identity)."""
+    c = small_random(seed)
+    sv = exact.statevector(c)
+    ps = exact.path_sum(c)
+    dense = exact.dense_unitary(c)[:, c.input]
+    assert np.allclose(sv, ps, atol=1e-12)
+    assert np.allclose(sv, dense, atol=1e-12)
+    assert abs(np.linalg.norm(sv) - 1.0) < 1e-12
+
+
+def test_tiny_amplitudes_and_phase_bins():
+    g = json.load(open(os.path.join(GOLD, "tiny_n3_d5.json")))
+    c = _circ(wc.tiny_ghz_t())
+    sv = exact.statevector(c)
+    want = np.zeros(8, dtype=complex)
+    for k, (re, im) in g["amplitudes"].items():
+        want[int(k)] = complex(re, im)
+    assert np.allclose(sv, want, atol=1e-12)
+    assert np.allclose(exact.path_sum(c), want, atol=1e-12)
+    comp = ocomp.compile_circuit(c)
+    assert comp.h == g["free_bits"]
+    assert comp.Z == pytest.approx(g["Z"], rel=1e-12)
+    # every path of the compiled lattice lands on one of the four outputs
+    # with the phase bin of its amplitude
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        assert str(a) in g["phase_bins"]
+        assert k == g["phase_bins"][str(a)]
+        assert m == pytest.approx(0.5)
+
+
+def test_hadamard_d2_worked_example():
+    """Sec. 4, Fig. 3: four equal-magnitude paths, 0->1->1 has the opposite
+    phase; output 0 collects 2, output 1 collects 0."""
+    g = json.load(open(os.path.join(GOLD, "hadamard_d2.json")))
+    c = _circ(wc.hadamard_chain(2, K=1))
+    _, paths = exact.path_sum(c, return_paths=True)
+    got = {tuple(s): w for s, w in paths}
+    assert len(got) == 4
+    for p in g["paths"]:
+        w = got[tuple(p["layers"])]
+        assert abs(w) == pytest.approx(g["path_magnitude"])
+        assert np.sign(w.real) == p["sign"]
+    comp = ocomp.compile_circuit(c)
+    sums = {0: 0, 1: 0}
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        sums[a] += 1 if k == 0 else -1
+    assert sums == {int(k): v for k, v in g["phase_sum"].items()}
+
+
+@pytest.mark.parametrize("d", [2, 4, 6, 8, 10])
+def test_peak_height_even_hadamard_chain(d):
+    """Sec. 4 'Sign problem': with uniform sampling the net signed count at
+    the correct output, as a fraction of all samples, is 2^(-d/2)."""
+    comp = ocomp.compile_circuit(_circ(wc.hadamard_chain(d, K=1)))
+    assert comp.h == d
+    net = 0
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        if a == 0:
+            net += 1 if k == 0 else -1
+    assert net / 2 ** comp.h == pytest.approx(2.0 ** (-d / 2))
+
+
+@pytest.mark.parametrize("d", [2, 4, 6, 8])
+def test_sigma_wrong_output_eq_stdT(d):
+    """Eq. (stdT): on the wrong output of an even-d Hadamard chain the
+    estimator's standard deviation is 2^(d/2) / sqrt(2T)."""
+    comp = ocomp.compile_circuit(_circ(wc.hadamard_chain(d, K=1)))
+    prob = np.zeros((2, 2))
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        prob[a, k] += 1.0 / 2 ** comp.h
+    T = 10 ** 6
+    sre, sim = oest.exact_sigma(prob, comp.Z, T)
+    assert comp.Z == pytest.approx(2.0 ** (d / 2))
+    assert sre[1] == pytest.approx(2.0 ** (d / 2) / math.sqrt(2 * T), rel=1e-12)
+    assert sim[1] == 0.0
+
+
+def test_tiny_sigma_closed_form():
+    """Config n=3: outputs 0 and 2 have W_C = Z = 2 with probability 1/4
+    each, so Var Re A = (4 - 1) / (4 T)."""
+    comp = ocomp.compile_circuit(_circ(wc.tiny_ghz_t()))
+    prob = np.zeros((8, 8))
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        prob[a, k] += 0.25
+    T = 2048000
+    sre, _ = oest.exact_sigma(prob, comp.Z, T)
+    assert sre[0] == pytest.approx(math.sqrt(3.0 / (4 * T)), rel=1e-12)
+    assert sre[5] == pytest.approx(math.sqrt(0.375 / T), rel=1e-12)
+
+
+def _eb_energy(U, s_out, s_in):
+    """Eq. (EB) with principal complex logs."""
+    a1, b1, c1, A1 = U[0, 0], U[0, 1], U[1, 0], U[1, 1]
+    L = cmath.log
+    return (-L(a1) + s_out * L(a1 / c1) + s_in * L(a1 / b1)
+            + s_in * s_out * L(b1 * c1 / (a1 * A1)))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_table_orientation_matches_eq_EB(seed):
+    """The oracle's magnitude/phase table entry at (out, in) reproduces
+    exp(-E) of the Boolean form Eq. (EB) at (s^(d), s^(d-1)) = (out, in);
+    a transposed table fails for non-symmetric U."""
+    rng = np.random.default_rng(seed)
+    K = 3
+    mags = rng.uniform(0.2, 1.0, size=(2, 2))
+    ks = rng.integers(0, 2 ** K, size=(2, 2))
+    U = mags * np.exp(2j * np.pi * ks / 2 ** K)
+    circ = oc.Circuit(1, 1, K, 0, [oc.Gate(1, [0], U)])
+    g = ocomp.compile_circuit(circ).gates[0]
+    for o in (0, 1):
+        for i in (0, 1):
+            val = cmath.exp(-_eb_energy(U, o, i))
+            tab = g.mag[o * 2 + i] * cmath.exp(2j * math.pi * g.ph[o * 2 + i] / 2 ** K)
+            assert abs(val - tab) < 1e-12
+            assert abs(val - U[o, i]) < 1e-12
+
+
+def test_eq2E_hadamard_energy():
+    """Eq. (eq2E): for two Hadamards the imaginary energy is
+    i pi (s1 s2 + s2 s3); the table phases sum to pi (s1 s2 + s2 s3)."""
+    comp = ocomp.compile_circuit(_circ(wc.hadamard_chain(2, K=1)))
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        s1, s2, s3 = int(x[0]), int(x[1]), int(x[2])
+        assert k == (s1 * s2 + s2 * s3) % 2
+    # a1 = b1 = c1 = -A1 = 1 in Eq. (EB): E = i pi s s'
+    U = np.array([[1, 1], [1, -1]], dtype=complex)
+    for o in (0, 1):
+        for i in (0, 1):
+            e = _eb_energy(U, o, i)
+            assert abs(cmath.exp(-e) - cmath.exp(-1j * math.pi * o * i)) < 1e-12
+
+
+def _one_gate(U, arity, n=2, K=3, inp=0):
+    qubits = [0] if arity == 1 else [0, 1]
+    return ocomp.compile_circuit(oc.Circuit(n, 1, K, inp, [oc.Gate(1, qubits, U)]))
+
+
+@pytest.mark.parametrize("inp", range(4))
+def test_appendix_cnot_is_xor(inp):
+    """Appendix, CNOT: with the paper's matrix (qubit 2 controls),
+    s1' = s1 XOR s2, s2' = s2, E = 0; no free p-bit is created."""
+    U = np.array(wc.mat_cnot_tc()[0], dtype=complex)
+    comp = _one_gate(U, 2, inp=inp)
+    assert comp.gates[0].kind == "derived" and comp.h == 0
+    s1, s2 = inp & 1, (inp >> 1) & 1
+    assert comp.const[2] == s1 ^ s2 and comp.const[3] == s2
+    assert comp.gates[0].ph.max() == 0
+
+
+@pytest.mark.parametrize("inp", [0, 1])
+def test_appendix_not_and_rz(inp):
+    """Appendix: Pauli-X sets s' = 1 - s with E = 0; Rz(gamma) keeps s' = s
+    and carries U = exp(-i gamma (1 - 2 s) / 2) (from -ln U directly)."""
+    comp = _one_gate(np.array(wc.mat_x()[0], dtype=complex), 1, n=1, inp=inp)
+    assert comp.gates[0].kind == "derived" and comp.const[1] == 1 - inp
+    gamma = math.pi / 2
+    re, im = wc.mat_rz(gamma)
+    U = np.array(re) + 1j * np.array(im)
+    comp = _one_gate(U, 1, n=1, K=3, inp=inp)
+    g = comp.gates[0]
+    assert g.kind == "copy" and comp.const[1] == inp
+    k = g.ph[inp * 2 + inp]
+    val = cmath.exp(2j * math.pi * k / 8)
+    assert abs(val - cmath.exp(-1j * gamma * (1 - 2 * inp) / 2)) < 1e-12
+
+
+def test_appendix_exchange_j12_copies():
+    gamma = math.pi / 2
+    e = cmath.exp(1j * gamma / 2)
+    U = np.diag([e, e.conjugate(), e.conjugate(), e])
+    comp = _one_gate(U, 2, K=3, inp=3)
+    assert comp.gates[0].kind == "copy" and comp.h == 0
+    assert comp.const[2] == 1 and comp.const[3] == 1
+
+
+def test_partial_zero_gate_rejected():
+    """Zero entries that are neither diagonal nor a permutation (a
+    controlled Hadamard) need the e^-J route, not exact elimination."""
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2)
+    U = np.eye(4, dtype=complex)
+    U[np.ix_([2, 3], [2, 3])] = H
+    with pytest.raises(ocomp.CompileError):
+        _one_gate(U, 2)
+
+
+@pytest.mark.parametrize("name", ["tiny", "rct12", "brick20", "brick16"])
+def test_workload_structure(name):
+    """Gate sets {H, S, T, sqrt X, CNOT, CZ, CP}: every magnitude is
+    constant, so the path law is uniform (one colour, no factors) and
+    Z = 2^(h/2)."""
+    comp = ocomp.compile_circuit(_circ(wc.workload_circuit(name)))
+    assert comp.ncolours == 1
+    assert all(len(f) == 0 for f in comp.factors)
+    assert comp.Z == pytest.approx(2.0 ** (comp.h / 2), rel=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_magnitude_marginal_matches_enumeration(seed):
+    """P_mag (magnitude circuit) equals the enumerated p_C marginal and
+    Z = sum |psi_C| = product of column sums."""
+    c = small_random(100 + seed)
+    comp = ocomp.compile_circuit(c)
+    pm, Z = exact.magnitude_marginal(c)
+    marg = np.zeros(2 ** c.n)
+    tot = 0.0
+    amp = np.zeros(2 ** c.n, dtype=complex)
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        marg[a] += m
+        tot += m
+        amp[a] += m * cmath.exp(2j * math.pi * k / 2 ** c.K)
+    assert tot == pytest.approx(Z, rel=1e-12)
+    assert comp.Z == pytest.approx(Z, rel=1e-12)
+    assert np.allclose(marg / tot, pm, atol=1e-12)
+    # summing the compiled paths reproduces the statevector
+    assert np.allclose(amp, exact.statevector(c), atol=1e-12)
+
+
+def test_rotated_hadamard_theta():
+    """Eq. (HadT): theta = pi/4 is the Hadamard gate (uniform law, one
+    colour); theta = pi/2 is the classical NOT (no free p-bit)."""
+    c = _circ(wc.rotated_hadamard_chain(6, math.pi / 4, K=1))
+    comp = ocomp.compile_circuit(c)
+    assert comp.h == 6 and all(not f for f in comp.factors)
+    c2 = _circ(wc.rotated_hadamard_chain(6, math.pi / 2, K=1))
+    comp2 = ocomp.compile_circuit(c2)
+    assert comp2.h == 0
+    c3 = _circ(wc.rotated_hadamard_chain(6, math.pi / 8, K=1))
+    comp3 = ocomp.compile_circuit(c3)
+    assert comp3.ncolours == 2 and comp3.h == 6
+    # the path law is non-uniform and enumerates to the magnitude circuit
+    pm, Z = exact.magnitude_marginal(c3)
+    assert comp3.Z == pytest.approx(Z, rel=1e-12)
