@@ -1,0 +1,162 @@
+"""Benchmark of the Gibbs hot path on one MI355X.
+
+A step is one full pbit_gibbs_run of the workload (every chain: burn-in +
+binned sweeps, phase polynomial, histogram), inputs resident in HBM.  Prints
+one JSON line with the p-bit update rate, the roofline of the sampling
+kernel (algorithmic integer-VALU ops over the kernel time measured with HIP
+events on the launch stream), and the CPU oracle timed on the host cores on
+a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload rct12]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU slots
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Philox4x32-10: 10 rounds x (2 wide multiplies at quarter rate = 8 slots
+# + 2 three-input XORs); a block serves 4 updates
+PHILOX_SLOTS_PER_UPDATE = 10 * (2 * 4 + 2) / 4.0
+UPDATE_FIXED_SLOTS = 3  # compare, old-bit extract, flip test
+
+HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19, OFF_QD=20, WS=28)
+
+
+def algorithmic_ops(blob):
+    """Integer-VALU slot-ops one sweep (all updates) and one sample need."""
+    g = lambda k: int(blob[HDR[k]])
+    h, W, WS, K = g("H"), g("W"), g("WS"), g("K")
+    cone = blob[g("OFF_CONE"):g("OFF_CONE") + h * WS].reshape(h, WS)[:, :W]
+    nnz = int(np.count_nonzero(cone))
+    per_sweep = h * (PHILOX_SLOTS_PER_UPDATE + UPDATE_FIXED_SLOTS) + nnz
+    lin = blob[g("OFF_LIN"):g("OFF_LIN") + K * WS].reshape(K, WS)[:, :W]
+    per_sample = 2 * int(np.count_nonzero(lin))
+    o = g("OFF_QD")
+    st = 2 + K * WS
+    for q in range(g("NQD")):
+        planes = blob[o + q * st + 2:o + (q + 1) * st].reshape(K, WS)[:, :W]
+        used = int(np.count_nonzero(planes.any(axis=0)))
+        per_sample += 2 * used + 2 * int(np.count_nonzero(planes))
+    per_sample += 3  # alpha funnel shift + mask, histogram index
+    return per_sweep, per_sample, nnz
+
+
+def cpu_baseline(c, h, burn, sweeps, chains_sample):
+    from oracle import chain as och
+    from oracle import circuit as oc
+    from oracle import compile as ocomp
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    och.gibbs(comp, chains_sample, burn, sweeps, seed=0, threads=threads)
+    dt = time.perf_counter() - t0
+    ups = chains_sample * (burn + sweeps) * h / dt
+    return {"value": ups, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d chains x (%d + %d) sweeps of the same circuit (first chains of the "
+                      "workload), %.1f s" % (chains_sample, burn, sweeps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rct12")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-chains", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(chains shard trivially; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_07379_amd import pbit
+    from workloads import circuits as wc
+
+    w = wc.WORKLOADS[args.workload]
+    c = wc.workload_circuit(args.workload)
+    chains, burn, sweeps = w["chains"], w["burn_in"], w["sweeps"]
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    h = info["h"]
+    blob = s.export(0)
+    per_sweep, per_sample, nnz = algorithmic_ops(blob)
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev)
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device=dev)
+
+    def step():
+        hist.zero_()
+        s.gibbs_run([chains], burn, sweeps, hist, state, seed=0, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        s.gibbs_run([chains], burn, sweeps, hist, state, seed=0, stream=stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = [a.elapsed_time(b) for a, b in ev]
+    kernel_s = float(np.mean(kms)) / 1e3
+    ms_per_step = wall / args.steps * 1e3
+    updates = chains * (burn + sweeps) * h
+    value = updates / (ms_per_step / 1e3)
+    ops = chains * ((burn + sweeps) * per_sweep + sweeps * per_sample)
+    achieved = ops / kernel_s
+    out = {
+        "metric": "p-bit updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %s, n=%d d=%d K=%d, %d chains x (%d burn-in + %d) sweeps, h=%d free p-bits"
+                        % (args.workload, c.get("name", ""), info["n"], info["d"], info["K"], chains,
+                           burn, sweeps, h),
+            "chains": chains, "sweeps": sweeps, "burn_in": burn, "free_bits": h,
+        },
+        "samples_per_s": chains * sweeps / (ms_per_step / 1e3),
+        "lattice_bit_updates_per_s": value * info["L"] / max(h, 1),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": VALU_PEAK / 1e12,
+            "unit": "Tslot-op/s",
+            "frac": achieved / VALU_PEAK,
+            "traffic": None,
+            "kernel": "gibbs_kernel<%d,%s>" % (int(blob[HDR["WS"]]), "true" if info["uniform"] else "false"),
+            "kernel_ms": kernel_s * 1e3,
+            "ops_per_update": per_sweep / max(h, 1),
+            "ops_per_sample": per_sample,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(c, h, burn, sweeps, min(args.cpu_chains, chains))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * pbit.h -- C ABI of the MI355X (gfx950) Feynman-path sampler.
+ *
+ * The problem (Sec. 3 of Chowdhury, Camsari, Datta, "Emulating Quantum
+ * Interference with Generalized Ising Machines"): given n qubits, a
+ * layered gate sequence U^(1..d) and an input basis state beta, estimate
+ * U_{alpha,beta} for every output alpha (Eq. (U)) as the sum over Feynman
+ * paths of Eq. (path), by sampling paths with probability proportional to
+ * |psi_C| = exp(-Re E) (Eq. (weightedS)) and adding each sample's phase
+ * exp(-i Im E) to its output bin (Fig. 2, steps 1-3); Eq. (U23) then turns
+ * the bins into amplitudes.
+ *
+ * Conventions used by every entry point
+ *  - Gate matrices are U[out][in] (Sec. 2 one/two-qubit tables).  A
+ *    two-qubit gate on (q[0], q[1]) indexes rows and columns by
+ *    s_{q[0]} + 2 s_{q[1]} (the column order |00>,|10>,|01>,|11> of
+ *    Eq. (ET2)).  Basis states are little-endian: qubit q is bit q.
+ *  - The p-bit lattice has d+1 layers of n bits; bit (layer l, qubit q) has
+ *    index l*n + q and lives in 32-bit word (l*n+q)/32, bit (l*n+q)%32.
+ *    W = ceil(n(d+1)/32) words per chain.
+ *  - Zero entries are eliminated exactly (Appendix): a gate whose matrix is
+ *    diagonal copies its input p-bits, a gate whose matrix is a permutation
+ *    (times phases) fixes its outputs as an affine GF(2) function of its
+ *    inputs (NOT, CNOT = XOR), and only gates with no zero entry create new
+ *    independent ("free") p-bits.  Other zero patterns are rejected.
+ *  - Every nonzero entry must have a phase on the grid 2 pi k / 2^K; the
+ *    sample phase is then an integer bin k in [0, 2^K).
+ *  - Histograms are uint32[2^n][2^K] (index alpha * 2^K + k), owned and
+ *    zeroed by the caller; runs add into them.
+ *  - Device buffers are plain device pointers (e.g. a PyTorch tensor's
+ *    data_ptr()); streams are hipStream_t passed as void*.  All run entry
+ *    points are asynchronous on that stream; results are valid after the
+ *    stream is synchronised.
+ *  - Errors: negative status codes; argument errors are detected before any
+ *    work is enqueued; pbit_last_error() returns a thread-local message.
+ *    Device errors surface as PBIT_E_DEVICE.
+ *  - Compiled handles are immutable and may be shared by runs on different
+ *    streams.
+ */
+#ifndef PBIT_H
+#define PBIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pbit_status;
+enum {
+    PBIT_OK = 0,
+    PBIT_E_INVALID_ARG = -1,
+    PBIT_E_UNSUPPORTED_GATE = -2, /* zero pattern neither full, diagonal nor permutation */
+    PBIT_E_PHASE_OFF_GRID = -3,   /* an entry's phase is not a multiple of 2 pi / 2^K */
+    PBIT_E_TOO_LARGE = -4,        /* lattice > 1024 bits, > 256 free bits, n > 24, ... */
+    PBIT_E_DEVICE = -5,
+    PBIT_E_COUNT_OVERFLOW = -6,   /* chains x sweeps of one call could overflow a uint32 bin */
+    PBIT_E_OOM = -7,
+    PBIT_E_MODE_UNAVAILABLE = -8  /* exact-Z normalisation without constant column sums */
+};
+
+enum { PBIT_INIT_ZERO = 0, PBIT_INIT_RESUME = 1 };
+enum { PBIT_NORM_EXACT_Z = 0, PBIT_NORM_L2 = 1 };
+
+typedef struct pbit_circuit_s *pbit_circuit;
+typedef struct pbit_proposal_s *pbit_proposal;
+
+/* One gate.  layer in 1..d; gates of one layer act on disjoint qubits; an
+ * idle qubit carries the identity.  re/im hold U[out][in] row-major
+ * (2x2 uses the first 4 entries). */
+typedef struct {
+    uint32_t layer;
+    uint32_t arity; /* 1 or 2 */
+    uint32_t q[2];
+    double re[16];
+    double im[16];
+} pbit_gate;
+
+/* One circuit.  input_state is beta (bit q = qubit q).  zero_tol: an entry
+ * with |U| <= zero_tol is a zero (<= 0 selects 1e-12); phase_tol: allowed
+ * distance of arg U from the 2 pi / 2^K grid (<= 0 selects 1e-9).
+ * circuit_id (< 2^16) enters every random-number counter. */
+typedef struct {
+    uint32_t n, d;
+    const pbit_gate *gates;
+    uint32_t n_gates;
+    uint64_t input_state;
+    uint32_t K; /* 1..8 */
+    double zero_tol, phase_tol;
+    uint32_t circuit_id;
+} pbit_circuit_desc;
+
+typedef struct {
+    uint32_t n, d, K, W, L; /* L = n (d+1) lattice bits in W words */
+    uint32_t h;             /* free p-bits */
+    uint32_t n_colours;     /* colours of the free-bit conflict graph */
+    uint32_t uniform;       /* 1 if every conditional is exactly 1/2 */
+    uint32_t n_gates;
+    uint32_t n_quad_offsets; /* distinct index offsets of quadratic phase terms */
+    uint32_t hist_bins;      /* 2^(n+K) */
+    uint32_t circuit_id;
+    int32_t has_exact_z;     /* 1 if Z = product of gate column sums is exact */
+    double Z;                /* sum over all paths of |psi_C| (valid if has_exact_z) */
+    uint64_t hist_offset;    /* start of this circuit's bins in a set's histogram */
+} pbit_circuit_info;
+
+/* Compile n_circuits circuits (Sec. 2 energies Eq. (UE), Appendix
+ * eliminations) into one immutable handle ("circuit set").  Host only: no
+ * device is needed until the first run.  Returns UNSUPPORTED_GATE,
+ * PHASE_OFF_GRID or TOO_LARGE for circuits outside the supported class.
+ * The handle is freed with pbit_circuit_free. */
+pbit_status pbit_compile_circuit(const pbit_circuit_desc *descs, uint32_t n_circuits,
+                                 pbit_circuit *out);
+void pbit_circuit_free(pbit_circuit c);
+uint32_t pbit_circuit_count(pbit_circuit c);
+pbit_status pbit_circuit_info_get(pbit_circuit c, uint32_t idx, pbit_circuit_info *out);
+
+/* Copies the compiled device image of circuit idx (uint32 words) into buf.
+ * With buf == NULL only *len (in words) is set.  The layout is documented
+ * in paper_2007_07379_amd/csrc/blob.h; it is used to check the compile
+ * against an independent one. */
+pbit_status pbit_circuit_export(pbit_circuit c, uint32_t idx, uint32_t *buf, size_t *len);
+
+typedef struct {
+    const uint32_t *chains;     /* host array: chains per circuit of the set */
+    uint32_t chain_begin;       /* global index of each circuit's first chain */
+    uint32_t burn_in, sweeps;   /* sweeps not binned, then binned */
+    uint64_t seed;              /* Philox key */
+    uint32_t sweep_offset;      /* first sweep counter (resume) */
+    uint32_t init;              /* PBIT_INIT_ZERO: all free bits 0; RESUME: read d_state */
+    uint32_t sweeps_per_launch; /* sweep-group size; 0 = autotuned */
+    uint32_t block_size;        /* chains per workgroup (64..1024, multiple of 64); 0 = autotuned */
+    uint32_t use_graph;         /* 1: replay the sweep groups as a captured hipGraph */
+    uint32_t hist_mode;         /* 0 = auto, 1 = LDS-privatised, 2 = global atomics */
+} pbit_gibbs_cfg;
+
+/* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its
+ * free p-bits colour by colour, each update drawing u from Philox4x32-10 at
+ * counter (sweep, b/4, chain, circuit_id) (word b%4) and setting the bit to
+ * (u < T_b), T_b the uint32 threshold of its exact conditional; after each of
+ * the last `sweeps` sweeps the chain adds 1 to hist[alpha * 2^K + k].
+ * d_state: device, sum_i chains_i * W_i uint32; circuit i starts at
+ *          S_i = sum_{j<i} chains_j * W_j and is word-major (word w of chain
+ *          c at S_i + w * chains_i + c); written at the end, read at the
+ *          start when init == RESUME; may be NULL with init == ZERO.
+ * d_hist:  device, sum_i 2^(n_i+K_i) uint32 at hist_offset; added to.
+ * COUNT_OVERFLOW if some chains_i * sweeps >= 2^32. */
+pbit_status pbit_gibbs_run(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state,
+                           uint32_t *d_hist, void *hip_stream);
+
+/* Amplitude recovery (Eqs. (U343), (U23), (U26), (U30); Fig. 2 step 4), host
+ * FP64.  counts: host uint64[2^n][2^K] of circuit idx (a run's histogram,
+ * possibly summed over runs), T = number of samples.
+ * mode EXACT_Z: A_alpha = Z / T sum_k c_{alpha,k} exp(2 pi i k / 2^K) with
+ *   sig_re/sig_im the per-component standard deviations of Eq. (U26);
+ *   MODE_UNAVAILABLE if the circuit has no exact Z.
+ * mode L2: A = B / ||B||_2 with B_alpha = sum_k c_{alpha,k} exp(2 pi i k/2^K);
+ *   sig_* are set to zero (the normalisation is itself random).
+ * Outputs are host arrays of 2^n doubles (sig_* may be NULL). */
+pbit_status pbit_amplitudes(pbit_circuit c, uint32_t idx, const uint64_t *counts, uint64_t T,
+                            int mode, double *amp_re, double *amp_im, double *sig_re,
+                            double *sig_im);
+
+const char *pbit_last_error(void);
+
+/* Blocks until all work the library enqueued on hip_stream is done; returns
+ * PBIT_E_DEVICE if the device reported an error. */
+pbit_status pbit_sync(void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBIT_H */

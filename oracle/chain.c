@@ -134,6 +134,14 @@ static void sample(const oracle_run *R, const uint32_t *x, uint64_t *hist) {
     hist[((uint64_t)alpha << K) | phi] += 1;
 }
 
+/* The conditional threshold of free bit b at lattice x (as used above). */
+uint32_t oracle_threshold(const oracle_run *R, int b, const uint32_t *x) {
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * R->W);
+    uint32_t t = threshold(R, b, x, tmp);
+    free(tmp);
+    return t;
+}
+
 typedef struct {
     const oracle_run *R;
     uint32_t c0, c1; /* local chain range */

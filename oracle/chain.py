@@ -104,6 +104,33 @@ class Tables:
         self.order = np.array(comp.order or [0], dtype=np.int32)
 
 
+def _fill(r, comp, t):
+    r.n, r.d, r.K, r.L, r.W, r.h = comp.n, comp.d, comp.K, comp.L, comp.W, comp.h
+    r.const_words = t.const_words.ctypes.data
+    r.free_pos = t.free_pos.ctypes.data
+    r.cone = t.cone.ctypes.data
+    r.G = t.G
+    r.arity = t.arity.ctypes.data
+    r.in_bits = t.in_bits.ctypes.data
+    r.out_bits = t.out_bits.ctypes.data
+    r.mag = t.mag.ctypes.data
+    r.ph = t.ph.ctypes.data
+    r.factor_off = t.factor_off.ctypes.data
+    r.factor_ids = t.factor_ids.ctypes.data
+    r.order = t.order.ctypes.data
+
+
+def threshold(comp, b, x_words, tables=None):
+    """The uint32 threshold of free bit b at lattice x (packed words)."""
+    t = tables if tables is not None else Tables(comp)
+    x = np.ascontiguousarray(x_words, dtype=np.uint32)
+    r = _Run()
+    _fill(r, comp, t)
+    L = lib()
+    L.oracle_threshold.restype = C.c_uint32
+    return int(L.oracle_threshold(C.byref(r), int(b), C.c_void_p(x.ctypes.data)))
+
+
 def gibbs(comp, chains, burn_in, sweeps, seed=0, circuit_id=0, chain_begin=0,
           sweep_offset=0, init_state=None, threads=1, tag=TAG_GIBBS, tables=None):
     """Replay `chains` chains (global indices chain_begin...).  Returns
@@ -121,19 +148,7 @@ def gibbs(comp, chains, burn_in, sweeps, seed=0, circuit_id=0, chain_begin=0,
         if a is not None:
             assert a.flags["C_CONTIGUOUS"]
     r = _Run()
-    r.n, r.d, r.K, r.L, r.W, r.h = comp.n, comp.d, comp.K, comp.L, W, comp.h
-    r.const_words = t.const_words.ctypes.data
-    r.free_pos = t.free_pos.ctypes.data
-    r.cone = t.cone.ctypes.data
-    r.G = t.G
-    r.arity = t.arity.ctypes.data
-    r.in_bits = t.in_bits.ctypes.data
-    r.out_bits = t.out_bits.ctypes.data
-    r.mag = t.mag.ctypes.data
-    r.ph = t.ph.ctypes.data
-    r.factor_off = t.factor_off.ctypes.data
-    r.factor_ids = t.factor_ids.ctypes.data
-    r.order = t.order.ctypes.data
+    _fill(r, comp, t)
     r.seed = int(seed)
     r.circuit_id = int(circuit_id)
     r.tag = int(tag)

@@ -1,0 +1,27 @@
+// Launch interface of the Gibbs sampling kernel (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pbit {
+
+struct GibbsLaunch {
+    const uint32_t *blob;   // device image of the circuit (blob.h)
+    uint32_t *state;        // word-major lattice words, n_chains per word; may be NULL
+    uint32_t *hist;         // this circuit's uint32[2^(n+K)] histogram
+    uint32_t n_chains;
+    uint32_t chain_begin;   // global index of local chain 0
+    uint32_t seed_lo, seed_hi;
+    uint32_t sweep_begin;   // Philox sweep counter of the launch's first sweep
+    uint32_t n_sweeps;
+    uint32_t bin_from;      // sweeps with counter >= bin_from are binned
+    uint32_t resume;        // 1: read the lattice from state; 0: start from all-zero free bits
+    uint32_t lds_hist;      // 1: histogram privatised in LDS
+};
+
+// Launches the kernel compiled for lattice width Wk (one of KERNEL_WIDTHS).
+hipError_t launch_gibbs(uint32_t Wk, bool uniform, const GibbsLaunch &a, uint32_t block, size_t lds_bytes,
+                        hipStream_t stream);
+
+}  // namespace pbit

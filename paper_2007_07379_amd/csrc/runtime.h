@@ -1,0 +1,54 @@
+// Library-internal runtime: compiled handle, device images, run planning.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pbit.h"
+#include "compile.h"
+
+namespace pbit {
+
+pbit_status set_error(pbit_status st, const std::string &msg);
+pbit_status hip_error(hipError_t e, const char *what);
+
+// A device buffer owned by a handle, one per device ordinal.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Captured sweep-group graph, replayed while the run signature is unchanged.
+struct GraphCache {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+}  // namespace pbit
+
+struct pbit_circuit_s {
+    std::vector<pbit::CompiledCircuit> circuits;
+    std::vector<uint64_t> hist_off;
+    uint64_t hist_total = 0;
+    std::mutex mu;
+    std::map<int, pbit::DevBuf> blobs;    // all circuit images, concatenated
+    std::vector<uint64_t> blob_off;       // word offset of each circuit's image
+    std::map<int, pbit::DevBuf> scratch;  // lattice state between sweep groups
+    std::map<int, pbit::DevBuf> work;     // persistent work list (batched runs)
+    std::map<int, pbit::GraphCache> graphs;
+    ~pbit_circuit_s();
+};
+
+namespace pbit {
+
+pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
+                      hipStream_t stream);
+
+// Device image of every circuit of the handle on the current device.
+pbit_status device_blobs(pbit_circuit c, const uint32_t **base);
+
+}  // namespace pbit

@@ -1,0 +1,218 @@
+"""Python binding of libpbit (argument marshalling only).
+
+Every function mirrors one C entry point of include/pbit.h.  Device buffers
+are passed as PyTorch tensors (their data_ptr()) or raw device addresses;
+streams as torch.cuda.Stream or raw hipStream_t values.  All sampling work
+runs in the HIP library: if libpbit.so is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbit.so")
+
+PBIT_OK = 0
+ERRORS = {
+    -1: "INVALID_ARG", -2: "UNSUPPORTED_GATE", -3: "PHASE_OFF_GRID", -4: "TOO_LARGE",
+    -5: "DEVICE", -6: "COUNT_OVERFLOW", -7: "OOM", -8: "MODE_UNAVAILABLE",
+}
+INIT_ZERO, INIT_RESUME = 0, 1
+NORM_EXACT_Z, NORM_L2 = 0, 1
+
+
+class PbitError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(status, "?"), status, msg))
+        self.status = status
+        self.name = ERRORS.get(status, "?")
+
+
+class Gate(C.Structure):
+    _fields_ = [("layer", C.c_uint32), ("arity", C.c_uint32), ("q", C.c_uint32 * 2),
+                ("re", C.c_double * 16), ("im", C.c_double * 16)]
+
+
+class CircuitDesc(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("d", C.c_uint32), ("gates", C.POINTER(Gate)),
+                ("n_gates", C.c_uint32), ("input_state", C.c_uint64), ("K", C.c_uint32),
+                ("zero_tol", C.c_double), ("phase_tol", C.c_double), ("circuit_id", C.c_uint32)]
+
+
+class CircuitInfo(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("d", C.c_uint32), ("K", C.c_uint32), ("W", C.c_uint32),
+                ("L", C.c_uint32), ("h", C.c_uint32), ("n_colours", C.c_uint32),
+                ("uniform", C.c_uint32), ("n_gates", C.c_uint32), ("n_quad_offsets", C.c_uint32),
+                ("hist_bins", C.c_uint32), ("circuit_id", C.c_uint32), ("has_exact_z", C.c_int32),
+                ("Z", C.c_double), ("hist_offset", C.c_uint64)]
+
+
+class GibbsCfg(C.Structure):
+    _fields_ = [("chains", C.POINTER(C.c_uint32)), ("chain_begin", C.c_uint32),
+                ("burn_in", C.c_uint32), ("sweeps", C.c_uint32), ("seed", C.c_uint64),
+                ("sweep_offset", C.c_uint32), ("init", C.c_uint32),
+                ("sweeps_per_launch", C.c_uint32), ("block_size", C.c_uint32),
+                ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpbit.so is missing: run python -m paper_2007_07379_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.pbit_last_error.restype = C.c_char_p
+        L.pbit_compile_circuit.argtypes = [C.POINTER(CircuitDesc), C.c_uint32, C.POINTER(C.c_void_p)]
+        L.pbit_circuit_free.argtypes = [C.c_void_p]
+        L.pbit_circuit_free.restype = None
+        L.pbit_circuit_count.argtypes = [C.c_void_p]
+        L.pbit_circuit_count.restype = C.c_uint32
+        L.pbit_circuit_info_get.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(CircuitInfo)]
+        L.pbit_circuit_export.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(C.c_size_t)]
+        L.pbit_gibbs_run.argtypes = [C.c_void_p, C.POINTER(GibbsCfg), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.pbit_amplitudes.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64, C.c_int,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.pbit_sync.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != PBIT_OK:
+        raise PbitError(st, lib().pbit_last_error().decode())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _gates_of(c):
+    out = []
+    for g in c["gates"]:
+        m = g if "re" in g else c["matrices"][g["kind"]]
+        re = np.asarray(m["re"], dtype=np.float64).ravel()
+        im = np.asarray(m["im"], dtype=np.float64).ravel()
+        G = Gate()
+        G.layer = g["layer"]
+        G.arity = len(g["qubits"])
+        G.q[0] = g["qubits"][0]
+        G.q[1] = g["qubits"][1] if len(g["qubits"]) > 1 else 0
+        for i, v in enumerate(re):
+            G.re[i] = v
+        for i, v in enumerate(im):
+            G.im[i] = v
+        out.append(G)
+    return out
+
+
+class CircuitSet:
+    """A compiled handle (pbit_circuit) over one or more circuits."""
+
+    def __init__(self, circuits, circuit_ids=None, zero_tol=0.0, phase_tol=0.0):
+        if isinstance(circuits, dict):
+            circuits = [circuits]
+        self.circuits = list(circuits)
+        n = len(self.circuits)
+        ids = list(circuit_ids) if circuit_ids is not None else list(range(n))
+        descs = (CircuitDesc * n)()
+        self._keep = []
+        for i, c in enumerate(self.circuits):
+            gl = _gates_of(c)
+            arr = (Gate * max(len(gl), 1))(*gl)
+            self._keep.append(arr)
+            descs[i].n = c["n"]
+            descs[i].d = c["d"]
+            descs[i].gates = C.cast(arr, C.POINTER(Gate))
+            descs[i].n_gates = len(gl)
+            descs[i].input_state = c.get("input", 0)
+            descs[i].K = c["K"]
+            descs[i].zero_tol = zero_tol
+            descs[i].phase_tol = phase_tol
+            descs[i].circuit_id = ids[i]
+        h = C.c_void_p()
+        _check(lib().pbit_compile_circuit(descs, n, C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.pbit_circuit_free(h)
+            self.handle = None
+
+    def __len__(self):
+        return int(lib().pbit_circuit_count(self.handle))
+
+    def info(self, idx=0):
+        i = CircuitInfo()
+        _check(lib().pbit_circuit_info_get(self.handle, idx, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in CircuitInfo._fields_}
+
+    def export(self, idx=0):
+        n = C.c_size_t(0)
+        _check(lib().pbit_circuit_export(self.handle, idx, None, C.byref(n)))
+        buf = np.zeros(n.value, dtype=np.uint32)
+        _check(lib().pbit_circuit_export(self.handle, idx, buf.ctypes.data, C.byref(n)))
+        return buf
+
+    def state_words(self, chains):
+        return sum(int(ch) * self.info(i)["W"] for i, ch in enumerate(chains))
+
+    def hist_bins(self):
+        last = self.info(len(self) - 1)
+        return int(last["hist_offset"] + last["hist_bins"])
+
+    def gibbs_run(self, chains, burn_in, sweeps, d_hist, d_state=None, seed=0, chain_begin=0,
+                  sweep_offset=0, resume=False, sweeps_per_launch=0, block_size=0, use_graph=False,
+                  hist_mode=0, stream=None):
+        if isinstance(chains, int):
+            chains = [chains]
+        arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
+        cfg = GibbsCfg()
+        cfg.chains = C.cast(arr, C.POINTER(C.c_uint32))
+        cfg.chain_begin = chain_begin
+        cfg.burn_in = burn_in
+        cfg.sweeps = sweeps
+        cfg.seed = seed
+        cfg.sweep_offset = sweep_offset
+        cfg.init = INIT_RESUME if resume else INIT_ZERO
+        cfg.sweeps_per_launch = sweeps_per_launch
+        cfg.block_size = block_size
+        cfg.use_graph = 1 if use_graph else 0
+        cfg.hist_mode = hist_mode
+        _check(lib().pbit_gibbs_run(self.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
+                                    _stream(stream)))
+
+    def amplitudes(self, counts, T=None, idx=0, mode=NORM_EXACT_Z):
+        counts = np.ascontiguousarray(counts, dtype=np.uint64)
+        T = int(counts.sum()) if T is None else int(T)
+        na = 1 << self.info(idx)["n"]
+        are = np.zeros(na)
+        aim = np.zeros(na)
+        sre = np.zeros(na)
+        sim = np.zeros(na)
+        _check(lib().pbit_amplitudes(self.handle, idx, counts.ctypes.data, T, mode, are.ctypes.data,
+                                     aim.ctypes.data, sre.ctypes.data, sim.ctypes.data))
+        return are + 1j * aim, sre, sim
+
+
+def sync(stream=None):
+    _check(lib().pbit_sync(_stream(stream)))

@@ -1,0 +1,181 @@
+"""GPU parity of the Gibbs path (MI355X): final lattice words of every chain
+and uint32 phase-bin counts must equal the CPU oracle's bit for bit on the
+same Philox streams; at full workload sizes sampled chains are replayed by
+the oracle one by one and the histogram is checked against the exact
+amplitudes (4-sigma rule, TV of the path marginal)."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import chain as och
+from oracle import circuit as oc
+from oracle import compile as ocomp
+from oracle import estimator as oest
+from oracle import exact
+from workloads import circuits as wc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_07379_amd import pbit
+    return torch, pbit
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(env, c, chains, burn_in, sweeps, seed=0, chain_begin=0, **kw):
+    torch, pbit = env
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    s.gibbs_run([chains], burn_in, sweeps, hist, state, seed=seed, chain_begin=chain_begin,
+                stream=stream, **kw)
+    torch.cuda.synchronize()
+    W = info["W"]
+    st = state.cpu().numpy().view(np.uint32).reshape(W, chains).T.copy()
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    return st, h, s
+
+
+def oracle_run(c, chains, burn_in, sweeps, seed=0, chain_begin=0):
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    st, h = och.gibbs(comp, chains, burn_in, sweeps, seed=seed, chain_begin=chain_begin,
+                      threads=os.cpu_count() or 8)
+    return st, h, comp
+
+
+CASES = [
+    # name, circuit, chains, burn_in, sweeps, chain_begin
+    ("tiny", lambda: wc.tiny_ghz_t(), 1024, 200, 2000, 0),
+    ("rct12", lambda: wc.workload_circuit("rct12"), 1000, 20, 60, 4321),
+    ("brick20", lambda: wc.workload_circuit("brick20"), 700, 10, 30, 0),
+    ("brick16", lambda: wc.workload_circuit("brick16"), 513, 10, 40, 77),
+    ("rhchain", lambda: wc.rotated_hadamard_chain(10, math.pi / 8, K=1), 999, 20, 300, 0),
+    ("rbrick", lambda: wc.rotated_brickwork(5, 8, 3, math.pi / 7, K=3), 640, 20, 100, 9),
+    ("hchain_odd", lambda: wc.hadamard_chain(33, K=1), 300, 5, 50, 0),
+    ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 20, 0),
+]
+
+
+@pytest.mark.parametrize("name,mk,chains,burn,sweeps,cb", CASES, ids=[c[0] for c in CASES])
+def test_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb):
+    c = mk()
+    say("case", name, chains, burn, sweeps, cb)
+    st_g, h_g, _ = run_gpu(env, c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
+                           chain_begin=cb)
+    st_o, h_o, comp = oracle_run(c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
+                                 chain_begin=cb)
+    assert np.array_equal(st_g, st_o)
+    assert np.array_equal(h_g, h_o)
+    assert int(h_g.sum()) == chains * sweeps
+
+
+def test_launch_shapes_and_graph_are_bit_identical(env):
+    """Block sizes, sweep groups (state round-trips through HBM), global
+    atomics vs LDS privatisation and hipGraph replay change nothing."""
+    torch, pbit = env
+    c = wc.random_clifford_t(8, 20, 5, K=3)
+    ref_st, ref_h, _ = run_gpu(env, c, 2000, 7, 33)
+    for kw in [dict(block_size=64), dict(block_size=128), dict(sweeps_per_launch=5),
+               dict(hist_mode=2), dict(hist_mode=1, block_size=192)]:
+        say("shape", kw)
+        st, h, _ = run_gpu(env, c, 2000, 7, 33, **kw)
+        assert np.array_equal(st, ref_st), kw
+        assert np.array_equal(h, ref_h), kw
+    # graph replay on a side stream, twice, eager work in between
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+        state = torch.zeros(2000 * info["W"], dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        s.gibbs_run([2000], 7, 33, hist, state, sweeps_per_launch=4, use_graph=True, stream=stream)
+        stream.synchronize()
+        h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(ref_h.shape)
+        assert np.array_equal(h, ref_h), rep
+        _ = torch.ones(1000, device="cuda").sum().item()
+
+
+def test_resume_matches_uninterrupted(env):
+    torch, pbit = env
+    c = wc.workload_circuit("rct12")
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    ch = 512
+    full_st, full_h, _ = run_gpu(env, c, ch, 10, 40)
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(ch * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([ch], 10, 15, hist, state)
+    s.gibbs_run([ch], 0, 25, hist, state, sweep_offset=25, resume=True)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], ch).T
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(full_h.shape)
+    assert np.array_equal(st, full_st)
+    assert np.array_equal(h, full_h)
+
+
+def _full_run(env, name, spl=0):
+    torch, pbit = env
+    w = wc.WORKLOADS[name]
+    c = wc.workload_circuit(name)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    chains, burn, sweeps = w["chains"], w["burn_in"], w["sweeps"]
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([chains], burn, sweeps, hist, state, sweeps_per_launch=spl)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    return c, s, st, h, chains, burn, sweeps
+
+
+def test_full_rct12_sampled_chains_and_amplitudes(env):
+    """Full random Clifford+T workload (65,536 chains x 10,000 sweeps after
+    200 burn-in): sampled chains replayed by the oracle match bit for bit;
+    the histogram passes the 4-sigma rule against the 2^12 statevector and
+    the path-marginal TV is at the iid level and <= 0.01."""
+    c, s, st, h, chains, burn, sweeps = _full_run(env, "rct12")
+    T = chains * sweeps
+    assert int(h.sum()) == T
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    rng = np.random.default_rng(0)
+    picks = [0, 1, 63, 64, chains - 1] + [int(v) for v in rng.integers(0, chains, size=3)]
+    for ci in picks:
+        so, _ = och.gibbs(comp, 1, burn, sweeps, seed=0, chain_begin=ci, threads=1)
+        assert np.array_equal(st[ci], so[0]), ci
+    circ = oc.from_dict(c)
+    psi = exact.statevector(circ)
+    pm, _ = exact.magnitude_marginal(circ)
+    amp, sre, sim = s.amplitudes(h, T)
+    ok, info = oest.z_gate(amp, sre, sim, psi)
+    say("z-gate", info)
+    assert ok, info
+    tv = oest.tv_path(h, pm)
+    say("TV_path", tv, "iid", oest.expected_iid_tv(pm, T))
+    assert tv <= 0.01 and tv < 3 * oest.expected_iid_tv(pm, T)
+
+
+def test_full_tiny_born_tv(env):
+    c, s, st, h, chains, burn, sweeps = _full_run(env, "tiny")
+    _, h_o, comp = oracle_run(c, chains, burn, sweeps)
+    assert np.array_equal(h, h_o)
+    psi = exact.statevector(oc.from_dict(c))
+    amp, sre, sim = s.amplitudes(h)
+    assert oest.tv_born(amp, psi) < 0.01
+    ok, info = oest.z_gate(amp, sre, sim, psi)
+    assert ok, info

@@ -1,0 +1,216 @@
+"""Host-side checks of the HIP library (no GPU): the C ABI loads and exports
+every declared symbol, the library's circuit compile equals the oracle's
+independent compile, error codes, and FP64 amplitude recovery."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import chain as och
+from oracle import circuit as oc
+from oracle import compile as ocomp
+from oracle import estimator as oest
+from workloads import circuits as wc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2007_07379_amd", "libpbit.so")
+
+
+@pytest.fixture(scope="module")
+def pb():
+    if not os.path.exists(LIB):
+        from paper_2007_07379_amd import build
+        build.build()
+    from paper_2007_07379_amd import pbit
+    return pbit
+
+
+def test_every_declared_symbol_is_exported(pb):
+    decl = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        txt = open(os.path.join(ROOT, "include", f)).read()
+        decl |= set(re.findall(r"\b(pbit_[a-z0-9_]+)\s*\(", txt))
+    out = subprocess.check_output(["nm", "-D", "--defined-only", LIB], text=True)
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    missing = decl - exported
+    assert not missing, missing
+    assert {"pbit_compile_circuit", "pbit_gibbs_run", "pbit_amplitudes"} <= decl
+
+
+# --- blob reader (layout of paper_2007_07379_amd/csrc/blob.h) -------------
+H = dict(MAGIC=0, N=1, D=2, K=3, W=4, H=5, L=6, CID=7, NCOL=8, UNIFORM=9, AWORD=10, ASHIFT=11,
+         PCONST=12, LINMASK=13, NQD=14, FW=15, OFF_CONST=16, OFF_FPOS=17, OFF_CONE=18, OFF_LIN=19,
+         OFF_QD=20, OFF_COLIDX=21, OFF_COLENT=22, OFF_THRINFO=23, OFF_THRTAB=24, THR_TOTAL=25,
+         HBITS=26, TOTAL=27, WS=28)
+MAX_FW = 8
+THR_STRIDE = 14
+
+
+class Blob:
+    def __init__(self, b):
+        self.b = b
+        g = lambda k: int(b[H[k]])
+        self.n, self.d, self.K, self.W, self.h = g("N"), g("D"), g("K"), g("W"), g("H")
+        self.WS = g("WS")
+        self.ncol = g("NCOL")
+        self.uniform = g("UNIFORM")
+        o = g("OFF_CONST")
+        self.const = b[o:o + self.W]
+        o = g("OFF_FPOS")
+        self.fpos = [int(v) for v in b[o:o + self.h]]
+        o = g("OFF_CONE")
+        self.cone = b[o:o + self.h * self.WS].reshape(self.h, self.WS)[:, :self.W] if self.h else None
+        o = g("OFF_LIN")
+        self.lin = b[o:o + self.K * self.WS].reshape(self.K, self.WS)
+        self.pconst = g("PCONST")
+        self.qd = []
+        o = g("OFF_QD")
+        st = 2 + self.K * self.WS
+        for q in range(g("NQD")):
+            rec = b[o + q * st:o + (q + 1) * st]
+            self.qd.append((int(rec[0]), rec[2:].reshape(self.K, self.WS)))
+        ci, ce = g("OFF_COLIDX"), g("OFF_COLENT")
+        self.colour = [None] * self.h
+        for c in range(self.ncol):
+            for k in range(MAX_FW):
+                off, cnt = int(b[ci + (c * MAX_FW + k) * 2]), int(b[ci + (c * MAX_FW + k) * 2 + 1])
+                for e in range(cnt):
+                    ent = int(b[ce + off + e])
+                    j, m = ent >> 4, ent & 15
+                    for t in range(4):
+                        if m >> t & 1:
+                            assert self.colour[4 * j + t] is None
+                            self.colour[4 * j + t] = c
+        self.thr_off = g("OFF_THRINFO")
+        self.tab_off = g("OFF_THRTAB")
+        self.aword, self.ashift = g("AWORD"), g("ASHIFT")
+
+    def threshold(self, bidx, x):
+        if self.uniform:
+            return 1 << 31
+        rec = self.b[self.thr_off + bidx * THR_STRIDE:self.thr_off + (bidx + 1) * THR_STRIDE]
+        toff, ns = int(rec[0]), int(rec[1])
+        idx = 0
+        for j in range(ns):
+            p = int(rec[2 + j])
+            idx |= ((int(x[p >> 5]) >> (p & 31)) & 1) << j
+        return int(self.b[self.tab_off + toff + idx])
+
+    def phase(self, x):
+        xi = 0
+        for w in range(self.W):
+            xi |= int(x[w]) << (32 * w)
+        acc = self.pconst
+        for t in range(self.K):
+            m = 0
+            for w in range(self.W):
+                m |= int(self.lin[t, w]) << (32 * w)
+            acc += bin(xi & m).count("1") << t
+        for delta, planes in self.qd:
+            y = xi & (xi >> delta)
+            for t in range(self.K):
+                m = 0
+                for w in range(self.W):
+                    m |= int(planes[t, w]) << (32 * w)
+                acc += bin(y & m).count("1") << t
+        return acc % (1 << self.K)
+
+
+def _cases():
+    return [
+        ("tiny", wc.tiny_ghz_t()),
+        ("rct12", wc.workload_circuit("rct12")),
+        ("brick20", wc.workload_circuit("brick20")),
+        ("brick16", wc.workload_circuit("brick16")),
+        ("rct_small", wc.random_clifford_t(5, 7, 77, K=3)),
+        ("rhchain", wc.rotated_hadamard_chain(10, math.pi / 8, K=1)),
+        ("rhchain3", wc.rotated_hadamard_chain(7, math.pi / 3, K=2)),
+        ("rbrick", wc.rotated_brickwork(4, 6, 5, math.pi / 8, K=3)),
+        ("hchain", wc.hadamard_chain(9, K=1)),
+    ]
+
+
+@pytest.mark.parametrize("name,c", _cases(), ids=[n for n, _ in _cases()])
+def test_library_compile_equals_oracle(pb, name, c):
+    lib_set = pb.CircuitSet(c)
+    blob = Blob(lib_set.export(0))
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    info = lib_set.info(0)
+    assert (blob.n, blob.d, blob.K, blob.W, blob.h) == (comp.n, comp.d, comp.K, comp.W, comp.h)
+    assert blob.ncol == comp.ncolours
+    assert bool(blob.uniform) == all(not f for f in comp.factors)
+    assert np.array_equal(blob.const, ocomp.pack_words(comp.const, comp.W))
+    assert blob.fpos == list(comp.free_pos)
+    tables = och.Tables(comp)
+    if comp.h:
+        assert np.array_equal(blob.cone, tables.cone[:comp.h])
+    assert blob.colour == list(comp.colour)
+    assert (blob.aword * 32 + blob.ashift) == comp.d * comp.n
+    if comp.Z is not None:
+        assert info["has_exact_z"] == 1 and info["Z"] == pytest.approx(comp.Z, rel=1e-12)
+    rng = np.random.default_rng(1)
+    for trial in range(40):
+        f = rng.integers(0, 2, size=comp.h)
+        x = ocomp.lattice_from_free(comp, f)
+        xw = ocomp.pack_words(x, comp.W)
+        m, k = ocomp.path_weight(comp, x)
+        assert blob.phase(xw) == k, (trial, name)
+        for b in range(comp.h):
+            assert blob.threshold(b, xw) == och.threshold(comp, b, xw, tables), (trial, b)
+
+
+def _err(pb, c):
+    with pytest.raises(pb.PbitError) as e:
+        pb.CircuitSet(c)
+    return e.value.name
+
+
+def test_error_codes(pb):
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2)
+    U = np.eye(4, dtype=complex)
+    U[np.ix_([2, 3], [2, 3])] = H
+    ch = {"name": "ch", "n": 2, "d": 1, "K": 3, "input": 0, "matrices": {},
+          "gates": [{"layer": 1, "qubits": [0, 1], "kind": "CH", "re": U.real.tolist(),
+                     "im": U.imag.tolist()}]}
+    assert _err(pb, ch) == "UNSUPPORTED_GATE"
+    rz = wc.mat_rz(0.3)
+    off = {"name": "off", "n": 1, "d": 1, "K": 3, "input": 0, "matrices": {},
+           "gates": [{"layer": 1, "qubits": [0], "kind": "RZ", "re": rz[0], "im": rz[1]}]}
+    assert _err(pb, off) == "PHASE_OFF_GRID"
+    c = wc.hadamard_chain(2)
+    c["gates"].append(dict(c["gates"][0]))
+    assert _err(pb, c) == "INVALID_ARG"
+    assert _err(pb, wc.hadamard_chain(1100, K=1)) == "TOO_LARGE"
+    big = wc.brickwork(25, 2, 1)
+    assert _err(pb, big) == "TOO_LARGE"
+
+
+def test_amplitudes_match_oracle_estimator(pb):
+    c = wc.random_clifford_t(4, 6, 5, K=3)
+    s = pb.CircuitSet(c)
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    rng = np.random.default_rng(3)
+    counts = rng.integers(0, 1000, size=(16, 8)).astype(np.uint64)
+    amp, sre, sim = s.amplitudes(counts)
+    a2, s2r, s2i = oest.amplitudes(counts, comp.Z)
+    assert np.allclose(amp, a2, rtol=1e-12, atol=1e-14)
+    assert np.allclose(sre, s2r, rtol=1e-9, atol=1e-15)
+    assert np.allclose(sim, s2i, rtol=1e-9, atol=1e-15)
+    l2, _, _ = s.amplitudes(counts, mode=pb.NORM_L2)
+    assert np.allclose(l2, oest.amplitudes_l2(counts), rtol=1e-12, atol=1e-14)
+
+
+def test_gibbs_argument_errors_before_device(pb):
+    s = pb.CircuitSet(wc.tiny_ghz_t())
+    with pytest.raises(pb.PbitError) as e:
+        s.gibbs_run([1 << 20], 0, 1 << 13, d_hist=1)
+    assert e.value.name == "COUNT_OVERFLOW"
+    with pytest.raises(pb.PbitError) as e:
+        s.gibbs_run([64], 0, 10, d_hist=None)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(pb.PbitError) as e:
+        s.gibbs_run([64], 0, 10, d_hist=1, resume=True)
+    assert e.value.name == "INVALID_ARG"
