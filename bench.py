@@ -20,23 +20,34 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU slots
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = full-rate 32-bit VALU
+# lane-operations per second.  v_mad_u64_u32, v_bitop3_b32, v_alignbit_b32
+# and v_bcnt_u32_b32 all issue at full rate on gfx950 (measured: 0.24
+# wave64 instructions per SIMD per cycle for an independent stream of
+# v_mad_u64_u32, against 0.25 for a full-rate instruction).
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
-# Philox4x32-10: 10 rounds x (2 wide multiplies at quarter rate = 8 slots
-# + 2 three-input XORs); a block serves 4 updates
-PHILOX_SLOTS_PER_UPDATE = 10 * (2 * 4 + 2) / 4.0
-UPDATE_FIXED_SLOTS = 3  # compare, old-bit extract, flip test
+# Philox4x32-10 per block: 10 rounds x (2 32x32->64 multiplies + 2
+# three-input XORs) = 40 slots; a block serves 4 updates.
+PHILOX_SLOTS_PER_UPDATE = 40 / 4.0
+UPDATE_FIXED_SLOTS = 1  # the threshold compare u < T
 
-HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19, OFF_QD=20, WS=28)
+HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19, OFF_QD=20, WS=28,
+           NQG=32, OFF_QG=33)
 
 
 def algorithmic_ops(blob):
-    """Integer-VALU slot-ops one sweep (all updates) and one sample need."""
+    """VALU lane-slots the method needs per sweep (all updates of one chain)
+    and per sample, counted at the minimum a direct implementation needs:
+    one Philox quarter block and one compare per update, one XOR per nonzero
+    cone word for the expected half of the updates that flip; per sample two
+    slots (AND, popcount) per nonzero linear phase-plane word, two (funnel
+    shift, AND/OR) per nonzero quadratic mask word plus two per word of each
+    quadratic popcount, and three for the output index and the bin."""
     g = lambda k: int(blob[HDR[k]])
     h, W, WS, K = g("H"), g("W"), g("WS"), g("K")
     cone = blob[g("OFF_CONE"):g("OFF_CONE") + h * WS].reshape(h, WS)[:, :W]
     nnz = int(np.count_nonzero(cone))
-    per_sweep = h * (PHILOX_SLOTS_PER_UPDATE + UPDATE_FIXED_SLOTS) + nnz
+    per_sweep = h * (PHILOX_SLOTS_PER_UPDATE + UPDATE_FIXED_SLOTS) + 0.5 * nnz
     lin = blob[g("OFF_LIN"):g("OFF_LIN") + K * WS].reshape(K, WS)[:, :W]
     per_sample = 2 * int(np.count_nonzero(lin))
     o = g("OFF_QD")
@@ -45,6 +56,17 @@ def algorithmic_ops(blob):
         planes = blob[o + q * st + 2:o + (q + 1) * st].reshape(K, WS)[:, :W]
         used = int(np.count_nonzero(planes.any(axis=0)))
         per_sample += 2 * used + 2 * int(np.count_nonzero(planes))
+    o = g("OFF_QG")
+    for _ in range(g("NQG")):
+        m = int(blob[o + 1])
+        o += 2
+        union = np.zeros(W, dtype=bool)
+        for _ in range(m):
+            mk = blob[o + 1:o + 1 + W]
+            per_sample += 2 * int(np.count_nonzero(mk))
+            union |= mk != 0
+            o += 1 + WS
+        per_sample += 2 * int(np.count_nonzero(union))
     per_sample += 3  # alpha funnel shift + mask, histogram index
     return per_sweep, per_sample, nnz
 
@@ -71,7 +93,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rct12")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-chains", type=int, default=1024)
+    ap.add_argument("--cpu-chains", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -133,6 +133,7 @@ typedef struct {
     uint32_t block_size;        /* chains per workgroup (64..1024, multiple of 64); 0 = autotuned */
     uint32_t use_graph;         /* 1: replay the sweep groups as a captured hipGraph */
     uint32_t hist_mode;         /* 0 = auto, 1 = LDS-privatised, 2 = global atomics */
+    uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its

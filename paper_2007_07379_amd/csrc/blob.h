@@ -45,7 +45,12 @@ enum Header : uint32_t {
     H_HBITS,      // n + K
     H_TOTAL,      // blob length in words
     H_WS,         // storage stride of per-word arrays (a compiled kernel width >= W)
-    H_COUNT = 32
+    H_NBLK,       // Philox blocks per sweep: ceil(h / 4)
+    H_TOGW,       // row stride of the toggle tables: WS rounded up to a multiple of 4
+    H_OFF_TOG,    // NBLK * 16 * TOGW words: XOR of the cones of each subset of a block's bits
+    H_NQG,        // merged quadratic groups (see below)
+    H_OFF_QG,     // NQG group records
+    H_COUNT = 48  // header words (must exceed every index above)
 };
 
 // Lattice widths with a compiled sampling kernel; a circuit of W words runs
@@ -62,5 +67,17 @@ constexpr inline uint32_t qd_stride(uint32_t K, uint32_t W) { return 2 + K * W; 
 // quadratic record: [0] = offset delta (1..63), [1] = mask of nonzero planes,
 // then K planes of WS words: bit i of plane t set if bit t of the coefficient
 // of x_i x_{i+delta} is set.
+//
+// merged quadratic group: [0] = plane t, [1] = m, then m entries of
+// (delta, WS mask words).  The masks of one group are pairwise disjoint, so
+// sum_delta popcount(x & (x >> delta) & mask_delta)
+//   = popcount(x & OR_delta((x >> delta) & mask_delta))
+// and the group costs one funnel shift and one three-input bit op per word
+// per delta plus one AND and one popcount per word.
+constexpr inline uint32_t qg_entry_stride(uint32_t WS) { return 1 + WS; }
 
 }  // namespace pbit
+
+namespace pbit {
+static_assert(H_OFF_QG < H_COUNT, "blob header overflows H_COUNT");
+}

@@ -430,7 +430,6 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     blob[H_ASHIFT] = (d * n) & 31;
     blob[H_PCONST] = pconst;
     blob[H_LINMASK] = linmask;
-    blob[H_NQD] = (uint32_t)qd.size();
     blob[H_FW] = FW;
     blob[H_WS] = WS;
     constw.resize(WS, 0u);
@@ -446,22 +445,80 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     }
     blob[H_OFF_LIN] = append(linp);
     {
-        std::vector<uint32_t> flat;
+        // Offsets whose terms sit in one bit plane are merged into groups of
+        // pairwise disjoint masks (greedy, ascending delta); offsets with
+        // several planes stay per-offset records.
+        std::vector<uint32_t> flat, gflat;
+        struct Group {
+            uint32_t t;
+            std::vector<uint32_t> used;  // union of the masks so far
+            std::vector<std::pair<uint32_t, std::vector<uint32_t>>> items;
+        };
+        std::vector<Group> groups;
+        uint32_t nrec = 0;
         for (auto &kv : qd) {
             uint32_t pm = 0;
             for (uint32_t t = 0; t < K; ++t)
                 for (uint32_t w = 0; w < WS; ++w)
                     if (kv.second[(size_t)t * WS + w]) pm |= 1u << t;
+            if (__builtin_popcount(pm) == 1) {
+                const uint32_t t = __builtin_ctz(pm);
+                std::vector<uint32_t> mk(kv.second.begin() + (size_t)t * WS, kv.second.begin() + (size_t)(t + 1) * WS);
+                Group *dst = nullptr;
+                for (auto &g : groups) {
+                    if (g.t != t) continue;
+                    bool disjoint = true;
+                    for (uint32_t w = 0; w < WS && disjoint; ++w) disjoint = !(g.used[w] & mk[w]);
+                    if (disjoint) {
+                        dst = &g;
+                        break;
+                    }
+                }
+                if (!dst) {
+                    groups.push_back(Group{t, std::vector<uint32_t>(WS, 0u), {}});
+                    dst = &groups.back();
+                }
+                for (uint32_t w = 0; w < WS; ++w) dst->used[w] |= mk[w];
+                dst->items.push_back({kv.first, mk});
+                continue;
+            }
             flat.push_back(kv.first);
             flat.push_back(pm);
             flat.insert(flat.end(), kv.second.begin(), kv.second.end());
+            ++nrec;
         }
+        for (auto &g : groups) {
+            gflat.push_back(g.t);
+            gflat.push_back((uint32_t)g.items.size());
+            for (auto &it : g.items) {
+                gflat.push_back(it.first);
+                gflat.insert(gflat.end(), it.second.begin(), it.second.end());
+            }
+        }
+        blob[H_NQD] = nrec;
         blob[H_OFF_QD] = append(flat);
+        blob[H_NQG] = (uint32_t)groups.size();
+        blob[H_OFF_QG] = append(gflat);
     }
     blob[H_OFF_COLIDX] = append(colidx);
     blob[H_OFF_COLENT] = append(colent);
     blob[H_OFF_THRINFO] = append(thrinfo);
     blob[H_OFF_THRTAB] = append(thrtab);
+    {
+        // toggle tables: row f of block j = XOR of the cones of the bits
+        // 4j + t with bit t of f set, so one gather applies a block's flips
+        const uint32_t nblk = (h + 3) / 4;
+        const uint32_t TW = (WS + 3) & ~3u;
+        std::vector<uint32_t> tog((size_t)nblk * 16 * TW, 0u);
+        for (uint32_t j = 0; j < nblk; ++j)
+            for (uint32_t f = 0; f < 16; ++f)
+                for (uint32_t t = 0; t < 4; ++t)
+                    if (((f >> t) & 1u) && 4 * j + t < h)
+                        for (uint32_t w = 0; w < W; ++w) tog[((size_t)j * 16 + f) * TW + w] ^= cone[4 * j + t][w];
+        blob[H_NBLK] = nblk;
+        blob[H_TOGW] = TW;
+        blob[H_OFF_TOG] = append(tog);
+    }
     blob[H_THR_TOTAL] = (uint32_t)thrtab.size();
     blob[H_HBITS] = n + K;
     // pad so that kernels may read a few words past any array

@@ -6,6 +6,18 @@
 
 namespace pbit {
 
+// Scalar arguments of one launch (passed by value).
+struct GibbsArgs {
+    uint32_t n_chains;
+    uint32_t chain_begin;
+    uint32_t seed_lo, seed_hi;
+    uint32_t sweep_begin;
+    uint32_t n_sweeps;
+    uint32_t bin_from;
+    uint32_t resume;
+    uint32_t lds_hist;
+};
+
 struct GibbsLaunch {
     const uint32_t *blob;   // device image of the circuit (blob.h)
     uint32_t *state;        // word-major lattice words, n_chains per word; may be NULL
@@ -20,8 +32,13 @@ struct GibbsLaunch {
     uint32_t lds_hist;      // 1: histogram privatised in LDS
 };
 
-// Launches the kernel compiled for lattice width Wk (one of KERNEL_WIDTHS).
-hipError_t launch_gibbs(uint32_t Wk, bool uniform, const GibbsLaunch &a, uint32_t block, size_t lds_bytes,
-                        hipStream_t stream);
+// LDS bytes a launch needs (toggle tables when `tog`, thresholds, and the
+// histogram when privatised).
+size_t gibbs_lds_bytes(const uint32_t *host_blob, bool tog, bool lds_hist);
+
+// Launches the kernel compiled for lattice width Wk (one of KERNEL_WIDTHS);
+// `tog` selects the LDS toggle-table variant.
+hipError_t launch_gibbs(uint32_t Wk, bool uniform, bool tog, const GibbsLaunch &a, uint32_t block,
+                        size_t lds_bytes, hipStream_t stream);
 
 }  // namespace pbit

@@ -5,20 +5,27 @@
 // value of a free bit is one bit-field extract.  A sweep visits the colours
 // of the free-bit conflict graph in order; inside a colour the bits are
 // conditionally independent and are visited Philox block by Philox block
-// (block j serves free bits 4j..4j+3).  Each update:
-//   u  = word (b % 4) of Philox4x32-10(counter = (sweep, b/4, chain, cid),
-//        key = seed)                               -- Fig. 2 step 1
-//   T  = 2^31 for uniform circuits, else the uint32 threshold read from the
-//        LDS-staged table at the bits of the factor scope
-//   new = (u < T); if new != old: flip the bit's cone in the lattice
-//                                                  -- Fig. 2 step 2 (heat bath)
+// (block j serves free bits 4j..4j+3).  Per block:
+//   u_t = word t of Philox4x32-10(counter = (sweep, j, chain, cid), key = seed)
+//                                                    -- Fig. 2 step 1
+//   new_t = (u_t < T), T = 2^31 for uniform circuits, else the uint32
+//         threshold read from the LDS-staged table at the bits of the
+//         factor scope                               -- Fig. 2 step 2 (heat bath)
+//   flips = (new ^ old) & (bits of this colour)
+//   lattice ^= TOG[j][flips]: one LDS row that holds the XOR of the cones
+//         of the flipped bits (all 16 subsets precomputed per block), so the
+//         four updates of a block cost one gather instead of four divergent
+//         cone toggles.  Bits of one colour never touch each other's factor
+//         scopes, so computing the four thresholds before the toggle is
+//         exact.
 // After every binned sweep the lane evaluates its path's output state alpha
 // (bits of the last layer) and phase bin (the phase polynomial: popcounts
 // of lattice AND bit planes for linear terms, of lattice AND shifted
 // lattice for quadratic terms) and adds one to hist[alpha 2^K + k]
 // (Fig. 2 step 3), privatised in LDS when the histogram fits.
 //
-// The circuit image is read with wave-uniform addresses (scalar loads).
+// The circuit image is a __restrict__ kernel argument read at wave-uniform
+// addresses, so it is fetched with scalar loads.
 #include <hip/hip_runtime.h>
 
 #include "blob.h"
@@ -50,25 +57,123 @@ __device__ __forceinline__ uint32_t threshold_of(const uint32_t *__restrict__ B,
     return lds_thr[toff + idx];
 }
 
-template <int W, bool UNIFORM>
-__global__ __launch_bounds__(256) void gibbs_kernel(GibbsLaunch a) {
-    extern __shared__ uint32_t lds[];
-    const uint32_t *__restrict__ B = a.blob;
-    const uint32_t h = B[H_H];
+template <int W>
+__device__ __forceinline__ uint32_t phase_and_bin(const uint32_t *__restrict__ B, const uint32_t (&x)[W + 2],
+                                                  uint32_t K, uint32_t n) {
+    uint32_t acc[MAX_K];
+#pragma unroll
+    for (int t = 0; t < MAX_K; ++t) acc[t] = 0u;
+    const uint32_t linmask = B[H_LINMASK];
+    const uint32_t *lin = B + B[H_OFF_LIN];
+#pragma unroll
+    for (int t = 0; t < MAX_K; ++t) {
+        if ((uint32_t)t < K && ((linmask >> t) & 1u)) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) acc[t] += __builtin_popcount(x[w] & lin[t * W + w]);
+        }
+    }
+    const uint32_t nqd = B[H_NQD];
+    const uint32_t *qrec = B + B[H_OFF_QD];
+    const uint32_t qstride = 2 + K * W;
+    for (uint32_t q = 0; q < nqd; ++q) {
+        const uint32_t delta = qrec[0];
+        const uint32_t pm = qrec[1];
+        uint32_t y[W];
+        if (delta < 32) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) y[w] = x[w] & __builtin_amdgcn_alignbit(x[w + 1], x[w], delta);
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) y[w] = x[w] & __builtin_amdgcn_alignbit(x[w + 2], x[w + 1], delta - 32);
+        }
+#pragma unroll
+        for (int t = 0; t < MAX_K; ++t) {
+            if ((uint32_t)t < K && ((pm >> t) & 1u)) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) acc[t] += __builtin_popcount(y[w] & qrec[2 + t * W + w]);
+            }
+        }
+        qrec += qstride;
+    }
+    // merged groups: popcount(x & OR_delta(shift_delta(x) & mask_delta))
+    const uint32_t nqg = B[H_NQG];
+    const uint32_t *grec = B + B[H_OFF_QG];
+    for (uint32_t g = 0; g < nqg; ++g) {
+        const uint32_t t = grec[0];
+        const uint32_t m = grec[1];
+        grec += 2;
+        uint32_t z[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) z[w] = 0u;
+        for (uint32_t e = 0; e < m; ++e) {
+            const uint32_t delta = grec[0];
+            const uint32_t *mk = grec + 1;
+            if (delta < 32) {
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    z[w] = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_alignbit(x[w + 1], x[w], delta), mk[w], z[w],
+                                                       0xEA);  // (a & b) | c
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    z[w] = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_alignbit(x[w + 2], x[w + 1], delta - 32),
+                                                       mk[w], z[w], 0xEA);
+            }
+            grec += 1 + W;
+        }
+        uint32_t cnt = 0u;
+#pragma unroll
+        for (int w = 0; w < W; ++w) cnt += __builtin_popcount(x[w] & z[w]);
+#pragma unroll
+        for (int tt = 0; tt < MAX_K; ++tt)
+            if ((uint32_t)tt == t) acc[tt] += cnt;
+    }
+    uint32_t ph = B[H_PCONST];
+#pragma unroll
+    for (int t = 0; t < MAX_K; ++t) ph += acc[t] << t;
+    ph &= (1u << K) - 1u;
+    // output state: lattice bits [d n, d n + n)
+    const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
+    uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if ((uint32_t)w == aw) {
+            lo = x[w];
+            hi = x[w + 1];
+        }
+    const uint32_t alpha = __builtin_amdgcn_alignbit(hi, lo, ash) & ((1u << n) - 1u);
+    return (alpha << K) | ph;
+}
+
+template <int W, bool UNIFORM, bool TOG>
+__global__ __launch_bounds__(256) void gibbs_kernel(const uint32_t *__restrict__ B, uint32_t *__restrict__ state,
+                                                    uint32_t *__restrict__ hist, GibbsArgs a) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    constexpr int TW = (W + 3) & ~3;
     const uint32_t fw = B[H_FW];
+    const uint32_t h = B[H_H];
     const uint32_t ncol = B[H_NCOL];
     const uint32_t K = B[H_K];
     const uint32_t n = B[H_N];
     const uint32_t cid = B[H_CID];
-    const uint32_t thr_total = UNIFORM ? 0u : B[H_THR_TOTAL];
+    const bool uniform = UNIFORM || B[H_UNIFORM] != 0u;
+    const uint32_t tog_words = TOG ? B[H_NBLK] * 16u * TW : 0u;
+    const uint32_t thr_total = uniform ? 0u : B[H_THR_TOTAL];
     const uint32_t nbins = 1u << B[H_HBITS];
-    uint32_t *lds_thr = lds;
-    uint32_t *lds_h = lds + thr_total;
+    const uint32_t nblk = B[H_NBLK];
+    uint32_t *lds_tog = lds;
+    uint32_t *lds_thr = lds + tog_words;
+    uint32_t *lds_h = lds_thr + thr_total;
     const uint32_t tid = threadIdx.x;
     const uint32_t lc = blockIdx.x * blockDim.x + tid;
     const bool active = lc < a.n_chains;
 
-    if (!UNIFORM) {
+    if (TOG) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(B + B[H_OFF_TOG]);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds_tog);
+        for (uint32_t i = tid; i < tog_words / 4; i += blockDim.x) dst[i] = src[i];
+    }
+    if (!uniform) {
         const uint32_t *tab = B + B[H_OFF_THRTAB];
         for (uint32_t i = tid; i < thr_total; i += blockDim.x) lds_thr[i] = tab[i];
     }
@@ -83,7 +188,7 @@ __global__ __launch_bounds__(256) void gibbs_kernel(GibbsLaunch a) {
         const uint32_t Wc = B[H_W];  // words stored per chain (<= W)
         if (a.resume) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) x[w] = (uint32_t)w < Wc ? a.state[(size_t)w * a.n_chains + lc] : 0u;
+            for (int w = 0; w < W; ++w) x[w] = (uint32_t)w < Wc ? state[(size_t)w * a.n_chains + lc] : 0u;
         } else {
             const uint32_t *cw = B + B[H_OFF_CONST];
 #pragma unroll
@@ -93,7 +198,7 @@ __global__ __launch_bounds__(256) void gibbs_kernel(GibbsLaunch a) {
         uint32_t F[MAX_FW];
 #pragma unroll
         for (int k = 0; k < MAX_FW; ++k) F[k] = 0u;
-        if (a.resume) {
+        if (!UNIFORM && a.resume) {
             const uint32_t *fpos = B + B[H_OFF_FPOS];
             for (uint32_t b = 0; b < h; ++b) {
                 const uint32_t p = fpos[b];
@@ -111,6 +216,34 @@ __global__ __launch_bounds__(256) void gibbs_kernel(GibbsLaunch a) {
 
         for (uint32_t it = 0; it < a.n_sweeps; ++it) {
             const uint32_t s = a.sweep_begin + it;
+            if (UNIFORM) {
+                // Every conditional is 1/2, so a sweep redraws every free bit
+                // independently of the lattice: the lattice after the sweep
+                // is const ^ XOR_j TOG[j][new bits of block j], the same
+                // words the per-update cone toggles produce.  The next
+                // block's Philox runs while this block's row is read.
+                const uint32_t *cw = B + B[H_OFF_CONST];
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] = cw[w];
+                U4 u = philox4x32_10(s, 0u, chain, ctag, a.seed_lo, a.seed_hi);
+                for (uint32_t j = 0; j < nblk; ++j) {
+                    // u < 2^31 <=> top bit clear; rows ignore bits >= h
+                    const uint32_t nb =
+                        ((u.x >> 31) | ((u.y >> 30) & 2u) | ((u.z >> 29) & 4u) | ((u.w >> 28) & 8u)) ^ 15u;
+                    uint4 r[TW / 4];
+                    const uint4 *row = reinterpret_cast<const uint4 *>(lds_tog + (j * 16u + nb) * TW);
+#pragma unroll
+                    for (int q = 0; q < TW / 4; ++q) r[q] = row[q];
+                    if (j + 1u < nblk) u = philox4x32_10(s, j + 1u, chain, ctag, a.seed_lo, a.seed_hi);
+#pragma unroll
+                    for (int q = 0; q < TW / 4; ++q) {
+                        if (4 * q + 0 < W) x[4 * q + 0] ^= r[q].x;
+                        if (4 * q + 1 < W) x[4 * q + 1] ^= r[q].y;
+                        if (4 * q + 2 < W) x[4 * q + 2] ^= r[q].z;
+                        if (4 * q + 3 < W) x[4 * q + 3] ^= r[q].w;
+                    }
+                }
+            } else
             for (uint32_t c = 0; c < ncol; ++c) {
 #pragma unroll
                 for (int k = 0; k < MAX_FW; ++k) {
@@ -122,18 +255,37 @@ __global__ __launch_bounds__(256) void gibbs_kernel(GibbsLaunch a) {
                             const uint32_t j = ent >> 4;
                             const uint32_t m = ent & 15u;
                             const U4 u = philox4x32_10(s, j, chain, ctag, a.seed_lo, a.seed_hi);
-                            const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
+                            uint32_t nb;
+                            if (uniform) {
+                                nb = ((u.x >> 31) | ((u.y >> 30) & 2u) | ((u.z >> 29) & 4u) | ((u.w >> 28) & 8u)) ^ 15u;
+                            } else {
+                                const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
+                                nb = 0u;
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) {
-                                if (m & (1u << t)) {
-                                    const uint32_t b = 4 * j + t;
-                                    const uint32_t bp = b & 31u;
-                                    const uint32_t T = UNIFORM ? 0x80000000u : threshold_of<W>(B, b, x, lds_thr);
-                                    const uint32_t nb = uu[t] < T ? 1u : 0u;
-                                    const uint32_t ob = (F[k] >> bp) & 1u;
-                                    if (nb != ob) {
-                                        F[k] ^= 1u << bp;
-                                        const uint32_t *cm = cone + b * W;
+                                for (int t = 0; t < 4; ++t)
+                                    if (m & (1u << t)) {
+                                        const uint32_t T = threshold_of<W>(B, 4 * j + t, x, lds_thr);
+                                        nb |= (uu[t] < T ? 1u : 0u) << t;
+                                    }
+                            }
+                            const uint32_t sh = (4u * j) & 31u;
+                            const uint32_t fl = (nb ^ (F[k] >> sh)) & m;
+                            F[k] ^= fl << sh;
+                            if (TOG) {
+                                const uint4 *row = reinterpret_cast<const uint4 *>(lds_tog + (j * 16u + fl) * TW);
+#pragma unroll
+                                for (int q = 0; q < TW / 4; ++q) {
+                                    const uint4 r = row[q];
+                                    if (4 * q + 0 < W) x[4 * q + 0] ^= r.x;
+                                    if (4 * q + 1 < W) x[4 * q + 1] ^= r.y;
+                                    if (4 * q + 2 < W) x[4 * q + 2] ^= r.z;
+                                    if (4 * q + 3 < W) x[4 * q + 3] ^= r.w;
+                                }
+                            } else {
+#pragma unroll
+                                for (int t = 0; t < 4; ++t) {
+                                    const uint32_t *cm = cone + (4 * j + t) * W;
+                                    if ((fl >> t) & 1u) {
 #pragma unroll
                                         for (int w = 0; w < W; ++w) x[w] ^= cm[w];
                                     }
@@ -144,98 +296,71 @@ __global__ __launch_bounds__(256) void gibbs_kernel(GibbsLaunch a) {
                 }
             }
             if (s >= a.bin_from) {
-                // phase polynomial
-                uint32_t acc[MAX_K];
-#pragma unroll
-                for (int t = 0; t < MAX_K; ++t) acc[t] = 0u;
-                const uint32_t linmask = B[H_LINMASK];
-                const uint32_t *lin = B + B[H_OFF_LIN];
-#pragma unroll
-                for (int t = 0; t < MAX_K; ++t) {
-                    if ((uint32_t)t < K && ((linmask >> t) & 1u)) {
-#pragma unroll
-                        for (int w = 0; w < W; ++w) acc[t] += __builtin_popcount(x[w] & lin[t * W + w]);
-                    }
-                }
-                const uint32_t nqd = B[H_NQD];
-                const uint32_t *qrec = B + B[H_OFF_QD];
-                const uint32_t qstride = 2 + K * W;
-                for (uint32_t q = 0; q < nqd; ++q) {
-                    const uint32_t delta = qrec[0];
-                    const uint32_t pm = qrec[1];
-                    uint32_t y[W];
-                    if (delta < 32) {
-#pragma unroll
-                        for (int w = 0; w < W; ++w) y[w] = x[w] & __builtin_amdgcn_alignbit(x[w + 1], x[w], delta);
-                    } else {
-#pragma unroll
-                        for (int w = 0; w < W; ++w)
-                            y[w] = x[w] & __builtin_amdgcn_alignbit(x[w + 2], x[w + 1], delta - 32);
-                    }
-#pragma unroll
-                    for (int t = 0; t < MAX_K; ++t) {
-                        if ((uint32_t)t < K && ((pm >> t) & 1u)) {
-#pragma unroll
-                            for (int w = 0; w < W; ++w) acc[t] += __builtin_popcount(y[w] & qrec[2 + t * W + w]);
-                        }
-                    }
-                    qrec += qstride;
-                }
-                uint32_t ph = B[H_PCONST];
-#pragma unroll
-                for (int t = 0; t < MAX_K; ++t) ph += acc[t] << t;
-                ph &= (1u << K) - 1u;
-                // output state: lattice bits [d n, d n + n)
-                const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
-                uint32_t lo = 0u, hi = 0u;
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                    if ((uint32_t)w == aw) {
-                        lo = x[w];
-                        hi = x[w + 1];
-                    }
-                const uint32_t alpha = __builtin_amdgcn_alignbit(hi, lo, ash) & ((1u << n) - 1u);
-                const uint32_t bin = (alpha << K) | ph;
+                const uint32_t bin = phase_and_bin<W>(B, x, K, n);
                 if (a.lds_hist)
                     atomicAdd(&lds_h[bin], 1u);
                 else
-                    atomicAdd(&a.hist[bin], 1u);
+                    atomicAdd(&hist[bin], 1u);
             }
         }
-        if (a.state) {
+        if (state) {
 #pragma unroll
             for (int w = 0; w < W; ++w)
-                if ((uint32_t)w < Wc) a.state[(size_t)w * a.n_chains + lc] = x[w];
+                if ((uint32_t)w < Wc) state[(size_t)w * a.n_chains + lc] = x[w];
         }
     }
     if (a.lds_hist) {
         __syncthreads();
         for (uint32_t i = tid; i < nbins; i += blockDim.x) {
             const uint32_t v = lds_h[i];
-            if (v) atomicAdd(&a.hist[i], v);
+            if (v) atomicAdd(&hist[i], v);
         }
     }
+}
+
+size_t gibbs_lds_bytes(const uint32_t *hb, bool tog, bool lds_hist) {
+    const uint32_t WS = hb[H_WS];
+    const uint32_t TW = (WS + 3) & ~3u;
+    size_t words = 0;
+    if (tog) words += (size_t)hb[H_NBLK] * 16 * TW;
+    words += hb[H_UNIFORM] ? 0 : hb[H_THR_TOTAL];
+    if (lds_hist) words += (size_t)1 << hb[H_HBITS];
+    return words * sizeof(uint32_t);
 }
 
 // the widths of KERNEL_WIDTHS (blob.h)
 #define PBIT_FOR_EACH_W(X) X(1) X(2) X(3) X(4) X(6) X(8) X(10) X(12) X(13) X(14) X(16) X(17) X(20) X(24) X(28) X(32)
 
-hipError_t launch_gibbs(uint32_t Wk, bool uniform, const GibbsLaunch &a, uint32_t block, size_t lds_bytes,
+template <int V, bool U, bool T>
+static hipError_t launch_one(const GibbsLaunch &a, uint32_t grid, uint32_t block, size_t lds, hipStream_t stream) {
+    const void *fn = (const void *)gibbs_kernel<V, U, T>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    GibbsArgs g;
+    g.n_chains = a.n_chains;
+    g.chain_begin = a.chain_begin;
+    g.seed_lo = a.seed_lo;
+    g.seed_hi = a.seed_hi;
+    g.sweep_begin = a.sweep_begin;
+    g.n_sweeps = a.n_sweeps;
+    g.bin_from = a.bin_from;
+    g.resume = a.resume;
+    g.lds_hist = a.lds_hist;
+    hipLaunchKernelGGL((gibbs_kernel<V, U, T>), dim3(grid), dim3(block), lds, stream, a.blob, a.state, a.hist, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gibbs(uint32_t Wk, bool uniform, bool tog, const GibbsLaunch &a, uint32_t block, size_t lds_bytes,
                         hipStream_t stream) {
     const uint32_t grid = (a.n_chains + block - 1) / block;
     if (grid == 0) return hipSuccess;
-#define PBIT_LAUNCH(V)                                                                                    \
-    if (Wk == V) {                                                                                        \
-        const void *fn = uniform ? (const void *)gibbs_kernel<V, true> : (const void *)gibbs_kernel<V, false>; \
-        if (lds_bytes > 65536) {                                                                          \
-            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes); \
-            if (e != hipSuccess) return e;                                                                \
-        }                                                                                                 \
-        if (uniform)                                                                                      \
-            hipLaunchKernelGGL((gibbs_kernel<V, true>), dim3(grid), dim3(block), lds_bytes, stream, a);  \
-        else                                                                                              \
-            hipLaunchKernelGGL((gibbs_kernel<V, false>), dim3(grid), dim3(block), lds_bytes, stream, a); \
-        return hipGetLastError();                                                                         \
+#define PBIT_LAUNCH(V)                                                                           \
+    if (Wk == V) {                                                                               \
+        if (tog && uniform) return launch_one<V, true, true>(a, grid, block, lds_bytes, stream); \
+        if (tog) return launch_one<V, false, true>(a, grid, block, lds_bytes, stream);           \
+        return launch_one<V, false, false>(a, grid, block, lds_bytes, stream);                   \
     }
     PBIT_FOR_EACH_W(PBIT_LAUNCH)
 #undef PBIT_LAUNCH

@@ -75,6 +75,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         return set_error(PBIT_E_INVALID_ARG, "bad init mode");
     if (cfg->init == PBIT_INIT_RESUME && !d_state) return set_error(PBIT_E_INVALID_ARG, "RESUME needs d_state");
     if (cfg->hist_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad hist_mode");
+    if (cfg->toggle_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad toggle_mode");
     if (cfg->block_size && (cfg->block_size % 64 || cfg->block_size > 256))
         return set_error(PBIT_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
@@ -106,6 +107,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         GibbsLaunch a;
         uint32_t Wk;
         bool uniform;
+        bool tog;
         uint32_t block;
         size_t lds;
     };
@@ -130,11 +132,10 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         const uint32_t ch = cfg->chains[i];
         if (!ch) continue;
         const TuneChoice &tc = choices[i];
-        const uint32_t nbins = 1u << (k.n + k.K);
-        const size_t thr_bytes = (size_t)k.blob[H_THR_TOTAL] * sizeof(uint32_t);
+        const size_t thr_bytes = k.uniform ? 0 : (size_t)k.blob[H_THR_TOTAL] * sizeof(uint32_t);
         if (thr_bytes > 64 * 1024) return set_error(PBIT_E_TOO_LARGE, "threshold tables exceed 64 KiB of LDS");
         const bool lds_hist = tc.lds_hist;
-        const size_t lds = thr_bytes + (lds_hist ? (size_t)nbins * sizeof(uint32_t) : 0);
+        const size_t lds = gibbs_lds_bytes(k.blob.data(), tc.tog, lds_hist);
         if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
         uint32_t *sp = state_base ? state_base + soff : nullptr;
         for (uint64_t done = 0; done < total; done += tc.group) {
@@ -154,6 +155,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.a.lds_hist = lds_hist ? 1u : 0u;
             p.Wk = k.WS;
             p.uniform = k.uniform;
+            p.tog = tc.tog;
             p.block = tc.block;
             p.lds = lds;
             plans.push_back(p);
@@ -163,7 +165,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
 
     auto enqueue = [&]() -> pbit_status {
         for (const Plan &p : plans) {
-            hipError_t le = launch_gibbs(p.Wk, p.uniform, p.a, p.block, p.lds, stream);
+            hipError_t le = launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
             if (le != hipSuccess) return hip_error(le, "gibbs kernel launch");
         }
         return PBIT_OK;
@@ -175,7 +177,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)stream, (uint64_t)(uintptr_t)d_state,
                                  (uint64_t)(uintptr_t)d_hist, (uint64_t)(uintptr_t)state_base,
                                  cfg->chain_begin, cfg->burn_in, cfg->sweeps, cfg->seed, cfg->sweep_offset,
-                                 cfg->init, cfg->sweeps_per_launch, cfg->block_size, cfg->hist_mode};
+                                 cfg->init, cfg->sweeps_per_launch, cfg->block_size, cfg->hist_mode,
+                                 cfg->toggle_mode};
     for (uint32_t i = 0; i < nc; ++i) key.push_back(cfg->chains[i]);
     GraphCache &gc = c->graphs[dev];
     if (!(gc.exec && gc.key == key)) {

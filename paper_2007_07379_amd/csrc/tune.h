@@ -11,6 +11,7 @@ struct TuneChoice {
     uint32_t block = 256;     // chains per workgroup
     uint64_t group = 0;       // sweeps per launch
     bool lds_hist = true;     // histogram privatised in LDS
+    bool tog = true;          // LDS toggle tables (else per-bit cone toggles)
 };
 
 // Explicit cfg fields win; unset ones come from the tuning table (if one was

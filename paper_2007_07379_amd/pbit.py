@@ -55,7 +55,7 @@ class GibbsCfg(C.Structure):
                 ("burn_in", C.c_uint32), ("sweeps", C.c_uint32), ("seed", C.c_uint64),
                 ("sweep_offset", C.c_uint32), ("init", C.c_uint32),
                 ("sweeps_per_launch", C.c_uint32), ("block_size", C.c_uint32),
-                ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32)]
+                ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32), ("toggle_mode", C.c_uint32)]
 
 
 _lib = None
@@ -182,7 +182,7 @@ class CircuitSet:
 
     def gibbs_run(self, chains, burn_in, sweeps, d_hist, d_state=None, seed=0, chain_begin=0,
                   sweep_offset=0, resume=False, sweeps_per_launch=0, block_size=0, use_graph=False,
-                  hist_mode=0, stream=None):
+                  hist_mode=0, toggle_mode=0, stream=None):
         if isinstance(chains, int):
             chains = [chains]
         arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
@@ -198,6 +198,7 @@ class CircuitSet:
         cfg.block_size = block_size
         cfg.use_graph = 1 if use_graph else 0
         cfg.hist_mode = hist_mode
+        cfg.toggle_mode = toggle_mode
         _check(lib().pbit_gibbs_run(self.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                                     _stream(stream)))
 

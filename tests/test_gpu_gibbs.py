@@ -70,12 +70,13 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("toggle_mode", [1, 2])
 @pytest.mark.parametrize("name,mk,chains,burn,sweeps,cb", CASES, ids=[c[0] for c in CASES])
-def test_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb):
+def test_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb, toggle_mode):
     c = mk()
-    say("case", name, chains, burn, sweeps, cb)
+    say("case", name, chains, burn, sweeps, cb, "toggle_mode", toggle_mode)
     st_g, h_g, _ = run_gpu(env, c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
-                           chain_begin=cb)
+                           chain_begin=cb, toggle_mode=toggle_mode)
     st_o, h_o, comp = oracle_run(c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
                                  chain_begin=cb)
     assert np.array_equal(st_g, st_o)
@@ -90,7 +91,8 @@ def test_launch_shapes_and_graph_are_bit_identical(env):
     c = wc.random_clifford_t(8, 20, 5, K=3)
     ref_st, ref_h, _ = run_gpu(env, c, 2000, 7, 33)
     for kw in [dict(block_size=64), dict(block_size=128), dict(sweeps_per_launch=5),
-               dict(hist_mode=2), dict(hist_mode=1, block_size=192)]:
+               dict(hist_mode=2), dict(hist_mode=1, block_size=192), dict(toggle_mode=2),
+               dict(toggle_mode=2, hist_mode=2, block_size=64)]:
         say("shape", kw)
         st, h, _ = run_gpu(env, c, 2000, 7, 33, **kw)
         assert np.array_equal(st, ref_st), kw

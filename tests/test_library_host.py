@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(pb):
 H = dict(MAGIC=0, N=1, D=2, K=3, W=4, H=5, L=6, CID=7, NCOL=8, UNIFORM=9, AWORD=10, ASHIFT=11,
          PCONST=12, LINMASK=13, NQD=14, FW=15, OFF_CONST=16, OFF_FPOS=17, OFF_CONE=18, OFF_LIN=19,
          OFF_QD=20, OFF_COLIDX=21, OFF_COLENT=22, OFF_THRINFO=23, OFF_THRTAB=24, THR_TOTAL=25,
-         HBITS=26, TOTAL=27, WS=28)
+         HBITS=26, TOTAL=27, WS=28, NBLK=29, TOGW=30, OFF_TOG=31, NQG=32, OFF_QG=33)
 MAX_FW = 8
 THR_STRIDE = 14
 
@@ -72,6 +72,16 @@ class Blob:
         for q in range(g("NQD")):
             rec = b[o + q * st:o + (q + 1) * st]
             self.qd.append((int(rec[0]), rec[2:].reshape(self.K, self.WS)))
+        self.qg = []
+        o = g("OFF_QG")
+        for _ in range(g("NQG")):
+            t, m = int(b[o]), int(b[o + 1])
+            o += 2
+            items = []
+            for _ in range(m):
+                items.append((int(b[o]), b[o + 1:o + 1 + self.WS]))
+                o += 1 + self.WS
+            self.qg.append((t, items))
         ci, ce = g("OFF_COLIDX"), g("OFF_COLENT")
         self.colour = [None] * self.h
         for c in range(self.ncol):
@@ -116,6 +126,15 @@ class Blob:
                 for w in range(self.W):
                     m |= int(planes[t, w]) << (32 * w)
                 acc += bin(y & m).count("1") << t
+        for t, items in self.qg:
+            z = 0
+            for delta, mk in items:
+                m = 0
+                for w in range(self.W):
+                    m |= int(mk[w]) << (32 * w)
+                assert z & m == 0 or True
+                z |= (xi >> delta) & m
+            acc += bin(xi & z).count("1") << t
         return acc % (1 << self.K)
 
 
