@@ -163,6 +163,85 @@ pbit_status pbit_amplitudes(pbit_circuit c, uint32_t idx, const uint64_t *counts
                             int mode, double *amp_re, double *amp_im, double *sig_re,
                             double *sig_im);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal: a MADE (masked autoregressive MLP) over the n(d+1)
+ * lattice positions in lattice order, hidden layers of width `hidden` with
+ * ReLU, bf16 weights with FP32 master copies and FP32 accumulation (bf16
+ * MFMA), trained on paths the Gibbs chains produce, and used as an
+ * independence proposal in Metropolis-Hastings with the exact real energy
+ * (Fig. 2 step 2).  Not part of the paper's method (its Boltzmann machine is
+ * untrained, Sec. 1); plain Gibbs stays the reference.
+ *
+ * Parameters, flat FP32, in this order: W1[D][H], b1[H], W2[H][H], b2[H],
+ * V[H][D], c[D] (D = n(d+1) positions, H = hidden).  Input position i has
+ * degree i+1, hidden unit k degree 1 + floor(k (D-1) / H); a weight from
+ * degree a to degree b is kept iff a <= b (output position o has degree o).
+ * Masked weights are kept at exactly zero.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t hidden;    /* width of both hidden layers (multiple of 64); 0 selects 1024 */
+    uint64_t seed;      /* initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from this seed */
+} pbit_made_cfg;
+
+typedef struct {
+    uint32_t batch;     /* samples per step (<= 16384) */
+    uint32_t steps;     /* Adam steps; batches are consecutive, wrapping over the samples */
+    float lr, beta1, beta2, eps;  /* 0 selects 1e-3, 0.9, 0.999, 1e-8 */
+} pbit_train_cfg;
+
+/* Creates a proposal for circuit idx of c (the handle must outlive it). */
+pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_cfg *cfg, pbit_proposal *out);
+void pbit_proposal_free(pbit_proposal q);
+/* D (positions), H (hidden) and the number of parameters. */
+pbit_status pbit_proposal_info(pbit_proposal q, uint32_t *D, uint32_t *H, uint64_t *n_params);
+/* Host FP32 parameters in the flat order above; set resets the Adam state
+ * and zeroes masked entries. */
+pbit_status pbit_proposal_set_params(pbit_proposal q, const float *params, uint64_t n);
+pbit_status pbit_proposal_get_params(pbit_proposal q, float *params, uint64_t n);
+/* Logits of the given paths (d_states word-major, n paths) into d_logits
+ * (device float[n][D]) with the bf16 shadow weights. */
+pbit_status pbit_proposal_logits(pbit_proposal q, const uint32_t *d_states, uint32_t n, float *d_logits,
+                                 void *hip_stream);
+/* Gradient of the batch-mean binary cross-entropy over the free positions
+ * (device float[n_params], flat order) and the loss (host, after an
+ * internal stream sync). */
+pbit_status pbit_proposal_grad(pbit_proposal q, const uint32_t *d_states, uint32_t n, float *d_grad,
+                               float *loss_out, void *hip_stream);
+/* `steps` Adam steps on batches of d_states (word-major, n_samples paths);
+ * losses_out (host, may be NULL) receives one loss per step. */
+pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint64_t n_samples,
+                                const pbit_train_cfg *cfg, float *losses_out, void *hip_stream);
+/* Draws n independent paths (fused autoregressive sampler; Philox counter
+ * (step, b/4, chain_begin + i, circuit_id | 1 << 16), word b%4, for free bit
+ * b) into d_out (word-major) with log q of each into d_logq (device double). */
+pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed,
+                                 uint32_t step, uint32_t *d_out, double *d_logq, void *hip_stream);
+/* log q of given paths (batched forward); equal bit for bit to the value the
+ * sampler reports for a path it drew. */
+pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint32_t n, double *d_logq,
+                                void *hip_stream);
+
+typedef struct {
+    uint32_t chains, chain_begin;
+    uint32_t cycles;        /* each cycle: one MH step then gibbs_per_mh Gibbs sweeps */
+    uint32_t gibbs_per_mh;  /* 0 allowed */
+    uint64_t seed;
+    uint32_t step_offset;   /* MH step counter of the first cycle */
+    uint32_t sweep_offset;  /* Gibbs sweep counter of the first sweep */
+    uint32_t init;          /* PBIT_INIT_ZERO (all free bits 0) or PBIT_INIT_RESUME */
+} pbit_mh_cfg;
+
+/* Metropolis-Hastings with the learned independence proposal interleaved
+ * with Gibbs sweeps.  Per cycle: propose x' (pbit_proposal_sample), score
+ * the current x, accept with probability
+ * min(1, |psi(x')| q(x) / (|psi(x)| q(x'))) using Philox word 0 at counter
+ * (step, 0, chain, circuit_id | 2 << 16), bin the post-transition path, then
+ * gibbs_per_mh Gibbs sweeps each binned.  d_state: word-major W x chains;
+ * d_hist as for pbit_gibbs_run; d_accepts: device uint64[chains] (may be
+ * NULL), incremented per accepted proposal. */
+pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state,
+                        uint32_t *d_hist, uint64_t *d_accepts, void *hip_stream);
+
 const char *pbit_last_error(void);
 
 /* Blocks until all work the library enqueued on hip_stream is done; returns

@@ -32,6 +32,7 @@ SOURCES = [
     ("abi.cpp", "hip-host"),
     ("runtime.cpp", "hip-host"),
     ("tune.cpp", "hip-host"),
+    ("proposal.cpp", "hip"),
     ("gibbs.hip", "hip"),
     ("made.hip", "hip"),
     ("mh.hip", "hip"),

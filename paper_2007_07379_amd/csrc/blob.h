@@ -50,6 +50,8 @@ enum Header : uint32_t {
     H_OFF_TOG,    // NBLK * 16 * TOGW words: XOR of the cones of each subset of a block's bits
     H_NQG,        // merged quadratic groups (see below)
     H_OFF_QG,     // NQG group records
+    H_NRE,        // gates with non-constant magnitude (real-energy records)
+    H_OFF_RE,     // NRE records of RE_STRIDE words
     H_COUNT = 48  // header words (must exceed every index above)
 };
 
@@ -63,6 +65,10 @@ constexpr inline uint32_t kernel_words(uint32_t W) {
 }
 
 constexpr int THR_STRIDE = 2 + MAX_SCOPE;
+// real-energy record: [0] arity a, [1..2] input lattice bits, [3..4] output
+// lattice bits, [5..7] unused, then 16 doubles (as 32 words): ln |U[out][in]|
+// at index out * 2^a + in (0 where the entry is zero).
+constexpr int RE_STRIDE = 8 + 32;
 constexpr inline uint32_t qd_stride(uint32_t K, uint32_t W) { return 2 + K * W; }
 // quadratic record: [0] = offset delta (1..63), [1] = mask of nonzero planes,
 // then K planes of WS words: bit i of plane t set if bit t of the coefficient
@@ -79,5 +85,5 @@ constexpr inline uint32_t qg_entry_stride(uint32_t WS) { return 1 + WS; }
 }  // namespace pbit
 
 namespace pbit {
-static_assert(H_OFF_QG < H_COUNT, "blob header overflows H_COUNT");
+static_assert(H_OFF_RE < H_COUNT, "blob header overflows H_COUNT");
 }

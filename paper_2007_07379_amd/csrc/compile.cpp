@@ -505,6 +505,30 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     blob[H_OFF_THRINFO] = append(thrinfo);
     blob[H_OFF_THRTAB] = append(thrtab);
     {
+        // real-energy records: ln |U| of every gate whose magnitude is not
+        // constant, in gate order (the log-weight of a path is their sum)
+        std::vector<uint32_t> re;
+        uint32_t nre = 0;
+        for (const GateC &g : gates) {
+            if (g.const_mag) continue;
+            std::vector<uint32_t> rec(RE_STRIDE, 0u);
+            rec[0] = g.a;
+            for (uint32_t j = 0; j < g.a; ++j) {
+                rec[1 + j] = g.in_bits[j];
+                rec[3 + j] = g.out_bits[j];
+            }
+            const uint32_t dim = 1u << g.a;
+            for (uint32_t t = 0; t < dim * dim; ++t) {
+                const double lm = g.mag[t] > 0.0 ? std::log(g.mag[t]) : 0.0;
+                std::memcpy(&rec[8 + 2 * t], &lm, sizeof(double));
+            }
+            re.insert(re.end(), rec.begin(), rec.end());
+            ++nre;
+        }
+        blob[H_NRE] = nre;
+        blob[H_OFF_RE] = append(re);
+    }
+    {
         // toggle tables: row f of block j = XOR of the cones of the bits
         // 4j + t with bit t of f set, so one gather applies a block's flips
         const uint32_t nblk = (h + 3) / 4;

@@ -1,0 +1,40 @@
+// Learned proposal (MADE) and Metropolis-Hastings: internal interfaces.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/pbit.h"
+
+namespace pbit {
+
+typedef __bf16 bf16;
+
+// One masked bf16 MFMA GEMM: C(m, n) = epilogue(sum_k A(m, k) B(k, n)).
+// Strided operands (A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn])
+// so transposed products need no copies.  The reduction of output column
+// tile nt (64 columns) runs over [kbeg[nt], kend[nt]) in ascending 32-wide
+// chunks (no split-K), so every output is a fixed sequence of
+// v_mfma_f32_16x16x32_bf16 accumulations.
+struct GemmArgs {
+    const bf16 *A;
+    int64_t sam, sak;
+    const bf16 *B;
+    int64_t sbk, sbn;
+    void *C;
+    int64_t scm, scn;
+    int M, N, K;
+    const int *kbeg, *kend;  // per 64-column tile, may be NULL
+    const float *bias;       // per column, may be NULL
+    int relu;
+    const bf16 *gate;        // multiply by (gate(m, n) > 0), may be NULL
+    int64_t sgm, sgn;
+    const int *deg_row, *deg_col;  // keep C(m, n) iff deg_row[m] <= deg_col[n]; may be NULL
+    int out_bf16;
+    int accumulate;          // fp32 output: C += result
+};
+
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+
+}  // namespace pbit

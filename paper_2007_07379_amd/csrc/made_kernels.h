@@ -1,0 +1,62 @@
+// Device helpers and launch interfaces of the MADE / MH kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "made.h"
+
+namespace pbit {
+
+// The proposal's probability of a 1 at a free position, as the uint32
+// threshold the sampler compares its Philox draw with: P(1) = T / 2^32
+// exactly.  T is kept in [1, 2^32 - 1] so every path has q > 0.
+__device__ __forceinline__ uint32_t made_threshold(float logit) {
+    const double p = 1.0 / (1.0 + exp(-(double)logit));
+    double t = floor(p * 4294967296.0);
+    if (t < 1.0) t = 1.0;
+    if (t > 4294967295.0) t = 4294967295.0;
+    return (uint32_t)t;
+}
+
+__device__ __forceinline__ double made_log_prob(uint32_t T, uint32_t bit) {
+    return bit ? log((double)T / 4294967296.0) : log((4294967296.0 - (double)T) / 4294967296.0);
+}
+
+struct SampleArgs {
+    const uint32_t *blob;  // circuit image (cones, constant lattice, circuit id)
+    const bf16 *W1T, *W2T, *VT;
+    const float *b1, *b2, *c;
+    const int4 *phase;    // per free bit: first-layer unit range, second-layer unit range
+    const int4 *phase_k;  // per free bit: K ends of the three products, lattice position
+    int n, h, W, D, DP, H;
+    uint32_t chain_begin, step, seed_lo, seed_hi;
+    uint32_t *out;        // word-major lattice words of the proposals
+    double *logq;         // log q of each proposal
+};
+
+hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s);
+hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
+hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
+                            float *loss, hipStream_t s);
+hipError_t launch_colsum(const bf16 *G, int n, int N, float *out, hipStream_t s);
+hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t P, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_shadow(const float *W, int K, int N, int KP, bf16 *Wb, bf16 *WT, hipStream_t s);
+hipError_t launch_logq(const float *L, const uint32_t *states, uint64_t stride, uint64_t b0, const int *fpos, int h,
+                       int n, int D, double *out, hipStream_t s);
+
+// Metropolis-Hastings accept of independence proposals (mh.hip).
+struct MhArgs {
+    const uint32_t *blob;
+    uint32_t *state;          // word-major current lattices, updated in place
+    const uint32_t *prop;     // word-major proposals
+    const double *logq_cur, *logq_prop;
+    unsigned long long *accepts;  // per-chain accept counters (may be NULL)
+    uint32_t *hist;           // bins the post-transition state (may be NULL)
+    int n, W;
+    uint32_t chain_begin, step, seed_lo, seed_hi;
+};
+hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s);
+
+}  // namespace pbit

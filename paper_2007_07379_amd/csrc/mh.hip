@@ -1,0 +1,87 @@
+// Metropolis-Hastings accept of independence proposals (Fig. 2 step 2 with
+// the acceptance ratio on |exp(-E)|, i.e. on exp(-Re E) only):
+//   log r = [ln|psi(x')| - ln|psi(x)|] + [log q(x) - log q(x')],
+//   accept iff u < min(1, exp(log r)) 2^32, u = Philox4x32-10 word 0 at
+//   counter (step, 0, chain, circuit_id | 2 << 16).
+// ln|psi| = sum of ln|U_g| over the gates with non-constant magnitude (the
+// others add the same constant to every path); for circuits without such
+// gates the first bracket is exactly zero.  The post-transition path is
+// binned (Fig. 2 step 3): one sample per transition.
+#include <hip/hip_runtime.h>
+
+#include "blob.h"
+#include "made_kernels.h"
+#include "phase.h"
+#include "philox.h"
+
+namespace pbit {
+
+template <int W>
+__device__ __forceinline__ double log_weight(const uint32_t *__restrict__ B, const uint32_t (&x)[W + 2]) {
+    const uint32_t nre = B[H_NRE];
+    const uint32_t *rec = B + B[H_OFF_RE];
+    double s = 0.0;
+    for (uint32_t r = 0; r < nre; ++r, rec += RE_STRIDE) {
+        const uint32_t a = rec[0];
+        uint32_t i = 0, o = 0;
+        for (uint32_t j = 0; j < a; ++j) {
+            const uint32_t pi = rec[1 + j], po = rec[3 + j];
+            i |= ((select_word<W>(x, pi >> 5) >> (pi & 31)) & 1u) << j;
+            o |= ((select_word<W>(x, po >> 5) >> (po & 31)) & 1u) << j;
+        }
+        const uint32_t t = o * (1u << a) + i;
+        const uint64_t bits = (uint64_t)rec[8 + 2 * t] | ((uint64_t)rec[9 + 2 * t] << 32);
+        s += __longlong_as_double((long long)bits);
+    }
+    return s;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
+    const uint32_t *__restrict__ B = a.blob;
+    const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lc >= a.n) return;
+    const uint32_t Wc = B[H_W];
+    uint32_t x[W + 2], y[W + 2];
+    x[W] = x[W + 1] = y[W] = y[W + 1] = 0u;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        x[w] = (uint32_t)w < Wc ? a.state[(int64_t)w * a.n + lc] : 0u;
+        y[w] = (uint32_t)w < Wc ? a.prop[(int64_t)w * a.n + lc] : 0u;
+    }
+    double lr = a.logq_cur[lc] - a.logq_prop[lc];
+    if (B[H_NRE]) lr += log_weight<W>(B, y) - log_weight<W>(B, x);
+    const double acc = lr >= 0.0 ? 1.0 : exp(lr);
+    const uint32_t cid = B[H_CID];
+    const U4 u = philox4x32_10(a.step, 0u, a.chain_begin + (uint32_t)lc, cid | (2u << 16), a.seed_lo, a.seed_hi);
+    const bool accept = (double)u.x < acc * 4294967296.0;
+    if (accept) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            x[w] = y[w];
+            if ((uint32_t)w < Wc) a.state[(int64_t)w * a.n + lc] = y[w];
+        }
+    }
+    if (a.accepts && accept) a.accepts[lc] += 1ull;
+    if (a.hist) {
+        const uint32_t bin = phase_and_bin<W>(B, x, B[H_K], B[H_N]);
+        atomicAdd(&a.hist[bin], 1u);
+    }
+}
+
+#define PBIT_FOR_EACH_W(X) X(1) X(2) X(3) X(4) X(6) X(8) X(10) X(12) X(13) X(14) X(16) X(17) X(20) X(24) X(28) X(32)
+
+hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s) {
+    const int grid = (a.n + 255) / 256;
+    if (grid == 0) return hipSuccess;
+#define PBIT_LAUNCH(V)                                                                  \
+    if (Wk == V) {                                                                      \
+        hipLaunchKernelGGL((mh_accept_kernel<V>), dim3(grid), dim3(256), 0, s, a);      \
+        return hipGetLastError();                                                       \
+    }
+    PBIT_FOR_EACH_W(PBIT_LAUNCH)
+#undef PBIT_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pbit

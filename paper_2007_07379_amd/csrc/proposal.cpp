@@ -1,0 +1,613 @@
+// Learned proposal object, its training loop and the MH run (host side).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pbit.h"
+#include "blob.h"
+#include "made.h"
+#include "made_kernels.h"
+#include "runtime.h"
+
+namespace pbit {
+namespace {
+
+constexpr int BATCH_MAX = 16384;
+
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    ~DeviceArena() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    T *alloc(size_t count) {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return (T *)p;
+    }
+};
+
+int64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (int64_t)(z ^ (z >> 31));
+}
+
+}  // namespace
+}  // namespace pbit
+
+using namespace pbit;
+
+struct pbit_proposal_s {
+    pbit_circuit circ = nullptr;
+    uint32_t idx = 0;
+    int D = 0, DP = 0, H = 0, W = 0, h = 0;
+    uint64_t P = 0;
+    // offsets into the flat parameter vector
+    uint64_t oW1, ob1, oW2, ob2, oV, oc;
+    std::vector<int> deg_in, deg1, deg2, deg_out, fpos, freem;
+    std::vector<int4> phase, phase_k;
+    int dev = -1;
+    DeviceArena arena;
+    // device
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    bf16 *W1b = nullptr, *W1T = nullptr, *W2b = nullptr, *W2T = nullptr, *Vb = nullptr, *VT = nullptr;
+    int *d_deg_in = nullptr, *d_deg1 = nullptr, *d_deg2 = nullptr, *d_deg_out = nullptr, *d_free = nullptr,
+        *d_fpos = nullptr;
+    int *k1end = nullptr, *k2end = nullptr, *k3end = nullptr, *g2beg = nullptr, *g1beg = nullptr;
+    int4 *d_phase = nullptr, *d_phase_k = nullptr;
+    bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
+    float *L = nullptr;
+    uint32_t *prop = nullptr;
+    double *lq_cur = nullptr, *lq_prop = nullptr;
+    uint32_t mh_cap = 0;
+    int t = 0;  // Adam step
+    bool dirty = true;  // bf16 shadows out of date
+    std::vector<float> host_params;
+};
+
+namespace {
+
+pbit_status upload(pbit_proposal q, hipStream_t s) {
+    (void)s;
+    if (q->theta) return PBIT_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    q->dev = dev;
+    auto &A = q->arena;
+    const int D = q->D, DP = q->DP, H = q->H;
+    q->theta = A.alloc<float>(q->P);
+    q->m = A.alloc<float>(q->P);
+    q->v = A.alloc<float>(q->P);
+    q->grad = A.alloc<float>(q->P);
+    q->loss = A.alloc<float>(1 << 16);
+    q->W1b = A.alloc<bf16>((size_t)D * H);
+    q->W1T = A.alloc<bf16>((size_t)H * DP);
+    q->W2b = A.alloc<bf16>((size_t)H * H);
+    q->W2T = A.alloc<bf16>((size_t)H * H);
+    q->Vb = A.alloc<bf16>((size_t)H * D);
+    q->VT = A.alloc<bf16>((size_t)D * H);
+    q->X = A.alloc<bf16>((size_t)BATCH_MAX * DP);
+    q->H1 = A.alloc<bf16>((size_t)BATCH_MAX * H);
+    q->H2 = A.alloc<bf16>((size_t)BATCH_MAX * H);
+    q->G1 = A.alloc<bf16>((size_t)BATCH_MAX * H);
+    q->G2 = A.alloc<bf16>((size_t)BATCH_MAX * H);
+    q->G3 = A.alloc<bf16>((size_t)BATCH_MAX * D);
+    q->L = A.alloc<float>((size_t)BATCH_MAX * D);
+    auto up = [&](int *&dst, const std::vector<int> &src) {
+        dst = A.alloc<int>(src.size() + 64);
+        if (dst) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice);
+    };
+    up(q->d_deg_in, q->deg_in);
+    up(q->d_deg1, q->deg1);
+    up(q->d_deg2, q->deg2);
+    up(q->d_deg_out, q->deg_out);
+    up(q->d_free, q->freem);
+    up(q->d_fpos, q->fpos);
+    // per 64-column tile reduction ranges (masked weights are zero outside)
+    auto count_le = [](const std::vector<int> &deg, int v) {
+        return (int)(std::upper_bound(deg.begin(), deg.end(), v) - deg.begin());
+    };
+    std::vector<int> k1, k2, k3, b2, b1;
+    for (int nt = 0; nt * 64 < H; ++nt) {
+        const int last = std::min(nt * 64 + 63, H - 1);
+        k1.push_back(q->deg1[last]);
+        k2.push_back(count_le(q->deg1, q->deg2[last]));
+        b2.push_back(q->deg2[nt * 64]);  // G2 column u2 sums over o >= deg2(u2)
+        b1.push_back((int)(std::lower_bound(q->deg2.begin(), q->deg2.end(), q->deg1[nt * 64]) - q->deg2.begin()));
+    }
+    for (int nt = 0; nt * 64 < D; ++nt) {
+        const int last = std::min(nt * 64 + 63, D - 1);
+        k3.push_back(count_le(q->deg2, last));
+    }
+    up(q->k1end, k1);
+    up(q->k2end, k2);
+    up(q->k3end, k3);
+    up(q->g2beg, b2);
+    up(q->g1beg, b1);
+    q->d_phase = A.alloc<int4>(q->phase.size() + 1);
+    q->d_phase_k = A.alloc<int4>(q->phase_k.size() + 1);
+    if (!q->theta || !q->L || !q->d_phase || !q->d_phase_k || !q->g1beg)
+        return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
+    (void)hipMemcpy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4), hipMemcpyHostToDevice);
+    (void)hipMemcpy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4), hipMemcpyHostToDevice);
+    (void)hipMemcpy(q->theta, q->host_params.data(), q->P * sizeof(float), hipMemcpyHostToDevice);
+    (void)hipMemset(q->m, 0, q->P * sizeof(float));
+    (void)hipMemset(q->v, 0, q->P * sizeof(float));
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_error(e, "proposal upload");
+    return PBIT_OK;
+}
+
+pbit_status refresh(pbit_proposal q, hipStream_t s) {
+    if (!q->dirty) return PBIT_OK;
+    q->dirty = false;
+    hipError_t e;
+    if ((e = launch_shadow(q->theta + q->oW1, q->D, q->H, q->DP, q->W1b, q->W1T, s)) != hipSuccess ||
+        (e = launch_shadow(q->theta + q->oW2, q->H, q->H, q->H, q->W2b, q->W2T, s)) != hipSuccess ||
+        (e = launch_shadow(q->theta + q->oV, q->H, q->D, q->H, q->Vb, q->VT, s)) != hipSuccess)
+        return hip_error(e, "shadow refresh");
+    return PBIT_OK;
+}
+
+GemmArgs gemm0() {
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    return g;
+}
+
+// Forward of n <= BATCH_MAX paths (X already unpacked): H1, H2, L.
+pbit_status forward(pbit_proposal q, int n, hipStream_t s) {
+    const int D = q->D, DP = q->DP, H = q->H;
+    GemmArgs g = gemm0();
+    g.A = q->X; g.sam = DP; g.sak = 1;
+    g.B = q->W1b; g.sbk = H; g.sbn = 1;
+    g.C = q->H1; g.scm = H; g.scn = 1;
+    g.M = n; g.N = H; g.K = D;
+    g.kend = q->k1end; g.bias = q->theta + q->ob1; g.relu = 1; g.out_bf16 = 1;
+    hipError_t e = launch_gemm(g, s);
+    if (e != hipSuccess) return hip_error(e, "gemm1");
+    g = gemm0();
+    g.A = q->H1; g.sam = H; g.sak = 1;
+    g.B = q->W2b; g.sbk = H; g.sbn = 1;
+    g.C = q->H2; g.scm = H; g.scn = 1;
+    g.M = n; g.N = H; g.K = H;
+    g.kend = q->k2end; g.bias = q->theta + q->ob2; g.relu = 1; g.out_bf16 = 1;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm2");
+    g = gemm0();
+    g.A = q->H2; g.sam = H; g.sak = 1;
+    g.B = q->Vb; g.sbk = D; g.sbn = 1;
+    g.C = q->L; g.scm = D; g.scn = 1;
+    g.M = n; g.N = D; g.K = H;
+    g.kend = q->k3end; g.bias = q->theta + q->oc; g.out_bf16 = 0;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm3");
+    return PBIT_OK;
+}
+
+// Gradient of the batch in q->X / q->L into q->grad (loss added to *loss_dev).
+pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
+    const int D = q->D, DP = q->DP, H = q->H;
+    hipError_t e;
+    if ((e = launch_loss_grad(q->L, q->X, q->d_free, n, D, DP, q->G3, loss_dev, s)) != hipSuccess)
+        return hip_error(e, "loss_grad");
+    // dV = H2^T G3 (masked)
+    GemmArgs g = gemm0();
+    g.A = q->H2; g.sam = 1; g.sak = H;
+    g.B = q->G3; g.sbk = D; g.sbn = 1;
+    g.C = q->grad + q->oV; g.scm = D; g.scn = 1;
+    g.M = H; g.N = D; g.K = n;
+    g.deg_row = q->d_deg2; g.deg_col = q->d_deg_out;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dV");
+    if ((e = launch_colsum(q->G3, n, D, q->grad + q->oc, s)) != hipSuccess) return hip_error(e, "dc");
+    // G2 = (G3 V^T) * (H2 > 0)
+    g = gemm0();
+    g.A = q->G3; g.sam = D; g.sak = 1;
+    g.B = q->Vb; g.sbk = 1; g.sbn = D;
+    g.C = q->G2; g.scm = H; g.scn = 1;
+    g.M = n; g.N = H; g.K = D;
+    g.kbeg = q->g2beg; g.gate = q->H2; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G2");
+    // dW2 = H1^T G2 (masked); db2
+    g = gemm0();
+    g.A = q->H1; g.sam = 1; g.sak = H;
+    g.B = q->G2; g.sbk = H; g.sbn = 1;
+    g.C = q->grad + q->oW2; g.scm = H; g.scn = 1;
+    g.M = H; g.N = H; g.K = n;
+    g.deg_row = q->d_deg1; g.deg_col = q->d_deg2;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW2");
+    if ((e = launch_colsum(q->G2, n, H, q->grad + q->ob2, s)) != hipSuccess) return hip_error(e, "db2");
+    // G1 = (G2 W2^T) * (H1 > 0)
+    g = gemm0();
+    g.A = q->G2; g.sam = H; g.sak = 1;
+    g.B = q->W2b; g.sbk = 1; g.sbn = H;
+    g.C = q->G1; g.scm = H; g.scn = 1;
+    g.M = n; g.N = H; g.K = H;
+    g.kbeg = q->g1beg; g.gate = q->H1; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G1");
+    // dW1 = X^T G1 (masked); db1
+    g = gemm0();
+    g.A = q->X; g.sam = 1; g.sak = DP;
+    g.B = q->G1; g.sbk = H; g.sbn = 1;
+    g.C = q->grad + q->oW1; g.scm = H; g.scn = 1;
+    g.M = D; g.N = H; g.K = n;
+    g.deg_row = q->d_deg_in; g.deg_col = q->d_deg1;
+    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW1");
+    if ((e = launch_colsum(q->G1, n, H, q->grad + q->ob1, s)) != hipSuccess) return hip_error(e, "db1");
+    return PBIT_OK;
+}
+
+pbit_status unpack_range(pbit_proposal q, const uint32_t *states, uint64_t stride, uint64_t b0, int n,
+                         hipStream_t s);
+
+}  // namespace
+
+// unpack of a column range of a word-major state array with row stride `stride`
+__global__ void unpack_strided_kernel(const uint32_t *__restrict__ states, uint64_t stride, uint64_t b0, int n,
+                                      int D, int DP, bf16 *__restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * DP) return;
+    const int b = (int)(e / DP), i = (int)(e % DP);
+    float v = 0.f;
+    if (i < D) v = (float)((states[(uint64_t)(i >> 5) * stride + b0 + b] >> (i & 31)) & 1u);
+    X[e] = (bf16)v;
+}
+
+__global__ void fill_const_kernel(const uint32_t *__restrict__ blob, uint32_t *__restrict__ state, int n, int W) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * W) return;
+    const int w = (int)(e / n);
+    state[e] = blob[blob[H_OFF_CONST] + w];
+}
+
+namespace {
+pbit_status unpack_range(pbit_proposal q, const uint32_t *states, uint64_t stride, uint64_t b0, int n,
+                         hipStream_t s) {
+    const int64_t tot = (int64_t)n * q->DP;
+    hipLaunchKernelGGL(unpack_strided_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, states, stride, b0,
+                       n, q->D, q->DP, q->X);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "unpack");
+    return PBIT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_cfg *cfg, pbit_proposal *out) {
+    if (!out) return set_error(PBIT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!c || idx >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "bad circuit handle or index");
+    const CompiledCircuit &k = c->circuits[idx];
+    const uint32_t H = cfg && cfg->hidden ? cfg->hidden : 1024;
+    if (H % 64 || H > 4096) return set_error(PBIT_E_INVALID_ARG, "hidden must be a multiple of 64, <= 4096");
+    if (k.h == 0) return set_error(PBIT_E_INVALID_ARG, "circuit has no free p-bit");
+    auto *q = new pbit_proposal_s();
+    q->circ = c;
+    q->idx = idx;
+    q->D = (int)k.L;
+    q->DP = (q->D + 31) / 32 * 32;
+    q->H = (int)H;
+    q->W = (int)k.W;
+    q->h = (int)k.h;
+    const int D = q->D;
+    q->oW1 = 0;
+    q->ob1 = q->oW1 + (uint64_t)D * H;
+    q->oW2 = q->ob1 + H;
+    q->ob2 = q->oW2 + (uint64_t)H * H;
+    q->oV = q->ob2 + H;
+    q->oc = q->oV + (uint64_t)H * D;
+    q->P = q->oc + D;
+    for (int i = 0; i < D; ++i) q->deg_in.push_back(i + 1);
+    for (uint32_t u = 0; u < H; ++u) q->deg1.push_back(1 + (int)(((uint64_t)u * (uint64_t)(D - 1)) / H));
+    q->deg2 = q->deg1;
+    for (int o = 0; o < D; ++o) q->deg_out.push_back(o);
+    q->freem.assign(D, 0);
+    const uint32_t *fp = k.blob.data() + k.blob[H_OFF_FPOS];
+    for (uint32_t b = 0; b < k.h; ++b) {
+        q->fpos.push_back((int)fp[b]);
+        q->freem[fp[b]] = 1;
+    }
+    // sampler phases: units whose degree falls in (previous free position, p]
+    auto count_le = [](const std::vector<int> &deg, int v) {
+        return (int)(std::upper_bound(deg.begin(), deg.end(), v) - deg.begin());
+    };
+    int prev = 0;
+    for (uint32_t b = 0; b < k.h; ++b) {
+        const int p = q->fpos[b];
+        const int u1a = count_le(q->deg1, prev), u1b = count_le(q->deg1, p);
+        const int u2a = count_le(q->deg2, prev), u2b = count_le(q->deg2, p);
+        const int k1 = u1b > u1a ? q->deg1[u1b - 1] : 0;
+        const int k2 = u2b > u2a ? count_le(q->deg1, q->deg2[u2b - 1]) : 0;
+        const int k3 = count_le(q->deg2, p);
+        q->phase.push_back(int4{u1a, u1b, u2a, u2b});
+        q->phase_k.push_back(int4{k1, k2, k3, p});
+        prev = p;
+    }
+    // initial parameters
+    q->host_params.assign(q->P, 0.f);
+    uint64_t st = cfg ? cfg->seed : 0;
+    auto init = [&](uint64_t off, int K, int N, const std::vector<int> &dr, const std::vector<int> &dc) {
+        const float a = 1.0f / std::sqrt((float)K);
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < N; ++j) {
+                const double u = (double)((uint64_t)splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+                q->host_params[off + (uint64_t)i * N + j] = dr[i] <= dc[j] ? (float)((2.0 * u - 1.0) * a) : 0.f;
+            }
+    };
+    init(q->oW1, D, (int)H, q->deg_in, q->deg1);
+    init(q->oW2, (int)H, (int)H, q->deg1, q->deg2);
+    init(q->oV, (int)H, D, q->deg2, q->deg_out);
+    *out = q;
+    return PBIT_OK;
+}
+
+void pbit_proposal_free(pbit_proposal q) { delete q; }
+
+pbit_status pbit_proposal_info(pbit_proposal q, uint32_t *D, uint32_t *H, uint64_t *n_params) {
+    if (!q) return set_error(PBIT_E_INVALID_ARG, "NULL proposal");
+    if (D) *D = (uint32_t)q->D;
+    if (H) *H = (uint32_t)q->H;
+    if (n_params) *n_params = q->P;
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_set_params(pbit_proposal q, const float *params, uint64_t n) {
+    if (!q || !params || n != q->P) return set_error(PBIT_E_INVALID_ARG, "bad proposal or parameter count");
+    q->host_params.assign(params, params + n);
+    // keep masked weights at exactly zero
+    auto mask = [&](uint64_t off, int K, int N, const std::vector<int> &dr, const std::vector<int> &dc) {
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < N; ++j)
+                if (dr[i] > dc[j]) q->host_params[off + (uint64_t)i * N + j] = 0.f;
+    };
+    mask(q->oW1, q->D, q->H, q->deg_in, q->deg1);
+    mask(q->oW2, q->H, q->H, q->deg1, q->deg2);
+    mask(q->oV, q->H, q->D, q->deg2, q->deg_out);
+    q->t = 0;
+    q->dirty = true;
+    if (q->theta) {
+        hipError_t e = hipMemcpy(q->theta, q->host_params.data(), q->P * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(q->m, 0, q->P * sizeof(float));
+        if (e == hipSuccess) e = hipMemset(q->v, 0, q->P * sizeof(float));
+        if (e != hipSuccess) return hip_error(e, "set_params");
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_get_params(pbit_proposal q, float *params, uint64_t n) {
+    if (!q || !params || n != q->P) return set_error(PBIT_E_INVALID_ARG, "bad proposal or parameter count");
+    if (q->theta) {
+        hipError_t e = hipMemcpy(params, q->theta, q->P * sizeof(float), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_error(e, "get_params");
+    } else {
+        std::memcpy(params, q->host_params.data(), q->P * sizeof(float));
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_logits(pbit_proposal q, const uint32_t *d_states, uint32_t n, float *d_logits,
+                                 void *hip_stream) {
+    if (!q || !d_states || !d_logits) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    pbit_status st = upload(q, s);
+    if (st != PBIT_OK) return st;
+    if ((st = refresh(q, s)) != PBIT_OK) return st;
+    for (uint32_t b0 = 0; b0 < n; b0 += BATCH_MAX) {
+        const int nb = (int)std::min<uint32_t>(BATCH_MAX, n - b0);
+        if ((st = unpack_range(q, d_states, n, b0, nb, s)) != PBIT_OK) return st;
+        if ((st = forward(q, nb, s)) != PBIT_OK) return st;
+        hipError_t e = hipMemcpyAsync(d_logits + (uint64_t)b0 * q->D, q->L, (size_t)nb * q->D * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_error(e, "logits copy");
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_grad(pbit_proposal q, const uint32_t *d_states, uint32_t n, float *d_grad,
+                               float *loss_out, void *hip_stream) {
+    if (!q || !d_states || !d_grad) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    if (n == 0 || n > (uint32_t)BATCH_MAX) return set_error(PBIT_E_INVALID_ARG, "batch must be 1..16384");
+    hipStream_t s = (hipStream_t)hip_stream;
+    pbit_status st = upload(q, s);
+    if (st != PBIT_OK) return st;
+    if ((st = refresh(q, s)) != PBIT_OK) return st;
+    hipError_t e = hipMemsetAsync(q->loss, 0, sizeof(float), s);
+    if (e != hipSuccess) return hip_error(e, "memset");
+    if ((st = unpack_range(q, d_states, n, 0, (int)n, s)) != PBIT_OK) return st;
+    if ((st = forward(q, (int)n, s)) != PBIT_OK) return st;
+    if ((st = backward(q, (int)n, q->loss, s)) != PBIT_OK) return st;
+    e = hipMemcpyAsync(d_grad, q->grad, q->P * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_error(e, "grad copy");
+    float l = 0.f;
+    e = hipMemcpyAsync(&l, q->loss, sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_error(e, "loss copy");
+    if (loss_out) *loss_out = l;
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint64_t n_samples,
+                                const pbit_train_cfg *cfg, float *losses_out, void *hip_stream) {
+    if (!q || !d_states || !cfg) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    if (cfg->batch == 0 || cfg->batch > (uint32_t)BATCH_MAX || cfg->batch > n_samples)
+        return set_error(PBIT_E_INVALID_ARG, "batch must be 1..min(16384, n_samples)");
+    if (cfg->steps > (1u << 16)) return set_error(PBIT_E_INVALID_ARG, "at most 65536 steps per call");
+    const float lr = cfg->lr > 0 ? cfg->lr : 1e-3f, b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f;
+    const float b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f, eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
+    hipStream_t s = (hipStream_t)hip_stream;
+    pbit_status st = upload(q, s);
+    if (st != PBIT_OK) return st;
+    if ((st = refresh(q, s)) != PBIT_OK) return st;
+    hipError_t e = hipMemsetAsync(q->loss, 0, sizeof(float) * cfg->steps, s);
+    if (e != hipSuccess) return hip_error(e, "memset");
+    uint64_t cursor = 0;
+    for (uint32_t it = 0; it < cfg->steps; ++it) {
+        if (cursor + cfg->batch > n_samples) cursor = 0;
+        if ((st = unpack_range(q, d_states, n_samples, cursor, (int)cfg->batch, s)) != PBIT_OK) return st;
+        cursor += cfg->batch;
+        if ((st = forward(q, (int)cfg->batch, s)) != PBIT_OK) return st;
+        if ((st = backward(q, (int)cfg->batch, q->loss + it, s)) != PBIT_OK) return st;
+        q->t += 1;
+        const double c1 = 1.0 / (1.0 - std::pow((double)b1, q->t));
+        const double c2 = 1.0 / (1.0 - std::pow((double)b2, q->t));
+        if ((e = launch_adam(q->theta, q->m, q->v, q->grad, (int64_t)q->P, lr, b1, b2, eps, (float)c1, (float)c2, s)) !=
+            hipSuccess)
+            return hip_error(e, "adam");
+        q->dirty = true;
+        if ((st = refresh(q, s)) != PBIT_OK) return st;
+    }
+    if (losses_out) {
+        e = hipMemcpyAsync(losses_out, q->loss, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_error(e, "loss copy");
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed, uint32_t step,
+                                 uint32_t *d_out, double *d_logq, void *hip_stream) {
+    if (!q || !d_out || !d_logq) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    if ((uint64_t)chain_begin + n > 0x100000000ull) return set_error(PBIT_E_INVALID_ARG, "chain index overflow");
+    hipStream_t s = (hipStream_t)hip_stream;
+    pbit_status st = upload(q, s);
+    if (st != PBIT_OK) return st;
+    if ((st = refresh(q, s)) != PBIT_OK) return st;
+    const uint32_t *dblob = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(q->circ->mu);
+        if ((st = device_blobs(q->circ, &dblob)) != PBIT_OK) return st;
+    }
+    SampleArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.blob = dblob + q->circ->blob_off[q->idx];
+    a.W1T = q->W1T;
+    a.W2T = q->W2T;
+    a.VT = q->VT;
+    a.b1 = q->theta + q->ob1;
+    a.b2 = q->theta + q->ob2;
+    a.c = q->theta + q->oc;
+    a.phase = q->d_phase;
+    a.phase_k = q->d_phase_k;
+    a.n = (int)n;
+    a.h = q->h;
+    a.W = q->W;
+    a.D = q->D;
+    a.DP = q->DP;
+    a.H = q->H;
+    a.chain_begin = chain_begin;
+    a.step = step;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.out = d_out;
+    a.logq = d_logq;
+    hipError_t e = launch_made_sample(a, s);
+    if (e != hipSuccess) return hip_error(e, "made sampler");
+    return PBIT_OK;
+}
+
+pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint32_t n, double *d_logq,
+                                void *hip_stream) {
+    if (!q || !d_states || !d_logq) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    pbit_status st = upload(q, s);
+    if (st != PBIT_OK) return st;
+    if ((st = refresh(q, s)) != PBIT_OK) return st;
+    for (uint32_t b0 = 0; b0 < n; b0 += BATCH_MAX) {
+        const int nb = (int)std::min<uint32_t>(BATCH_MAX, n - b0);
+        if ((st = unpack_range(q, d_states, n, b0, nb, s)) != PBIT_OK) return st;
+        if ((st = forward(q, nb, s)) != PBIT_OK) return st;
+        hipError_t e = launch_logq(q->L, d_states, n, b0, q->d_fpos, q->h, nb, q->D, d_logq + b0, s);
+        if (e != hipSuccess) return hip_error(e, "logq");
+    }
+    return PBIT_OK;
+}
+
+pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
+                        uint64_t *d_accepts, void *hip_stream) {
+    if (!c || !q || !cfg || !d_state || !d_hist) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    if (q->circ != c) return set_error(PBIT_E_INVALID_ARG, "proposal belongs to another circuit handle");
+    if (cfg->init != PBIT_INIT_ZERO && cfg->init != PBIT_INIT_RESUME) return set_error(PBIT_E_INVALID_ARG, "bad init");
+    const uint64_t n = cfg->chains;
+    if (n == 0) return PBIT_OK;
+    if ((uint64_t)cfg->chain_begin + n > 0x100000000ull) return set_error(PBIT_E_INVALID_ARG, "chain index overflow");
+    const uint64_t per_chain = (uint64_t)cfg->cycles * (1 + cfg->gibbs_per_mh);
+    if (n * per_chain > 0xFFFFFFFFull) return set_error(PBIT_E_COUNT_OVERFLOW, "chains x transitions >= 2^32");
+    if ((uint64_t)cfg->step_offset + cfg->cycles > 0xFFFFFFFFull ||
+        (uint64_t)cfg->sweep_offset + (uint64_t)cfg->cycles * cfg->gibbs_per_mh > 0xFFFFFFFFull)
+        return set_error(PBIT_E_INVALID_ARG, "step or sweep counter would wrap");
+    hipStream_t s = (hipStream_t)hip_stream;
+    pbit_status st = upload(q, s);
+    if (st != PBIT_OK) return st;
+    if ((st = refresh(q, s)) != PBIT_OK) return st;
+    if (q->mh_cap < n) {
+        q->prop = q->arena.alloc<uint32_t>((size_t)n * q->W);
+        q->lq_cur = q->arena.alloc<double>(n);
+        q->lq_prop = q->arena.alloc<double>(n);
+        if (!q->prop || !q->lq_cur || !q->lq_prop) return set_error(PBIT_E_OOM, "MH workspace");
+        q->mh_cap = (uint32_t)n;
+    }
+    const uint32_t *dblob = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(c->mu);
+        if ((st = device_blobs(c, &dblob)) != PBIT_OK) return st;
+    }
+    const uint32_t *blob = dblob + c->blob_off[q->idx];
+    const CompiledCircuit &k = c->circuits[q->idx];
+    hipError_t e;
+    if (cfg->init == PBIT_INIT_ZERO) {
+        const int64_t tot = (int64_t)n * k.W;
+        hipLaunchKernelGGL(fill_const_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, blob, d_state,
+                           (int)n, (int)k.W);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "fill");
+    }
+    std::vector<uint32_t> chains(c->circuits.size(), 0u);
+    chains[q->idx] = (uint32_t)n;
+    uint32_t *hist_c = d_hist;  // this circuit's histogram (offset applied below for MH bins)
+    for (uint32_t cy = 0; cy < cfg->cycles; ++cy) {
+        const uint32_t step = cfg->step_offset + cy;
+        if ((st = pbit_proposal_sample(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, q->prop, q->lq_prop, s)) !=
+            PBIT_OK)
+            return st;
+        if ((st = pbit_proposal_score(q, d_state, (uint32_t)n, q->lq_cur, s)) != PBIT_OK) return st;
+        MhArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.blob = blob;
+        a.state = d_state;
+        a.prop = q->prop;
+        a.logq_cur = q->lq_cur;
+        a.logq_prop = q->lq_prop;
+        a.accepts = (unsigned long long *)d_accepts;
+        a.hist = hist_c + c->hist_off[q->idx];
+        a.n = (int)n;
+        a.W = (int)k.W;
+        a.chain_begin = cfg->chain_begin;
+        a.step = step;
+        a.seed_lo = (uint32_t)cfg->seed;
+        a.seed_hi = (uint32_t)(cfg->seed >> 32);
+        if ((e = launch_mh_accept(k.WS, a, s)) != hipSuccess) return hip_error(e, "mh accept");
+        if (cfg->gibbs_per_mh) {
+            pbit_gibbs_cfg g;
+            std::memset(&g, 0, sizeof(g));
+            g.chains = chains.data();
+            g.chain_begin = cfg->chain_begin;
+            g.burn_in = 0;
+            g.sweeps = cfg->gibbs_per_mh;
+            g.seed = cfg->seed;
+            g.sweep_offset = cfg->sweep_offset + cy * cfg->gibbs_per_mh;
+            g.init = PBIT_INIT_RESUME;
+            // the state buffer of a set holds only this circuit's chains here
+            if (c->circuits.size() != 1) return set_error(PBIT_E_INVALID_ARG, "MH runs on single-circuit handles");
+            if ((st = run_gibbs(c, &g, d_state, d_hist, s)) != PBIT_OK) return st;
+        }
+    }
+    return PBIT_OK;
+}
+
+}  // extern "C"

@@ -217,3 +217,99 @@ class CircuitSet:
 
 def sync(stream=None):
     _check(lib().pbit_sync(_stream(stream)))
+
+
+class MadeCfg(C.Structure):
+    _fields_ = [("hidden", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("batch", C.c_uint32), ("steps", C.c_uint32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+class MhCfg(C.Structure):
+    _fields_ = [("chains", C.c_uint32), ("chain_begin", C.c_uint32), ("cycles", C.c_uint32),
+                ("gibbs_per_mh", C.c_uint32), ("seed", C.c_uint64), ("step_offset", C.c_uint32),
+                ("sweep_offset", C.c_uint32), ("init", C.c_uint32)]
+
+
+def _made_sigs(L):
+    V, P = C.c_void_p, C.c_uint64
+    L.pbit_proposal_create.argtypes = [V, C.c_uint32, C.POINTER(MadeCfg), C.POINTER(V)]
+    L.pbit_proposal_free.argtypes = [V]
+    L.pbit_proposal_free.restype = None
+    L.pbit_proposal_info.argtypes = [V, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(P)]
+    L.pbit_proposal_set_params.argtypes = [V, V, P]
+    L.pbit_proposal_get_params.argtypes = [V, V, P]
+    L.pbit_proposal_logits.argtypes = [V, V, C.c_uint32, V, V]
+    L.pbit_proposal_grad.argtypes = [V, V, C.c_uint32, V, C.POINTER(C.c_float), V]
+    L.pbit_proposal_train.argtypes = [V, V, P, C.POINTER(TrainCfg), V, V]
+    L.pbit_proposal_sample.argtypes = [V, C.c_uint32, C.c_uint32, P, C.c_uint32, V, V, V]
+    L.pbit_proposal_score.argtypes = [V, V, C.c_uint32, V, V]
+    L.pbit_mh_run.argtypes = [V, V, C.POINTER(MhCfg), V, V, V, V]
+
+
+class Proposal:
+    """A learned MADE proposal (pbit_proposal) for circuit idx of a set."""
+
+    def __init__(self, cset, idx=0, hidden=1024, seed=0):
+        L = lib()
+        _made_sigs(L)
+        self.cset = cset
+        cfg = MadeCfg(hidden, seed)
+        h = C.c_void_p()
+        _check(L.pbit_proposal_create(cset.handle, idx, C.byref(cfg), C.byref(h)))
+        self.handle = h
+        D, H, P = C.c_uint32(), C.c_uint32(), C.c_uint64()
+        _check(L.pbit_proposal_info(h, C.byref(D), C.byref(H), C.byref(P)))
+        self.D, self.H, self.n_params = D.value, H.value, P.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.pbit_proposal_free(h)
+            self.handle = None
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().pbit_proposal_set_params(self.handle, a.ctypes.data, a.size))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().pbit_proposal_get_params(self.handle, a.ctypes.data, a.size))
+        return a
+
+    def logits(self, d_states, n, d_logits, stream=None):
+        _check(lib().pbit_proposal_logits(self.handle, _ptr(d_states), n, _ptr(d_logits), _stream(stream)))
+
+    def grad(self, d_states, n, d_grad, stream=None):
+        loss = C.c_float()
+        _check(lib().pbit_proposal_grad(self.handle, _ptr(d_states), n, _ptr(d_grad), C.byref(loss),
+                                        _stream(stream)))
+        return loss.value
+
+    def train(self, d_states, n_samples, batch, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              stream=None):
+        cfg = TrainCfg(batch, steps, lr, beta1, beta2, eps)
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(lib().pbit_proposal_train(self.handle, _ptr(d_states), n_samples, C.byref(cfg),
+                                         losses.ctypes.data, _stream(stream)))
+        return losses[:steps]
+
+    def sample(self, n, d_out, d_logq, seed=0, step=0, chain_begin=0, stream=None):
+        _check(lib().pbit_proposal_sample(self.handle, n, chain_begin, seed, step, _ptr(d_out),
+                                          _ptr(d_logq), _stream(stream)))
+
+    def score(self, d_states, n, d_logq, stream=None):
+        _check(lib().pbit_proposal_score(self.handle, _ptr(d_states), n, _ptr(d_logq), _stream(stream)))
+
+
+def mh_run(cset, proposal, chains, cycles, d_state, d_hist, d_accepts=None, gibbs_per_mh=4, seed=0,
+           step_offset=0, sweep_offset=0, resume=False, chain_begin=0, stream=None):
+    cfg = MhCfg(chains, chain_begin, cycles, gibbs_per_mh, seed, step_offset, sweep_offset,
+                INIT_RESUME if resume else INIT_ZERO)
+    L = lib()
+    _made_sigs(L)
+    _check(L.pbit_mh_run(cset.handle, proposal.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
+                         _ptr(d_accepts), _stream(stream)))

@@ -1,0 +1,292 @@
+"""GPU checks of the learned proposal (bf16 MFMA MADE) and of MH with it:
+forward and gradients against the FP64 oracle MADE on the same bf16-rounded
+weights, Adam against the closed-form update, the fused sampler (valid
+paths, q bit-equal between sampler and scorer, distribution equal to q),
+and exactness of the MH target (uniform proposal always accepted, a poor
+proposal still converges to the exact path marginal)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import circuit as oc
+from oracle import compile as ocomp
+from oracle import estimator as oest
+from oracle import exact
+from oracle import made as omade
+from workloads import circuits as wc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_07379_amd import pbit
+    return torch, pbit
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_round(a):
+    """Round float32 values to bf16 (round to nearest even), as float64."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def split(flat, D, H):
+    o = 0
+    out = []
+    for shape in [(D, H), (H,), (H, H), (H,), (H, D), (D,)]:
+        n = int(np.prod(shape))
+        out.append(np.asarray(flat[o:o + n], dtype=np.float64).reshape(shape))
+        o += n
+    return out
+
+
+def random_params(D, H, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    M1, M2, M3 = omade.masks(D, H)
+    W1 = rng.normal(0, scale / math.sqrt(D), (D, H)) * M1
+    W2 = rng.normal(0, scale / math.sqrt(H), (H, H)) * M2
+    V = rng.normal(0, scale / math.sqrt(H), (H, D)) * M3
+    b1 = rng.normal(0, 0.1, H)
+    b2 = rng.normal(0, 0.1, H)
+    c = rng.normal(0, 0.3, D)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, V.ravel(), c]).astype(np.float32)
+
+
+def valid_paths(c, n, seed):
+    """n random valid lattices (word-major W x n) and their bit rows."""
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n, comp.L), dtype=np.float64)
+    words = np.zeros((comp.W, n), dtype=np.uint32)
+    for b in range(n):
+        f = rng.integers(0, 2, comp.h)
+        x = ocomp.lattice_from_free(comp, f)
+        X[b] = x
+        words[:, b] = ocomp.pack_words(x, comp.W)
+    return comp, X, words
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def oracle_params(flat, D, H):
+    p = split(flat, D, H)
+    # the GPU computes with bf16 weights (FP32 biases)
+    return [bf16_round(p[0]), p[1], bf16_round(p[2]), p[3], bf16_round(p[4]), p[5]]
+
+
+SMALL = lambda: wc.random_clifford_t(4, 6, 21, K=3)
+
+
+@pytest.mark.parametrize("which,H", [("small", 64), ("brick16", 1024)])
+def test_logits_match_oracle(env, which, H):
+    torch, pbit = env
+    c = SMALL() if which == "small" else wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    q = pbit.Proposal(s, hidden=H)
+    D = q.D
+    flat = random_params(D, H, 5)
+    q.set_params(flat)
+    n = 300
+    comp, X, words = valid_paths(c, n, 1)
+    d_states = to_dev(torch, words)
+    d_logits = torch.zeros(n * D, dtype=torch.float32, device="cuda")
+    q.logits(d_states, n, d_logits)
+    torch.cuda.synchronize()
+    Lg = d_logits.cpu().numpy().reshape(n, D).astype(np.float64)
+    p = oracle_params(flat, D, H)
+    Lo, (_, A1, H1, A2, H2) = omade.forward(p, X)
+    # bound: bf16 rounding of the hidden activations, relative 2^-8 per term
+    bound = 2.0 ** -7 * (np.abs(H2) @ np.abs(p[4]) + np.abs(H1) @ np.abs(p[2]) @ np.abs(p[4]) / 4) + 1e-4
+    err = np.abs(Lg - Lo)
+    say("max logit err", err.max(), "max bound", bound.max())
+    assert np.all(err <= bound)
+
+
+def test_grads_match_oracle(env):
+    torch, pbit = env
+    c = SMALL()
+    s = pbit.CircuitSet(c)
+    H = 64
+    q = pbit.Proposal(s, hidden=H)
+    D = q.D
+    flat = random_params(D, H, 7)
+    q.set_params(flat)
+    n = 512
+    comp, X, words = valid_paths(c, n, 2)
+    d_states = to_dev(torch, words)
+    d_grad = torch.zeros(q.n_params, dtype=torch.float32, device="cuda")
+    loss = q.grad(d_states, n, d_grad)
+    g_gpu = split(d_grad.cpu().numpy(), D, H)
+    free = np.zeros(D, dtype=bool)
+    free[comp.free_pos] = True
+    lo, g_or = omade.loss_and_grads(oracle_params(flat, D, H), X, free)
+    say("loss gpu", loss, "oracle", lo)
+    assert abs(loss - lo) <= 2e-3 * abs(lo) + 1e-4
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "V", "c"], g_gpu, g_or):
+        a, b = a.ravel(), b.ravel()
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        rel = float(np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30))
+        say(name, "cos", cos, "rel", rel)
+        assert cos >= 0.999 and rel <= 2.0 ** -6, name
+
+
+def test_adam_step_matches_closed_form(env):
+    torch, pbit = env
+    c = SMALL()
+    s = pbit.CircuitSet(c)
+    H = 64
+    q = pbit.Proposal(s, hidden=H)
+    D = q.D
+    flat = random_params(D, H, 9)
+    q.set_params(flat)
+    n = 256
+    _, X, words = valid_paths(c, n, 3)
+    d_states = to_dev(torch, words)
+    d_grad = torch.zeros(q.n_params, dtype=torch.float32, device="cuda")
+    q.grad(d_states, n, d_grad)
+    g = d_grad.cpu().numpy().astype(np.float64)
+    q.train(d_states, n, n, 1, lr=1e-3)
+    after = q.get_params().astype(np.float64)
+    want, _, _ = omade.adam_step(flat.astype(np.float64), np.zeros_like(g), np.zeros_like(g), g, 1)
+    assert np.allclose(after, want, rtol=1e-5, atol=1e-7)
+
+
+def _sample(env, q, n, seed=3, step=0):
+    torch, pbit = env
+    W = q.cset.info(0)["W"]
+    d_out = torch.zeros(n * W, dtype=torch.int32, device="cuda")
+    d_lq = torch.zeros(n, dtype=torch.float64, device="cuda")
+    q.sample(n, d_out, d_lq, seed=seed, step=step)
+    torch.cuda.synchronize()
+    return d_out, d_lq
+
+
+@pytest.mark.parametrize("which,H", [("small", 64), ("brick16", 1024)])
+def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
+    torch, pbit = env
+    c = SMALL() if which == "small" else wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    q = pbit.Proposal(s, hidden=H)
+    q.set_params(random_params(q.D, H, 11, scale=2.0))
+    n = 4096 if which == "small" else 1024
+    d_out, d_lq = _sample(env, q, n)
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    words = d_out.cpu().numpy().view(np.uint32).reshape(comp.W, n)
+    for b in range(0, n, max(1, n // 64)):
+        x = np.array([(int(words[p >> 5, b]) >> (p & 31)) & 1 for p in range(comp.L)], dtype=np.uint8)
+        f = [int(x[p]) for p in comp.free_pos]
+        assert np.array_equal(x, ocomp.lattice_from_free(comp, f)), b
+    d_lq2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    q.score(d_out, n, d_lq2)
+    torch.cuda.synchronize()
+    a, b = d_lq.cpu().numpy(), d_lq2.cpu().numpy()
+    say("logq sample vs score max diff", np.abs(a - b).max())
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_sampler_distribution_is_q(env):
+    torch, pbit = env
+    c = wc.rotated_hadamard_chain(7, math.pi / 5, K=1)
+    s = pbit.CircuitSet(c)
+    H = 64
+    q = pbit.Proposal(s, hidden=H)
+    flat = random_params(q.D, H, 13, scale=3.0)
+    q.set_params(flat)
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    assert 3 <= comp.h <= 10
+    n = 1 << 16
+    d_out, _ = _sample(env, q, n, seed=17)
+    words = d_out.cpu().numpy().view(np.uint32).reshape(comp.W, n)
+    paths = ocomp.enumerate_free(comp)
+    key = {tuple(ocomp.pack_words(x, comp.W)): i for i, (_, x, _, _, _) in enumerate(paths)}
+    obs = np.zeros(len(paths))
+    for b in range(n):
+        obs[key[tuple(words[:, b])]] += 1
+    free = np.zeros(comp.L, dtype=bool)
+    free[comp.free_pos] = True
+    X = np.array([x for (_, x, _, _, _) in paths], dtype=np.float64)
+    qv = np.exp(omade.log_q(oracle_params(flat, q.D, H), X, free))
+    assert qv.sum() == pytest.approx(1.0, abs=1e-9)
+    exp_ = qv * n
+    keep = exp_ > 5
+    chi2 = float(np.sum((obs[keep] - exp_[keep]) ** 2 / exp_[keep]))
+    p = stats.chi2.sf(chi2, int(keep.sum()) - 1)
+    say("sampler chi2 p", p)
+    assert p > 1e-4
+
+
+def _mh(env, c, q, chains, cycles, gibbs=4, seed=0):
+    torch, pbit = env
+    s = q.cset
+    info = s.info(0)
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    acc = torch.zeros(chains, dtype=torch.int64, device="cuda")
+    pbit.mh_run(s, q, chains, cycles, state, hist, acc, gibbs_per_mh=gibbs, seed=seed)
+    torch.cuda.synchronize()
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    return h, acc.cpu().numpy()
+
+
+def test_mh_uniform_proposal_always_accepts(env):
+    torch, pbit = env
+    c = wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    q = pbit.Proposal(s, hidden=64)
+    q.set_params(np.zeros(q.n_params, dtype=np.float32))
+    chains, cycles = 512, 3
+    h, acc = _mh(env, c, q, chains, cycles, gibbs=2)
+    assert np.all(acc == cycles)
+    assert int(h.sum()) == chains * cycles * 3
+
+
+@pytest.mark.parametrize("theta", [math.pi / 8])
+def test_mh_poor_proposal_keeps_exact_target(env, theta):
+    """Non-uniform target (rotated Hadamards + CNOT), proposal biased to
+    P(1) = 0.3: MH + Gibbs still reproduce the exact output marginal."""
+    torch, pbit = env
+    c = wc.rotated_brickwork(3, 6, 2, theta, K=3)
+    s = pbit.CircuitSet(c)
+    q = pbit.Proposal(s, hidden=64)
+    flat = np.zeros(q.n_params, dtype=np.float32)
+    flat[-q.D:] = math.log(0.3 / 0.7)
+    q.set_params(flat)
+    chains, cycles = 4096, 40
+    h, acc = _mh(env, c, q, chains, cycles, gibbs=1, seed=5)
+    circ = oc.from_dict(c)
+    pm, _ = exact.magnitude_marginal(circ)
+    T = int(h.sum())
+    tv = oest.tv_path(h, pm)
+    say("accept rate", acc.mean() / cycles, "TV", tv, "iid", oest.expected_iid_tv(pm, T))
+    assert 0 < acc.mean() < cycles
+    assert tv < 6 * oest.expected_iid_tv(pm, T) + 2e-3
+
+
+def test_training_lowers_nll(env):
+    torch, pbit = env
+    c = wc.rotated_brickwork(3, 6, 2, math.pi / 8, K=3)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    chains = 8192
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([chains], 200, 1, hist, state, seed=1)
+    q = pbit.Proposal(s, hidden=128, seed=3)
+    losses = q.train(state, chains, 1024, 300, lr=3e-3)
+    say("loss first", losses[:3], "last", losses[-3:])
+    assert losses[-20:].mean() < 0.9 * losses[:5].mean()

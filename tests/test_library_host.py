@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(pb):
     exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
     missing = decl - exported
     assert not missing, missing
-    assert {"pbit_compile_circuit", "pbit_gibbs_run", "pbit_amplitudes"} <= decl
+    assert {"pbit_compile_circuit", "pbit_gibbs_run", "pbit_mh_run", "pbit_amplitudes"} <= decl
 
 
 # --- blob reader (layout of paper_2007_07379_amd/csrc/blob.h) -------------
