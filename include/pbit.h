@@ -134,6 +134,8 @@ typedef struct {
     uint32_t use_graph;         /* 1: replay the sweep groups as a captured hipGraph */
     uint32_t hist_mode;         /* 0 = auto, 1 = LDS-privatised, 2 = global atomics */
     uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
+    uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
+    uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its
@@ -146,7 +148,11 @@ typedef struct {
  *          c at S_i + w * chains_i + c); written at the end, read at the
  *          start when init == RESUME; may be NULL with init == ZERO.
  * d_hist:  device, sum_i 2^(n_i+K_i) uint32 at hist_offset; added to.
- * COUNT_OVERFLOW if some chains_i * sweeps >= 2^32. */
+ * COUNT_OVERFLOW if some chains_i * sweeps >= 2^32.
+ * Persistent mode: every circuit with uniform conditionals is cut into
+ * tiles of 256 chains, tiles are sorted by decreasing cost and one
+ * persistent launch per lattice-width class (W <= 8, <= 17, <= 32) pulls
+ * them from an atomic counter; results equal separate runs bit for bit. */
 pbit_status pbit_gibbs_run(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state,
                            uint32_t *d_hist, void *hip_stream);
 
@@ -241,6 +247,16 @@ typedef struct {
  * NULL), incremented per accepted proposal. */
 pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state,
                         uint32_t *d_hist, uint64_t *d_accepts, void *hip_stream);
+
+/* Autotuner.  Times candidate launch shapes (workgroup size, histogram
+ * privatisation, toggle tables, sweeps per launch, persistent grid size) on
+ * short runs of cfg's workload on hip_stream and keeps the fastest per
+ * circuit (and per batched class) in the handle; later runs whose cfg
+ * leaves those fields 0 use it.  With cache_path the choices are read from /
+ * written to that JSON file, keyed by a hash of the compiled circuits, so a
+ * second process skips the timing.  Uses temporary device buffers; blocks
+ * until done. */
+pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char *cache_path, void *hip_stream);
 
 const char *pbit_last_error(void);
 

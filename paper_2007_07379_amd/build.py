@@ -33,6 +33,7 @@ SOURCES = [
     ("runtime.cpp", "hip-host"),
     ("tune.cpp", "hip-host"),
     ("proposal.cpp", "hip"),
+    ("autotune.cpp", "hip-host"),
     ("gibbs.hip", "hip"),
     ("made.hip", "hip"),
     ("mh.hip", "hip"),

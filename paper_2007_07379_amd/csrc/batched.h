@@ -1,0 +1,36 @@
+// Persistent batched launch interface (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pbit {
+
+struct BatchCirc {
+    const uint32_t *blob;  // device image of the circuit
+    uint32_t *state;       // this circuit's word-major lattice words
+    uint32_t *hist;        // this circuit's histogram
+    uint32_t n_chains;
+    uint32_t lds_hist;     // histogram privatised in LDS for this circuit
+    uint32_t Wk;           // compiled width (image stride)
+    uint32_t pad;
+};
+
+struct BatchTile {
+    uint32_t circ;  // index into the BatchCirc array
+    uint32_t c0;    // first local chain of the tile
+};
+
+struct BatchArgs {
+    const BatchCirc *circs;
+    const BatchTile *tiles;
+    uint32_t ntiles;
+    uint32_t *queue;  // tile counter, reset before every launch
+    uint32_t chain_begin, seed_lo, seed_hi;
+    uint32_t sweep_begin, n_sweeps, bin_from, resume;
+};
+
+// lattice-width class of a circuit: 0 for W <= 8, 1 for W <= 17, 2 above
+int batched_class_of(uint32_t Wk);
+hipError_t launch_batched(int cls, const BatchArgs &a, uint32_t grid, size_t lds, hipStream_t s);
+
+}  // namespace pbit

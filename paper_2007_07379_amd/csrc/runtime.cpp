@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "batched.h"
 #include "blob.h"
 #include "gibbs.h"
 #include "tune.h"
@@ -76,6 +77,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (cfg->init == PBIT_INIT_RESUME && !d_state) return set_error(PBIT_E_INVALID_ARG, "RESUME needs d_state");
     if (cfg->hist_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad hist_mode");
     if (cfg->toggle_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad toggle_mode");
+    if (cfg->persistent > 2) return set_error(PBIT_E_INVALID_ARG, "bad persistent mode");
+    if (cfg->wg_per_cu > 16) return set_error(PBIT_E_INVALID_ARG, "wg_per_cu must be <= 16");
     if (cfg->block_size && (cfg->block_size % 64 || cfg->block_size > 256))
         return set_error(PBIT_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
@@ -102,7 +105,31 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     pbit_status st = device_blobs(c, &dblob);
     if (st != PBIT_OK) return st;
 
-    // plan every launch first (argument errors before any enqueue)
+    // ---- plan (every argument error before any enqueue) --------------------
+    const bool persistent = cfg->persistent == 1 || (cfg->persistent == 0 && nc > 1);
+    std::vector<TuneChoice> choices(nc);
+    std::vector<bool> batched(nc, false);
+    for (uint32_t i = 0; i < nc; ++i) {
+        if (!cfg->chains[i]) continue;
+        choices[i] = tune_choice(c, i, cfg->chains[i], total, cfg);
+        const CompiledCircuit &k = c->circuits[i];
+        batched[i] = persistent && k.uniform && gibbs_lds_bytes(k.blob.data(), true, false) <= 64 * 1024 &&
+                     cfg->toggle_mode != 2;
+    }
+    const BatchTuning bt = tune_batch(c, cfg);
+    uint64_t group = total;
+    if (cfg->sweeps_per_launch) group = std::min<uint64_t>(cfg->sweeps_per_launch, total);
+    bool multi_group = group < total;
+    for (uint32_t i = 0; i < nc; ++i)
+        if (cfg->chains[i] && !batched[i] && choices[i].group < total) multi_group = true;
+    uint32_t *state_base = d_state;
+    if (!d_state && multi_group) {
+        void *p = nullptr;
+        st = ensure_buf(c->scratch, dev, std::max<uint64_t>(state_words, 1) * sizeof(uint32_t), &p);
+        if (st != PBIT_OK) return st;
+        state_base = (uint32_t *)p;
+    }
+
     struct Plan {
         GibbsLaunch a;
         uint32_t Wk;
@@ -112,32 +139,46 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         size_t lds;
     };
     std::vector<Plan> plans;
-    uint32_t *state_base = d_state;
-    bool need_scratch = false;
-    std::vector<TuneChoice> choices(nc);
-    for (uint32_t i = 0; i < nc; ++i) {
-        if (!cfg->chains[i]) continue;
-        choices[i] = tune_choice(c->circuits[i], cfg->chains[i], total, cfg);
-        if (!d_state && choices[i].group < total) need_scratch = true;
-    }
-    if (need_scratch) {
-        void *p = nullptr;
-        st = ensure_buf(c->scratch, dev, std::max<uint64_t>(state_words, 1) * sizeof(uint32_t), &p);
-        if (st != PBIT_OK) return st;
-        state_base = (uint32_t *)p;
-    }
+    // persistent classes
+    std::vector<BatchCirc> bcirc;
+    std::vector<std::vector<BatchTile>> btiles(3);
+    std::vector<std::vector<std::pair<uint64_t, uint32_t>>> border(3);  // (cost, circ) for sorting
+    size_t blds[3] = {0, 0, 0};
+    std::vector<uint32_t> bcirc_of(nc, 0);
     uint64_t soff = 0;
     for (uint32_t i = 0; i < nc; ++i) {
         const CompiledCircuit &k = c->circuits[i];
         const uint32_t ch = cfg->chains[i];
         if (!ch) continue;
+        uint32_t *sp = state_base ? state_base + soff : nullptr;
+        soff += (uint64_t)ch * k.W;
+        if (batched[i]) {
+            const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
+            const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode == 0 && hb <= bt.hist_lds_max);
+            const size_t lds = gibbs_lds_bytes(k.blob.data(), true, lh);
+            if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
+            BatchCirc bc;
+            bc.blob = dblob + c->blob_off[i];
+            bc.state = sp;
+            bc.hist = d_hist + c->hist_off[i];
+            bc.n_chains = ch;
+            bc.lds_hist = lh ? 1u : 0u;
+            bc.Wk = k.WS;
+            bc.pad = 0;
+            const int cls = batched_class_of(k.WS);
+            bcirc_of[i] = (uint32_t)bcirc.size();
+            bcirc.push_back(bc);
+            blds[cls] = std::max(blds[cls], lds);
+            // cost of one tile: Philox blocks x (Philox + toggle row) per sweep
+            const uint64_t cost = (uint64_t)k.blob[H_NBLK] * (40 + ((k.WS + 3) & ~3u)) + 64;
+            border[cls].push_back({cost, i});
+            continue;
+        }
         const TuneChoice &tc = choices[i];
         const size_t thr_bytes = k.uniform ? 0 : (size_t)k.blob[H_THR_TOTAL] * sizeof(uint32_t);
         if (thr_bytes > 64 * 1024) return set_error(PBIT_E_TOO_LARGE, "threshold tables exceed 64 KiB of LDS");
-        const bool lds_hist = tc.lds_hist;
-        const size_t lds = gibbs_lds_bytes(k.blob.data(), tc.tog, lds_hist);
+        const size_t lds = gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist);
         if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
-        uint32_t *sp = state_base ? state_base + soff : nullptr;
         for (uint64_t done = 0; done < total; done += tc.group) {
             Plan p;
             std::memset(&p.a, 0, sizeof(p.a));
@@ -152,7 +193,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.a.n_sweeps = (uint32_t)std::min<uint64_t>(tc.group, total - done);
             p.a.bin_from = cfg->sweep_offset + cfg->burn_in;
             p.a.resume = done > 0 ? 1u : (cfg->init == PBIT_INIT_RESUME ? 1u : 0u);
-            p.a.lds_hist = lds_hist ? 1u : 0u;
+            p.a.lds_hist = tc.lds_hist ? 1u : 0u;
             p.Wk = k.WS;
             p.uniform = k.uniform;
             p.tog = tc.tog;
@@ -160,13 +201,85 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.lds = lds;
             plans.push_back(p);
         }
-        soff += (uint64_t)ch * k.W;
     }
+    // tiles in decreasing cost order (longest first), 256 chains each
+    uint32_t tiles_total = 0;
+    for (int cls = 0; cls < 3; ++cls) {
+        std::stable_sort(border[cls].begin(), border[cls].end(),
+                         [](const std::pair<uint64_t, uint32_t> &a, const std::pair<uint64_t, uint32_t> &b) {
+                             return a.first > b.first;
+                         });
+        for (auto &oc : border[cls]) {
+            const uint32_t i = oc.second;
+            for (uint32_t c0 = 0; c0 < cfg->chains[i]; c0 += 256) btiles[cls].push_back(BatchTile{bcirc_of[i], c0});
+        }
+        tiles_total += (uint32_t)btiles[cls].size();
+    }
+    BatchCirc *d_bcirc = nullptr;
+    BatchTile *d_btile[3] = {nullptr, nullptr, nullptr};
+    uint32_t *d_queue = nullptr;
+    if (!bcirc.empty()) {
+        const size_t nb = bcirc.size() * sizeof(BatchCirc);
+        const size_t nt = (size_t)tiles_total * sizeof(BatchTile);
+        const size_t bytes = nb + nt + 3 * 256 + 256;
+        void *p = nullptr;
+        if ((st = ensure_buf(c->work, dev, bytes, &p)) != PBIT_OK) return st;
+        std::vector<unsigned char> &host = c->work_host[dev];
+        std::vector<unsigned char> prev;
+        prev.swap(host);
+        host.assign(bytes, 0);
+        std::memcpy(host.data(), bcirc.data(), nb);
+        size_t o = nb;
+        for (int cls = 0; cls < 3; ++cls) {
+            d_btile[cls] = (BatchTile *)((unsigned char *)p + o);
+            std::memcpy(host.data() + o, btiles[cls].data(), btiles[cls].size() * sizeof(BatchTile));
+            o += btiles[cls].size() * sizeof(BatchTile);
+        }
+        o = (o + 255) & ~(size_t)255;
+        d_queue = (uint32_t *)((unsigned char *)p + o);
+        d_bcirc = (BatchCirc *)p;
+        // stream-ordered upload, only when the list changed; the host copy
+        // stays alive in the handle until the next change
+        if (prev.size() != host.size() || std::memcmp(prev.data(), host.data(), o) != 0 ||
+            c->work_uploaded[dev] != p) {
+            e = hipMemcpyAsync(p, host.data(), o, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return hip_error(e, "upload of the batched work list");
+            c->work_uploaded[dev] = p;
+        } else {
+            host.swap(prev);
+        }
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
     auto enqueue = [&]() -> pbit_status {
         for (const Plan &p : plans) {
             hipError_t le = launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
             if (le != hipSuccess) return hip_error(le, "gibbs kernel launch");
+        }
+        if (bcirc.empty()) return PBIT_OK;
+        for (uint64_t done = 0; done < total; done += group) {
+            for (int cls = 0; cls < 3; ++cls) {
+                if (btiles[cls].empty()) continue;
+                BatchArgs a;
+                std::memset(&a, 0, sizeof(a));
+                a.circs = d_bcirc;
+                a.tiles = d_btile[cls];
+                a.ntiles = (uint32_t)btiles[cls].size();
+                a.queue = d_queue + cls * 64;
+                a.chain_begin = cfg->chain_begin;
+                a.seed_lo = (uint32_t)cfg->seed;
+                a.seed_hi = (uint32_t)(cfg->seed >> 32);
+                a.sweep_begin = (uint32_t)(cfg->sweep_offset + done);
+                a.n_sweeps = (uint32_t)std::min<uint64_t>(group, total - done);
+                a.bin_from = cfg->sweep_offset + cfg->burn_in;
+                a.resume = done > 0 ? 1u : (cfg->init == PBIT_INIT_RESUME ? 1u : 0u);
+                uint32_t wg = cfg->wg_per_cu ? cfg->wg_per_cu : bt.wg_per_cu[cls];
+                if (blds[cls]) wg = std::min<uint32_t>(wg, std::max<uint32_t>(1, (uint32_t)(LDS_LIMIT / blds[cls])));
+                const uint32_t grid = std::min<uint32_t>(a.ntiles, (uint32_t)cus * std::max<uint32_t>(wg, 1));
+                hipError_t le = launch_batched(cls, a, grid, blds[cls], stream);
+                if (le != hipSuccess) return hip_error(le, "batched kernel launch");
+            }
         }
         return PBIT_OK;
     };
@@ -176,9 +289,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     // graph replay keyed by everything that shapes the captured launches
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)stream, (uint64_t)(uintptr_t)d_state,
                                  (uint64_t)(uintptr_t)d_hist, (uint64_t)(uintptr_t)state_base,
-                                 cfg->chain_begin, cfg->burn_in, cfg->sweeps, cfg->seed, cfg->sweep_offset,
-                                 cfg->init, cfg->sweeps_per_launch, cfg->block_size, cfg->hist_mode,
-                                 cfg->toggle_mode};
+                                 (uint64_t)(uintptr_t)d_bcirc, cfg->chain_begin, cfg->burn_in, cfg->sweeps,
+                                 cfg->seed, cfg->sweep_offset, cfg->init, cfg->sweeps_per_launch, cfg->block_size,
+                                 cfg->hist_mode, cfg->toggle_mode, cfg->persistent, cfg->wg_per_cu, c->tune_epoch};
     for (uint32_t i = 0; i < nc; ++i) key.push_back(cfg->chains[i]);
     GraphCache &gc = c->graphs[dev];
     if (!(gc.exec && gc.key == key)) {

@@ -21,6 +21,20 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Autotuned shape of one circuit's single-circuit launches.
+struct TunedSingle {
+    uint32_t block = 256;
+    bool lds_hist = true;
+    bool tog = true;
+};
+
+// Autotuned persistent-launch shape: workgroups per CU for each width class
+// and the largest histogram privatised in LDS.
+struct TunedBatch {
+    uint32_t wg_per_cu[3] = {4, 3, 2};
+    uint32_t hist_lds_max = 16 * 1024;
+};
+
 // Captured sweep-group graph, replayed while the run signature is unchanged.
 struct GraphCache {
     std::vector<uint64_t> key;
@@ -39,7 +53,14 @@ struct pbit_circuit_s {
     std::vector<uint64_t> blob_off;       // word offset of each circuit's image
     std::map<int, pbit::DevBuf> scratch;  // lattice state between sweep groups
     std::map<int, pbit::DevBuf> work;     // persistent work list (batched runs)
+    std::map<int, std::vector<unsigned char>> work_host;  // its host image
+    std::map<int, void *> work_uploaded;
     std::map<int, pbit::GraphCache> graphs;
+    // autotuned launch shapes (pbit_autotune)
+    std::map<uint32_t, pbit::TunedSingle> tuned;
+    bool tuned_batch_valid = false;
+    pbit::TunedBatch tuned_batch;
+    uint64_t tune_epoch = 0;
     ~pbit_circuit_s();
 };
 

@@ -1,4 +1,5 @@
-// Launch-shape rules for the Gibbs kernels.
+// Launch-shape choice: explicit cfg fields, then the handle's autotuned
+// table, then static rules.
 #include "tune.h"
 
 #include <algorithm>
@@ -8,28 +9,44 @@
 
 namespace pbit {
 
-TuneChoice tune_choice(const CompiledCircuit &k, uint32_t chains, uint64_t total_sweeps,
+TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t total_sweeps,
                        const pbit_gibbs_cfg *cfg) {
+    const CompiledCircuit &k = c->circuits[i];
     TuneChoice t;
     constexpr size_t LDS_MAX = 160 * 1024;
     const size_t hist_bytes = ((size_t)1 << (k.n + k.K)) * 4;
-    // toggle tables when they leave room; the histogram privatised in LDS
-    // when it fits next to them and the threshold tables
+    // static rules: toggle tables when they leave room; the histogram
+    // privatised in LDS when it fits next to them and the threshold tables;
+    // small workgroups when a short run would not fill 256 CUs
     t.tog = gibbs_lds_bytes(k.blob.data(), true, false) <= 96 * 1024;
+    t.lds_hist = gibbs_lds_bytes(k.blob.data(), t.tog, true) <= LDS_MAX;
+    t.block = 256;
+    if (chains < 256u * 256u && hist_bytes <= 32 * 1024) t.block = 64;
+    auto it = c->tuned.find(i);
+    if (it != c->tuned.end()) {
+        t.block = it->second.block;
+        t.lds_hist = it->second.lds_hist;
+        t.tog = it->second.tog;
+    }
     if (cfg->toggle_mode == 1) t.tog = true;
     if (cfg->toggle_mode == 2) t.tog = false;
-    t.lds_hist = gibbs_lds_bytes(k.blob.data(), t.tog, true) <= LDS_MAX;
     if (cfg->hist_mode == 1) t.lds_hist = true;
     if (cfg->hist_mode == 2) t.lds_hist = false;
     if (t.lds_hist && gibbs_lds_bytes(k.blob.data(), t.tog, true) > LDS_MAX) t.tog = false;
-    // one workgroup per CU when a large histogram occupies the LDS; smaller
-    // groups otherwise so that short runs still spread over 256 CUs
-    t.block = 256;
-    if (chains < 256u * 256u && hist_bytes <= 32 * 1024) t.block = 64;
+    if (t.lds_hist && gibbs_lds_bytes(k.blob.data(), t.tog, true) > LDS_MAX && cfg->hist_mode != 1)
+        t.lds_hist = false;
     if (cfg->block_size) t.block = cfg->block_size;
     t.group = total_sweeps;
     if (cfg->sweeps_per_launch) t.group = std::min<uint64_t>(cfg->sweeps_per_launch, total_sweeps);
     return t;
+}
+
+BatchTuning tune_batch(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
+    (void)cfg;
+    BatchTuning b;
+    for (int i = 0; i < 3; ++i) b.wg_per_cu[i] = c->tuned_batch.wg_per_cu[i];
+    b.hist_lds_max = c->tuned_batch.hist_lds_max;
+    return b;
 }
 
 }  // namespace pbit

@@ -4,6 +4,7 @@
 
 #include "../../include/pbit.h"
 #include "compile.h"
+#include "runtime.h"
 
 namespace pbit {
 
@@ -14,9 +15,15 @@ struct TuneChoice {
     bool tog = true;          // LDS toggle tables (else per-bit cone toggles)
 };
 
-// Explicit cfg fields win; unset ones come from the tuning table (if one was
-// loaded or measured for this circuit class) or from the static rules.
-TuneChoice tune_choice(const CompiledCircuit &k, uint32_t chains, uint64_t total_sweeps,
+// Explicit cfg fields win; unset ones come from the autotuned table of the
+// handle (if pbit_autotune ran or loaded a cache) or from the static rules.
+TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t total_sweeps,
                        const pbit_gibbs_cfg *cfg);
+
+struct BatchTuning {
+    uint32_t wg_per_cu[3];
+    size_t hist_lds_max;
+};
+BatchTuning tune_batch(pbit_circuit c, const pbit_gibbs_cfg *cfg);
 
 }  // namespace pbit

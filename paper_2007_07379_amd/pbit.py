@@ -55,7 +55,8 @@ class GibbsCfg(C.Structure):
                 ("burn_in", C.c_uint32), ("sweeps", C.c_uint32), ("seed", C.c_uint64),
                 ("sweep_offset", C.c_uint32), ("init", C.c_uint32),
                 ("sweeps_per_launch", C.c_uint32), ("block_size", C.c_uint32),
-                ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32), ("toggle_mode", C.c_uint32)]
+                ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32), ("toggle_mode", C.c_uint32),
+                ("persistent", C.c_uint32), ("wg_per_cu", C.c_uint32)]
 
 
 _lib = None
@@ -182,7 +183,7 @@ class CircuitSet:
 
     def gibbs_run(self, chains, burn_in, sweeps, d_hist, d_state=None, seed=0, chain_begin=0,
                   sweep_offset=0, resume=False, sweeps_per_launch=0, block_size=0, use_graph=False,
-                  hist_mode=0, toggle_mode=0, stream=None):
+                  hist_mode=0, toggle_mode=0, persistent=0, wg_per_cu=0, stream=None):
         if isinstance(chains, int):
             chains = [chains]
         arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
@@ -199,8 +200,24 @@ class CircuitSet:
         cfg.use_graph = 1 if use_graph else 0
         cfg.hist_mode = hist_mode
         cfg.toggle_mode = toggle_mode
+        cfg.persistent = persistent
+        cfg.wg_per_cu = wg_per_cu
         _check(lib().pbit_gibbs_run(self.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                                     _stream(stream)))
+
+    def autotune(self, chains, burn_in, sweeps, cache_path=None, persistent=0, stream=None):
+        if isinstance(chains, int):
+            chains = [chains]
+        arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
+        cfg = GibbsCfg()
+        cfg.chains = C.cast(arr, C.POINTER(C.c_uint32))
+        cfg.burn_in = burn_in
+        cfg.sweeps = sweeps
+        cfg.persistent = persistent
+        L = lib()
+        L.pbit_autotune.argtypes = [C.c_void_p, C.POINTER(GibbsCfg), C.c_char_p, C.c_void_p]
+        _check(L.pbit_autotune(self.handle, C.byref(cfg),
+                               cache_path.encode() if cache_path else None, _stream(stream)))
 
     def amplitudes(self, counts, T=None, idx=0, mode=NORM_EXACT_Z):
         counts = np.ascontiguousarray(counts, dtype=np.uint64)
