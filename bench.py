@@ -86,6 +86,164 @@ def cpu_baseline(c, h, burn, sweeps, chains_sample):
                       "workload), %.1f s" % (chains_sample, burn, sweeps, dt)}
 
 
+def geyer_tau(x):
+    """Integrated autocorrelation time of an observable series x[steps,
+    chains] (Geyer's initial positive sequence on the chain-pooled
+    autocorrelation)."""
+    x = x - x.mean()
+    v = float((x * x).mean())
+    if v <= 0:
+        return float("nan")
+    S = x.shape[0]
+    rho = [1.0] + [float((x[t:] * x[:-t]).mean() / v) for t in range(1, S // 2)]
+    tau = -1.0
+    k = 0
+    while 2 * k + 1 < len(rho):
+        g = rho[2 * k] + rho[2 * k + 1]
+        if g <= 0:
+            break
+        tau += 2 * g
+        k += 1
+    return tau
+
+
+def output_parities(torch, state, info, masks):
+    """+-1 parity characters of the output state alpha of every chain."""
+    n, d, W = info["n"], info["d"], info["W"]
+    ch = state.numel() // W
+    st = state.view(W, ch).to(torch.int64) & 0xFFFFFFFF
+    lo = d * n
+    alpha = torch.zeros(ch, dtype=torch.int64, device=state.device)
+    for q in range(n):
+        p = lo + q
+        alpha |= ((st[p >> 5] >> (p & 31)) & 1) << q
+    out = []
+    for m in masks:
+        v = alpha & m
+        par = torch.zeros_like(v)
+        for q in range(n):
+            par ^= (v >> q) & 1
+        out.append((1 - 2 * par).to(torch.float64))
+    return torch.stack(out)  # [n_obs, chains]
+
+
+MH_WORKLOADS = {
+    # name: (circuit factory, chains, burn_in, steps, hidden, train_samples, train_steps, batch)
+    "brick16": (lambda wc: wc.workload_circuit("brick16"), 131072, 200, 48, 1024, 1 << 20, 2560, 4096, 400),
+    "rhchain48": (lambda wc: wc.rotated_hadamard_chain(48, 3.141592653589793 / 64, K=1), 131072, 2000, 96, 128,
+                  1 << 18, 1500, 4096, 200),
+}
+
+
+def mh_mode(args):
+    """ESS per second of plain Gibbs against the learned-proposal MH (1 MH
+    step : gibbs_per_mh Gibbs sweeps) on the same chains and GPU."""
+    import torch
+    from paper_2007_07379_amd import pbit
+    from oracle import circuit as oc
+    from oracle import estimator as oest
+    from oracle import exact
+    from workloads import circuits as wc
+
+    mk, chains, burn, steps, hidden, ntrain, tsteps, batch, long_cycles = MH_WORKLOADS[args.workload]
+    G = args.gibbs_per_mh
+    c = mk(wc)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    W, h = info["W"], info["h"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rng = np.random.default_rng(0)
+    masks = [int(m) for m in rng.integers(1, 1 << info["n"], size=16)] if info["n"] > 1 else [1]
+    pm, _ = exact.magnitude_marginal(oc.from_dict(c))
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # --- plain Gibbs: burn-in, then one sweep per call with snapshots --------
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev)
+    state = torch.zeros(chains * W, dtype=torch.int32, device=dev)
+    s.gibbs_run([chains], burn, 0, hist, state, seed=1, stream=stream)
+    s.gibbs_run([chains], 0, 1, hist, state, seed=1, sweep_offset=burn, resume=True, stream=stream)
+    start = state.clone()
+    hist.zero_()
+    series = []
+    for t in range(steps):
+        s.gibbs_run([chains], 0, 1, hist, state, seed=1, sweep_offset=burn + 1 + t, resume=True, stream=stream)
+        series.append(output_parities(torch, state, info, masks))
+    ser = torch.stack(series).cpu().numpy()  # [steps, obs, chains]
+    tau_g = max(geyer_tau(ser[:, o, :]) for o in range(ser.shape[1]))
+    # long uninterrupted run: time per sweep and TV of its histogram
+    n_long = long_cycles * (1 + G)
+    st2 = start.clone()
+    hist.zero_()
+    e0, e1 = ev(), ev()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.gibbs_run([chains], 0, n_long, hist, st2, seed=1, sweep_offset=burn + 1, resume=True, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_g = e0.elapsed_time(e1) / 1e3 / n_long  # seconds per sweep
+    hist_g = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    tv_g = oest.tv_path(hist_g, pm)
+    ess_g = chains / (tau_g * t_g)
+
+    # --- training the proposal on Gibbs samples ------------------------------
+    train = torch.zeros(ntrain * W, dtype=torch.int32, device=dev)
+    th = torch.zeros(pbit.CircuitSet(c).info(0)["hist_bins"], dtype=torch.int32, device=dev)
+    s.gibbs_run([ntrain], burn, 1, th, train, seed=7, stream=stream)
+    q = pbit.Proposal(s, hidden=hidden, seed=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = q.train(train, ntrain, batch, tsteps, lr=args.lr, stream=stream)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del train
+
+    # --- MH + Gibbs: transition-level snapshots --------------------------------
+    state = start.clone()
+    hist.zero_()
+    acc = torch.zeros(chains, dtype=torch.int64, device=dev)
+    series = []
+    for t in range(steps):
+        pbit.mh_run(s, q, chains, 1, state, hist, acc, gibbs_per_mh=0, seed=1, step_offset=t, resume=True,
+                    stream=stream)
+        series.append(output_parities(torch, state, info, masks))
+        for g in range(G):
+            s.gibbs_run([chains], 0, 1, hist, state, seed=1, sweep_offset=(1 << 30) + t * G + g, resume=True,
+                        stream=stream)
+            series.append(output_parities(torch, state, info, masks))
+    ser = torch.stack(series).cpu().numpy()
+    tau_m = max(geyer_tau(ser[:, o, :]) for o in range(ser.shape[1]))
+    acc_rate = float(acc.double().mean().item()) / steps
+    st2 = start.clone()
+    hist.zero_()
+    e0, e1 = ev(), ev()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    pbit.mh_run(s, q, chains, long_cycles, st2, hist, None, gibbs_per_mh=G, seed=2, resume=True, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_m = e0.elapsed_time(e1) / 1e3 / n_long  # seconds per transition
+    hist_m = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    tv_m = oest.tv_path(hist_m, pm)
+    ess_m = chains / (tau_m * t_m)
+    out = {
+        "metric": "effective samples/s (TV<=0.01), Gibbs vs learned-proposal MH",
+        "workload": "%s: n=%d d=%d, h=%d free p-bits, %d chains, MADE hidden %d, 1 MH : %d Gibbs"
+                    % (args.workload, info["n"], info["d"], h, chains, hidden, G),
+        "gibbs": {"tau_int_sweeps": tau_g, "s_per_sweep": t_g, "ess_per_s": ess_g, "tv_path": tv_g,
+                  "tv_samples": chains * n_long},
+        "mh": {"tau_int_transitions": tau_m, "s_per_transition": t_m, "ess_per_s": ess_m, "tv_path": tv_m,
+               "tv_samples": chains * n_long, "accept_rate": acc_rate},
+        "train": {"samples": ntrain, "steps": tsteps, "batch": batch, "seconds": t_train,
+                  "loss_first": float(losses[0]), "loss_last": float(losses[-20:].mean())},
+        "ess_ratio_mh_over_gibbs": ess_m / ess_g,
+        "tv_ok": bool(tv_g <= 0.01 and tv_m <= 0.01),
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,11 +252,20 @@ def main():
     ap.add_argument("--workload", default="rct12")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=8192)
+    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh"])
+    ap.add_argument("--gibbs-per-mh", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(chains shard trivially; see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "mh":
+        if args.workload == "rct12":
+            args.workload = "brick16"
+        mh_mode(args)
+        return
 
     import torch
     from paper_2007_07379_amd import pbit
