@@ -136,6 +136,8 @@ typedef struct {
     uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
     uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
     uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */
+    uint32_t lanes_per_chain;   /* 0 = auto, 1, or 2 (two lanes share a chain: circuits whose
+                                   conditionals are all 1/2, single-circuit launches) */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its

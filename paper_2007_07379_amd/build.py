@@ -35,6 +35,7 @@ SOURCES = [
     ("proposal.cpp", "hip"),
     ("autotune.cpp", "hip-host"),
     ("gibbs.hip", "hip"),
+    ("gibbs_pair.hip", "hip"),
     ("made.hip", "hip"),
     ("mh.hip", "hip"),
     ("batched.hip", "hip"),

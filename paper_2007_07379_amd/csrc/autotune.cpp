@@ -50,13 +50,14 @@ bool load_cache(pbit_circuit c, const char *path, const std::string &key) {
         const char *s = std::strstr(line, "\"single\": [");
         if (s) {
             s += std::strlen("\"single\": [");
-            unsigned i, blk, lh, tg;
+            unsigned i, blk, lh, tg, pr;
             int used = 0;
-            while (std::sscanf(s, " [%u, %u, %u, %u]%n", &i, &blk, &lh, &tg, &used) == 4) {
+            while (std::sscanf(s, " [%u, %u, %u, %u, %u]%n", &i, &blk, &lh, &tg, &pr, &used) == 5) {
                 TunedSingle t;
                 t.block = blk;
                 t.lds_hist = lh != 0;
                 t.tog = tg != 0;
+                t.pair = pr != 0;
                 c->tuned[i] = t;
                 s += used;
                 while (*s == ',' || *s == ' ') ++s;
@@ -76,8 +77,8 @@ void save_cache(pbit_circuit c, const char *path, const std::string &key) {
                  c->tuned_batch.hist_lds_max);
     bool first = true;
     for (auto &kv : c->tuned) {
-        std::fprintf(f, "%s[%u, %u, %u, %u]", first ? "" : ", ", kv.first, kv.second.block,
-                     kv.second.lds_hist ? 1u : 0u, kv.second.tog ? 1u : 0u);
+        std::fprintf(f, "%s[%u, %u, %u, %u, %u]", first ? "" : ", ", kv.first, kv.second.block,
+                     kv.second.lds_hist ? 1u : 0u, kv.second.tog ? 1u : 0u, kv.second.pair ? 1u : 0u);
         first = false;
     }
     std::fprintf(f, "]}\n");
@@ -172,7 +173,10 @@ extern "C" pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, 
         only[i] = cfg->chains[i];
         float best = 1e30f;
         TunedSingle bt;
+        for (uint32_t lanes : {1u, 2u}) {
+            if (lanes == 2 && !k.uniform) continue;
         for (uint32_t tog : {1u, 2u}) {
+            if (lanes == 2 && tog == 2) continue;
             if (tog == 1 && gibbs_lds_bytes(k.blob.data(), true, false) > 96 * 1024) continue;
             for (uint32_t hmode : {1u, 2u}) {
                 if (hmode == 1 && gibbs_lds_bytes(k.blob.data(), tog == 1, true) > 160 * 1024) continue;
@@ -183,16 +187,19 @@ extern "C" pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, 
                     t.block_size = blk;
                     t.hist_mode = hmode;
                     t.toggle_mode = tog;
+                    t.lanes_per_chain = lanes;
                     float ms = 0;
                     if ((status = time_cfg(t, &ms)) != PBIT_OK) goto done;
                     if (ms < best) {
                         best = ms;
-                        bt.block = blk;
+                        bt.block = lanes == 2 ? 2 * blk : blk;
                         bt.lds_hist = hmode == 1;
                         bt.tog = tog == 1;
+                        bt.pair = lanes == 2;
                     }
                 }
             }
+        }
         }
         c->tuned[i] = bt;
     }

@@ -41,4 +41,10 @@ size_t gibbs_lds_bytes(const uint32_t *host_blob, bool tog, bool lds_hist);
 hipError_t launch_gibbs(uint32_t Wk, bool uniform, bool tog, const GibbsLaunch &a, uint32_t block,
                         size_t lds_bytes, hipStream_t stream);
 
+// Two-lanes-per-chain variant for circuits whose conditionals are all 1/2
+// (gibbs_pair.hip); block is 64..512 threads, i.e. half as many chains.
+size_t gibbs_pair_lds_bytes(const uint32_t *host_blob, bool lds_hist);
+hipError_t launch_gibbs_pair(uint32_t Wk, const GibbsLaunch &a, uint32_t block, size_t lds_bytes,
+                             hipStream_t stream);
+
 }  // namespace pbit

@@ -79,6 +79,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (cfg->toggle_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad toggle_mode");
     if (cfg->persistent > 2) return set_error(PBIT_E_INVALID_ARG, "bad persistent mode");
     if (cfg->wg_per_cu > 16) return set_error(PBIT_E_INVALID_ARG, "wg_per_cu must be <= 16");
+    if (cfg->lanes_per_chain > 2) return set_error(PBIT_E_INVALID_ARG, "lanes_per_chain must be 0, 1 or 2");
     if (cfg->block_size && (cfg->block_size % 64 || cfg->block_size > 256))
         return set_error(PBIT_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
@@ -135,6 +136,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         uint32_t Wk;
         bool uniform;
         bool tog;
+        bool pair;
         uint32_t block;
         size_t lds;
     };
@@ -177,7 +179,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         const TuneChoice &tc = choices[i];
         const size_t thr_bytes = k.uniform ? 0 : (size_t)k.blob[H_THR_TOTAL] * sizeof(uint32_t);
         if (thr_bytes > 64 * 1024) return set_error(PBIT_E_TOO_LARGE, "threshold tables exceed 64 KiB of LDS");
-        const size_t lds = gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist);
+        const size_t lds = tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
+                                   : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist);
         if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
         for (uint64_t done = 0; done < total; done += tc.group) {
             Plan p;
@@ -197,6 +200,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.Wk = k.WS;
             p.uniform = k.uniform;
             p.tog = tc.tog;
+            p.pair = tc.pair;
             p.block = tc.block;
             p.lds = lds;
             plans.push_back(p);
@@ -254,7 +258,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
 
     auto enqueue = [&]() -> pbit_status {
         for (const Plan &p : plans) {
-            hipError_t le = launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
+            hipError_t le = p.pair ? launch_gibbs_pair(p.Wk, p.a, p.block, p.lds, stream)
+                                   : launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
             if (le != hipSuccess) return hip_error(le, "gibbs kernel launch");
         }
         if (bcirc.empty()) return PBIT_OK;
@@ -291,7 +296,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                                  (uint64_t)(uintptr_t)d_hist, (uint64_t)(uintptr_t)state_base,
                                  (uint64_t)(uintptr_t)d_bcirc, cfg->chain_begin, cfg->burn_in, cfg->sweeps,
                                  cfg->seed, cfg->sweep_offset, cfg->init, cfg->sweeps_per_launch, cfg->block_size,
-                                 cfg->hist_mode, cfg->toggle_mode, cfg->persistent, cfg->wg_per_cu, c->tune_epoch};
+                                 cfg->hist_mode, cfg->toggle_mode, cfg->persistent, cfg->wg_per_cu,
+                                 cfg->lanes_per_chain, c->tune_epoch};
     for (uint32_t i = 0; i < nc; ++i) key.push_back(cfg->chains[i]);
     GraphCache &gc = c->graphs[dev];
     if (!(gc.exec && gc.key == key)) {

@@ -26,6 +26,7 @@ struct TunedSingle {
     uint32_t block = 256;
     bool lds_hist = true;
     bool tog = true;
+    bool pair = false;
 };
 
 // Autotuned persistent-launch shape: workgroups per CU for each width class

@@ -22,12 +22,19 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     t.lds_hist = gibbs_lds_bytes(k.blob.data(), t.tog, true) <= LDS_MAX;
     t.block = 256;
     if (chains < 256u * 256u && hist_bytes <= 32 * 1024) t.block = 64;
+    // two lanes per chain when the chains alone would leave SIMDs with a
+    // single wave (256 CUs x 4 SIMDs x 64 lanes = 65,536 chains)
+    t.pair = k.uniform && chains <= 98304u && gibbs_pair_lds_bytes(k.blob.data(), false) <= 96 * 1024;
     auto it = c->tuned.find(i);
-    if (it != c->tuned.end()) {
+    const bool tuned = it != c->tuned.end();
+    if (tuned) {
         t.block = it->second.block;
         t.lds_hist = it->second.lds_hist;
         t.tog = it->second.tog;
+        t.pair = it->second.pair;
     }
+    if (cfg->lanes_per_chain == 1) t.pair = false;
+    if (cfg->lanes_per_chain == 2) t.pair = k.uniform;
     if (cfg->toggle_mode == 1) t.tog = true;
     if (cfg->toggle_mode == 2) t.tog = false;
     if (cfg->hist_mode == 1) t.lds_hist = true;
@@ -35,7 +42,22 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     if (t.lds_hist && gibbs_lds_bytes(k.blob.data(), t.tog, true) > LDS_MAX) t.tog = false;
     if (t.lds_hist && gibbs_lds_bytes(k.blob.data(), t.tog, true) > LDS_MAX && cfg->hist_mode != 1)
         t.lds_hist = false;
-    if (cfg->block_size) t.block = cfg->block_size;
+    // the pair kernel always stages its own split toggle tables
+    if (t.pair && cfg->toggle_mode == 2) t.pair = false;
+    if (t.pair) {
+        t.tog = true;
+        if (!tuned || !it->second.pair) {
+            t.lds_hist = gibbs_pair_lds_bytes(k.blob.data(), true) <= LDS_MAX;
+            t.block = 512;  // 256 chains
+        }
+        if (cfg->hist_mode == 1) t.lds_hist = true;
+        if (cfg->hist_mode == 2) t.lds_hist = false;
+        if (cfg->block_size) t.block = 2 * cfg->block_size;
+    } else if (cfg->block_size) {
+        t.block = cfg->block_size;
+    } else if (t.block > 256) {
+        t.block = 256;  // a tuned pair shape, overridden to one lane per chain
+    }
     t.group = total_sweeps;
     if (cfg->sweeps_per_launch) t.group = std::min<uint64_t>(cfg->sweeps_per_launch, total_sweeps);
     return t;

@@ -13,6 +13,7 @@ struct TuneChoice {
     uint64_t group = 0;       // sweeps per launch
     bool lds_hist = true;     // histogram privatised in LDS
     bool tog = true;          // LDS toggle tables (else per-bit cone toggles)
+    bool pair = false;        // two lanes per chain (uniform circuits)
 };
 
 // Explicit cfg fields win; unset ones come from the autotuned table of the

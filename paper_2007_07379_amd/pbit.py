@@ -56,7 +56,7 @@ class GibbsCfg(C.Structure):
                 ("sweep_offset", C.c_uint32), ("init", C.c_uint32),
                 ("sweeps_per_launch", C.c_uint32), ("block_size", C.c_uint32),
                 ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32), ("toggle_mode", C.c_uint32),
-                ("persistent", C.c_uint32), ("wg_per_cu", C.c_uint32)]
+                ("persistent", C.c_uint32), ("wg_per_cu", C.c_uint32), ("lanes_per_chain", C.c_uint32)]
 
 
 _lib = None
@@ -183,7 +183,8 @@ class CircuitSet:
 
     def gibbs_run(self, chains, burn_in, sweeps, d_hist, d_state=None, seed=0, chain_begin=0,
                   sweep_offset=0, resume=False, sweeps_per_launch=0, block_size=0, use_graph=False,
-                  hist_mode=0, toggle_mode=0, persistent=0, wg_per_cu=0, stream=None):
+                  hist_mode=0, toggle_mode=0, persistent=0, wg_per_cu=0, lanes_per_chain=0,
+                  stream=None):
         if isinstance(chains, int):
             chains = [chains]
         arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
@@ -202,6 +203,7 @@ class CircuitSet:
         cfg.toggle_mode = toggle_mode
         cfg.persistent = persistent
         cfg.wg_per_cu = wg_per_cu
+        cfg.lanes_per_chain = lanes_per_chain
         _check(lib().pbit_gibbs_run(self.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                                     _stream(stream)))
 

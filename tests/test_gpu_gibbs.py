@@ -70,13 +70,23 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("toggle_mode", [1, 2])
+MODES = {
+    "tog": dict(toggle_mode=1, lanes_per_chain=1),
+    "cone": dict(toggle_mode=2),
+    # two lanes per chain (circuits whose conditionals are all 1/2; the
+    # others run one lane per chain whatever is asked)
+    "pair": dict(lanes_per_chain=2),
+    "pair_ghist": dict(lanes_per_chain=2, hist_mode=2),
+}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("name,mk,chains,burn,sweeps,cb", CASES, ids=[c[0] for c in CASES])
-def test_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb, toggle_mode):
+def test_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb, mode):
     c = mk()
-    say("case", name, chains, burn, sweeps, cb, "toggle_mode", toggle_mode)
+    say("case", name, chains, burn, sweeps, cb, "mode", mode)
     st_g, h_g, _ = run_gpu(env, c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
-                           chain_begin=cb, toggle_mode=toggle_mode)
+                           chain_begin=cb, **MODES[mode])
     st_o, h_o, comp = oracle_run(c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
                                  chain_begin=cb)
     assert np.array_equal(st_g, st_o)
@@ -92,7 +102,9 @@ def test_launch_shapes_and_graph_are_bit_identical(env):
     ref_st, ref_h, _ = run_gpu(env, c, 2000, 7, 33)
     for kw in [dict(block_size=64), dict(block_size=128), dict(sweeps_per_launch=5),
                dict(hist_mode=2), dict(hist_mode=1, block_size=192), dict(toggle_mode=2),
-               dict(toggle_mode=2, hist_mode=2, block_size=64)]:
+               dict(toggle_mode=2, hist_mode=2, block_size=64), dict(lanes_per_chain=1),
+               dict(lanes_per_chain=2, block_size=64), dict(lanes_per_chain=2, block_size=256),
+               dict(lanes_per_chain=2, sweeps_per_launch=5), dict(lanes_per_chain=2, hist_mode=2)]:
         say("shape", kw)
         st, h, _ = run_gpu(env, c, 2000, 7, 33, **kw)
         assert np.array_equal(st, ref_st), kw
@@ -101,28 +113,31 @@ def test_launch_shapes_and_graph_are_bit_identical(env):
     s = pbit.CircuitSet(c)
     info = s.info(0)
     stream = torch.cuda.Stream()
-    for rep in range(3):
+    for rep in range(6):
+        lanes = 1 + rep % 2
         hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
         state = torch.zeros(2000 * info["W"], dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
-        s.gibbs_run([2000], 7, 33, hist, state, sweeps_per_launch=4, use_graph=True, stream=stream)
+        s.gibbs_run([2000], 7, 33, hist, state, sweeps_per_launch=4, use_graph=True, stream=stream,
+                    lanes_per_chain=lanes)
         stream.synchronize()
         h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(ref_h.shape)
         assert np.array_equal(h, ref_h), rep
         _ = torch.ones(1000, device="cuda").sum().item()
 
 
-def test_resume_matches_uninterrupted(env):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_resume_matches_uninterrupted(env, lanes):
     torch, pbit = env
     c = wc.workload_circuit("rct12")
     s = pbit.CircuitSet(c)
     info = s.info(0)
     ch = 512
-    full_st, full_h, _ = run_gpu(env, c, ch, 10, 40)
+    full_st, full_h, _ = run_gpu(env, c, ch, 10, 40, lanes_per_chain=1)
     hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
     state = torch.zeros(ch * info["W"], dtype=torch.int32, device="cuda")
-    s.gibbs_run([ch], 10, 15, hist, state)
-    s.gibbs_run([ch], 0, 25, hist, state, sweep_offset=25, resume=True)
+    s.gibbs_run([ch], 10, 15, hist, state, lanes_per_chain=lanes)
+    s.gibbs_run([ch], 0, 25, hist, state, sweep_offset=25, resume=True, lanes_per_chain=3 - lanes)
     torch.cuda.synchronize()
     st = state.cpu().numpy().view(np.uint32).reshape(info["W"], ch).T
     h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(full_h.shape)
