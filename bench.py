@@ -244,6 +244,51 @@ def mh_mode(args):
     print(json.dumps(out))
 
 
+def copy_mode(args):
+    """One plain device-to-device copy of known size, the reference point that
+    scales the FETCH_SIZE / WRITE_SIZE hardware counters to bytes."""
+    import torch
+    n = args.copy_mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    assert bool((b == 1).all())
+    print(json.dumps({"copy_bytes": 4 * n, "read_kib": 4 * n / 1024, "write_kib": 4 * n / 1024}))
+
+
+def source_digest(*names):
+    import hashlib
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2007_07379_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# HBM traffic per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over
+# `bench.py --steps 1 --warmup 0 --no-cpu`, scaled by the same counters read
+# for a 256 MiB device copy (FETCH_SIZE reads 0.5 of the copy's bytes on this
+# part, WRITE_SIZE 1.0).  Keyed by kernel, workload and a digest of the kernel
+# sources: a figure is reported only while the sources it was taken on are
+# unchanged.
+MEASURED_TRAFFIC = {
+    # (kernel, workload): (source digest, sources, read bytes, written bytes)
+    ("gibbs_pair_kernel<16>", "rct12"): ("1cc1ef522bb50502", ('gibbs_pair.hip', 'philox.h', 'blob.h', 'gibbs.h'), 157.5 * 1024 * 2, 36864 * 1024 * 1),
+}
+
+
+def measured_traffic(kernel, workload):
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None:
+        return None
+    digest, srcs, rd, wr = rec
+    if source_digest(*srcs) != digest:
+        return None
+    return rd + wr
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,15 +297,19 @@ def main():
     ap.add_argument("--workload", default="rct12")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=8192)
-    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh"])
+    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy"])
+    ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--gibbs-per-mh", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(chains shard trivially; see DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: chains are independent, so N GPUs would each run "
+              "their own share of them; no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "copy":
+        copy_mode(args)
+        return
     if args.mode == "mh":
         if args.workload == "rct12":
             args.workload = "brick16"
@@ -289,6 +338,11 @@ def main():
         hist.zero_()
         s.gibbs_run([chains], burn, sweeps, hist, state, seed=0, stream=stream)
 
+    shape = s.launch_shape([chains], burn, sweeps)
+    kname = {pbit.KERNEL_ONE_LANE: "gibbs_kernel<%d,%s>" % (shape["kernel_words"],
+                                                          "true" if info["uniform"] else "false"),
+             pbit.KERNEL_TWO_LANE: "gibbs_pair_kernel<%d>" % shape["kernel_words"],
+             pbit.KERNEL_PERSISTENT: "batched_kernel"}[shape["kernel"]]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -335,8 +389,9 @@ def main():
             "peak": VALU_PEAK / 1e12,
             "unit": "Tslot-op/s",
             "frac": achieved / VALU_PEAK,
-            "traffic": None,
-            "kernel": "gibbs_kernel<%d,%s>" % (int(blob[HDR["WS"]]), "true" if info["uniform"] else "false"),
+            "traffic": measured_traffic(kname, args.workload),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
+            "kernel": kname,
             "kernel_ms": kernel_s * 1e3,
             "ops_per_update": per_sweep / max(h, 1),
             "ops_per_sample": per_sample,

@@ -260,6 +260,28 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
  * until done. */
 pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char *cache_path, void *hip_stream);
 
+/* Launch shape that pbit_gibbs_run would use for circuit `index` under
+ * cfg (after the handle's autotuned choices and cfg's explicit fields):
+ * which kernel, threads per workgroup, histogram privatisation, toggle
+ * tables, the kernel's lattice width in words, dynamic LDS bytes and sweeps
+ * per launch.  Host only; enqueues nothing. */
+enum {
+    PBIT_KERNEL_ONE_LANE = 0,   /* one chain per lane */
+    PBIT_KERNEL_TWO_LANE = 1,   /* two lanes per chain (all conditionals 1/2) */
+    PBIT_KERNEL_PERSISTENT = 2  /* batched persistent tile queue */
+};
+typedef struct {
+    uint32_t kernel;
+    uint32_t block;
+    uint32_t lds_hist;
+    uint32_t toggle_tables;
+    uint32_t kernel_words;
+    uint32_t lds_bytes;
+    uint64_t sweeps_per_launch;
+} pbit_launch_shape;
+pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t index,
+                                  pbit_launch_shape *out);
+
 const char *pbit_last_error(void);
 
 /* Blocks until all work the library enqueued on hip_stream is done; returns

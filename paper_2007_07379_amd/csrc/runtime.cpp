@@ -68,6 +68,14 @@ pbit_status device_blobs(pbit_circuit c, const uint32_t **base) {
     return PBIT_OK;
 }
 
+bool runs_batched(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
+    const uint32_t nc = (uint32_t)c->circuits.size();
+    const bool persistent = cfg->persistent == 1 || (cfg->persistent == 0 && nc > 1);
+    const CompiledCircuit &k = c->circuits[i];
+    return persistent && k.uniform && gibbs_lds_bytes(k.blob.data(), true, false) <= 64 * 1024 &&
+           cfg->toggle_mode != 2;
+}
+
 pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
                       hipStream_t stream) {
     if (!c || !cfg || !cfg->chains) return set_error(PBIT_E_INVALID_ARG, "NULL handle, cfg or chains");
@@ -107,15 +115,12 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (st != PBIT_OK) return st;
 
     // ---- plan (every argument error before any enqueue) --------------------
-    const bool persistent = cfg->persistent == 1 || (cfg->persistent == 0 && nc > 1);
     std::vector<TuneChoice> choices(nc);
     std::vector<bool> batched(nc, false);
     for (uint32_t i = 0; i < nc; ++i) {
         if (!cfg->chains[i]) continue;
         choices[i] = tune_choice(c, i, cfg->chains[i], total, cfg);
-        const CompiledCircuit &k = c->circuits[i];
-        batched[i] = persistent && k.uniform && gibbs_lds_bytes(k.blob.data(), true, false) <= 64 * 1024 &&
-                     cfg->toggle_mode != 2;
+        batched[i] = runs_batched(c, i, cfg);
     }
     const BatchTuning bt = tune_batch(c, cfg);
     uint64_t group = total;
@@ -329,3 +334,37 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
 }
 
 }  // namespace pbit
+
+using namespace pbit;
+
+extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t index,
+                                             pbit_launch_shape *out) {
+    if (!c || !cfg || !cfg->chains || !out) return set_error(PBIT_E_INVALID_ARG, "NULL handle, cfg or out");
+    if (index >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
+    std::lock_guard<std::mutex> lock(c->mu);
+    const CompiledCircuit &k = c->circuits[index];
+    const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
+    std::memset(out, 0, sizeof(*out));
+    out->kernel_words = k.WS;
+    if (runs_batched(c, index, cfg)) {
+        const BatchTuning bt = tune_batch(c, cfg);
+        const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
+        const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode == 0 && hb <= bt.hist_lds_max);
+        out->kernel = PBIT_KERNEL_PERSISTENT;
+        out->block = 256;
+        out->lds_hist = lh ? 1u : 0u;
+        out->toggle_tables = 1;
+        out->lds_bytes = (uint32_t)gibbs_lds_bytes(k.blob.data(), true, lh);
+        out->sweeps_per_launch = cfg->sweeps_per_launch ? std::min<uint64_t>(cfg->sweeps_per_launch, total) : total;
+        return PBIT_OK;
+    }
+    const TuneChoice tc = tune_choice(c, index, cfg->chains[index], total, cfg);
+    out->kernel = tc.pair ? PBIT_KERNEL_TWO_LANE : PBIT_KERNEL_ONE_LANE;
+    out->block = tc.block;
+    out->lds_hist = tc.lds_hist ? 1u : 0u;
+    out->toggle_tables = tc.tog ? 1u : 0u;
+    out->lds_bytes = (uint32_t)(tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
+                                        : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
+    out->sweeps_per_launch = tc.group;
+    return PBIT_OK;
+}

@@ -59,6 +59,14 @@ class GibbsCfg(C.Structure):
                 ("persistent", C.c_uint32), ("wg_per_cu", C.c_uint32), ("lanes_per_chain", C.c_uint32)]
 
 
+class LaunchShape(C.Structure):
+    _fields_ = [("kernel", C.c_uint32), ("block", C.c_uint32), ("lds_hist", C.c_uint32),
+                ("toggle_tables", C.c_uint32), ("kernel_words", C.c_uint32), ("lds_bytes", C.c_uint32),
+                ("sweeps_per_launch", C.c_uint64)]
+
+
+KERNEL_ONE_LANE, KERNEL_TWO_LANE, KERNEL_PERSISTENT = 0, 1, 2
+
 _lib = None
 
 
@@ -206,6 +214,24 @@ class CircuitSet:
         cfg.lanes_per_chain = lanes_per_chain
         _check(lib().pbit_gibbs_run(self.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                                     _stream(stream)))
+
+    def launch_shape(self, chains, burn_in, sweeps, idx=0, **kw):
+        """Launch shape gibbs_run would use for circuit idx (same keyword
+        fields as gibbs_run)."""
+        if isinstance(chains, int):
+            chains = [chains]
+        arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
+        cfg = GibbsCfg()
+        cfg.chains = C.cast(arr, C.POINTER(C.c_uint32))
+        cfg.burn_in = burn_in
+        cfg.sweeps = sweeps
+        for k, v in kw.items():
+            setattr(cfg, k, int(v))
+        out = LaunchShape()
+        L = lib()
+        L.pbit_launch_shape_get.argtypes = [C.c_void_p, C.POINTER(GibbsCfg), C.c_uint32, C.POINTER(LaunchShape)]
+        _check(L.pbit_launch_shape_get(self.handle, C.byref(cfg), idx, C.byref(out)))
+        return {f: getattr(out, f) for f, _ in LaunchShape._fields_}
 
     def autotune(self, chains, burn_in, sweeps, cache_path=None, persistent=0, stream=None):
         if isinstance(chains, int):

@@ -233,3 +233,31 @@ def test_gibbs_argument_errors_before_device(pb):
     with pytest.raises(pb.PbitError) as e:
         s.gibbs_run([64], 0, 10, d_hist=1, resume=True)
     assert e.value.name == "INVALID_ARG"
+    with pytest.raises(pb.PbitError) as e:
+        s.gibbs_run([64], 0, 10, d_hist=1, lanes_per_chain=3)
+    assert e.value.name == "INVALID_ARG"
+
+
+def test_launch_shape_rules(pb):
+    """Static launch-shape rules: two lanes per chain for circuits whose
+    conditionals are all 1/2 when the chains alone leave SIMDs with one wave;
+    one lane for non-uniform circuits whatever is asked; the persistent tile
+    queue for uniform circuits of a multi-circuit handle."""
+    s = pb.CircuitSet(wc.workload_circuit("rct12"))
+    sh = s.launch_shape([65536], 200, 10000)
+    assert sh["kernel"] == pb.KERNEL_TWO_LANE and sh["block"] == 512 and sh["toggle_tables"] == 1
+    assert sh["lds_bytes"] <= 160 * 1024 and sh["sweeps_per_launch"] == 10200
+    sh = s.launch_shape([65536], 200, 10000, lanes_per_chain=1)
+    assert sh["kernel"] == pb.KERNEL_ONE_LANE and sh["block"] <= 256
+    sh = s.launch_shape([1 << 20], 200, 1000)
+    assert sh["kernel"] == pb.KERNEL_ONE_LANE
+    sh = s.launch_shape([65536], 0, 100, lanes_per_chain=2, block_size=64, sweeps_per_launch=7)
+    assert sh["kernel"] == pb.KERNEL_TWO_LANE and sh["block"] == 128 and sh["sweeps_per_launch"] == 7
+    r = pb.CircuitSet(wc.rotated_hadamard_chain(10, math.pi / 8, K=1))
+    assert r.launch_shape([1000], 0, 10, lanes_per_chain=2)["kernel"] == pb.KERNEL_ONE_LANE
+    m = pb.CircuitSet([wc.tiny_ghz_t(), wc.rotated_hadamard_chain(6, math.pi / 8, K=1)])
+    assert m.launch_shape([100, 100], 0, 10, idx=0)["kernel"] == pb.KERNEL_PERSISTENT
+    assert m.launch_shape([100, 100], 0, 10, idx=1)["kernel"] == pb.KERNEL_ONE_LANE
+    assert m.launch_shape([100, 100], 0, 10, idx=0, persistent=2)["kernel"] != pb.KERNEL_PERSISTENT
+    with pytest.raises(pb.PbitError):
+        m.launch_shape([100, 100], 0, 10, idx=2)
