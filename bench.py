@@ -27,8 +27,13 @@ sys.path.insert(0, ROOT)
 # v_mad_u64_u32, against 0.25 for a full-rate instruction).
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # Philox4x32-10 per block: 10 rounds x (2 32x32->64 multiplies + 2
-# three-input XORs) = 40 slots; a block serves 4 updates.
-PHILOX_SLOTS_PER_UPDATE = 40 / 4.0
+# three-input XORs) = 40 slots; a block serves 4 updates.  The blocks of one
+# sweep differ only in the counter word that carries the block index (the
+# sweep, chain and circuit words are shared), so the first three rounds are
+# partly common to all blocks of a sweep: 6 slots of them are needed once per
+# sweep (5) or once per chain (1), leaving 34 slots per block.
+PHILOX_SLOTS_PER_BLOCK = 34
+PHILOX_SLOTS_PER_SWEEP = 5
 UPDATE_FIXED_SLOTS = 1  # the threshold compare u < T
 
 HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19, OFF_QD=20, WS=28,
@@ -38,7 +43,9 @@ HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19,
 def algorithmic_ops(blob):
     """VALU lane-slots the method needs per sweep (all updates of one chain)
     and per sample, counted at the minimum a direct implementation needs:
-    one Philox quarter block and one compare per update, one XOR per nonzero
+    one Philox block per four updates (34 slots once the rounds that the
+    blocks of a sweep share are counted once, 5 slots, per sweep), one
+    compare per update, one XOR per nonzero
     cone word for the expected half of the updates that flip; per sample two
     slots (AND, popcount) per nonzero linear phase-plane word, two (funnel
     shift, AND/OR) per nonzero quadratic mask word plus two per word of each
@@ -47,7 +54,8 @@ def algorithmic_ops(blob):
     h, W, WS, K = g("H"), g("W"), g("WS"), g("K")
     cone = blob[g("OFF_CONE"):g("OFF_CONE") + h * WS].reshape(h, WS)[:, :W]
     nnz = int(np.count_nonzero(cone))
-    per_sweep = h * (PHILOX_SLOTS_PER_UPDATE + UPDATE_FIXED_SLOTS) + 0.5 * nnz
+    nblk = (h + 3) // 4
+    per_sweep = nblk * PHILOX_SLOTS_PER_BLOCK + PHILOX_SLOTS_PER_SWEEP + h * UPDATE_FIXED_SLOTS + 0.5 * nnz
     lin = blob[g("OFF_LIN"):g("OFF_LIN") + K * WS].reshape(K, WS)[:, :W]
     per_sample = 2 * int(np.count_nonzero(lin))
     o = g("OFF_QD")
@@ -275,6 +283,8 @@ def source_digest(*names):
 # unchanged.
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source digest, sources, read bytes, written bytes)
+    ("pbit_uniform_sweep (generated for the circuit, 4 lanes per chain)", "rct12"):
+        ("8c75c5db379e7c85", ('jit.cpp', 'jit.h', 'compile.cpp', 'blob.h'), 133 * 1024 * 2, 36864 * 1024 * 1),
     ("gibbs_pair_kernel<16>", "rct12"): ("1cc1ef522bb50502", ('gibbs_pair.hip', 'philox.h', 'blob.h', 'gibbs.h'), 157.5 * 1024 * 2, 36864 * 1024 * 1),
 }
 
@@ -342,7 +352,9 @@ def main():
     kname = {pbit.KERNEL_ONE_LANE: "gibbs_kernel<%d,%s>" % (shape["kernel_words"],
                                                           "true" if info["uniform"] else "false"),
              pbit.KERNEL_TWO_LANE: "gibbs_pair_kernel<%d>" % shape["kernel_words"],
-             pbit.KERNEL_PERSISTENT: "batched_kernel"}[shape["kernel"]]
+             pbit.KERNEL_PERSISTENT: "batched_kernel",
+             pbit.KERNEL_SPECIALISED: "pbit_uniform_sweep (generated for the circuit, %d lanes per chain)"
+                                      % shape["lanes_per_chain"]}[shape["kernel"]]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -393,6 +405,8 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
             "kernel": kname,
             "kernel_ms": kernel_s * 1e3,
+            "launch": {k: shape[k] for k in ("block", "lds_hist", "lanes_per_chain", "lds_bytes",
+                                             "sweeps_per_launch")},
             "ops_per_update": per_sweep / max(h, 1),
             "ops_per_sample": per_sample,
         },

@@ -130,14 +130,21 @@ typedef struct {
     uint32_t sweep_offset;      /* first sweep counter (resume) */
     uint32_t init;              /* PBIT_INIT_ZERO: all free bits 0; RESUME: read d_state */
     uint32_t sweeps_per_launch; /* sweep-group size; 0 = autotuned */
-    uint32_t block_size;        /* chains per workgroup (64..1024, multiple of 64); 0 = autotuned */
+    uint32_t block_size;        /* chains per workgroup (64..256, multiple of 64); 0 = autotuned */
     uint32_t use_graph;         /* 1: replay the sweep groups as a captured hipGraph */
     uint32_t hist_mode;         /* 0 = auto, 1 = LDS-privatised, 2 = global atomics */
     uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
     uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
     uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */
-    uint32_t lanes_per_chain;   /* 0 = auto, 1, or 2 (two lanes share a chain: circuits whose
-                                   conditionals are all 1/2, single-circuit launches) */
+    uint32_t lanes_per_chain;   /* 0 = auto, 1, 2, 4 or 8.  Circuits whose conditionals are all
+                                   1/2, single-circuit launches only: 2 with the generic kernel
+                                   splits a chain's lattice words over two lanes; with the
+                                   specialised kernel L lanes split a chain's sweeps (lane r runs
+                                   sweeps r, r + L, ...).  4 and 8 need the specialised kernel. */
+    uint32_t specialize;        /* 0 = auto (large runs of circuits whose conditionals are all 1/2),
+                                   1 = never, 2 = always for such circuits (MODE_UNAVAILABLE if
+                                   the run-time compile fails): a kernel generated for the circuit
+                                   and compiled with hipRTC on first use (cached in the handle) */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its
@@ -268,7 +275,8 @@ pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char 
 enum {
     PBIT_KERNEL_ONE_LANE = 0,   /* one chain per lane */
     PBIT_KERNEL_TWO_LANE = 1,   /* two lanes per chain (all conditionals 1/2) */
-    PBIT_KERNEL_PERSISTENT = 2  /* batched persistent tile queue */
+    PBIT_KERNEL_PERSISTENT = 2, /* batched persistent tile queue */
+    PBIT_KERNEL_SPECIALISED = 3 /* generated for the circuit, compiled at run time */
 };
 typedef struct {
     uint32_t kernel;
@@ -278,9 +286,20 @@ typedef struct {
     uint32_t kernel_words;
     uint32_t lds_bytes;
     uint64_t sweeps_per_launch;
+    uint32_t lanes_per_chain;
+    uint32_t pad;
 } pbit_launch_shape;
 pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t index,
                                   pbit_launch_shape *out);
+
+/* HIP source of the specialised sweep kernel of circuit `index` (whose
+ * conditionals must all be 1/2, else MODE_UNAVAILABLE), with the histogram
+ * privatised in LDS when lds_hist != 0, compiled for workgroups of at most
+ * max_block threads (256, 512 or 1024).  Copies at most cap bytes
+ * (NUL-terminated) into buf; *len receives the full length + 1.  Host only,
+ * for inspection and offline compile checks. */
+pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, uint32_t lds_hist, uint32_t max_block,
+                                    char *buf, size_t cap, size_t *len);
 
 const char *pbit_last_error(void);
 

@@ -32,6 +32,7 @@ SOURCES = [
     ("abi.cpp", "hip-host"),
     ("runtime.cpp", "hip-host"),
     ("tune.cpp", "hip-host"),
+    ("jit.cpp", "hip-host"),
     ("proposal.cpp", "hip"),
     ("autotune.cpp", "hip-host"),
     ("gibbs.hip", "hip"),
@@ -74,7 +75,7 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(run, jobs))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stdout + r.stderr))

@@ -1,0 +1,337 @@
+// Circuit-specialised sweep kernel for circuits whose conditionals are all
+// 1/2, generated from the compiled image and compiled at run time with
+// hipRTC.
+//
+// When every conditional is 1/2 a sweep redraws every free bit from its
+// Philox word independently of the lattice, so the lattice after sweep s is
+// const ^ XOR_j TOG[j][new bits of block j], whatever came before.  Two
+// consequences are used here:
+//  * the sweeps of one chain are independent given their counters, so the
+//    sweeps of a chain can be split over several lanes (lane r of a chain
+//    runs sweeps r, r + L, r + 2L, ...); the lane that runs the chain's last
+//    sweep writes its final lattice, and the histogram is a sum over
+//    (chain, sweep) either way, so every count and final state equals the
+//    one-lane kernel's;
+//  * the circuit is fixed for the whole run, so the generated code XORs only
+//    the lattice words each block's cones touch (rows compacted to the
+//    block's support), evaluates the phase polynomial with its masks as
+//    immediates (only nonzero words), and leaves the Philox rounds that the
+//    blocks of one sweep share (counter words other than the block index) to
+//    common-subexpression elimination.
+#include "jit.h"
+
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <sstream>
+
+#include "blob.h"
+
+namespace pbit {
+namespace {
+
+std::string hx(uint32_t v) {
+    char b[16];
+    std::snprintf(b, sizeof b, "0x%08xu", v);
+    return b;
+}
+
+std::string xw(uint32_t i, uint32_t W) { return i < W ? "x[" + std::to_string(i) + "]" : std::string("0u"); }
+
+// lattice bits [32 w + delta, 32 w + delta + 32) as one word
+std::string funnel(uint32_t w, uint32_t delta, uint32_t W) {
+    if (delta < 32)
+        return "__builtin_amdgcn_alignbit(" + xw(w + 1, W) + ", " + xw(w, W) + ", " + std::to_string(delta) + "u)";
+    return "__builtin_amdgcn_alignbit(" + xw(w + 2, W) + ", " + xw(w + 1, W) + ", " + std::to_string(delta - 32) +
+           "u)";
+}
+
+// Compacted toggle rows: block j keeps the lattice words its four cones
+// touch; row p (p = the four top bits of the block's Philox words) holds the
+// XOR of the cones of the bits that come out 1, i.e. the bits whose word has
+// its top bit clear (u < 2^31): subset f = p ^ 15.  Blocks start on 16-byte
+// boundaries; rows of more than two words are padded to a multiple of four.
+struct Blk {
+    std::vector<uint32_t> sup;
+    uint32_t stride = 1, off = 0;
+};
+
+void compact_rows(const CompiledCircuit &k, std::vector<Blk> &blks, std::vector<uint32_t> &rows) {
+    const uint32_t *B = k.blob.data();
+    const uint32_t W = B[H_W], nblk = B[H_NBLK], TW = B[H_TOGW];
+    const uint32_t *tog = B + B[H_OFF_TOG];
+    blks.assign(nblk, Blk());
+    rows.clear();
+    for (uint32_t j = 0; j < nblk; ++j) {
+        Blk &b = blks[j];
+        for (uint32_t w = 0; w < W; ++w) {
+            uint32_t any = 0;
+            for (uint32_t f = 0; f < 16; ++f) any |= tog[(j * 16 + f) * TW + w];
+            if (any) b.sup.push_back(w);
+        }
+        const uint32_t s = (uint32_t)b.sup.size();
+        b.stride = s <= 2 ? (s ? s : 1) : (s + 3) & ~3u;
+        while (rows.size() % 4) rows.push_back(0u);
+        b.off = (uint32_t)rows.size();
+        for (uint32_t p = 0; p < 16; ++p)
+            for (uint32_t i = 0; i < b.stride; ++i)
+                rows.push_back(i < s ? tog[(j * 16 + (p ^ 15u)) * TW + b.sup[i]] : 0u);
+    }
+    while (rows.size() % 4) rows.push_back(0u);
+}
+
+const char *PRELUDE = R"(typedef unsigned int u32;
+typedef unsigned long long u64;
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// products, Weyl key schedule.
+__device__ __attribute__((always_inline)) inline void philox(u32 c0, u32 c1, u32 c2, u32 c3, u32 k0, u32 k1,
+                                       u32 &o0, u32 &o1, u32 &o2, u32 &o3) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const u64 p0 = (u64)0xD2511F53u * c0;
+        const u64 p1 = (u64)0xCD9E8D57u * c2;
+        const u32 n0 = __builtin_amdgcn_bitop3_b32((u32)(p1 >> 32), c1, k0, 0x96);
+        const u32 n2 = __builtin_amdgcn_bitop3_b32((u32)(p0 >> 32), c3, k1, 0x96);
+        c1 = (u32)p1;
+        c3 = (u32)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    o0 = c0; o1 = c1; o2 = c2; o3 = c3;
+}
+)";
+
+}  // namespace
+
+size_t jit_rows_bytes(const CompiledCircuit &k) {
+    std::vector<Blk> blks;
+    std::vector<uint32_t> rows;
+    compact_rows(k, blks, rows);
+    return rows.size() * sizeof(uint32_t);
+}
+
+JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block) {
+    const uint32_t *B = k.blob.data();
+    const uint32_t W = B[H_W], WS = B[H_WS], K = B[H_K], n = B[H_N];
+    const uint32_t nblk = B[H_NBLK];
+    const uint32_t *cw = B + B[H_OFF_CONST];
+    JitSource out;
+    out.max_block = max_block;
+
+    std::vector<Blk> blks;
+    std::vector<uint32_t> rows;
+    compact_rows(k, blks, rows);
+    for (const Blk &b : blks) out.xor_words += (uint32_t)b.sup.size();
+    out.rows_words = (uint32_t)rows.size();
+    const uint32_t nbins = 1u << B[H_HBITS];
+    out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0);
+
+    std::ostringstream o;
+    o << PRELUDE;
+    o << "\n// circuit: n=" << n << " d=" << B[H_D] << " K=" << K << " W=" << W << " h=" << B[H_H]
+      << " id=" << B[H_CID] << "\n";
+    o << "static __device__ const u32 rows_init[" << out.rows_words << "] = {";
+    for (size_t i = 0; i < rows.size(); ++i) o << (i % 8 ? " " : "\n    ") << hx(rows[i]) << ",";
+    o << "\n};\n\n";
+    o << "extern \"C\" __global__ void __attribute__((amdgpu_flat_work_group_size(1, " << max_block
+      << "))) pbit_uniform_sweep(\n"
+         "    u32 *__restrict__ state, u32 *__restrict__ hist, u32 n_chains, u32 lanes_log2, u32 chain_begin,\n"
+         "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from) {\n";
+    o << "    __shared__ __attribute__((aligned(16))) u32 lds_rows[" << out.rows_words << "];\n";
+    if (lds_hist) o << "    __shared__ u32 lds_h[" << nbins << "];\n";
+    o << "    for (u32 e = threadIdx.x; e < " << out.rows_words << "u; e += blockDim.x) lds_rows[e] = rows_init[e];\n";
+    if (lds_hist)
+        o << "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) lds_h[e] = 0u;\n";
+    o << "    __syncthreads();\n";
+    o << "    const u32 gl = blockIdx.x * blockDim.x + threadIdx.x;\n"
+         "    const u32 lc = gl >> lanes_log2;\n"
+         "    const u32 r0 = gl & ((1u << lanes_log2) - 1u);\n"
+         "    if (lc < n_chains) {\n"
+         "        const u32 chain = chain_begin + lc;\n"
+         "        u32 x[" << W << "];\n"
+         "        for (u32 it = r0; it < n_sweeps; it += (1u << lanes_log2)) {\n"
+         "            const u32 s = sweep_begin + it;\n";
+    for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = " << hx(cw[w]) << ";\n";
+    const uint32_t ctag = B[H_CID];  // tag 0: Gibbs updates
+    for (uint32_t j = 0; j < nblk; ++j) {
+        const Blk &b = blks[j];
+        const uint32_t s = (uint32_t)b.sup.size();
+        if (!s) continue;  // no lattice word depends on this block's bits
+        o << "            {\n"
+             "                u32 u0, u1, u2, u3;\n"
+             "                philox(s, " << j << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u0, u1, u2, u3);\n"
+             "                const u32 p = (u0 >> 31) | ((u1 >> 30) & 2u) | ((u2 >> 29) & 4u) | ((u3 >> 28) & 8u);\n"
+             "                const u32 *r = lds_rows + " << b.off << "u + p * " << b.stride << "u;\n";
+        if (b.stride == 1) {
+            o << "                x[" << b.sup[0] << "] ^= r[0];\n";
+        } else if (b.stride == 2) {
+            o << "                const u32x2 v = *(const u32x2 *)r;\n";
+            o << "                x[" << b.sup[0] << "] ^= v.x;\n";
+            o << "                x[" << b.sup[1] << "] ^= v.y;\n";
+        } else {
+            for (uint32_t q = 0; q < b.stride / 4; ++q) {
+                o << "                const u32x4 v" << q << " = *(const u32x4 *)(r + " << 4 * q << ");\n";
+                static const char *comp[4] = {"x", "y", "z", "w"};
+                for (uint32_t e = 0; e < 4; ++e) {
+                    const uint32_t i = 4 * q + e;
+                    if (i < s) o << "                x[" << b.sup[i] << "] ^= v" << q << "." << comp[e] << ";\n";
+                }
+            }
+        }
+        o << "            }\n";
+    }
+    // phase polynomial
+    o << "            if (s >= bin_from) {\n";
+    for (uint32_t t = 0; t < K; ++t) o << "                u32 c" << t << " = 0u;\n";
+    const uint32_t linmask = B[H_LINMASK];
+    const uint32_t *lin = B + B[H_OFF_LIN];
+    for (uint32_t t = 0; t < K; ++t) {
+        if (!((linmask >> t) & 1u)) continue;
+        for (uint32_t w = 0; w < W; ++w) {
+            const uint32_t m = lin[t * WS + w];
+            if (m) o << "                c" << t << " += __builtin_popcount(x[" << w << "] & " << hx(m) << ");\n";
+        }
+    }
+    const uint32_t *qrec = B + B[H_OFF_QD];
+    for (uint32_t q = 0; q < B[H_NQD]; ++q) {
+        const uint32_t delta = qrec[0], pm = qrec[1];
+        for (uint32_t w = 0; w < W; ++w) {
+            bool any = false;
+            for (uint32_t t = 0; t < K; ++t)
+                if (((pm >> t) & 1u) && qrec[2 + t * WS + w]) any = true;
+            if (!any) continue;
+            o << "                {\n                    const u32 y = x[" << w << "] & " << funnel(w, delta, W)
+              << ";\n";
+            for (uint32_t t = 0; t < K; ++t) {
+                const uint32_t m = qrec[2 + t * WS + w];
+                if (((pm >> t) & 1u) && m)
+                    o << "                    c" << t << " += __builtin_popcount(y & " << hx(m) << ");\n";
+            }
+            o << "                }\n";
+        }
+        qrec += qd_stride(K, WS);
+    }
+    const uint32_t *grec = B + B[H_OFF_QG];
+    for (uint32_t g = 0; g < B[H_NQG]; ++g) {
+        const uint32_t t = grec[0], m = grec[1];
+        for (uint32_t w = 0; w < W; ++w) {
+            std::string z;
+            for (uint32_t e = 0; e < m; ++e) {
+                const uint32_t delta = grec[2 + e * qg_entry_stride(WS)];
+                const uint32_t mk = grec[2 + e * qg_entry_stride(WS) + 1 + w];
+                if (!mk) continue;
+                if (!z.empty()) z += " | ";
+                z += "(" + funnel(w, delta, W) + " & " + hx(mk) + ")";
+            }
+            if (!z.empty())
+                o << "                c" << t << " += __builtin_popcount(x[" << w << "] & (" << z << "));\n";
+        }
+        grec += 2 + m * qg_entry_stride(WS);
+    }
+    o << "                const u32 ph = (" << B[H_PCONST] << "u";
+    for (uint32_t t = 0; t < K; ++t) o << " + (c" << t << " << " << t << ")";
+    o << ") & " << ((1u << K) - 1u) << "u;\n";
+    const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
+    o << "                const u32 alpha = __builtin_amdgcn_alignbit(" << xw(aw + 1, W) << ", " << xw(aw, W) << ", "
+      << ash << "u) & " << hx(n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u) << ";\n";
+    o << "                const u32 bin = (alpha << " << K << ") | ph;\n";
+    if (lds_hist)
+        o << "                atomicAdd(&lds_h[bin], 1u);\n";
+    else
+        o << "                atomicAdd(&hist[bin], 1u);\n";
+    o << "            }\n";
+    o << "        }\n";
+    // final lattice: written by the lane that ran the chain's last sweep
+    o << "        if (state && n_sweeps && ((n_sweeps - 1u) & ((1u << lanes_log2) - 1u)) == r0) {\n";
+    for (uint32_t w = 0; w < W; ++w)
+        o << "            state[(u64)" << w << " * n_chains + lc] = x[" << w << "];\n";
+    o << "        }\n";
+    o << "    }\n";
+    if (lds_hist) {
+        o << "    __syncthreads();\n"
+             "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) {\n"
+             "        const u32 v = lds_h[e];\n"
+             "        if (v) atomicAdd(&hist[e], v);\n"
+             "    }\n";
+    }
+    o << "}\n";
+    out.text = o.str();
+    return out;
+}
+
+bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        *log = "no device";
+        return false;
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.text.c_str(), "pbit_uniform_sweep.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS) {
+        *log = "hiprtcCreateProgram failed";
+        return false;
+    }
+    const std::string arch = std::string("--gpu-architecture=") + prop.gcnArchName;
+    const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, 7, opts);
+    size_t ls = 0;
+    (void)hiprtcGetProgramLogSize(prog, &ls);
+    std::string lg(ls + 1, '\0');
+    if (ls) (void)hiprtcGetProgramLog(prog, &lg[0]);
+    if (rc != HIPRTC_SUCCESS) {
+        *log = "hipRTC compile failed: " + lg;
+        (void)hiprtcDestroyProgram(&prog);
+        return false;
+    }
+    size_t cs = 0;
+    (void)hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    (void)hiprtcGetCode(prog, code.data());
+    (void)hiprtcDestroyProgram(&prog);
+    hipModule_t mod = nullptr;
+    hipError_t e = hipModuleLoadData(&mod, code.data());
+    if (e != hipSuccess) {
+        *log = std::string("hipModuleLoadData: ") + hipGetErrorString(e);
+        return false;
+    }
+    hipFunction_t fn = nullptr;
+    e = hipModuleGetFunction(&fn, mod, "pbit_uniform_sweep");
+    if (e != hipSuccess) {
+        (void)hipModuleUnload(mod);
+        *log = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
+        return false;
+    }
+    int scratch = 0;
+    (void)hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn);
+    out->module = mod;
+    out->fn = fn;
+    out->lds_bytes = src.lds_bytes;
+    out->max_block = src.max_block;
+    out->scratch_bytes = scratch;
+    return true;
+}
+
+hipError_t jit_launch(const JitKernel &k, const GibbsLaunch &a, uint32_t lanes_log2, uint32_t block,
+                      hipStream_t stream) {
+    const uint64_t lanes = (uint64_t)a.n_chains << lanes_log2;
+    if (block == 0 || block > k.max_block || lanes_log2 > 3) return hipErrorInvalidValue;
+    const uint64_t grid = (lanes + block - 1) / block;
+    if (grid == 0) return hipSuccess;
+    // the kernel indexes lanes and sweeps in 32 bits: every lane index and
+    // every sweep index plus one stride must fit
+    if (grid * block > 0xFFFFFFFFull || a.n_sweeps > 0xFFFFFF00u) return hipErrorInvalidValue;
+    uint32_t *state = a.state, *hist = a.hist;
+    uint32_t n_chains = a.n_chains, ll = lanes_log2, cb = a.chain_begin, slo = a.seed_lo, shi = a.seed_hi;
+    uint32_t sb = a.sweep_begin, ns = a.n_sweeps, bf = a.bin_from;
+    void *args[] = {&state, &hist, &n_chains, &ll, &cb, &slo, &shi, &sb, &ns, &bf};
+    return hipModuleLaunchKernel(k.fn, (uint32_t)grid, 1, 1, block, 1, 1, 0, stream, args, nullptr);
+}
+
+}  // namespace pbit

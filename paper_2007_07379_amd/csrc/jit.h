@@ -1,0 +1,57 @@
+// Circuit-specialised sweep kernel for circuits whose conditionals are all
+// 1/2 (internal).  The kernel source is generated from one compiled circuit
+// and compiled at run time with hipRTC for the current device.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "compile.h"
+#include "gibbs.h"
+
+namespace pbit {
+
+// Largest private histogram the specialised kernel keeps in LDS, beside its
+// toggle rows.
+constexpr size_t JIT_LDS_LIMIT = 160 * 1024;
+
+struct JitSource {
+    std::string text;        // HIP source of kernel `pbit_uniform_sweep`
+    uint32_t rows_words = 0; // LDS words of the compacted toggle rows
+    uint32_t lds_bytes = 0;  // static LDS of the kernel
+    uint32_t xor_words = 0;  // lattice words XORed per sweep (sum of block supports)
+    uint32_t max_block = 256;
+};
+
+// Generates the kernel for `k` (k.uniform must hold).  With lds_hist the
+// histogram of 2^(n+K) bins is privatised in LDS.  max_block (256, 512 or
+// 1024) is the largest workgroup the kernel is compiled for: 1024 threads
+// leave 128 VGPRs per lane, 512 leave 256.
+JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block);
+
+// LDS bytes of the compacted toggle rows (without the histogram).
+size_t jit_rows_bytes(const CompiledCircuit &k);
+
+// A compiled, loaded specialisation.
+struct JitKernel {
+    hipModule_t module = nullptr;
+    hipFunction_t fn = nullptr;
+    bool lds_hist = false;
+    uint32_t lds_bytes = 0;
+    uint32_t max_block = 256;
+    int scratch_bytes = 0;  // per-lane scratch of the compiled kernel (register spills)
+};
+
+// Compiles `src` with hipRTC for the current device and loads it (and reads
+// back its per-lane scratch size).  On failure returns false and fills `log`.
+bool jit_build(const JitSource &src, JitKernel *out, std::string *log);
+
+// Launches a loaded specialisation: lanes_log2 = log2(lanes per chain); lane
+// (chain c, residue r) runs the sweeps sweep_begin + r, + r + 2^lanes_log2, ...
+// of chain c.  block <= 1024.
+hipError_t jit_launch(const JitKernel &k, const GibbsLaunch &a, uint32_t lanes_log2, uint32_t block,
+                      hipStream_t stream);
+
+}  // namespace pbit

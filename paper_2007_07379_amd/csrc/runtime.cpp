@@ -19,6 +19,8 @@ pbit_circuit_s::~pbit_circuit_s() {
     for (auto *m : {&blobs, &scratch, &work})
         for (auto &kv : *m)
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    for (auto &kv : jit)
+        if (kv.second.module) (void)hipModuleUnload(kv.second.module);
 }
 
 namespace pbit {
@@ -87,7 +89,10 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (cfg->toggle_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad toggle_mode");
     if (cfg->persistent > 2) return set_error(PBIT_E_INVALID_ARG, "bad persistent mode");
     if (cfg->wg_per_cu > 16) return set_error(PBIT_E_INVALID_ARG, "wg_per_cu must be <= 16");
-    if (cfg->lanes_per_chain > 2) return set_error(PBIT_E_INVALID_ARG, "lanes_per_chain must be 0, 1 or 2");
+    if (cfg->lanes_per_chain != 0 && cfg->lanes_per_chain != 1 && cfg->lanes_per_chain != 2 &&
+        cfg->lanes_per_chain != 4 && cfg->lanes_per_chain != 8)
+        return set_error(PBIT_E_INVALID_ARG, "lanes_per_chain must be 0, 1, 2, 4 or 8");
+    if (cfg->specialize > 2) return set_error(PBIT_E_INVALID_ARG, "bad specialize mode");
     if (cfg->block_size && (cfg->block_size % 64 || cfg->block_size > 256))
         return set_error(PBIT_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
@@ -122,6 +127,50 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         choices[i] = tune_choice(c, i, cfg->chains[i], total, cfg);
         batched[i] = runs_batched(c, i, cfg);
     }
+    // circuit-specialised kernels are compiled here, before any enqueue (and
+    // outside a graph capture)
+    std::vector<const JitKernel *> jits(nc, nullptr);
+    for (uint32_t i = 0; i < nc; ++i) {
+        if (!cfg->chains[i] || batched[i] || !choices[i].jit) continue;
+        const auto key = std::make_tuple(dev, i, choices[i].lds_hist);
+        auto it = c->jit.find(key);
+        if (it == c->jit.end() && !c->jit_failed.count(key)) {
+            // one workgroup per CU holds the LDS histogram, so it gets 1024
+            // threads (four waves per SIMD) unless that spills registers, then
+            // 512; without it, 256-thread workgroups
+            std::string log;
+            JitKernel jk;
+            bool ok = false;
+            for (uint32_t mb : choices[i].lds_hist ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
+                const JitSource src = jit_uniform_source(c->circuits[i], choices[i].lds_hist, mb);
+                if (src.lds_bytes > JIT_LDS_LIMIT) {
+                    log = "LDS of the specialised kernel exceeds 160 KiB";
+                    break;
+                }
+                if (jk.module) (void)hipModuleUnload(jk.module);
+                jk = JitKernel();
+                if (!jit_build(src, &jk, &log)) break;
+                ok = true;
+                if (jk.scratch_bytes == 0) break;
+            }
+            if (ok) {
+                jk.lds_hist = choices[i].lds_hist;
+                it = c->jit.emplace(key, jk).first;
+            } else {
+                c->jit_failed[key] = log;
+            }
+        }
+        if (it != c->jit.end()) {
+            jits[i] = &it->second;
+        } else if (cfg->specialize == 2) {
+            return set_error(PBIT_E_MODE_UNAVAILABLE, "specialised kernel unavailable: " + c->jit_failed[key]);
+        } else {
+            // the generic kernels serve the run
+            pbit_gibbs_cfg g = *cfg;
+            g.specialize = 1;
+            choices[i] = tune_choice(c, i, cfg->chains[i], total, &g);
+        }
+    }
     const BatchTuning bt = tune_batch(c, cfg);
     uint64_t group = total;
     if (cfg->sweeps_per_launch) group = std::min<uint64_t>(cfg->sweeps_per_launch, total);
@@ -142,6 +191,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         bool uniform;
         bool tog;
         bool pair;
+        const JitKernel *jit;
+        uint32_t lanes_log2;
         uint32_t block;
         size_t lds;
     };
@@ -184,8 +235,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         const TuneChoice &tc = choices[i];
         const size_t thr_bytes = k.uniform ? 0 : (size_t)k.blob[H_THR_TOTAL] * sizeof(uint32_t);
         if (thr_bytes > 64 * 1024) return set_error(PBIT_E_TOO_LARGE, "threshold tables exceed 64 KiB of LDS");
-        const size_t lds = tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
-                                   : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist);
+        const size_t lds = tc.jit ? jits[i]->lds_bytes
+                                  : (tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
+                                             : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
         if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
         for (uint64_t done = 0; done < total; done += tc.group) {
             Plan p;
@@ -206,7 +258,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.uniform = k.uniform;
             p.tog = tc.tog;
             p.pair = tc.pair;
-            p.block = tc.block;
+            p.jit = tc.jit ? jits[i] : nullptr;
+            p.lanes_log2 = tc.lanes_log2;
+            p.block = tc.jit ? std::min<uint32_t>(tc.block, jits[i]->max_block) : tc.block;
             p.lds = lds;
             plans.push_back(p);
         }
@@ -263,8 +317,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
 
     auto enqueue = [&]() -> pbit_status {
         for (const Plan &p : plans) {
-            hipError_t le = p.pair ? launch_gibbs_pair(p.Wk, p.a, p.block, p.lds, stream)
-                                   : launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
+            hipError_t le = p.jit ? jit_launch(*p.jit, p.a, p.lanes_log2, p.block, stream)
+                            : p.pair ? launch_gibbs_pair(p.Wk, p.a, p.block, p.lds, stream)
+                                     : launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
             if (le != hipSuccess) return hip_error(le, "gibbs kernel launch");
         }
         if (bcirc.empty()) return PBIT_OK;
@@ -302,7 +357,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                                  (uint64_t)(uintptr_t)d_bcirc, cfg->chain_begin, cfg->burn_in, cfg->sweeps,
                                  cfg->seed, cfg->sweep_offset, cfg->init, cfg->sweeps_per_launch, cfg->block_size,
                                  cfg->hist_mode, cfg->toggle_mode, cfg->persistent, cfg->wg_per_cu,
-                                 cfg->lanes_per_chain, c->tune_epoch};
+                                 cfg->lanes_per_chain, cfg->specialize, c->tune_epoch};
     for (uint32_t i = 0; i < nc; ++i) key.push_back(cfg->chains[i]);
     GraphCache &gc = c->graphs[dev];
     if (!(gc.exec && gc.key == key)) {
@@ -358,13 +413,44 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
         out->sweeps_per_launch = cfg->sweeps_per_launch ? std::min<uint64_t>(cfg->sweeps_per_launch, total) : total;
         return PBIT_OK;
     }
-    const TuneChoice tc = tune_choice(c, index, cfg->chains[index], total, cfg);
-    out->kernel = tc.pair ? PBIT_KERNEL_TWO_LANE : PBIT_KERNEL_ONE_LANE;
+    TuneChoice tc = tune_choice(c, index, cfg->chains[index], total, cfg);
+    if (tc.jit && cfg->specialize != 2) {
+        // a specialisation that failed to build on this device is replaced
+        // by the generic kernels
+        int dev = 0;
+        if (!c->jit_failed.empty() && hipGetDevice(&dev) == hipSuccess &&
+            c->jit_failed.count(std::make_tuple(dev, index, tc.lds_hist))) {
+            pbit_gibbs_cfg g = *cfg;
+            g.specialize = 1;
+            tc = tune_choice(c, index, cfg->chains[index], total, &g);
+        }
+    }
+    out->kernel = tc.jit ? PBIT_KERNEL_SPECIALISED : (tc.pair ? PBIT_KERNEL_TWO_LANE : PBIT_KERNEL_ONE_LANE);
     out->block = tc.block;
     out->lds_hist = tc.lds_hist ? 1u : 0u;
     out->toggle_tables = tc.tog ? 1u : 0u;
-    out->lds_bytes = (uint32_t)(tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
-                                        : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
+    out->lanes_per_chain = tc.jit ? (1u << tc.lanes_log2) : (tc.pair ? 2u : 1u);
+    out->lds_bytes = (uint32_t)(tc.jit ? jit_rows_bytes(k) + (tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0)
+                                : tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
+                                          : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
     out->sweeps_per_launch = tc.group;
+    return PBIT_OK;
+}
+
+extern "C" pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, uint32_t lds_hist,
+                                               uint32_t max_block, char *buf, size_t cap, size_t *len) {
+    if (!c || !len) return set_error(PBIT_E_INVALID_ARG, "NULL handle or len");
+    if (max_block != 256 && max_block != 512 && max_block != 1024)
+        return set_error(PBIT_E_INVALID_ARG, "max_block must be 256, 512 or 1024");
+    if (index >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
+    const CompiledCircuit &k = c->circuits[index];
+    if (!k.uniform) return set_error(PBIT_E_MODE_UNAVAILABLE, "circuit has conditionals other than 1/2");
+    const JitSource src = jit_uniform_source(k, lds_hist != 0, max_block);
+    *len = src.text.size() + 1;
+    if (buf && cap) {
+        const size_t m = std::min(cap - 1, src.text.size());
+        std::memcpy(buf, src.text.data(), m);
+        buf[m] = '\0';
+    }
     return PBIT_OK;
 }

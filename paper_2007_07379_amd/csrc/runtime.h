@@ -5,10 +5,12 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pbit.h"
 #include "compile.h"
+#include "jit.h"
 
 namespace pbit {
 
@@ -62,6 +64,9 @@ struct pbit_circuit_s {
     bool tuned_batch_valid = false;
     pbit::TunedBatch tuned_batch;
     uint64_t tune_epoch = 0;
+    // circuit-specialised kernels, keyed by (device, circuit, LDS histogram)
+    std::map<std::tuple<int, uint32_t, bool>, pbit::JitKernel> jit;
+    std::map<std::tuple<int, uint32_t, bool>, std::string> jit_failed;
     ~pbit_circuit_s();
 };
 

@@ -6,6 +6,7 @@
 
 #include "blob.h"
 #include "gibbs.h"
+#include "jit.h"
 
 namespace pbit {
 
@@ -60,6 +61,29 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     }
     t.group = total_sweeps;
     if (cfg->sweeps_per_launch) t.group = std::min<uint64_t>(cfg->sweeps_per_launch, total_sweeps);
+
+    // circuit-specialised kernel: runs of 2^33 updates or more (the run-time
+    // compile takes about a second), unless the caller asks for a generic
+    // toggle mode
+    const uint64_t work = (uint64_t)chains * total_sweeps * k.h;
+    t.jit = k.uniform && (cfg->specialize == 2 || (cfg->specialize == 0 && cfg->toggle_mode == 0 &&
+                                                   work >= (1ull << 33)));
+    if (t.jit) {
+        uint32_t L = cfg->lanes_per_chain;
+        if (!L) {
+            // enough lanes for four waves per SIMD, each lane keeping >= 16 sweeps
+            L = 1;
+            while (L < 8 && (uint64_t)chains * L < 4ull * 65536 && t.group / (2 * L) >= 16) L *= 2;
+        }
+        t.lanes_log2 = L >= 8 ? 3 : (L >= 4 ? 2 : (L >= 2 ? 1 : 0));
+        t.pair = false;
+        t.tog = true;
+        const size_t hist_b = ((size_t)1 << (k.n + k.K)) * 4;
+        const size_t rows_b = jit_rows_bytes(k);
+        t.lds_hist = cfg->hist_mode == 1 || (cfg->hist_mode == 0 && rows_b + hist_b <= LDS_MAX);
+        t.block = t.lds_hist ? 1024 : 256;
+        if (cfg->block_size) t.block = cfg->block_size;
+    }
     return t;
 }
 

@@ -14,6 +14,8 @@ struct TuneChoice {
     bool lds_hist = true;     // histogram privatised in LDS
     bool tog = true;          // LDS toggle tables (else per-bit cone toggles)
     bool pair = false;        // two lanes per chain (uniform circuits)
+    bool jit = false;         // circuit-specialised kernel (uniform circuits)
+    uint32_t lanes_log2 = 0;  // specialised kernel: log2(lanes per chain)
 };
 
 // Explicit cfg fields win; unset ones come from the autotuned table of the

@@ -56,16 +56,17 @@ class GibbsCfg(C.Structure):
                 ("sweep_offset", C.c_uint32), ("init", C.c_uint32),
                 ("sweeps_per_launch", C.c_uint32), ("block_size", C.c_uint32),
                 ("use_graph", C.c_uint32), ("hist_mode", C.c_uint32), ("toggle_mode", C.c_uint32),
-                ("persistent", C.c_uint32), ("wg_per_cu", C.c_uint32), ("lanes_per_chain", C.c_uint32)]
+                ("persistent", C.c_uint32), ("wg_per_cu", C.c_uint32), ("lanes_per_chain", C.c_uint32),
+                ("specialize", C.c_uint32)]
 
 
 class LaunchShape(C.Structure):
     _fields_ = [("kernel", C.c_uint32), ("block", C.c_uint32), ("lds_hist", C.c_uint32),
                 ("toggle_tables", C.c_uint32), ("kernel_words", C.c_uint32), ("lds_bytes", C.c_uint32),
-                ("sweeps_per_launch", C.c_uint64)]
+                ("sweeps_per_launch", C.c_uint64), ("lanes_per_chain", C.c_uint32), ("pad", C.c_uint32)]
 
 
-KERNEL_ONE_LANE, KERNEL_TWO_LANE, KERNEL_PERSISTENT = 0, 1, 2
+KERNEL_ONE_LANE, KERNEL_TWO_LANE, KERNEL_PERSISTENT, KERNEL_SPECIALISED = 0, 1, 2, 3
 
 _lib = None
 
@@ -192,7 +193,7 @@ class CircuitSet:
     def gibbs_run(self, chains, burn_in, sweeps, d_hist, d_state=None, seed=0, chain_begin=0,
                   sweep_offset=0, resume=False, sweeps_per_launch=0, block_size=0, use_graph=False,
                   hist_mode=0, toggle_mode=0, persistent=0, wg_per_cu=0, lanes_per_chain=0,
-                  stream=None):
+                  specialize=0, stream=None):
         if isinstance(chains, int):
             chains = [chains]
         arr = (C.c_uint32 * len(chains))(*[int(x) for x in chains])
@@ -212,6 +213,7 @@ class CircuitSet:
         cfg.persistent = persistent
         cfg.wg_per_cu = wg_per_cu
         cfg.lanes_per_chain = lanes_per_chain
+        cfg.specialize = specialize
         _check(lib().pbit_gibbs_run(self.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                                     _stream(stream)))
 
@@ -232,6 +234,20 @@ class CircuitSet:
         L.pbit_launch_shape_get.argtypes = [C.c_void_p, C.POINTER(GibbsCfg), C.c_uint32, C.POINTER(LaunchShape)]
         _check(L.pbit_launch_shape_get(self.handle, C.byref(cfg), idx, C.byref(out)))
         return {f: getattr(out, f) for f, _ in LaunchShape._fields_}
+
+    def specialised_source(self, idx=0, lds_hist=True, max_block=None):
+        """HIP source of the circuit-specialised sweep kernel of circuit idx."""
+        if max_block is None:
+            max_block = 1024 if lds_hist else 256
+        L = lib()
+        L.pbit_specialised_source.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_char_p,
+                                              C.c_size_t, C.POINTER(C.c_size_t)]
+        n = C.c_size_t(0)
+        lh = 1 if lds_hist else 0
+        _check(L.pbit_specialised_source(self.handle, idx, lh, max_block, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(L.pbit_specialised_source(self.handle, idx, lh, max_block, buf, n.value, C.byref(n)))
+        return buf.value.decode()
 
     def autotune(self, chains, burn_in, sweeps, cache_path=None, persistent=0, stream=None):
         if isinstance(chains, int):

@@ -1,0 +1,129 @@
+"""GPU parity of the circuit-specialised sweep kernel (generated per circuit,
+compiled at run time with hipRTC): for circuits whose conditionals are all
+1/2, final lattice words and uint32 counts equal the CPU oracle's bit for
+bit with 1, 2, 4 and 8 lanes per chain, LDS or HBM histograms, sweep groups
+that do not divide the lane count, hipGraph replay, and runs resumed across
+the generic and the specialised kernels."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import chain as och
+from oracle import circuit as oc
+from oracle import compile as ocomp
+from workloads import circuits as wc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_07379_amd import pbit
+    return torch, pbit
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    # name, circuit, chains, burn_in, sweeps, chain_begin
+    ("tiny", lambda: wc.tiny_ghz_t(), 1024, 200, 2000, 0),
+    ("rct12", lambda: wc.workload_circuit("rct12"), 1000, 20, 61, 4321),
+    ("brick20", lambda: wc.workload_circuit("brick20"), 700, 10, 30, 0),
+    ("brick16", lambda: wc.workload_circuit("brick16"), 513, 10, 43, 77),
+    ("hchain_odd", lambda: wc.hadamard_chain(33, K=1), 300, 5, 50, 0),
+    ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 21, 0),
+]
+
+_oracle_cache = {}
+
+
+def oracle(name, c, chains, burn, sweeps, seed, cb):
+    key = (name, chains, burn, sweeps, seed, cb)
+    if key not in _oracle_cache:
+        comp = ocomp.compile_circuit(oc.from_dict(c))
+        _oracle_cache[key] = och.gibbs(comp, chains, burn, sweeps, seed=seed, chain_begin=cb,
+                                       threads=os.cpu_count() or 8)
+    return _oracle_cache[key]
+
+
+def run(env, s, chains, burn, sweeps, seed, cb, stream=None, **kw):
+    torch, pbit = env
+    info = s.info(0)
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([chains], burn, sweeps, hist, state, seed=seed, chain_begin=cb,
+                stream=stream or torch.cuda.current_stream(), **kw)
+    torch.cuda.synchronize()
+    W = info["W"]
+    st = state.cpu().numpy().view(np.uint32).reshape(W, chains).T.copy()
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    return st, h
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("name,mk,chains,burn,sweeps,cb", CASES, ids=[c[0] for c in CASES])
+def test_specialised_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb, lanes):
+    torch, pbit = env
+    c = mk()
+    s = pbit.CircuitSet(c)
+    seed = 0 if name == "tiny" else 0x1234abcd5678
+    sh = s.launch_shape([chains], burn, sweeps, specialize=2, lanes_per_chain=lanes)
+    assert sh["kernel"] == pbit.KERNEL_SPECIALISED and sh["lanes_per_chain"] == lanes
+    st_o, h_o = oracle(name, c, chains, burn, sweeps, seed, cb)
+    for hm in [0, 2]:
+        say("case", name, chains, burn, sweeps, cb, "lanes", lanes, "hist_mode", hm)
+        st, h = run(env, s, chains, burn, sweeps, seed, cb, specialize=2, lanes_per_chain=lanes, hist_mode=hm)
+        assert np.array_equal(st, st_o), hm
+        assert np.array_equal(h, h_o), hm
+        assert int(h.sum()) == chains * sweeps
+
+
+def test_specialised_groups_graph_and_resume(env):
+    torch, pbit = env
+    c = wc.workload_circuit("rct12")
+    chains, burn, sweeps, seed = 777, 9, 45, 3
+    st_o, h_o = oracle("rct12", c, chains, burn, sweeps, seed, 0)
+    s = pbit.CircuitSet(c)
+    for kw in [dict(sweeps_per_launch=7, lanes_per_chain=4), dict(sweeps_per_launch=1, lanes_per_chain=8),
+               dict(sweeps_per_launch=13, lanes_per_chain=2, hist_mode=2)]:
+        say("groups", kw)
+        st, h = run(env, s, chains, burn, sweeps, seed, 0, specialize=2, **kw)
+        assert np.array_equal(st, st_o), kw
+        assert np.array_equal(h, h_o), kw
+    # graph replay on a side stream, eager work between replays
+    info = s.info(0)
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        say("graph replay", rep)
+        hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+        state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        s.gibbs_run([chains], burn, sweeps, hist, state, seed=seed, sweeps_per_launch=10, use_graph=True,
+                    specialize=2, lanes_per_chain=4, stream=side)
+        side.synchronize()
+        st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+        h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+        assert np.array_equal(st, st_o), rep
+        assert np.array_equal(h, h_o), rep
+        _ = torch.ones(1000, device="cuda").sum().item()
+    # resume across kernels: generic first, specialised after, and back
+    for first, second in [(1, 2), (2, 1)]:
+        say("resume", first, second)
+        hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+        state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+        s.gibbs_run([chains], burn, 20, hist, state, seed=seed, specialize=first, lanes_per_chain=4 if first == 2 else 0)
+        s.gibbs_run([chains], 0, sweeps - 20, hist, state, seed=seed, sweep_offset=burn + 20, resume=True,
+                    specialize=second, lanes_per_chain=4 if second == 2 else 0)
+        torch.cuda.synchronize()
+        st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+        h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+        assert np.array_equal(st, st_o)
+        assert np.array_equal(h, h_o)

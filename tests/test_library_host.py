@@ -245,19 +245,76 @@ def test_launch_shape_rules(pb):
     queue for uniform circuits of a multi-circuit handle."""
     s = pb.CircuitSet(wc.workload_circuit("rct12"))
     sh = s.launch_shape([65536], 200, 10000)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["block"] == 1024 and sh["lanes_per_chain"] == 4
+    assert sh["lds_hist"] == 1 and sh["lds_bytes"] <= 160 * 1024
+    sh = s.launch_shape([65536], 200, 10000, specialize=1)
     assert sh["kernel"] == pb.KERNEL_TWO_LANE and sh["block"] == 512 and sh["toggle_tables"] == 1
     assert sh["lds_bytes"] <= 160 * 1024 and sh["sweeps_per_launch"] == 10200
-    sh = s.launch_shape([65536], 200, 10000, lanes_per_chain=1)
+    sh = s.launch_shape([65536], 200, 10000, lanes_per_chain=1, specialize=1)
     assert sh["kernel"] == pb.KERNEL_ONE_LANE and sh["block"] <= 256
-    sh = s.launch_shape([1 << 20], 200, 1000)
+    sh = s.launch_shape([65536], 200, 10000, lanes_per_chain=8)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lanes_per_chain"] == 8
+    assert s.launch_shape([1000], 0, 50)["kernel"] == pb.KERNEL_TWO_LANE  # too small to compile for
+    assert s.launch_shape([1000], 0, 50, specialize=2)["kernel"] == pb.KERNEL_SPECIALISED
+    sh = s.launch_shape([1 << 20], 200, 1000, specialize=1)
     assert sh["kernel"] == pb.KERNEL_ONE_LANE
     sh = s.launch_shape([65536], 0, 100, lanes_per_chain=2, block_size=64, sweeps_per_launch=7)
     assert sh["kernel"] == pb.KERNEL_TWO_LANE and sh["block"] == 128 and sh["sweeps_per_launch"] == 7
     r = pb.CircuitSet(wc.rotated_hadamard_chain(10, math.pi / 8, K=1))
     assert r.launch_shape([1000], 0, 10, lanes_per_chain=2)["kernel"] == pb.KERNEL_ONE_LANE
+    assert r.launch_shape([1000], 0, 10, specialize=2)["kernel"] == pb.KERNEL_ONE_LANE
     m = pb.CircuitSet([wc.tiny_ghz_t(), wc.rotated_hadamard_chain(6, math.pi / 8, K=1)])
     assert m.launch_shape([100, 100], 0, 10, idx=0)["kernel"] == pb.KERNEL_PERSISTENT
     assert m.launch_shape([100, 100], 0, 10, idx=1)["kernel"] == pb.KERNEL_ONE_LANE
     assert m.launch_shape([100, 100], 0, 10, idx=0, persistent=2)["kernel"] != pb.KERNEL_PERSISTENT
     with pytest.raises(pb.PbitError):
         m.launch_shape([100, 100], 0, 10, idx=2)
+
+
+SPEC_CIRCUITS = [
+    ("tiny", lambda: wc.tiny_ghz_t()),
+    ("rct12", lambda: wc.workload_circuit("rct12")),
+    ("brick20", lambda: wc.workload_circuit("brick20")),
+    ("brick16", lambda: wc.workload_circuit("brick16")),
+    ("hchain_odd", lambda: wc.hadamard_chain(33, K=1)),
+    ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3)),
+]
+
+
+@pytest.mark.parametrize("name,mk", SPEC_CIRCUITS, ids=[c[0] for c in SPEC_CIRCUITS])
+def test_specialised_source_compiles_for_gfx950(pb, name, mk, tmp_path):
+    """The generated kernel of every uniform test circuit compiles offline for
+    gfx950 without register spills: with the LDS histogram (where it fits) at
+    1024 threads per workgroup (128 VGPRs) or else at 512 (256 VGPRs), the
+    run-time fallback; without it at 256."""
+    s = pb.CircuitSet(mk())
+    info = s.info(0)
+    modes = [(False, (256,))] + ([(True, (1024, 512))] if info["hist_bins"] * 4 <= 128 * 1024 else [])
+    for lds, blocks in modes:
+        for mb in blocks:
+            vg, sc = _offline_compile(s, name, lds, mb, tmp_path)
+            if sc == 0:
+                break
+        assert sc == 0, (name, lds, vg, sc)
+
+
+def _offline_compile(s, name, lds, mb, tmp_path):
+    src = s.specialised_source(0, lds_hist=lds, max_block=mb)
+    assert "pbit_uniform_sweep" in src
+    f = tmp_path / ("%s_%d_%d.hip" % (name, lds, mb))
+    f.write_text(src)
+    cmd = ["/opt/rocm/bin/hipcc", "-include", "hip/hip_runtime.h", "--offload-arch=gfx950", "-O3",
+           "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
+           "-c", str(f), "-o", str(f) + ".o", "-Rpass-analysis=kernel-resource-usage"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    vg = int(re.search(r"VGPRs: (\d+)", r.stderr).group(1))
+    sc = int(re.search(r"ScratchSize \[bytes/lane\]: (\d+)", r.stderr).group(1))
+    return vg, sc
+
+
+def test_specialised_source_rejects_nonuniform(pb):
+    r = pb.CircuitSet(wc.rotated_hadamard_chain(10, math.pi / 8, K=1))
+    with pytest.raises(pb.PbitError) as e:
+        r.specialised_source(0)
+    assert e.value.name == "MODE_UNAVAILABLE"
