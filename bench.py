@@ -299,6 +299,56 @@ def measured_traffic(kernel, workload):
     return rd + wr
 
 
+def batch_mode(args):
+    """256 random Clifford+T circuits (n 4..16, d 4..32, chains proportional
+    to 2^n, 2^22 in total), 200 + 2000 sweeps, one persistent launch per
+    lattice-width class."""
+    import torch
+    from paper_2007_07379_amd import pbit
+    from workloads import circuits as wc
+    data = json.load(open(os.path.join(wc.DATA_DIR, "batch256.json")))
+    circs, chains = data["circuits"], data["chains"]
+    burn, sweeps = 200, 2000
+    s = pbit.CircuitSet(circs)
+    infos = [s.info(i) for i in range(len(circs))]
+    updates = sum(ch * (burn + sweeps) * inf["h"] for ch, inf in zip(chains, infos))
+    ops = 0.0
+    for i, ch in enumerate(chains):
+        ps, pa, _ = algorithmic_ops(s.export(i))
+        ops += ch * ((burn + sweeps) * ps + sweeps * pa)
+    stream = torch.cuda.current_stream()
+    hist = torch.zeros(s.hist_bins(), dtype=torch.int32, device="cuda")
+    state = torch.zeros(s.state_words(chains), dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        hist.zero_()
+        s.gibbs_run(chains, burn, sweeps, hist, state, seed=0, persistent=1, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        s.gibbs_run(chains, burn, sweeps, hist, state, seed=0, persistent=1, stream=stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    ms_per_step = wall / args.steps * 1e3
+    out = {
+        "metric": "p-bit updates/s", "value": updates / (ms_per_step / 1e3), "unit": "updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batch256: 256 random Clifford+T circuits, n 4..16, d 4..32, %d chains "
+                               "in total (proportional to 2^n), %d burn-in + %d sweeps, persistent launch"
+                               % (sum(chains), burn, sweeps)},
+        "samples_per_s": sum(chains) * sweeps / (ms_per_step / 1e3),
+        "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tslot-op/s", "frac": ops / kernel_s / VALU_PEAK, "traffic": None,
+                     "kernel": "batched_kernel (3 width classes)", "kernel_ms": kernel_s * 1e3},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +375,9 @@ def main():
             args.workload = "brick16"
         mh_mode(args)
         return
+    if args.workload == "batch256":
+        batch_mode(args)
+        return
 
     import torch
     from paper_2007_07379_amd import pbit
@@ -341,14 +394,28 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev)
+    # uint32 counts: a run whose chains x sweeps reaches 2^32 is cut into
+    # parts (the chain state carries over), each with its own histogram
+    per_part = (2 ** 32 - 1) // chains
+    parts = []
+    done = 0
+    while done < sweeps:
+        n = min(per_part, sweeps - done)
+        parts.append((burn if done == 0 else 0, n, 0 if done == 0 else burn + done))
+        done += n
+    hists = [torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev) for _ in parts]
     state = torch.zeros(chains * info["W"], dtype=torch.int32, device=dev)
 
-    def step():
-        hist.zero_()
-        s.gibbs_run([chains], burn, sweeps, hist, state, seed=0, stream=stream)
+    def run_parts():
+        for (b, n, off), hh in zip(parts, hists):
+            s.gibbs_run([chains], b, n, hh, state, seed=0, sweep_offset=off, resume=off > 0, stream=stream)
 
-    shape = s.launch_shape([chains], burn, sweeps)
+    def step():
+        for hh in hists:
+            hh.zero_()
+        run_parts()
+
+    shape = s.launch_shape([chains], parts[0][0], parts[0][1])
     kname = {pbit.KERNEL_ONE_LANE: "gibbs_kernel<%d,%s>" % (shape["kernel_words"],
                                                           "true" if info["uniform"] else "false"),
              pbit.KERNEL_TWO_LANE: "gibbs_pair_kernel<%d>" % shape["kernel_words"],
@@ -363,7 +430,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
-        s.gibbs_run([chains], burn, sweeps, hist, state, seed=0, stream=stream)
+        run_parts()
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
