@@ -94,27 +94,6 @@ def cpu_baseline(c, h, burn, sweeps, chains_sample):
                       "workload), %.1f s" % (chains_sample, burn, sweeps, dt)}
 
 
-def geyer_tau(x):
-    """Integrated autocorrelation time of an observable series x[steps,
-    chains] (Geyer's initial positive sequence on the chain-pooled
-    autocorrelation)."""
-    x = x - x.mean()
-    v = float((x * x).mean())
-    if v <= 0:
-        return float("nan")
-    S = x.shape[0]
-    rho = [1.0] + [float((x[t:] * x[:-t]).mean() / v) for t in range(1, S // 2)]
-    tau = -1.0
-    k = 0
-    while 2 * k + 1 < len(rho):
-        g = rho[2 * k] + rho[2 * k + 1]
-        if g <= 0:
-            break
-        tau += 2 * g
-        k += 1
-    return tau
-
-
 def output_parities(torch, state, info, masks):
     """+-1 parity characters of the output state alpha of every chain."""
     n, d, W = info["n"], info["d"], info["W"]
@@ -135,17 +114,68 @@ def output_parities(torch, state, info, masks):
     return torch.stack(out)  # [n_obs, chains]
 
 
+def _rh(theta):
+    return lambda wc: wc.rotated_hadamard_chain(48, theta, K=1)
+
+
+PI = 3.141592653589793
 MH_WORKLOADS = {
-    # name: (circuit factory, chains, burn_in, steps, hidden, train_samples, train_steps, batch)
-    "brick16": (lambda wc: wc.workload_circuit("brick16"), 131072, 200, 48, 1024, 1 << 20, 2560, 4096, 400),
-    "rhchain48": (lambda wc: wc.rotated_hadamard_chain(48, 3.141592653589793 / 64, K=1), 131072, 2000, 96, 128,
-                  1 << 18, 1500, 4096, 200),
+    # chains: population timed for s/transition and binned for TV; tau_chains:
+    # chains whose output series gives tau_int; burn_in in sweeps
+    "brick16": dict(circuit=lambda wc: wc.workload_circuit("brick16"), chains=131072, burn_in=200, hidden=1024,
+                    train=1 << 20, train_steps=2560, batch=4096, long_cycles=400, tau_chains=4096),
+    "rhchain48": dict(circuit=_rh(PI / 64), chains=131072, burn_in=2000, hidden=128, train=1 << 18,
+                      train_steps=1500, batch=4096, long_cycles=200, tau_chains=4096),
 }
+for _k in (16, 32, 128, 256):
+    MH_WORKLOADS["rhchain48_pi%d" % _k] = dict(MH_WORKLOADS["rhchain48"], circuit=_rh(PI / _k),
+                                                burn_in=max(2000, _k * _k // 2))
+
+
+def tau_of_series(torch, ser):
+    """tau_int of a [steps, chains] series: chain-pooled autocovariance by
+    FFT, Geyer's initial positive sequence."""
+    x = ser - ser.mean()
+    S = x.shape[0]
+    f = torch.fft.rfft(x, n=2 * S, dim=0)
+    acov = torch.fft.irfft((f * f.conj()).real.sum(dim=1), n=2 * S)[:S] / (x.shape[1] * torch.arange(
+        S, 0, -1, device=x.device, dtype=x.dtype))
+    rho = (acov / acov[0]).cpu().numpy()
+    tau = -1.0
+    k = 0
+    while 2 * k + 1 < S // 2:
+        g = rho[2 * k] + rho[2 * k + 1]
+        if g <= 0:
+            break
+        tau += 2 * g
+        k += 1
+    return float(tau)
+
+
+def adaptive_tau(torch, advance, observe, min_len=512, max_len=65536):
+    """Runs `advance` (one transition of the tau population) and records
+    `observe` ([n_obs, chains]) until the series is at least 50 tau_int long
+    (or max_len); returns (tau_int, series length)."""
+    buf = []
+    tau = float("nan")
+    L = min_len
+    while True:
+        while len(buf) < L:
+            advance(len(buf))
+            buf.append(observe().to(torch.float32))
+        ser = torch.stack(buf)  # [S, n_obs, chains]
+        tau = max(tau_of_series(torch, ser[:, o, :]) for o in range(ser.shape[1]))
+        if L >= 50 * tau or L >= max_len:
+            return tau, L
+        L *= 2
 
 
 def mh_mode(args):
     """ESS per second of plain Gibbs against the learned-proposal MH (1 MH
-    step : gibbs_per_mh Gibbs sweeps) on the same chains and GPU."""
+    step : gibbs_per_mh Gibbs sweeps) on the same GPU.  tau_int comes from the
+    output parity series of a population of tau_chains chains, recorded
+    until it is 50 tau_int long; time per transition and TV come from long
+    runs of the full population."""
     import torch
     from paper_2007_07379_amd import pbit
     from oracle import circuit as oc
@@ -153,9 +183,11 @@ def mh_mode(args):
     from oracle import exact
     from workloads import circuits as wc
 
-    mk, chains, burn, steps, hidden, ntrain, tsteps, batch, long_cycles = MH_WORKLOADS[args.workload]
+    cfg = MH_WORKLOADS[args.workload]
+    chains, burn, hidden = cfg["chains"], cfg["burn_in"], cfg["hidden"]
+    long_cycles, tc = cfg["long_cycles"], cfg["tau_chains"]
     G = args.gibbs_per_mh
-    c = mk(wc)
+    c = cfg["circuit"](wc)
     s = pbit.CircuitSet(c)
     info = s.info(0)
     W, h = info["W"], info["h"]
@@ -168,27 +200,26 @@ def mh_mode(args):
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    # --- plain Gibbs: burn-in, then one sweep per call with snapshots --------
     hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev)
+
+    # --- plain Gibbs ---------------------------------------------------------
+    # tau population: burn-in, then one sweep per transition
+    st_t = torch.zeros(tc * W, dtype=torch.int32, device=dev)
+    s.gibbs_run([tc], burn, 0, hist, st_t, seed=11, stream=stream)
+    tau_g, len_g = adaptive_tau(
+        torch, lambda t: s.gibbs_run([tc], 0, 1, hist, st_t, seed=11, sweep_offset=burn + t, resume=True,
+                                     stream=stream),
+        lambda: output_parities(torch, st_t, info, masks))
+    # full population: burn-in, then a long timed run binned for TV
     state = torch.zeros(chains * W, dtype=torch.int32, device=dev)
     s.gibbs_run([chains], burn, 0, hist, state, seed=1, stream=stream)
-    s.gibbs_run([chains], 0, 1, hist, state, seed=1, sweep_offset=burn, resume=True, stream=stream)
     start = state.clone()
-    hist.zero_()
-    series = []
-    for t in range(steps):
-        s.gibbs_run([chains], 0, 1, hist, state, seed=1, sweep_offset=burn + 1 + t, resume=True, stream=stream)
-        series.append(output_parities(torch, state, info, masks))
-    ser = torch.stack(series).cpu().numpy()  # [steps, obs, chains]
-    tau_g = max(geyer_tau(ser[:, o, :]) for o in range(ser.shape[1]))
-    # long uninterrupted run: time per sweep and TV of its histogram
     n_long = long_cycles * (1 + G)
-    st2 = start.clone()
     hist.zero_()
     e0, e1 = ev(), ev()
     torch.cuda.synchronize()
     e0.record(stream)
-    s.gibbs_run([chains], 0, n_long, hist, st2, seed=1, sweep_offset=burn + 1, resume=True, stream=stream)
+    s.gibbs_run([chains], 0, n_long, hist, state, seed=1, sweep_offset=burn, resume=True, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     t_g = e0.elapsed_time(e1) / 1e3 / n_long  # seconds per sweep
@@ -197,39 +228,40 @@ def mh_mode(args):
     ess_g = chains / (tau_g * t_g)
 
     # --- training the proposal on Gibbs samples ------------------------------
+    ntrain = cfg["train"]
     train = torch.zeros(ntrain * W, dtype=torch.int32, device=dev)
-    th = torch.zeros(pbit.CircuitSet(c).info(0)["hist_bins"], dtype=torch.int32, device=dev)
+    th = torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev)
     s.gibbs_run([ntrain], burn, 1, th, train, seed=7, stream=stream)
     q = pbit.Proposal(s, hidden=hidden, seed=3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = q.train(train, ntrain, batch, tsteps, lr=args.lr, stream=stream)
+    losses = q.train(train, ntrain, cfg["batch"], cfg["train_steps"], lr=args.lr, stream=stream)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del train
+    del train, th
 
-    # --- MH + Gibbs: transition-level snapshots --------------------------------
-    state = start.clone()
-    hist.zero_()
-    acc = torch.zeros(chains, dtype=torch.int64, device=dev)
-    series = []
-    for t in range(steps):
-        pbit.mh_run(s, q, chains, 1, state, hist, acc, gibbs_per_mh=0, seed=1, step_offset=t, resume=True,
-                    stream=stream)
-        series.append(output_parities(torch, state, info, masks))
-        for g in range(G):
-            s.gibbs_run([chains], 0, 1, hist, state, seed=1, sweep_offset=(1 << 30) + t * G + g, resume=True,
+    # --- MH + Gibbs ------------------------------------------------------------
+    st_t = torch.zeros(tc * W, dtype=torch.int32, device=dev)
+    s.gibbs_run([tc], burn, 0, hist, st_t, seed=12, stream=stream)
+    acc = torch.zeros(tc, dtype=torch.int64, device=dev)
+
+    def mh_advance(t):
+        cy, r = divmod(t, 1 + G)
+        if r == 0:
+            pbit.mh_run(s, q, tc, 1, st_t, hist, acc, gibbs_per_mh=0, seed=12, step_offset=cy, resume=True,
                         stream=stream)
-            series.append(output_parities(torch, state, info, masks))
-    ser = torch.stack(series).cpu().numpy()
-    tau_m = max(geyer_tau(ser[:, o, :]) for o in range(ser.shape[1]))
-    acc_rate = float(acc.double().mean().item()) / steps
-    st2 = start.clone()
+        else:
+            s.gibbs_run([tc], 0, 1, hist, st_t, seed=12, sweep_offset=(1 << 30) + cy * G + r - 1, resume=True,
+                        stream=stream)
+
+    tau_m, len_m = adaptive_tau(torch, mh_advance, lambda: output_parities(torch, st_t, info, masks))
+    acc_rate = float(acc.double().mean().item()) / ((len_m + G) // (1 + G))
+    state = start.clone()
     hist.zero_()
     e0, e1 = ev(), ev()
     torch.cuda.synchronize()
     e0.record(stream)
-    pbit.mh_run(s, q, chains, long_cycles, st2, hist, None, gibbs_per_mh=G, seed=2, resume=True, stream=stream)
+    pbit.mh_run(s, q, chains, long_cycles, state, hist, None, gibbs_per_mh=G, seed=2, resume=True, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     t_m = e0.elapsed_time(e1) / 1e3 / n_long  # seconds per transition
@@ -240,11 +272,11 @@ def mh_mode(args):
         "metric": "effective samples/s (TV<=0.01), Gibbs vs learned-proposal MH",
         "workload": "%s: n=%d d=%d, h=%d free p-bits, %d chains, MADE hidden %d, 1 MH : %d Gibbs"
                     % (args.workload, info["n"], info["d"], h, chains, hidden, G),
-        "gibbs": {"tau_int_sweeps": tau_g, "s_per_sweep": t_g, "ess_per_s": ess_g, "tv_path": tv_g,
-                  "tv_samples": chains * n_long},
-        "mh": {"tau_int_transitions": tau_m, "s_per_transition": t_m, "ess_per_s": ess_m, "tv_path": tv_m,
-               "tv_samples": chains * n_long, "accept_rate": acc_rate},
-        "train": {"samples": ntrain, "steps": tsteps, "batch": batch, "seconds": t_train,
+        "gibbs": {"tau_int_sweeps": tau_g, "tau_series": len_g, "s_per_sweep": t_g, "ess_per_s": ess_g,
+                  "tv_path": tv_g, "tv_samples": chains * n_long},
+        "mh": {"tau_int_transitions": tau_m, "tau_series": len_m, "s_per_transition": t_m, "ess_per_s": ess_m,
+               "tv_path": tv_m, "tv_samples": chains * n_long, "accept_rate": acc_rate},
+        "train": {"samples": ntrain, "steps": cfg["train_steps"], "batch": cfg["batch"], "seconds": t_train,
                   "loss_first": float(losses[0]), "loss_last": float(losses[-20:].mean())},
         "ess_ratio_mh_over_gibbs": ess_m / ess_g,
         "tv_ok": bool(tv_g <= 0.01 and tv_m <= 0.01),

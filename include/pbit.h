@@ -231,8 +231,11 @@ pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint6
  * b) into d_out (word-major) with log q of each into d_logq (device double). */
 pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed,
                                  uint32_t step, uint32_t *d_out, double *d_logq, void *hip_stream);
-/* log q of given paths (batched forward); equal bit for bit to the value the
- * sampler reports for a path it drew. */
+/* log q of given paths (d_states word-major, valid paths such as chain
+ * states or proposals); equal bit for bit to the value the sampler reports
+ * for a path it drew.  Networks of width <= 256 are scored by the fused
+ * autoregressive kernel with its bits read from d_states, wider ones by the
+ * batched forward GEMMs. */
 pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint32_t n, double *d_logq,
                                 void *hip_stream);
 

@@ -178,12 +178,31 @@ __global__ void loss_grad_kernel(const float *__restrict__ L, const bf16 *__rest
     if (threadIdx.x == 0) atomicAdd(loss, red[0]);
 }
 
-// out[j] = sum_b G[b][j] (fp32), one thread per column.
-__global__ void colsum_kernel(const bf16 *__restrict__ G, int n, int N, float *__restrict__ out) {
+// Column sums of a row-major n x N bf16 matrix in two deterministic passes:
+// workgroup (column tile, row chunk) sums its 256 rows for 64 columns (four
+// row groups of 64 rows, combined in a fixed order), then each column adds
+// its chunk partials in ascending chunk order.
+__global__ __launch_bounds__(256) void colsum_part_kernel(const bf16 *__restrict__ G, int n, int N,
+                                                          float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + tx;
+    const int r0 = blockIdx.y * 256 + ty * 64;
+    float s = 0.f;
+    if (j < N) {
+        const int r1 = min(r0 + 64, n);
+        for (int b = r0; b < r1; ++b) s += (float)G[(int64_t)b * N + j];
+    }
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && j < N) part[(int64_t)blockIdx.y * N + j] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
+}
+
+__global__ void colsum_final_kernel(const float *__restrict__ part, int chunks, int N, float *__restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     float s = 0.f;
-    for (int b = 0; b < n; ++b) s += (float)G[(int64_t)b * N + j];
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * N + j];
     out[j] = s;
 }
 
@@ -239,6 +258,42 @@ __global__ void logq_kernel(const float *__restrict__ L, const uint32_t *__restr
 // uint32 threshold of sigmoid(logit), log q accumulates log(T/2^32) or
 // log(1 - T/2^32), and a set bit flips its cone in the inputs and in the
 // lattice words, so the deterministic positions after p are always set.
+// One chain of 16-row MFMA accumulations over nk 32-wide K chunks, in
+// ascending order from chunk 0 into one accumulator (the order the batched
+// GEMM uses, so every logit is the same bits).  The operands of up to eight
+// chunks are loaded before their products, so a phase waits for one round
+// of loads instead of one per chunk.
+__device__ __forceinline__ f32x4 mfma_chunks(const bf16 *__restrict__ arow, const bf16 *__restrict__ brow, int nk) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    constexpr int G = 8;
+    int c = 0;
+    for (; c + G <= nk; c += G) {
+        bf16x8 av[G], bv[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            av[g] = *reinterpret_cast<const bf16x8 *>(arow + (c + g) * 32);
+            bv[g] = *reinterpret_cast<const bf16x8 *>(brow + (c + g) * 32);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[g], bv[g], acc, 0, 0, 0);
+    }
+    if (c < nk) {
+        const int r = nk - c;  // 1..G-1 chunks left
+        bf16x8 av[G], bv[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g < r) {
+                av[g] = *reinterpret_cast<const bf16x8 *>(arow + (c + g) * 32);
+                bv[g] = *reinterpret_cast<const bf16x8 *>(brow + (c + g) * 32);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (g < r) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[g], bv[g], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int CS = 16;
@@ -267,17 +322,12 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     const int row = lane & 15, kq = (lane >> 4) * 8;
     for (int f = 0; f < a.h; ++f) {
         const int4 ph = a.phase[f];  // {u1a, u1b, u2a, u2b}
-        const int4 kk = a.phase_k[f];  // {K1 chunks end, K2 end, K3 end, position p}
+        const int4 kk = a.phase_k[f];  // {K1 end, K2 end, K3 end, position p}
         const int p = kk.w;
         // (a) first-layer units whose degree became <= p
         for (int u0 = ph.x; u0 < ph.y; u0 += 16) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int u = min(u0 + row, H - 1);
-            for (int k0 = 0; k0 < kk.x; k0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&Xs[row * DP + k0 + kq]);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&a.W1T[(int64_t)u * DP + k0 + kq]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-            }
+            const f32x4 acc = mfma_chunks(Xs + row * DP + kq, a.W1T + (int64_t)u * DP + kq, (kk.x + 31) / 32);
             const int un = u0 + row;
             if (un < ph.y) {
 #pragma unroll
@@ -291,13 +341,8 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
         __syncthreads();
         // (b) second-layer units whose degree became <= p
         for (int u0 = ph.z; u0 < ph.w; u0 += 16) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int u = min(u0 + row, H - 1);
-            for (int k0 = 0; k0 < kk.y; k0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&H1s[row * H + k0 + kq]);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&a.W2T[(int64_t)u * H + k0 + kq]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-            }
+            const f32x4 acc = mfma_chunks(H1s + row * H + kq, a.W2T + (int64_t)u * H + kq, (kk.y + 31) / 32);
             const int un = u0 + row;
             if (un < ph.w) {
 #pragma unroll
@@ -311,30 +356,32 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
         __syncthreads();
         // (c) logit of position p (every column of the tile computes it)
         {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int k0 = 0; k0 < kk.z; k0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&H2s[row * H + k0 + kq]);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&a.VT[(int64_t)p * H + k0 + kq]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-            }
+            const f32x4 acc = mfma_chunks(H2s + row * H + kq, a.VT + (int64_t)p * H + kq, (kk.z + 31) / 32);
             if (row == 0) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) logit[(lane >> 4) * 4 + e] = acc[e] + a.c[p];
             }
         }
         __syncthreads();
-        // (d) draw the bit, flip its cone
+        // (d) draw the bit (or read it from the scored path), flip its cone
         if (lane < CS) {
             const int chain = c0 + lane;
             if (chain < a.n) {
                 const uint32_t T = made_threshold(logit[lane]);
-                const U4 u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + chain, cid | (1u << 16),
-                                            a.seed_lo, a.seed_hi);
-                const uint32_t uu[4] = {u4.x, u4.y, u4.z, u4.w};
-                const uint32_t u = uu[f & 3];
-                const uint32_t bit = u < T ? 1u : 0u;
+                uint32_t bit;
+                if (a.score) {
+                    bit = (a.score[(int64_t)(p >> 5) * a.n + chain] >> (p & 31)) & 1u;
+                } else {
+                    const U4 u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + chain, cid | (1u << 16),
+                                                a.seed_lo, a.seed_hi);
+                    const uint32_t uu[4] = {u4.x, u4.y, u4.z, u4.w};
+                    bit = uu[f & 3] < T ? 1u : 0u;
+                }
                 lq += made_log_prob(T, bit);
-                if (bit) {
+                // the lattice bit at p is the free bit itself: flip its cone
+                // when the drawn value differs from the current one
+                const uint32_t cur = (lat[lane * W + (p >> 5)] >> (p & 31)) & 1u;
+                if (bit != cur) {
                     const uint32_t *cm = cone + (int64_t)f * WS;
                     for (int w = 0; w < W; ++w) {
                         uint32_t mw = cm[w];
@@ -354,7 +401,8 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     if (lane < CS) {
         const int chain = c0 + lane;
         if (chain < a.n) {
-            for (int w = 0; w < W; ++w) a.out[(int64_t)w * a.n + chain] = lat[lane * W + w];
+            if (a.out)
+                for (int w = 0; w < W; ++w) a.out[(int64_t)w * a.n + chain] = lat[lane * W + w];
             a.logq[chain] = lq;
         }
     }
@@ -386,8 +434,13 @@ hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const bf16 *G, int n, int N, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, G, n, N, out);
+hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s) {
+    const int chunks = (n + 255) / 256;
+    if (chunks == 0 || N == 0) return hipSuccess;
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, G, n, N, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, chunks, N, out);
     return hipGetLastError();
 }
 

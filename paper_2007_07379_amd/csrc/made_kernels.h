@@ -31,15 +31,18 @@ struct SampleArgs {
     const int4 *phase_k;  // per free bit: K ends of the three products, lattice position
     int n, h, W, D, DP, H;
     uint32_t chain_begin, step, seed_lo, seed_hi;
-    uint32_t *out;        // word-major lattice words of the proposals
+    uint32_t *out;        // word-major lattice words of the proposals (may be NULL)
     double *logq;         // log q of each proposal
+    const uint32_t *score;  // score mode: word-major paths whose bits are read instead of drawn
 };
 
 hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
 hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
                             float *loss, hipStream_t s);
-hipError_t launch_colsum(const bf16 *G, int n, int N, float *out, hipStream_t s);
+// out[j] = sum_b G[b][j]: partial sums over 256-row chunks into `part`
+// (ceil(n / 256) x N floats), then over the chunks in ascending order.
+hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s);
 hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t P, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_shadow(const float *W, int K, int N, int KP, bf16 *Wb, bf16 *WT, hipStream_t s);
@@ -56,6 +59,7 @@ struct MhArgs {
     uint32_t *hist;           // bins the post-transition state (may be NULL)
     int n, W;
     uint32_t chain_begin, step, seed_lo, seed_hi;
+    uint32_t hist_bins;       // 2^(n+K); privatised in LDS per workgroup when small
 };
 hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s);
 

@@ -36,8 +36,13 @@ __device__ __forceinline__ double log_weight(const uint32_t *__restrict__ B, con
     return s;
 }
 
+// Histograms of at most this many bins are privatised in LDS per workgroup
+// (every chain adds one count per transition, and circuits with few output
+// states would otherwise serialise on a handful of HBM addresses).
+constexpr uint32_t MH_LDS_BINS = 8192;
+
 template <int W>
-__global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
+__device__ __forceinline__ void mh_accept_body(const MhArgs &a, uint32_t *lds_h) {
     const uint32_t *__restrict__ B = a.blob;
     const int lc = blockIdx.x * blockDim.x + threadIdx.x;
     if (lc >= a.n) return;
@@ -65,7 +70,28 @@ __global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
     if (a.accepts && accept) a.accepts[lc] += 1ull;
     if (a.hist) {
         const uint32_t bin = phase_and_bin<W>(B, x, B[H_K], B[H_N]);
-        atomicAdd(&a.hist[bin], 1u);
+        if (lds_h)
+            atomicAdd(&lds_h[bin], 1u);
+        else
+            atomicAdd(&a.hist[bin], 1u);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
+    extern __shared__ uint32_t lds_h[];
+    const bool priv = a.hist && a.hist_bins <= MH_LDS_BINS;
+    if (priv) {
+        for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) lds_h[i] = 0u;
+        __syncthreads();
+    }
+    mh_accept_body<W>(a, priv ? lds_h : nullptr);
+    if (priv) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) {
+            const uint32_t v = lds_h[i];
+            if (v) atomicAdd(&a.hist[i], v);
+        }
     }
 }
 
@@ -74,9 +100,10 @@ __global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
 hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s) {
     const int grid = (a.n + 255) / 256;
     if (grid == 0) return hipSuccess;
+    const size_t lds = (a.hist && a.hist_bins <= MH_LDS_BINS) ? (size_t)a.hist_bins * 4 : 0;
 #define PBIT_LAUNCH(V)                                                                  \
     if (Wk == V) {                                                                      \
-        hipLaunchKernelGGL((mh_accept_kernel<V>), dim3(grid), dim3(256), 0, s, a);      \
+        hipLaunchKernelGGL((mh_accept_kernel<V>), dim3(grid), dim3(256), lds, s, a);    \
         return hipGetLastError();                                                       \
     }
     PBIT_FOR_EACH_W(PBIT_LAUNCH)

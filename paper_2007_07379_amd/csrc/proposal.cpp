@@ -17,6 +17,8 @@ namespace pbit {
 namespace {
 
 constexpr int BATCH_MAX = 16384;
+// networks up to this width are scored by the fused kernel
+constexpr int SCORE_FUSED_MAX_H = 256;
 
 struct DeviceArena {
     std::vector<void *> ptrs;
@@ -64,6 +66,7 @@ struct pbit_proposal_s {
     int4 *d_phase = nullptr, *d_phase_k = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
     float *L = nullptr;
+    float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / 256) x max(D, H)
     uint32_t *prop = nullptr;
     double *lq_cur = nullptr, *lq_prop = nullptr;
     uint32_t mh_cap = 0;
@@ -101,6 +104,7 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->G2 = A.alloc<bf16>((size_t)BATCH_MAX * H);
     q->G3 = A.alloc<bf16>((size_t)BATCH_MAX * D);
     q->L = A.alloc<float>((size_t)BATCH_MAX * D);
+    q->colpart = A.alloc<float>((size_t)(BATCH_MAX / 256) * std::max(D, H));
     auto up = [&](int *&dst, const std::vector<int> &src) {
         dst = A.alloc<int>(src.size() + 64);
         if (dst) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -134,7 +138,7 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     up(q->g1beg, b1);
     q->d_phase = A.alloc<int4>(q->phase.size() + 1);
     q->d_phase_k = A.alloc<int4>(q->phase_k.size() + 1);
-    if (!q->theta || !q->L || !q->d_phase || !q->d_phase_k || !q->g1beg)
+    if (!q->theta || !q->L || !q->colpart || !q->d_phase || !q->d_phase_k || !q->g1beg)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
     (void)hipMemcpy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4), hipMemcpyHostToDevice);
     (void)hipMemcpy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4), hipMemcpyHostToDevice);
@@ -205,7 +209,7 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     g.M = H; g.N = D; g.K = n;
     g.deg_row = q->d_deg2; g.deg_col = q->d_deg_out;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dV");
-    if ((e = launch_colsum(q->G3, n, D, q->grad + q->oc, s)) != hipSuccess) return hip_error(e, "dc");
+    if ((e = launch_colsum(q->G3, n, D, q->colpart, q->grad + q->oc, s)) != hipSuccess) return hip_error(e, "dc");
     // G2 = (G3 V^T) * (H2 > 0)
     g = gemm0();
     g.A = q->G3; g.sam = D; g.sak = 1;
@@ -222,7 +226,7 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     g.M = H; g.N = H; g.K = n;
     g.deg_row = q->d_deg1; g.deg_col = q->d_deg2;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW2");
-    if ((e = launch_colsum(q->G2, n, H, q->grad + q->ob2, s)) != hipSuccess) return hip_error(e, "db2");
+    if ((e = launch_colsum(q->G2, n, H, q->colpart, q->grad + q->ob2, s)) != hipSuccess) return hip_error(e, "db2");
     // G1 = (G2 W2^T) * (H1 > 0)
     g = gemm0();
     g.A = q->G2; g.sam = H; g.sak = 1;
@@ -239,12 +243,14 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     g.M = D; g.N = H; g.K = n;
     g.deg_row = q->d_deg_in; g.deg_col = q->d_deg1;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW1");
-    if ((e = launch_colsum(q->G1, n, H, q->grad + q->ob1, s)) != hipSuccess) return hip_error(e, "db1");
+    if ((e = launch_colsum(q->G1, n, H, q->colpart, q->grad + q->ob1, s)) != hipSuccess) return hip_error(e, "db1");
     return PBIT_OK;
 }
 
 pbit_status unpack_range(pbit_proposal q, const uint32_t *states, uint64_t stride, uint64_t b0, int n,
                          hipStream_t s);
+pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed, uint32_t step,
+                            uint32_t *d_out, double *d_logq, const uint32_t *score, hipStream_t hip_stream);
 
 }  // namespace
 
@@ -474,6 +480,17 @@ pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint6
 pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed, uint32_t step,
                                  uint32_t *d_out, double *d_logq, void *hip_stream) {
     if (!q || !d_out || !d_logq) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    return sample_or_score(q, n, chain_begin, seed, step, d_out, d_logq, nullptr, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The fused autoregressive kernel: draws paths (score == NULL) or reads
+// their bits from `score` and returns log q with the same arithmetic.
+pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed, uint32_t step,
+                            uint32_t *d_out, double *d_logq, const uint32_t *score, hipStream_t hip_stream) {
     if ((uint64_t)chain_begin + n > 0x100000000ull) return set_error(PBIT_E_INVALID_ARG, "chain index overflow");
     hipStream_t s = (hipStream_t)hip_stream;
     pbit_status st = upload(q, s);
@@ -507,15 +524,23 @@ pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_beg
     a.seed_hi = (uint32_t)(seed >> 32);
     a.out = d_out;
     a.logq = d_logq;
+    a.score = score;
     hipError_t e = launch_made_sample(a, s);
     if (e != hipSuccess) return hip_error(e, "made sampler");
     return PBIT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint32_t n, double *d_logq,
                                 void *hip_stream) {
     if (!q || !d_states || !d_logq) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)hip_stream;
+    // small networks: the fused kernel in score mode (one launch); large ones:
+    // the batched GEMMs.  Both give the same bits.
+    if (q->H <= SCORE_FUSED_MAX_H) return sample_or_score(q, n, 0, 0, 0, nullptr, d_logq, d_states, s);
     pbit_status st = upload(q, s);
     if (st != PBIT_OK) return st;
     if ((st = refresh(q, s)) != PBIT_OK) return st;
@@ -591,6 +616,7 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
         a.step = step;
         a.seed_lo = (uint32_t)cfg->seed;
         a.seed_hi = (uint32_t)(cfg->seed >> 32);
+        a.hist_bins = 1u << (k.n + k.K);
         if ((e = launch_mh_accept(k.WS, a, s)) != hipSuccess) return hip_error(e, "mh accept");
         if (cfg->gibbs_per_mh) {
             pbit_gibbs_cfg g;

@@ -176,8 +176,11 @@ def _sample(env, q, n, seed=3, step=0):
     return d_out, d_lq
 
 
-@pytest.mark.parametrize("which,H", [("small", 64), ("brick16", 1024)])
+@pytest.mark.parametrize("which,H", [("small", 64), ("small", 512), ("brick16", 1024)])
 def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
+    """Sampled paths are valid lattices; scoring them gives the sampler's log q
+    bit for bit (H = 64: the fused kernel in score mode; 512, 1024: the
+    batched GEMM forward)."""
     torch, pbit = env
     c = SMALL() if which == "small" else wc.workload_circuit("brick16")
     s = pbit.CircuitSet(c)
@@ -255,14 +258,16 @@ def test_mh_uniform_proposal_always_accepts(env):
     assert int(h.sum()) == chains * cycles * 3
 
 
-@pytest.mark.parametrize("theta", [math.pi / 8])
-def test_mh_poor_proposal_keeps_exact_target(env, theta):
+@pytest.mark.parametrize("theta,hidden", [(math.pi / 8, 64), (math.pi / 8, 512)])
+def test_mh_poor_proposal_keeps_exact_target(env, theta, hidden):
     """Non-uniform target (rotated Hadamards + CNOT), proposal biased to
-    P(1) = 0.3: MH + Gibbs still reproduce the exact output marginal."""
+    P(1) = 0.3: MH + Gibbs still reproduce the exact output marginal (the
+    current paths scored by the fused kernel at H = 64, by the GEMMs at
+    H = 512)."""
     torch, pbit = env
     c = wc.rotated_brickwork(3, 6, 2, theta, K=3)
     s = pbit.CircuitSet(c)
-    q = pbit.Proposal(s, hidden=64)
+    q = pbit.Proposal(s, hidden=hidden)
     flat = np.zeros(q.n_params, dtype=np.float32)
     flat[-q.D:] = math.log(0.3 / 0.7)
     q.set_params(flat)
