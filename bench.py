@@ -284,6 +284,60 @@ def mh_mode(args):
     print(json.dumps(out))
 
 
+BF16_PEAK = 2.5e15  # MI355X dense bf16 MFMA FLOP/s
+
+
+def train_mode(args):
+    """MADE training throughput on the config-5 network (D = 400 lattice
+    positions of the n=16, d=24 brickwork circuit, two masked hidden layers
+    of 1024, batch 4096): Adam steps per second and the MFMA roofline of the
+    masked products (forward, weight gradients, input gradients of the
+    hidden layers), counting only unmasked weights."""
+    import torch
+    from paper_2007_07379_amd import pbit
+    from workloads import circuits as wc
+    c = wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    H, batch, steps, ntrain = 1024, 4096, max(args.steps, 1) * 40, 1 << 16
+    train = torch.zeros(ntrain * info["W"], dtype=torch.int32, device="cuda")
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([ntrain], 200, 1, hist, train, seed=7)
+    q = pbit.Proposal(s, hidden=H, seed=3)
+    D = q.D
+    q.train(train, ntrain, batch, 5, lr=args.lr)  # warm-up
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    q.train(train, ntrain, batch, steps, lr=args.lr, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    # unmasked weights (degrees as in the network definition)
+    din = np.arange(1, D + 1)
+    dh = 1 + (np.arange(H) * (D - 1)) // H
+    dout = np.arange(D)
+    n1 = int((din[:, None] <= dh[None, :]).sum())
+    n2 = int((dh[:, None] <= dh[None, :]).sum())
+    n3 = int((dh[:, None] <= dout[None, :]).sum())
+    # forward (3 products), weight gradients (3), input gradients of the two
+    # hidden layers (2): 2 FLOP per multiply-add
+    flops_step = 2 * batch * (3 * (n1 + n2 + n3) - n1)
+    achieved = flops_step * steps / dt
+    print(json.dumps({
+        "metric": "MADE training steps/s", "value": steps / dt, "unit": "steps/s", "n_gpus": 1,
+        "steps": steps, "ms_per_step": dt / steps * 1e3, "higher_is_better": True, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "MADE D=%d, two masked hidden layers of %d, batch %d, Adam (brick16 paths)"
+                               % (D, H, batch)},
+        "samples_per_s": batch * steps / dt,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / BF16_PEAK, "traffic": None,
+                     "flops_per_step": flops_step, "dense_flops_per_step": 2 * batch * (3 * (2 * D * H + H * H) - D * H)},
+    }))
+
+
 def copy_mode(args):
     """One plain device-to-device copy of known size, the reference point that
     scales the FETCH_SIZE / WRITE_SIZE hardware counters to bytes."""
@@ -389,7 +443,7 @@ def main():
     ap.add_argument("--workload", default="rct12")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=8192)
-    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy"])
+    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train"])
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--gibbs-per-mh", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -401,6 +455,9 @@ def main():
 
     if args.mode == "copy":
         copy_mode(args)
+        return
+    if args.mode == "train":
+        train_mode(args)
         return
     if args.mode == "mh":
         if args.workload == "rct12":

@@ -15,8 +15,11 @@ typedef __bf16 bf16;
 // Strided operands (A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn])
 // so transposed products need no copies.  The reduction of output column
 // tile nt (64 columns) runs over [kbeg[nt], kend[nt]) in ascending 32-wide
-// chunks (no split-K), so every output is a fixed sequence of
-// v_mfma_f32_16x16x32_bf16 accumulations.
+// chunks, so every output is a fixed sequence of v_mfma_f32_16x16x32_bf16
+// accumulations (a workgroup of 128 columns runs the union of its two ranges:
+// the extra chunks multiply exact-zero masked weights).  Products that feed
+// the sampler's arithmetic never split K; the weight gradients may
+// (ksplit slices summed in a fixed order by a second kernel).
 struct GemmArgs {
     const bf16 *A;
     int64_t sam, sak;
@@ -33,6 +36,8 @@ struct GemmArgs {
     const int *deg_row, *deg_col;  // keep C(m, n) iff deg_row[m] <= deg_col[n]; may be NULL
     int out_bf16;
     int accumulate;          // fp32 output: C += result
+    int ksplit;              // > 1: K split in that many slices (fp32 out, no bias / relu / gate)
+    float *part;             // split-K workspace, ksplit x M x N floats
 };
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);

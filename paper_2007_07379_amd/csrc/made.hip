@@ -24,113 +24,328 @@ namespace pbit {
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64, TN = 64, TK = 32, LDSK = TK + 8;
+// Workgroup tile 128 x 128 (four waves of 64 x 64, each 4 x 4 MFMA tiles of
+// 16 x 16).  K advances in stages of two 32-wide chunks staged through
+// double-buffered LDS; the global loads of a stage are issued GEMM_P stages
+// ahead into registers, so their latency hides behind the products of the
+// stages in between.
+constexpr int TM = 128, TN = 128, TK = 32, TKS = 2 * TK, LDSK = TKS + 8;
+constexpr int GEMM_P = 3;
 
-// ---------------------------------------------------------------------------
-// GEMM
-// ---------------------------------------------------------------------------
-// Loads one 64 x 32 operand tile (rows r0.., k k0..) into LDS laid out
-// [row][k] (k contiguous), zero outside [0, R) x [0, kend).
-__device__ __forceinline__ void load_tile(bf16 (*T)[LDSK], const bf16 *src, int64_t sr, int64_t sk, int r0, int R,
-                                          int k0, int kend) {
+// Operands are addressed as X(r, k) = src[r sr + k sk]; everything outside
+// [0, R) x [0, kend) reads as zero.
+//   Mode 0 (sk == 1, sr a multiple of 8, 16-byte aligned base): each 16-byte
+//     load is 8 consecutive k of one row.
+//   Mode 1 (sr == 1, sk a multiple of 8, aligned base): loads come in pairs,
+//     rows k and k + 1 of 8 consecutive r, written to LDS as (k, k + 1)
+//     pairs per r.
+//   Mode 2: any other layout, element by element.
+// Modes 0 and 1 never branch per load: a stage that is not interior to the
+// operand loads from a clamped address and masks by dword, so every stage
+// issues the same loads and their latency overlaps with earlier stages.
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+
+struct StageRegs {
+    u32x4v v[4];
+    int rem[4];     // valid elements of each segment (masked at the LDS store,
+    bool interior;  // so no load waits before the stage is stored)
+};
+
+// dword d of a 16-byte segment holds elements 2d, 2d + 1; rem valid elements
+__device__ __forceinline__ u32x4v seg_mask(int rem) {
+    u32x4v m;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) m[d] = rem >= 2 * d + 2 ? 0xFFFFFFFFu : (rem == 2 * d + 1 ? 0x0000FFFFu : 0u);
+    return m;
+}
+
+template <int MODE>
+__device__ __forceinline__ void stage_load(StageRegs &st, const bf16 *__restrict__ src, int64_t sr, int64_t sk, int r0,
+                                           int R, int k0, int kend) {
     const int t = threadIdx.x;
-    if (sk == 1) {
-        const int r = t >> 2, kk = (t & 3) * 8;
-        const int gr = r0 + r, gk = k0 + kk;
-        const bf16 *p = src + (int64_t)gr * sr + gk;
-        if (gr < R && gk + 8 <= kend && (((uintptr_t)p) & 15) == 0) {
-            *reinterpret_cast<bf16x8 *>(&T[r][kk]) = *reinterpret_cast<const bf16x8 *>(p);
-        } else {
+    if (MODE == 0) {
+        st.interior = r0 + TM <= R && k0 + TKS <= kend;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) T[r][kk + i] = (gr < R && gk + i < kend) ? p[i] : (bf16)0.0f;
+        for (int j = 0; j < 4; ++j) {
+            const int seg = t + 256 * j;  // 128 rows x 8 segments of 8
+            const int r = seg >> 3, kk = (seg & 7) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            const int rem = st.interior ? 8 : (gr < R ? kend - gk : 0);
+            const bf16 *p = rem > 0 ? src + (int64_t)gr * sr + gk : src;
+            st.v[j] = *reinterpret_cast<const u32x4v *>(p);
+            st.rem[j] = rem;
         }
-    } else if (sr == 1) {
-        const int k = t >> 3, rr = (t & 7) * 8;
-        const int gk = k0 + k, gr = r0 + rr;
-        const bf16 *p = src + (int64_t)gk * sk + gr;
-        if (gk < kend && gr + 8 <= R && (((uintptr_t)p) & 15) == 0) {
-            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(p);
+    } else if (MODE == 1) {
+        st.interior = r0 + TM <= R && k0 + TKS <= kend;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) T[rr + i][k] = v[i];
-        } else {
+        for (int b = 0; b < 2; ++b) {
+            const int blk = t + 256 * b;  // 16 row blocks of 8 x 32 k pairs
+            const int rb = (blk & 15) * 8, kp = (blk >> 4) * 2;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) T[rr + i][k] = (gk < kend && gr + i < R) ? p[i] : (bf16)0.0f;
+            for (int j = 0; j < 2; ++j) {
+                const int gk = k0 + kp + j, gr = r0 + rb;
+                const int rem = st.interior ? 8 : (gk < kend ? R - gr : 0);
+                const bf16 *p = rem > 0 ? src + (int64_t)gk * sk + gr : src;
+                st.v[2 * b + j] = *reinterpret_cast<const u32x4v *>(p);
+                st.rem[2 * b + j] = rem;
+            }
         }
     } else {
-        for (int e = t; e < TM * TK; e += 256) {
-            const int r = e / TK, k = e % TK;
-            const int gr = r0 + r, gk = k0 + k;
-            T[r][k] = (gr < R && gk < kend) ? src[(int64_t)gr * sr + (int64_t)gk * sk] : (bf16)0.0f;
+        st.interior = true;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int seg = t + 256 * j;
+            const int r = seg >> 3, kk = (seg & 7) * 8;
+            const int gr = r0 + r, gk = k0 + kk;
+            bf16x8 e;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                e[i] = (gr < R && gk + i < kend) ? src[(int64_t)gr * sr + (int64_t)(gk + i) * sk] : (bf16)0.0f;
+            st.v[j] = __builtin_bit_cast(u32x4v, e);
         }
     }
 }
 
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-    __shared__ __align__(16) bf16 As[TM][LDSK];
-    __shared__ __align__(16) bf16 Bs[TN][LDSK];
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    const int nt = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    int kb = g.kbeg ? g.kbeg[nt] : 0;
-    int ke = g.kend ? g.kend[nt] : g.K;
-    // a tile whose every output is masked needs no reduction
-    bool dead = false;
-    if (g.deg_row && g.deg_col) {
-        const int mlast = min(m0 + TM, g.M) - 1, nlast = min(n0 + TN, g.N) - 1;
-        dead = g.deg_row[m0] > g.deg_col[nlast];
-        (void)mlast;
-    }
-    f32x4 acc[2][2];
+template <int MODE>
+__device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]) {
+    const int t = threadIdx.x;
+    u32x4v v[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 4; ++j) v[j] = st.interior ? st.v[j] : st.v[j] & seg_mask(st.rem[j]);
+    if (MODE != 1) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (!dead) {
-        for (int k0 = 0; k0 < ke; k0 += TK) {
-            if (k0 + TK <= kb) continue;  // chunks entirely below the range are zero
-            load_tile(As, g.A, g.sam, g.sak, m0, g.M, k0, ke);
-            load_tile(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, ke);
-            __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            const int seg = t + 256 * j;
+            *reinterpret_cast<u32x4v *>(&T[seg >> 3][(seg & 7) * 8]) = v[j];
+        }
+    } else {
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wr + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+        for (int b = 0; b < 2; ++b) {
+            const int blk = t + 256 * b;
+            const int rb = (blk & 15) * 8, kp = (blk >> 4) * 2;
+            const u32x4v a = v[2 * b], c = v[2 * b + 1];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[wc + j * 16 + (lane & 15)][(lane >> 4) * 8]);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
-                }
+            for (int q = 0; q < 4; ++q) {
+                // rows rb + 2q and rb + 2q + 1: (k, k + 1) pairs
+                *reinterpret_cast<uint32_t *>(&T[rb + 2 * q][kp]) = (a[q] & 0xFFFFu) | (c[q] << 16);
+                *reinterpret_cast<uint32_t *>(&T[rb + 2 * q + 1][kp]) = (a[q] >> 16) | (c[q] & 0xFFFF0000u);
             }
-            __syncthreads();
         }
     }
+}
+
+template <int MA, int MB>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    __shared__ __align__(16) bf16 As[2][TM][LDSK];
+    __shared__ __align__(16) bf16 Bs[2][TN][LDSK];
+    // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+    // XCDs (each with its own L2), so workgroup w runs on XCD w % 8; give each
+    // XCD a contiguous run of row-major tiles, i.e. a band of row tiles that
+    // share their A rows in that XCD's L2
+    const int tn = (g.N + TN - 1) / TN, tm = (g.M + TM - 1) / TM;
+    const int T = tn * tm, per = (T + 7) / 8;
+    const int tile = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+    if (tile >= T) return;
+    const int tile_m = tile / tn, tile_n = tile % tn;
+    const int m0 = tile_m * TM, n0 = tile_n * TN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    // K range of the tile: the union of its two 64-column ranges
+    const int t64 = tile_n * 2;
+    const int nt64 = (g.N + 63) / 64;
+    int kb = 0, ke = g.K;
+    if (g.kbeg) kb = t64 + 1 < nt64 ? min(g.kbeg[t64], g.kbeg[t64 + 1]) : g.kbeg[t64];
+    if (g.kend) ke = t64 + 1 < nt64 ? max(g.kend[t64], g.kend[t64 + 1]) : g.kend[t64];
+    int c_lo = kb / TK, c_hi = (ke + TK - 1) / TK;  // 32-wide chunks [c_lo, c_hi)
+    // split-K: slice blockIdx.z of the chunk range
+    if (g.ksplit > 1) {
+        const int nc = c_hi - c_lo, per = (nc + g.ksplit - 1) / g.ksplit;
+        c_lo = c_lo + (int)blockIdx.z * per;
+        c_hi = min(c_hi, c_lo + per);
+    }
+    // a tile whose every output is masked needs no reduction
+    if (g.deg_row && g.deg_col) {
+        const int nlast = min(n0 + TN, g.N) - 1;
+        if (g.deg_row[m0] > g.deg_col[nlast]) c_hi = c_lo;
+    }
+    f32x4 acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int S = c_hi > c_lo ? (c_hi - c_lo + 1) / 2 : 0;  // stages of two chunks
+    if (S > 0) {
+        // the stage's K end: the tile's, never past the slice
+        const int kst = min(ke, c_hi * TK);
+        StageRegs ra[GEMM_P], rb[GEMM_P];
+#pragma unroll
+        for (int i = 0; i < GEMM_P; ++i) {
+            if (i < S) {
+                stage_load<MA>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * i) * TK, kst);
+                stage_load<MB>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * i) * TK, kst);
+            }
+        }
+        stage_store<MA>(ra[0], As[0]);
+        stage_store<MB>(rb[0], Bs[0]);
+        __syncthreads();
+        for (int sb = 0; sb < S; sb += GEMM_P) {
+#pragma unroll
+            for (int i = 0; i < GEMM_P; ++i) {
+                const int st = sb + i;
+                if (st < S) {
+                    const int buf = st & 1;
+                    // the registers of stage st went to LDS last iteration:
+                    // reuse them for stage st + P
+                    if (st + GEMM_P < S) {
+                        stage_load<MA>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
+                        stage_load<MB>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk) {
+                        if (c_lo + 2 * st + kk < c_hi) {
+                            bf16x8 af[4], bfr[4];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+                                af[a] = *reinterpret_cast<const bf16x8 *>(
+                                    &As[buf][wr + a * 16 + (lane & 15)][kk * TK + (lane >> 4) * 8]);
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                bfr[b] = *reinterpret_cast<const bf16x8 *>(
+                                    &Bs[buf][wc + b * 16 + (lane & 15)][kk * TK + (lane >> 4) * 8]);
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                                for (int b = 0; b < 4; ++b)
+                                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0,
+                                                                                        0);
+                        }
+                    }
+                    if (st + 1 < S) {
+                        stage_store<MA>(ra[(i + 1) % GEMM_P], As[buf ^ 1]);
+                        stage_store<MB>(rb[(i + 1) % GEMM_P], Bs[buf ^ 1]);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    if (g.ksplit > 1) {
+        // raw partial sums of this slice; the reduction applies the epilogue
+        float *P = g.part + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
+                    const int n = n0 + wc + j * 16 + (lane & 15);
+                    if (m < g.M && n < g.N) P[(int64_t)m * g.N + n] = acc[i][j][e];
+                }
+        return;
+    }
+    // epilogue: every operand the epilogue reads is loaded first, without
+    // branches (clamped addresses), so the loads overlap; only the stores
+    // are guarded
+    float bias_j[4];
+    int dcol[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = n0 + wc + j * 16 + (lane & 15);
+        const int nc = n < g.N ? n : g.N - 1;
+        bias_j[j] = g.bias ? g.bias[nc] : 0.f;
+        dcol[j] = g.deg_col ? g.deg_col[nc] : 0;
+    }
+    int drow[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
+            drow[i][e] = g.deg_row ? g.deg_row[m < g.M ? m : g.M - 1] : 0;
+        }
+    const bool masked = g.deg_row && g.deg_col;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        bf16 gv[4][4];
+        if (g.gate) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
+                    const int n = n0 + wc + j * 16 + (lane & 15);
+                    const int mc = m < g.M ? m : g.M - 1, nc = n < g.N ? n : g.N - 1;
+                    gv[j][e] = g.gate[(int64_t)mc * g.sgm + (int64_t)nc * g.sgn];
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
                 const int n = n0 + wc + j * 16 + (lane & 15);
-                if (m >= g.M || n >= g.N) continue;
-                float v = acc[i][j][e];
-                if (g.bias) v += g.bias[n];
+                float v = acc[i][j][e] + bias_j[j];
                 if (g.relu) v = v > 0.f ? v : 0.f;
-                if (g.gate && !((float)g.gate[(int64_t)m * g.sgm + (int64_t)n * g.sgn] > 0.f)) v = 0.f;
-                if (g.deg_row && g.deg_col && g.deg_row[m] > g.deg_col[n]) v = 0.f;
-                const int64_t o = (int64_t)m * g.scm + (int64_t)n * g.scn;
-                if (g.out_bf16)
-                    reinterpret_cast<bf16 *>(g.C)[o] = (bf16)v;
-                else if (g.accumulate)
-                    reinterpret_cast<float *>(g.C)[o] += v;
-                else
-                    reinterpret_cast<float *>(g.C)[o] = v;
+                if (g.gate && !((float)gv[j][e] > 0.f)) v = 0.f;
+                if (masked && drow[i][e] > dcol[j]) v = 0.f;
+                if (m < g.M && n < g.N) {
+                    const int64_t o = (int64_t)m * g.scm + (int64_t)n * g.scn;
+                    if (g.out_bf16)
+                        reinterpret_cast<bf16 *>(g.C)[o] = (bf16)v;
+                    else if (g.accumulate)
+                        reinterpret_cast<float *>(g.C)[o] += v;
+                    else
+                        reinterpret_cast<float *>(g.C)[o] = v;
+                }
             }
+    }
+}
+
+// Split-K reduction: slices added in ascending order, degree mask, fp32 out.
+__global__ void splitk_reduce_kernel(GemmArgs g) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)g.M * g.N) return;
+    const int m = (int)(e / g.N), n = (int)(e % g.N);
+    float v = 0.f;
+    for (int z = 0; z < g.ksplit; ++z) v += g.part[(int64_t)z * g.M * g.N + e];
+    if (g.deg_row && g.deg_col && g.deg_row[m] > g.deg_col[n]) v = 0.f;
+    float *C = reinterpret_cast<float *>(g.C) + (int64_t)m * g.scm + (int64_t)n * g.scn;
+    if (g.accumulate)
+        *C += v;
+    else
+        *C = v;
+}
+
+// Operand mode (see stage_load) from the strides and the base alignment.
+// The vector modes read whole 8-element segments, so they also need every
+// segment that starts inside the operand to end inside its row: K <= sr for
+// mode 0, R <= sk for mode 1 (both strides multiples of 8).
+static int operand_mode(const bf16 *p, int64_t sr, int64_t sk, int R, int K) {
+    const bool aligned = (((uintptr_t)p) & 15) == 0;
+    if (aligned && sk == 1 && sr % 8 == 0 && K <= sr) return 0;
+    if (aligned && sr == 1 && sk % 8 == 0 && R <= sk) return 1;
+    return 2;
 }
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
-    dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
-    hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, g);
+    if (g.ksplit > 1 && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part)) return hipErrorInvalidValue;
+    const int tiles = ((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM);
+    dim3 grid(8 * ((tiles + 7) / 8), 1, g.ksplit > 1 ? g.ksplit : 1);
+    const int ma = operand_mode(g.A, g.sam, g.sak, g.M, g.K), mb = operand_mode(g.B, g.sbn, g.sbk, g.N, g.K);
+    const void *fn = nullptr;
+#define PBIT_GEMM(A_, B_) \
+    if (ma == A_ && mb == B_) fn = (const void *)gemm_kernel<A_, B_>;
+    PBIT_GEMM(0, 0) PBIT_GEMM(0, 1) PBIT_GEMM(0, 2)
+    PBIT_GEMM(1, 0) PBIT_GEMM(1, 1) PBIT_GEMM(1, 2)
+    PBIT_GEMM(2, 0) PBIT_GEMM(2, 1) PBIT_GEMM(2, 2)
+#undef PBIT_GEMM
+    void *args[] = {const_cast<GemmArgs *>(&g)};
+    hipError_t e = hipLaunchKernel(fn, grid, dim3(256), args, 0, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess || g.ksplit <= 1) return e;
+    const int64_t tot = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -148,8 +363,8 @@ __global__ void unpack_kernel(const uint32_t *__restrict__ states, int n, int D,
     X[e] = (bf16)v;
 }
 
-// dLoss/dL = (sigmoid(L) - x) / n on free positions; the batch-mean binary
-// cross-entropy is accumulated into *loss.
+// dLoss/dL = (sigmoid(L) - x) / n on free positions; each workgroup writes
+// its share of the batch-mean binary cross-entropy to loss[blockIdx.x].
 __global__ void loss_grad_kernel(const float *__restrict__ L, const bf16 *__restrict__ X, const int *__restrict__ freem,
                                  int n, int D, int DP, float inv_n, bf16 *__restrict__ G, float *__restrict__ loss) {
     __shared__ float red[256];
@@ -175,7 +390,21 @@ __global__ void loss_grad_kernel(const float *__restrict__ L, const bf16 *__rest
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(loss, red[0]);
+    if (threadIdx.x == 0) loss[blockIdx.x] = red[0];  // per-block partial
+}
+
+// Sums the per-block partial losses in a fixed order into *out.
+__global__ __launch_bounds__(256) void loss_sum_kernel(const float *__restrict__ part, int nb, float *__restrict__ out) {
+    __shared__ float red[256];
+    float v = 0.f;
+    for (int i = threadIdx.x; i < nb; i += 256) v += part[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // Column sums of a row-major n x N bf16 matrix in two deterministic passes:
@@ -196,6 +425,35 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const bf16 *__restrict
     red[ty][tx] = s;
     __syncthreads();
     if (ty == 0 && j < N) part[(int64_t)blockIdx.y * N + j] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
+}
+
+// Vector variant for N % 8 == 0 and a 16-byte aligned G: thread (column
+// group of 8, row group of 8) adds 32 rows with one 16-byte load per row; the
+// eight row groups are combined in a fixed order.
+__global__ __launch_bounds__(256) void colsum_part8_kernel(const bf16 *__restrict__ G, int n, int N,
+                                                           float *__restrict__ part) {
+    __shared__ float red[8][256];
+    const int cg = threadIdx.x & 31, rg = threadIdx.x >> 5;
+    const int c0 = blockIdx.x * 256 + cg * 8;
+    const int rbase = blockIdx.y * 256;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (c0 < N) {
+        for (int r = rbase + rg; r < min(rbase + 256, n); r += 8) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(G + (int64_t)r * N + c0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[rg][cg * 8 + i] = acc[i];
+    __syncthreads();
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < N) {
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += red[q][threadIdx.x];
+        part[(int64_t)blockIdx.y * N + c] = s;
+    }
 }
 
 __global__ void colsum_final_kernel(const float *__restrict__ part, int chunks, int N, float *__restrict__ out) {
@@ -297,17 +555,22 @@ __device__ __forceinline__ f32x4 mfma_chunks(const bf16 *__restrict__ arow, cons
 __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int CS = 16;
-    const int DP = a.DP, H = a.H, W = a.W;
+    const int DP = a.DP, H = a.H, W = a.W, h = a.h;
     bf16 *Xs = reinterpret_cast<bf16 *>(smem);           // [CS][DP]
     bf16 *H1s = Xs + CS * DP;                             // [CS][H]
     bf16 *H2s = H1s + CS * H;                             // [CS][H]
     float *logit = reinterpret_cast<float *>(H2s + CS * H);  // [CS]
     uint32_t *lat = reinterpret_cast<uint32_t *>(logit + CS);  // [CS][W]
+    uint32_t *Ts = lat + CS * W;                          // deferred: [h][CS] thresholds
+    uint32_t *cones = Ts + (a.defer ? h * CS : 0);        // deferred: [h][W] cone words
+    // deferred: [h][CS] log-probabilities, over the dead activations when they fit
+    double *lgs = reinterpret_cast<double *>(a.defer == 2 ? (void *)H1s
+                                                          : (void *)(cones + (a.defer ? ((h * W + 1) & ~1) : 0)));
     const int lane = threadIdx.x;
     const int c0 = blockIdx.x * CS;
     const uint32_t *B = a.blob;
     const uint32_t *cw = B + B[H_OFF_CONST];
-    const uint32_t *cone = B + B[H_OFF_CONE];
+    const uint32_t *cone_g = B + B[H_OFF_CONE];
     const uint32_t WS = B[H_WS];
     const uint32_t cid = B[H_CID];
 
@@ -317,10 +580,15 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     }
     for (int e = lane; e < 2 * CS * H; e += 64) H1s[e] = (bf16)0.f;
     for (int e = lane; e < CS * W; e += 64) lat[e] = cw[e % W];
+    if (a.defer)
+        for (int e = lane; e < h * W; e += 64) cones[e] = cone_g[(int64_t)(e / W) * WS + e % W];
     __syncthreads();
+    const uint32_t *cone = a.defer ? cones : cone_g;
+    const int cstride = a.defer ? W : (int)WS;
     double lq = 0.0;
+    U4 u4 = {0u, 0u, 0u, 0u};
     const int row = lane & 15, kq = (lane >> 4) * 8;
-    for (int f = 0; f < a.h; ++f) {
+    for (int f = 0; f < h; ++f) {
         const int4 ph = a.phase[f];  // {u1a, u1b, u2a, u2b}
         const int4 kk = a.phase_k[f];  // {K1 end, K2 end, K3 end, position p}
         const int p = kk.w;
@@ -372,17 +640,22 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
                 if (a.score) {
                     bit = (a.score[(int64_t)(p >> 5) * a.n + chain] >> (p & 31)) & 1u;
                 } else {
-                    const U4 u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + chain, cid | (1u << 16),
-                                                a.seed_lo, a.seed_hi);
-                    const uint32_t uu[4] = {u4.x, u4.y, u4.z, u4.w};
-                    bit = uu[f & 3] < T ? 1u : 0u;
+                    // one Philox block serves four consecutive free bits
+                    if ((f & 3) == 0)
+                        u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + chain, cid | (1u << 16),
+                                           a.seed_lo, a.seed_hi);
+                    const uint32_t u = (f & 3) == 0 ? u4.x : ((f & 3) == 1 ? u4.y : ((f & 3) == 2 ? u4.z : u4.w));
+                    bit = u < T ? 1u : 0u;
                 }
-                lq += made_log_prob(T, bit);
+                if (a.defer)
+                    Ts[f * CS + lane] = T;
+                else
+                    lq += made_log_prob(T, bit);
                 // the lattice bit at p is the free bit itself: flip its cone
                 // when the drawn value differs from the current one
                 const uint32_t cur = (lat[lane * W + (p >> 5)] >> (p & 31)) & 1u;
                 if (bit != cur) {
-                    const uint32_t *cm = cone + (int64_t)f * WS;
+                    const uint32_t *cm = cone + (int64_t)f * cstride;
                     for (int w = 0; w < W; ++w) {
                         uint32_t mw = cm[w];
                         lat[lane * W + w] ^= mw;
@@ -398,6 +671,22 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
         }
         __syncthreads();
     }
+    if (a.defer) {
+        // every lane computes log-probabilities (four lanes per chain), then
+        // each chain sums its own in free-bit order, as the batched scorer does
+        const int c = lane & 15;
+        const int chain = c0 + c;
+        if (chain < a.n) {
+            for (int f = lane >> 4; f < h; f += 4) {
+                const int p = a.phase_k[f].w;
+                const uint32_t bit = (lat[c * W + (p >> 5)] >> (p & 31)) & 1u;
+                lgs[f * CS + c] = made_log_prob(Ts[f * CS + c], bit);
+            }
+        }
+        __syncthreads();
+        if (lane < CS && chain < a.n)
+            for (int f = 0; f < h; ++f) lq += lgs[f * CS + lane];
+    }
     if (lane < CS) {
         const int chain = c0 + lane;
         if (chain < a.n) {
@@ -408,9 +697,20 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     }
 }
 
-hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s) {
+hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
+    SampleArgs a = a0;
     const int grid = (a.n + 15) / 16;
-    const size_t lds = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
+    const size_t base = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
+    // small networks defer the log-probabilities to the end and keep the cones
+    // in LDS; the log buffer reuses the activations when they are large enough
+    a.defer = 0;
+    size_t lds = base;
+    if (a.H <= 256) {
+        const size_t ts = (size_t)a.h * 16 * 4, cn = (size_t)((a.h * a.W + 1) & ~1) * 4;
+        const size_t lg = (size_t)a.h * 16 * 8;
+        a.defer = lg <= (size_t)2 * 16 * a.H * 2 ? 2 : 1;
+        lds = base + ts + cn + (a.defer == 1 ? lg : 0);
+    }
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)made_sample_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -427,17 +727,24 @@ hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, 
 }
 
 hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
-                            float *loss, hipStream_t s) {
+                            float *part, float *loss, hipStream_t s) {
     const int64_t tot = (int64_t)n * D;
-    hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, X, freem, n, D, DP,
-                       1.f / (float)n, G, loss);
+    const int nb = (int)((tot + 255) / 256);
+    hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)nb), dim3(256), 0, s, L, X, freem, n, D, DP, 1.f / (float)n, G,
+                       part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, part, nb, loss);
     return hipGetLastError();
 }
 
 hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s) {
     const int chunks = (n + 255) / 256;
     if (chunks == 0 || N == 0) return hipSuccess;
-    hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, G, n, N, part);
+    if (N % 8 == 0 && (((uintptr_t)G) & 15) == 0)
+        hipLaunchKernelGGL(colsum_part8_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, s, G, n, N, part);
+    else
+        hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, G, n, N, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, chunks, N, out);

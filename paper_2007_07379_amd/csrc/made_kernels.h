@@ -10,13 +10,15 @@ namespace pbit {
 
 // The proposal's probability of a 1 at a free position, as the uint32
 // threshold the sampler compares its Philox draw with: P(1) = T / 2^32
-// exactly.  T is kept in [1, 2^32 - 1] so every path has q > 0.
+// exactly, whatever rounding produced T.  The sigmoid is evaluated in FP32
+// (the logit is FP32 already); scaling by 2^32 is exact and the conversion
+// truncates.  T is kept in [1, 2^32 - 1] (a NaN logit gives 1) so every path
+// has q > 0.  The sampler and the scorer call this same function, so both
+// see the same T.
 __device__ __forceinline__ uint32_t made_threshold(float logit) {
-    const double p = 1.0 / (1.0 + exp(-(double)logit));
-    double t = floor(p * 4294967296.0);
-    if (t < 1.0) t = 1.0;
-    if (t > 4294967295.0) t = 4294967295.0;
-    return (uint32_t)t;
+    const float p = 1.0f / (1.0f + __expf(-logit));
+    const float t = p * 4294967296.0f;
+    return t >= 4294967296.0f ? 0xFFFFFFFFu : (t >= 1.0f ? (uint32_t)t : 1u);
 }
 
 __device__ __forceinline__ double made_log_prob(uint32_t T, uint32_t bit) {
@@ -34,12 +36,15 @@ struct SampleArgs {
     uint32_t *out;        // word-major lattice words of the proposals (may be NULL)
     double *logq;         // log q of each proposal
     const uint32_t *score;  // score mode: word-major paths whose bits are read instead of drawn
+    int defer;            // set by the launcher: 0 logs in the loop, 1/2 deferred (2: over the activations)
 };
 
 hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
+// G and the batch-mean loss, written to *loss (per-workgroup partials in
+// `part`, ceil(n D / 256) floats, summed in a fixed order).
 hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
-                            float *loss, hipStream_t s);
+                            float *part, float *loss, hipStream_t s);
 // out[j] = sum_b G[b][j]: partial sums over 256-row chunks into `part`
 // (ceil(n / 256) x N floats), then over the chunks in ascending order.
 hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s);

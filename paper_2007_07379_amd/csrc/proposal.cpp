@@ -67,6 +67,9 @@ struct pbit_proposal_s {
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
     float *L = nullptr;
     float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / 256) x max(D, H)
+    float *part = nullptr;     // split-K partial sums of the weight gradients
+    float *lpart = nullptr;    // per-workgroup partial losses
+    int64_t part_floats = 0;
     uint32_t *prop = nullptr;
     double *lq_cur = nullptr, *lq_prop = nullptr;
     uint32_t mh_cap = 0;
@@ -105,6 +108,10 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->G3 = A.alloc<bf16>((size_t)BATCH_MAX * D);
     q->L = A.alloc<float>((size_t)BATCH_MAX * D);
     q->colpart = A.alloc<float>((size_t)(BATCH_MAX / 256) * std::max(D, H));
+    q->part_floats = std::min<int64_t>((int64_t)16 * std::max<int64_t>((int64_t)H * H, (int64_t)D * H),
+                                       (int64_t)16 << 20);
+    q->part = A.alloc<float>((size_t)q->part_floats);
+    q->lpart = A.alloc<float>(((size_t)BATCH_MAX * D + 255) / 256);
     auto up = [&](int *&dst, const std::vector<int> &src) {
         dst = A.alloc<int>(src.size() + 64);
         if (dst) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -138,7 +145,7 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     up(q->g1beg, b1);
     q->d_phase = A.alloc<int4>(q->phase.size() + 1);
     q->d_phase_k = A.alloc<int4>(q->phase_k.size() + 1);
-    if (!q->theta || !q->L || !q->colpart || !q->d_phase || !q->d_phase_k || !q->g1beg)
+    if (!q->theta || !q->L || !q->colpart || !q->part || !q->lpart || !q->d_phase || !q->d_phase_k || !q->g1beg)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
     (void)hipMemcpy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4), hipMemcpyHostToDevice);
     (void)hipMemcpy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4), hipMemcpyHostToDevice);
@@ -167,12 +174,27 @@ GemmArgs gemm0() {
     return g;
 }
 
+// Weight gradients reduce over the batch (K = n) into few 128 x 128 tiles:
+// split K so the launch has about 256 workgroups (one per CU), within the
+// workspace.
+void splitk(pbit_proposal q, GemmArgs &g) {
+    const int64_t tiles = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
+    const int chunks = (g.K + 31) / 32;
+    int ks = (int)std::min<int64_t>(16, (256 + tiles - 1) / tiles);
+    ks = std::min(ks, std::max(1, chunks / 4));
+    ks = (int)std::min<int64_t>(ks, (int64_t)(q->part_floats / ((int64_t)g.M * g.N)));
+    if (ks > 1) {
+        g.ksplit = ks;
+        g.part = q->part;
+    }
+}
+
 // Forward of n <= BATCH_MAX paths (X already unpacked): H1, H2, L.
 pbit_status forward(pbit_proposal q, int n, hipStream_t s) {
     const int D = q->D, DP = q->DP, H = q->H;
     GemmArgs g = gemm0();
     g.A = q->X; g.sam = DP; g.sak = 1;
-    g.B = q->W1b; g.sbk = H; g.sbn = 1;
+    g.B = q->W1T; g.sbk = 1; g.sbn = DP;
     g.C = q->H1; g.scm = H; g.scn = 1;
     g.M = n; g.N = H; g.K = D;
     g.kend = q->k1end; g.bias = q->theta + q->ob1; g.relu = 1; g.out_bf16 = 1;
@@ -180,14 +202,14 @@ pbit_status forward(pbit_proposal q, int n, hipStream_t s) {
     if (e != hipSuccess) return hip_error(e, "gemm1");
     g = gemm0();
     g.A = q->H1; g.sam = H; g.sak = 1;
-    g.B = q->W2b; g.sbk = H; g.sbn = 1;
+    g.B = q->W2T; g.sbk = 1; g.sbn = H;
     g.C = q->H2; g.scm = H; g.scn = 1;
     g.M = n; g.N = H; g.K = H;
     g.kend = q->k2end; g.bias = q->theta + q->ob2; g.relu = 1; g.out_bf16 = 1;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm2");
     g = gemm0();
     g.A = q->H2; g.sam = H; g.sak = 1;
-    g.B = q->Vb; g.sbk = D; g.sbn = 1;
+    g.B = q->VT; g.sbk = 1; g.sbn = H;
     g.C = q->L; g.scm = D; g.scn = 1;
     g.M = n; g.N = D; g.K = H;
     g.kend = q->k3end; g.bias = q->theta + q->oc; g.out_bf16 = 0;
@@ -195,11 +217,11 @@ pbit_status forward(pbit_proposal q, int n, hipStream_t s) {
     return PBIT_OK;
 }
 
-// Gradient of the batch in q->X / q->L into q->grad (loss added to *loss_dev).
+// Gradient of the batch in q->X / q->L into q->grad; the batch-mean loss is written to *loss_dev.
 pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     const int D = q->D, DP = q->DP, H = q->H;
     hipError_t e;
-    if ((e = launch_loss_grad(q->L, q->X, q->d_free, n, D, DP, q->G3, loss_dev, s)) != hipSuccess)
+    if ((e = launch_loss_grad(q->L, q->X, q->d_free, n, D, DP, q->G3, q->lpart, loss_dev, s)) != hipSuccess)
         return hip_error(e, "loss_grad");
     // dV = H2^T G3 (masked)
     GemmArgs g = gemm0();
@@ -208,6 +230,7 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     g.C = q->grad + q->oV; g.scm = D; g.scn = 1;
     g.M = H; g.N = D; g.K = n;
     g.deg_row = q->d_deg2; g.deg_col = q->d_deg_out;
+    splitk(q, g);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dV");
     if ((e = launch_colsum(q->G3, n, D, q->colpart, q->grad + q->oc, s)) != hipSuccess) return hip_error(e, "dc");
     // G2 = (G3 V^T) * (H2 > 0)
@@ -225,6 +248,7 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     g.C = q->grad + q->oW2; g.scm = H; g.scn = 1;
     g.M = H; g.N = H; g.K = n;
     g.deg_row = q->d_deg1; g.deg_col = q->d_deg2;
+    splitk(q, g);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW2");
     if ((e = launch_colsum(q->G2, n, H, q->colpart, q->grad + q->ob2, s)) != hipSuccess) return hip_error(e, "db2");
     // G1 = (G2 W2^T) * (H1 > 0)
@@ -242,6 +266,7 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
     g.C = q->grad + q->oW1; g.scm = H; g.scn = 1;
     g.M = D; g.N = H; g.K = n;
     g.deg_row = q->d_deg_in; g.deg_col = q->d_deg1;
+    splitk(q, g);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW1");
     if ((e = launch_colsum(q->G1, n, H, q->colpart, q->grad + q->ob1, s)) != hipSuccess) return hip_error(e, "db1");
     return PBIT_OK;
