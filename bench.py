@@ -215,6 +215,11 @@ def mh_mode(args):
     s.gibbs_run([chains], burn, 0, hist, state, seed=1, stream=stream)
     start = state.clone()
     n_long = long_cycles * (1 + G)
+    # untimed warm-up of the same launch (a run this long may use the kernel
+    # generated for the circuit, compiled on first use)
+    warm = state.clone()
+    s.gibbs_run([chains], 0, n_long, hist, warm, seed=1, sweep_offset=burn, resume=True, stream=stream)
+    del warm
     hist.zero_()
     e0, e1 = ev(), ev()
     torch.cuda.synchronize()
