@@ -67,6 +67,7 @@ CASES = [
     ("rbrick", lambda: wc.rotated_brickwork(5, 8, 3, math.pi / 7, K=3), 640, 20, 100, 9),
     ("hchain_odd", lambda: wc.hadamard_chain(33, K=1), 300, 5, 50, 0),
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 20, 0),
+    ("rasym", lambda: wc.random_asymmetric(6, 10, 3, K=3), 777, 10, 40, 5),
 ]
 
 

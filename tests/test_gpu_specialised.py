@@ -40,6 +40,7 @@ CASES = [
     ("brick16", lambda: wc.workload_circuit("brick16"), 513, 10, 43, 77),
     ("hchain_odd", lambda: wc.hadamard_chain(33, K=1), 300, 5, 50, 0),
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 21, 0),
+    ("rasym", lambda: wc.random_asymmetric(6, 10, 3, K=3), 777, 10, 41, 5),
 ]
 
 _oracle_cache = {}

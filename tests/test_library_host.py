@@ -149,6 +149,7 @@ def _cases():
         ("rhchain3", wc.rotated_hadamard_chain(7, math.pi / 3, K=2)),
         ("rbrick", wc.rotated_brickwork(4, 6, 5, math.pi / 8, K=3)),
         ("hchain", wc.hadamard_chain(9, K=1)),
+        ("rasym", wc.random_asymmetric(6, 10, 3, K=3)),
     ]
 
 

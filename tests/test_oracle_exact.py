@@ -28,11 +28,19 @@ def small_random(seed):
     return _circ(wc.random_clifford_t(n, d, seed, K=3))
 
 
-@pytest.mark.parametrize("seed", range(12))
+def small_asym(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 4))
+    d = int(rng.integers(1, 5 if n < 3 else 4))
+    return _circ(wc.random_asymmetric(n, d, seed, K=3))
+
+
+@pytest.mark.parametrize("seed", range(18))
 def test_statevector_equals_path_sum_and_dense(seed):
     """Eq. (U) as a matrix product and Eq. (path) as an explicit sum over
-    every Feynman path are the same number (exact identity)."""
-    c = small_random(seed)
+    every Feynman path are the same number (exact identity); seeds >= 12 use
+    circuits with non-symmetric gates."""
+    c = small_random(seed) if seed < 12 else small_asym(seed)
     sv = exact.statevector(c)
     ps = exact.path_sum(c)
     dense = exact.dense_unitary(c)[:, c.input]
@@ -264,3 +272,51 @@ def test_rotated_hadamard_theta():
     # the path law is non-uniform and enumerates to the magnitude circuit
     pm, Z = exact.magnitude_marginal(c3)
     assert comp3.Z == pytest.approx(Z, rel=1e-12)
+
+
+def test_nonsymmetric_gate_closed_form():
+    """Gate orientation (rows = output, columns = input, Sec. 2): one H S
+    gate maps |0> to its column 0, (1, 1)/sqrt(2), and |1> to column 1,
+    (i, -i)/sqrt(2); S H maps |0> to (1, i)/sqrt(2).  Written out by hand."""
+    r = 1.0 / math.sqrt(2.0)
+    for kind, inp, want in [("HS", 0, [r, r]), ("HS", 1, [1j * r, -1j * r]), ("SH", 0, [r, 1j * r]),
+                            ("SH", 1, [r, -1j * r])]:
+        c = wc.circuit("one", 1, 1, 2, [wc.gate1(1, 0, kind)], inp)
+        assert np.allclose(exact.statevector(_circ(c)), want, atol=1e-15), (kind, inp)
+        assert np.allclose(exact.path_sum(_circ(c)), want, atol=1e-15), (kind, inp)
+
+
+def compiled_amplitudes(comp):
+    """Sum over the compiled lattice's paths of |psi_C| e^{2 pi i k / 2^K}
+    per output state (Eq. (path) on the eliminated lattice)."""
+    amp = np.zeros(2 ** comp.n, dtype=complex)
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        amp[a] += m * cmath.exp(2j * math.pi * k / 2 ** comp.K)
+    return amp
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_compiled_paths_reproduce_statevector(seed):
+    """The compile (Appendix eliminations, magnitude and phase tables, cones)
+    loses nothing: summing every path of the compiled lattice with its
+    magnitude and phase bin gives the matrix-product amplitudes, for
+    circuits with non-symmetric one-qubit gates (even seeds) and random
+    Clifford+T circuits (odd seeds)."""
+    c = small_asym(seed) if seed % 2 == 0 else small_random(seed)
+    comp = ocomp.compile_circuit(c)
+    assert np.allclose(compiled_amplitudes(comp), exact.statevector(c), atol=1e-12)
+
+
+def test_repeated_cnot_cancels_in_the_lattice():
+    """H(q0), CNOT(0->1), CNOT(0->1): the second CNOT undoes the first, so the
+    state is (|0> + |1>)/sqrt(2) on qubit 0 with qubit 1 back to 0 (indices 0
+    and 1, little-endian).  In the eliminated lattice qubit 1's last layer is
+    x0 XOR x0 = 0; every path of the compiled lattice must reproduce it."""
+    g = [wc.gate1(1, 0, "H"), wc.cnot(2, 0, 1), wc.cnot(3, 0, 1)]
+    c = _circ(wc.circuit("cnot2", 2, 3, 1, g, 0))
+    r = 1.0 / math.sqrt(2.0)
+    want = np.array([r, r, 0, 0], dtype=complex)
+    assert np.allclose(exact.statevector(c), want, atol=1e-15)
+    comp = ocomp.compile_circuit(c)
+    assert comp.h == 1
+    assert np.allclose(compiled_amplitudes(comp), want, atol=1e-12)

@@ -89,3 +89,19 @@ def test_adam_constant_gradient_closed_form():
     # constant g: bias-corrected m = g, v = g^2 at every step
     want = theta - 20 * lr * g / (np.abs(g) + eps)
     assert np.allclose(th, want, rtol=1e-12, atol=1e-15)
+
+
+def test_each_output_sees_its_predecessor():
+    """The masks keep every allowed connection: with generic weights logit o
+    changes when input o - 1 flips (a mask one degree too strict would cut
+    it)."""
+    D, H = 10, 40
+    p = _params(D, H, 5)
+    rng = np.random.default_rng(6)
+    x = rng.integers(0, 2, (1, D)).astype(float)
+    L0, _ = made.forward(p, x)
+    for o in range(1, D):
+        x2 = x.copy()
+        x2[0, o - 1] = 1 - x2[0, o - 1]
+        L1, _ = made.forward(p, x2)
+        assert abs(L1[0, o] - L0[0, o]) > 1e-9, o

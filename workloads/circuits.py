@@ -97,7 +97,17 @@ def mat_cp(k):
     return _mat([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, e]])
 
 
-ONE_Q = {"H": mat_h, "S": mat_s, "T": mat_t, "SX": mat_sx, "X": mat_x}
+def mat_hs():
+    """H S = 1/sqrt(2) [[1, i], [1, -i]] (not symmetric)."""
+    return _mat([[R2, complex(0, R2)], [R2, complex(0, -R2)]])
+
+
+def mat_sh():
+    """S H = 1/sqrt(2) [[1, 1], [i, -i]] (not symmetric)."""
+    return _mat([[R2, R2], [complex(0, R2), complex(0, -R2)]])
+
+
+ONE_Q = {"H": mat_h, "S": mat_s, "T": mat_t, "SX": mat_sx, "X": mat_x, "HS": mat_hs, "SH": mat_sh}
 
 
 def gate1(layer, q, kind, mat=None):
@@ -324,3 +334,32 @@ def main():
 
 if __name__ == "__main__":
     main()
+
+
+def random_asymmetric(n, d, seed, K=3):
+    """Random layers whose one-qubit gates include the non-symmetric H S and
+    S H (so a transposed gate matrix changes the result): per layer each
+    qubit gets, with probability 0.6, a gate from {H, S, T, HS, SH}, else
+    CNOT or CZ with an unused partner.  For checks of gate orientation."""
+    rng = random.Random(seed)
+    gates = []
+    for layer in range(1, d + 1):
+        order = list(range(n))
+        rng.shuffle(order)
+        used = set()
+        for q in order:
+            if q in used:
+                continue
+            free = [p for p in range(n) if p not in used and p != q]
+            if rng.random() < 0.6 or not free:
+                gates.append(gate1(layer, q, rng.choice(["H", "S", "T", "HS", "SH"])))
+                used.add(q)
+                continue
+            p = rng.choice(free)
+            if rng.random() < 0.5:
+                gates.append(cnot(layer, q, p))
+            else:
+                gates.append(cz(layer, min(q, p), max(q, p)))
+            used.add(q)
+            used.add(p)
+    return circuit(f"rasym_n{n}_d{d}_s{seed}", n, d, K, gates, 0)
