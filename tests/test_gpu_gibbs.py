@@ -188,6 +188,52 @@ def test_full_rct12_sampled_chains_and_amplitudes(env):
     assert tv <= 0.01 and tv < 3 * oest.expected_iid_tv(pm, T)
 
 
+def test_full_brick20_sampled_chains_and_amplitudes(env):
+    """Full brickwork workload (n=20, d=24, K=4; 262,144 chains x 20,000
+    sweeps after 200 burn-in, 5.2e9 samples into 2^24 bins in HBM), run as
+    two resumed launches of < 2^32 samples each, as bench.py times it: sampled
+    chains replayed by the oracle match bit for bit; the pooled histogram
+    passes the 4-sigma rule against the 2^20 statevector and TV_path is at
+    the iid level."""
+    torch, pbit = env
+    w = wc.WORKLOADS["brick20"]
+    c = wc.workload_circuit("brick20")
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    chains, burn, sweeps = w["chains"], w["burn_in"], w["sweeps"]
+    per = (2 ** 32 - 1) // chains
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    total = np.zeros(info["hist_bins"], dtype=np.uint64)
+    done = 0
+    while done < sweeps:
+        n = min(per, sweeps - done)
+        hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+        say("part", done, n)
+        s.gibbs_run([chains], burn if done == 0 else 0, n, hist, state, seed=0,
+                    sweep_offset=0 if done == 0 else burn + done, resume=done > 0)
+        torch.cuda.synchronize()
+        total += hist.cpu().numpy().view(np.uint32).astype(np.uint64)
+        done += n
+    h = total.reshape(1 << info["n"], 1 << info["K"])
+    T = chains * sweeps
+    assert int(h.sum()) == T
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    for ci in [0, 1, 12345, chains - 1]:
+        so, _ = och.gibbs(comp, 1, burn, sweeps, seed=0, chain_begin=ci, threads=1)
+        assert np.array_equal(st[ci], so[0]), ci
+    circ = oc.from_dict(c)
+    psi = exact.statevector(circ)
+    pm, _ = exact.magnitude_marginal(circ)
+    amp, sre, sim = s.amplitudes(h, T)
+    ok, zinfo = oest.z_gate(amp, sre, sim, psi)
+    say("z-gate", zinfo)
+    assert ok, zinfo
+    tv = oest.tv_path(h, pm)
+    say("TV_path", tv, "iid", oest.expected_iid_tv(pm, T))
+    assert tv <= 0.01 and tv < 3 * oest.expected_iid_tv(pm, T)
+
+
 def test_full_tiny_born_tv(env):
     c, s, st, h, chains, burn, sweeps = _full_run(env, "tiny")
     _, h_o, comp = oracle_run(c, chains, burn, sweeps)
