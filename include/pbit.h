@@ -132,7 +132,11 @@ typedef struct {
     uint32_t sweeps_per_launch; /* sweep-group size; 0 = autotuned */
     uint32_t block_size;        /* chains per workgroup (64..256, multiple of 64); 0 = autotuned */
     uint32_t use_graph;         /* 1: replay the sweep groups as a captured hipGraph */
-    uint32_t hist_mode;         /* 0 = auto, 1 = LDS-privatised, 2 = global atomics */
+    uint32_t hist_mode;         /* 0 = auto, 1 = LDS-privatised, 2 = global atomics, 3 = path
+                                   counts: circuits on the specialised kernel whose 2^h path
+                                   table (4 bytes a path) fits in LDS beside the toggle rows count
+                                   each sweep's free bits in LDS and bin every path that occurred
+                                   once at the end (the same histogram); other circuits take 0 */
     uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
     uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
     uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */
@@ -144,7 +148,10 @@ typedef struct {
     uint32_t specialize;        /* 0 = auto (large runs of circuits whose conditionals are all 1/2),
                                    1 = never, 2 = always for such circuits (MODE_UNAVAILABLE if
                                    the run-time compile fails): a kernel generated for the circuit
-                                   and compiled with hipRTC on first use (cached in the handle) */
+                                   and compiled with hipRTC on first use (cached in the handle).
+                                   In a persistent batch, 2 takes the heaviest circuits (chains x
+                                   free bits; as many as cover 90 % of the work, at most 64) out of
+                                   the batch into launches of their own specialised kernels. */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its
@@ -272,9 +279,10 @@ pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char 
 
 /* Launch shape that pbit_gibbs_run would use for circuit `index` under
  * cfg (after the handle's autotuned choices and cfg's explicit fields):
- * which kernel, threads per workgroup, histogram privatisation, toggle
- * tables, the kernel's lattice width in words, dynamic LDS bytes and sweeps
- * per launch.  Host only; enqueues nothing. */
+ * which kernel, threads per workgroup, histogram privatisation (lds_hist:
+ * 0 global atomics, 1 bins in LDS, 2 path counts in LDS), toggle tables, the
+ * kernel's lattice width in words, LDS bytes and sweeps per launch.  Host
+ * only; enqueues nothing. */
 enum {
     PBIT_KERNEL_ONE_LANE = 0,   /* one chain per lane */
     PBIT_KERNEL_TWO_LANE = 1,   /* two lanes per chain (all conditionals 1/2) */
@@ -297,7 +305,8 @@ pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uin
 
 /* HIP source of the specialised sweep kernel of circuit `index` (whose
  * conditionals must all be 1/2, else MODE_UNAVAILABLE), with the histogram
- * privatised in LDS when lds_hist != 0, compiled for workgroups of at most
+ * in global memory (lds_hist 0), its bins privatised in LDS (1) or path
+ * counts in LDS (2; h <= 16, else TOO_LARGE), compiled for workgroups of at most
  * max_block threads (256, 512 or 1024).  Copies at most cap bytes
  * (NUL-terminated) into buf; *len receives the full length + 1.  Host only,
  * for inspection and offline compile checks. */

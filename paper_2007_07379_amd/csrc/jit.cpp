@@ -23,6 +23,7 @@
 #include <hip/hiprtc.h>
 
 #include <cstdio>
+#include <algorithm>
 #include <sstream>
 
 #include "blob.h"
@@ -115,13 +116,14 @@ size_t jit_rows_bytes(const CompiledCircuit &k) {
     return rows.size() * sizeof(uint32_t);
 }
 
-JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block) {
+JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool path_hist) {
     const uint32_t *B = k.blob.data();
-    const uint32_t W = B[H_W], WS = B[H_WS], K = B[H_K], n = B[H_N];
+    const uint32_t W = B[H_W], WS = B[H_WS], K = B[H_K], n = B[H_N], h = B[H_H];
     const uint32_t nblk = B[H_NBLK];
     const uint32_t *cw = B + B[H_OFF_CONST];
     JitSource out;
     out.max_block = max_block;
+    if (path_hist) lds_hist = false;
 
     std::vector<Blk> blks;
     std::vector<uint32_t> rows;
@@ -129,12 +131,105 @@ JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     for (const Blk &b : blks) out.xor_words += (uint32_t)b.sup.size();
     out.rows_words = (uint32_t)rows.size();
     const uint32_t nbins = 1u << B[H_HBITS];
-    out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0);
+    const uint32_t npaths = path_hist ? 1u << h : 0u;
+    out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0) + npaths * 4;
+
+    // lattice = const ^ rows of every block, p_j given by an expression
+    auto emit_build = [&](std::ostringstream &o, const std::string &ind, auto pexpr) {
+        for (uint32_t w = 0; w < W; ++w) o << ind << "x[" << w << "] = " << hx(cw[w]) << ";\n";
+        for (uint32_t j = 0; j < nblk; ++j) {
+            const Blk &b = blks[j];
+            const uint32_t sz = (uint32_t)b.sup.size();
+            if (!sz) continue;  // no lattice word depends on this block's bits
+            o << ind << "{\n" << ind << "    const u32 p = " << pexpr(j) << ";\n"
+              << ind << "    const u32 *r = lds_rows + " << b.off << "u + p * " << b.stride << "u;\n";
+            if (b.stride == 1) {
+                o << ind << "    x[" << b.sup[0] << "] ^= r[0];\n";
+            } else if (b.stride == 2) {
+                o << ind << "    const u32x2 v = *(const u32x2 *)r;\n";
+                o << ind << "    x[" << b.sup[0] << "] ^= v.x;\n";
+                o << ind << "    x[" << b.sup[1] << "] ^= v.y;\n";
+            } else {
+                for (uint32_t q = 0; q < b.stride / 4; ++q) {
+                    o << ind << "    const u32x4 v" << q << " = *(const u32x4 *)(r + " << 4 * q << ");\n";
+                    static const char *comp[4] = {"x", "y", "z", "w"};
+                    for (uint32_t e = 0; e < 4; ++e) {
+                        const uint32_t i = 4 * q + e;
+                        if (i < sz) o << ind << "    x[" << b.sup[i] << "] ^= v" << q << "." << comp[e] << ";\n";
+                    }
+                }
+            }
+            o << ind << "}\n";
+        }
+    };
+    // phase polynomial and bin of the lattice in x: declares `bin`
+    auto emit_bin = [&](std::ostringstream &o, const std::string &ind) {
+        for (uint32_t t = 0; t < K; ++t) o << ind << "u32 c" << t << " = 0u;\n";
+        const uint32_t linmask = B[H_LINMASK];
+        const uint32_t *lin = B + B[H_OFF_LIN];
+        for (uint32_t t = 0; t < K; ++t) {
+            if (!((linmask >> t) & 1u)) continue;
+            for (uint32_t w = 0; w < W; ++w) {
+                const uint32_t m = lin[t * WS + w];
+                if (m) o << ind << "c" << t << " += __builtin_popcount(x[" << w << "] & " << hx(m) << ");\n";
+            }
+        }
+        const uint32_t *qrec = B + B[H_OFF_QD];
+        for (uint32_t q = 0; q < B[H_NQD]; ++q) {
+            const uint32_t delta = qrec[0], pm = qrec[1];
+            for (uint32_t w = 0; w < W; ++w) {
+                bool any = false;
+                for (uint32_t t = 0; t < K; ++t)
+                    if (((pm >> t) & 1u) && qrec[2 + t * WS + w]) any = true;
+                if (!any) continue;
+                o << ind << "{\n" << ind << "    const u32 y = x[" << w << "] & " << funnel(w, delta, W) << ";\n";
+                for (uint32_t t = 0; t < K; ++t) {
+                    const uint32_t m = qrec[2 + t * WS + w];
+                    if (((pm >> t) & 1u) && m) o << ind << "    c" << t << " += __builtin_popcount(y & " << hx(m) << ");\n";
+                }
+                o << ind << "}\n";
+            }
+            qrec += qd_stride(K, WS);
+        }
+        const uint32_t *grec = B + B[H_OFF_QG];
+        for (uint32_t g = 0; g < B[H_NQG]; ++g) {
+            const uint32_t t = grec[0], m = grec[1];
+            for (uint32_t w = 0; w < W; ++w) {
+                std::string z;
+                for (uint32_t e = 0; e < m; ++e) {
+                    const uint32_t delta = grec[2 + e * qg_entry_stride(WS)];
+                    const uint32_t mk = grec[2 + e * qg_entry_stride(WS) + 1 + w];
+                    if (!mk) continue;
+                    if (!z.empty()) z += " | ";
+                    z += "(" + funnel(w, delta, W) + " & " + hx(mk) + ")";
+                }
+                if (!z.empty()) o << ind << "c" << t << " += __builtin_popcount(x[" << w << "] & (" << z << "));\n";
+            }
+            grec += 2 + m * qg_entry_stride(WS);
+        }
+        o << ind << "const u32 ph = (" << B[H_PCONST] << "u";
+        for (uint32_t t = 0; t < K; ++t) o << " + (c" << t << " << " << t << ")";
+        o << ") & " << ((1u << K) - 1u) << "u;\n";
+        const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
+        o << ind << "const u32 alpha = __builtin_amdgcn_alignbit(" << xw(aw + 1, W) << ", " << xw(aw, W) << ", "
+          << ash << "u) & " << hx(n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u) << ";\n";
+        o << ind << "const u32 bin = (alpha << " << K << ") | ph;\n";
+    };
+    const uint32_t ctag = B[H_CID];  // tag 0: Gibbs updates
+    auto from_philox = [&](std::ostringstream &o, const std::string &ind, uint32_t j) {
+        o << ind << "u32 u0, u1, u2, u3;\n"
+          << ind << "philox(s, " << j << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u0, u1, u2, u3);\n";
+    };
+    auto from_path = [](const std::string &f) {
+        return [f](uint32_t j) {
+            return "(((" + f + " >> " + std::to_string(4 * j) + ") & 15u) ^ 15u)";
+        };
+    };
 
     std::ostringstream o;
     o << PRELUDE;
-    o << "\n// circuit: n=" << n << " d=" << B[H_D] << " K=" << K << " W=" << W << " h=" << B[H_H]
-      << " id=" << B[H_CID] << "\n";
+    o << "\n// circuit: n=" << n << " d=" << B[H_D] << " K=" << K << " W=" << W << " h=" << h
+      << " id=" << B[H_CID] << (path_hist ? " (path histogram)" : "") << "\n";
     o << "static __device__ const u32 rows_init[" << out.rows_words << "] = {";
     for (size_t i = 0; i < rows.size(); ++i) o << (i % 8 ? " " : "\n    ") << hx(rows[i]) << ",";
     o << "\n};\n\n";
@@ -144,110 +239,79 @@ JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
          "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from) {\n";
     o << "    __shared__ __attribute__((aligned(16))) u32 lds_rows[" << out.rows_words << "];\n";
     if (lds_hist) o << "    __shared__ u32 lds_h[" << nbins << "];\n";
+    if (path_hist) o << "    __shared__ u32 lds_p[" << npaths << "];\n";
     o << "    for (u32 e = threadIdx.x; e < " << out.rows_words << "u; e += blockDim.x) lds_rows[e] = rows_init[e];\n";
-    if (lds_hist)
-        o << "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) lds_h[e] = 0u;\n";
+    if (lds_hist) o << "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) lds_h[e] = 0u;\n";
+    if (path_hist) o << "    for (u32 e = threadIdx.x; e < " << npaths << "u; e += blockDim.x) lds_p[e] = 0u;\n";
     o << "    __syncthreads();\n";
     o << "    const u32 gl = blockIdx.x * blockDim.x + threadIdx.x;\n"
          "    const u32 lc = gl >> lanes_log2;\n"
          "    const u32 r0 = gl & ((1u << lanes_log2) - 1u);\n"
          "    if (lc < n_chains) {\n"
          "        const u32 chain = chain_begin + lc;\n"
-         "        u32 x[" << W << "];\n"
-         "        for (u32 it = r0; it < n_sweeps; it += (1u << lanes_log2)) {\n"
-         "            const u32 s = sweep_begin + it;\n";
-    for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = " << hx(cw[w]) << ";\n";
-    const uint32_t ctag = B[H_CID];  // tag 0: Gibbs updates
-    for (uint32_t j = 0; j < nblk; ++j) {
-        const Blk &b = blks[j];
-        const uint32_t s = (uint32_t)b.sup.size();
-        if (!s) continue;  // no lattice word depends on this block's bits
-        o << "            {\n"
-             "                u32 u0, u1, u2, u3;\n"
-             "                philox(s, " << j << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u0, u1, u2, u3);\n"
-             "                const u32 p = (u0 >> 31) | ((u1 >> 30) & 2u) | ((u2 >> 29) & 4u) | ((u3 >> 28) & 8u);\n"
-             "                const u32 *r = lds_rows + " << b.off << "u + p * " << b.stride << "u;\n";
-        if (b.stride == 1) {
-            o << "                x[" << b.sup[0] << "] ^= r[0];\n";
-        } else if (b.stride == 2) {
-            o << "                const u32x2 v = *(const u32x2 *)r;\n";
-            o << "                x[" << b.sup[0] << "] ^= v.x;\n";
-            o << "                x[" << b.sup[1] << "] ^= v.y;\n";
-        } else {
-            for (uint32_t q = 0; q < b.stride / 4; ++q) {
-                o << "                const u32x4 v" << q << " = *(const u32x4 *)(r + " << 4 * q << ");\n";
-                static const char *comp[4] = {"x", "y", "z", "w"};
-                for (uint32_t e = 0; e < 4; ++e) {
-                    const uint32_t i = 4 * q + e;
-                    if (i < s) o << "                x[" << b.sup[i] << "] ^= v" << q << "." << comp[e] << ";\n";
+         "        u32 x[" << W << "];\n";
+    if (!path_hist) {
+        o << "        for (u32 it = r0; it < n_sweeps; it += (1u << lanes_log2)) {\n"
+             "            const u32 s = sweep_begin + it;\n";
+        // each block's Philox draw, then its row
+        for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = " << hx(cw[w]) << ";\n";
+        for (uint32_t j = 0; j < nblk; ++j) {
+            const Blk &b = blks[j];
+            if (b.sup.empty()) continue;
+            o << "            {\n";
+            from_philox(o, "                ", j);
+            o << "                const u32 p = (u0 >> 31) | ((u1 >> 30) & 2u) | ((u2 >> 29) & 4u) | ((u3 >> 28) & 8u);\n"
+                 "                const u32 *r = lds_rows + " << b.off << "u + p * " << b.stride << "u;\n";
+            const uint32_t sz = (uint32_t)b.sup.size();
+            if (b.stride == 1) {
+                o << "                x[" << b.sup[0] << "] ^= r[0];\n";
+            } else if (b.stride == 2) {
+                o << "                const u32x2 v = *(const u32x2 *)r;\n";
+                o << "                x[" << b.sup[0] << "] ^= v.x;\n";
+                o << "                x[" << b.sup[1] << "] ^= v.y;\n";
+            } else {
+                for (uint32_t q = 0; q < b.stride / 4; ++q) {
+                    o << "                const u32x4 v" << q << " = *(const u32x4 *)(r + " << 4 * q << ");\n";
+                    static const char *comp[4] = {"x", "y", "z", "w"};
+                    for (uint32_t e = 0; e < 4; ++e) {
+                        const uint32_t i = 4 * q + e;
+                        if (i < sz) o << "                x[" << b.sup[i] << "] ^= v" << q << "." << comp[e] << ";\n";
+                    }
                 }
             }
+            o << "            }\n";
         }
+        o << "            if (s >= bin_from) {\n";
+        emit_bin(o, "                ");
+        if (lds_hist)
+            o << "                atomicAdd(&lds_h[bin], 1u);\n";
+        else
+            o << "                atomicAdd(&hist[bin], 1u);\n";
         o << "            }\n";
-    }
-    // phase polynomial
-    o << "            if (s >= bin_from) {\n";
-    for (uint32_t t = 0; t < K; ++t) o << "                u32 c" << t << " = 0u;\n";
-    const uint32_t linmask = B[H_LINMASK];
-    const uint32_t *lin = B + B[H_OFF_LIN];
-    for (uint32_t t = 0; t < K; ++t) {
-        if (!((linmask >> t) & 1u)) continue;
-        for (uint32_t w = 0; w < W; ++w) {
-            const uint32_t m = lin[t * WS + w];
-            if (m) o << "                c" << t << " += __builtin_popcount(x[" << w << "] & " << hx(m) << ");\n";
+        o << "        }\n";
+    } else {
+        // path histogram: a sweep only draws the free bits; the count goes to
+        // the path's index (bit b = free bit b), and the lattice, phase and
+        // bin of each path that occurred are evaluated once, at the flush
+        o << "        u32 last = 0u;\n"
+             "        for (u32 it = r0; it < n_sweeps; it += (1u << lanes_log2)) {\n"
+             "            const u32 s = sweep_begin + it;\n"
+             "            u32 f = 0u;\n";
+        for (uint32_t j = 0; j < nblk; ++j) {
+            const uint32_t bits = std::min<uint32_t>(4, h - 4 * j);
+            o << "            {\n";
+            from_philox(o, "                ", j);
+            o << "                const u32 p = (u0 >> 31) | ((u1 >> 30) & 2u) | ((u2 >> 29) & 4u) | ((u3 >> 28) & 8u);\n"
+                 "                f |= ((p ^ 15u) & " << ((1u << bits) - 1u) << "u) << " << 4 * j << ";\n"
+                 "            }\n";
         }
+        o << "            if (s >= bin_from) atomicAdd(&lds_p[f], 1u);\n"
+             "            last = f;\n"
+             "        }\n";
     }
-    const uint32_t *qrec = B + B[H_OFF_QD];
-    for (uint32_t q = 0; q < B[H_NQD]; ++q) {
-        const uint32_t delta = qrec[0], pm = qrec[1];
-        for (uint32_t w = 0; w < W; ++w) {
-            bool any = false;
-            for (uint32_t t = 0; t < K; ++t)
-                if (((pm >> t) & 1u) && qrec[2 + t * WS + w]) any = true;
-            if (!any) continue;
-            o << "                {\n                    const u32 y = x[" << w << "] & " << funnel(w, delta, W)
-              << ";\n";
-            for (uint32_t t = 0; t < K; ++t) {
-                const uint32_t m = qrec[2 + t * WS + w];
-                if (((pm >> t) & 1u) && m)
-                    o << "                    c" << t << " += __builtin_popcount(y & " << hx(m) << ");\n";
-            }
-            o << "                }\n";
-        }
-        qrec += qd_stride(K, WS);
-    }
-    const uint32_t *grec = B + B[H_OFF_QG];
-    for (uint32_t g = 0; g < B[H_NQG]; ++g) {
-        const uint32_t t = grec[0], m = grec[1];
-        for (uint32_t w = 0; w < W; ++w) {
-            std::string z;
-            for (uint32_t e = 0; e < m; ++e) {
-                const uint32_t delta = grec[2 + e * qg_entry_stride(WS)];
-                const uint32_t mk = grec[2 + e * qg_entry_stride(WS) + 1 + w];
-                if (!mk) continue;
-                if (!z.empty()) z += " | ";
-                z += "(" + funnel(w, delta, W) + " & " + hx(mk) + ")";
-            }
-            if (!z.empty())
-                o << "                c" << t << " += __builtin_popcount(x[" << w << "] & (" << z << "));\n";
-        }
-        grec += 2 + m * qg_entry_stride(WS);
-    }
-    o << "                const u32 ph = (" << B[H_PCONST] << "u";
-    for (uint32_t t = 0; t < K; ++t) o << " + (c" << t << " << " << t << ")";
-    o << ") & " << ((1u << K) - 1u) << "u;\n";
-    const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
-    o << "                const u32 alpha = __builtin_amdgcn_alignbit(" << xw(aw + 1, W) << ", " << xw(aw, W) << ", "
-      << ash << "u) & " << hx(n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u) << ";\n";
-    o << "                const u32 bin = (alpha << " << K << ") | ph;\n";
-    if (lds_hist)
-        o << "                atomicAdd(&lds_h[bin], 1u);\n";
-    else
-        o << "                atomicAdd(&hist[bin], 1u);\n";
-    o << "            }\n";
-    o << "        }\n";
     // final lattice: written by the lane that ran the chain's last sweep
     o << "        if (state && n_sweeps && ((n_sweeps - 1u) & ((1u << lanes_log2) - 1u)) == r0) {\n";
+    if (path_hist) emit_build(o, "            ", from_path("last"));
     for (uint32_t w = 0; w < W; ++w)
         o << "            state[(u64)" << w << " * n_chains + lc] = x[" << w << "];\n";
     o << "        }\n";
@@ -257,6 +321,18 @@ JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
              "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) {\n"
              "        const u32 v = lds_h[e];\n"
              "        if (v) atomicAdd(&hist[e], v);\n"
+             "    }\n";
+    }
+    if (path_hist) {
+        o << "    __syncthreads();\n"
+             "    for (u32 f = threadIdx.x; f < " << npaths << "u; f += blockDim.x) {\n"
+             "        const u32 cnt = lds_p[f];\n"
+             "        if (cnt) {\n"
+             "            u32 x[" << W << "];\n";
+        emit_build(o, "            ", from_path("f"));
+        emit_bin(o, "            ");
+        o << "            atomicAdd(&hist[bin], cnt);\n"
+             "        }\n"
              "    }\n";
     }
     o << "}\n";

@@ -29,7 +29,11 @@ struct JitSource {
 // histogram of 2^(n+K) bins is privatised in LDS.  max_block (256, 512 or
 // 1024) is the largest workgroup the kernel is compiled for: 1024 threads
 // leave 128 VGPRs per lane, 512 leave 256.
-JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block);
+// With path_hist (h <= 16) a sweep only draws the free bits and counts the
+// path (bit b = free bit b) in an LDS table of 2^h words; the lattice, phase
+// and bin of every path that occurred are evaluated once per workgroup at
+// the end, so the counts are the same as binning every sample.
+JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool path_hist = false);
 
 // LDS bytes of the compacted toggle rows (without the histogram).
 size_t jit_rows_bytes(const CompiledCircuit &k);
@@ -39,6 +43,7 @@ struct JitKernel {
     hipModule_t module = nullptr;
     hipFunction_t fn = nullptr;
     bool lds_hist = false;
+    bool path_hist = false;
     uint32_t lds_bytes = 0;
     uint32_t max_block = 256;
     int scratch_bytes = 0;  // per-lane scratch of the compiled kernel (register spills)

@@ -70,12 +70,42 @@ pbit_status device_blobs(pbit_circuit c, const uint32_t **base) {
     return PBIT_OK;
 }
 
-bool runs_batched(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
+bool batchable(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
     const uint32_t nc = (uint32_t)c->circuits.size();
     const bool persistent = cfg->persistent == 1 || (cfg->persistent == 0 && nc > 1);
     const CompiledCircuit &k = c->circuits[i];
     return persistent && k.uniform && gibbs_lds_bytes(k.blob.data(), true, false) <= 64 * 1024 &&
            cfg->toggle_mode != 2;
+}
+
+// With specialize == 2 the heaviest circuits of a persistent batch (by
+// chains x free bits; every circuit runs the same sweeps) leave the batch for
+// launches of their own circuit-specialised kernel: as many as cover 90 % of
+// the batch's work, at most 64, since each costs a run-time compile.
+std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
+    const uint32_t nc = (uint32_t)c->circuits.size();
+    std::vector<bool> out(nc, false);
+    if (cfg->specialize != 2) return out;
+    std::vector<std::pair<uint64_t, uint32_t>> cand;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < nc; ++i) {
+        if (!cfg->chains[i] || !batchable(c, i, cfg)) continue;
+        const uint64_t w = (uint64_t)cfg->chains[i] * c->circuits[i].h;
+        cand.push_back({w, i});
+        total += w;
+    }
+    std::stable_sort(cand.begin(), cand.end(), [](const std::pair<uint64_t, uint32_t> &a,
+                                                  const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
+    uint64_t cum = 0;
+    for (size_t r = 0; r < cand.size() && r < 64 && (double)cum < 0.9 * (double)total; ++r) {
+        out[cand[r].second] = true;
+        cum += cand[r].first;
+    }
+    return out;
+}
+
+bool runs_batched(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg, const std::vector<bool> &spec) {
+    return batchable(c, i, cfg) && !spec[i];
 }
 
 pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
@@ -85,7 +115,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (cfg->init != PBIT_INIT_ZERO && cfg->init != PBIT_INIT_RESUME)
         return set_error(PBIT_E_INVALID_ARG, "bad init mode");
     if (cfg->init == PBIT_INIT_RESUME && !d_state) return set_error(PBIT_E_INVALID_ARG, "RESUME needs d_state");
-    if (cfg->hist_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad hist_mode");
+    if (cfg->hist_mode > 3) return set_error(PBIT_E_INVALID_ARG, "bad hist_mode");
     if (cfg->toggle_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad toggle_mode");
     if (cfg->persistent > 2) return set_error(PBIT_E_INVALID_ARG, "bad persistent mode");
     if (cfg->wg_per_cu > 16) return set_error(PBIT_E_INVALID_ARG, "wg_per_cu must be <= 16");
@@ -122,27 +152,29 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     // ---- plan (every argument error before any enqueue) --------------------
     std::vector<TuneChoice> choices(nc);
     std::vector<bool> batched(nc, false);
+    const std::vector<bool> spec = batch_specialised(c, cfg);
     for (uint32_t i = 0; i < nc; ++i) {
         if (!cfg->chains[i]) continue;
         choices[i] = tune_choice(c, i, cfg->chains[i], total, cfg);
-        batched[i] = runs_batched(c, i, cfg);
+        batched[i] = runs_batched(c, i, cfg, spec);
     }
     // circuit-specialised kernels are compiled here, before any enqueue (and
     // outside a graph capture)
     std::vector<const JitKernel *> jits(nc, nullptr);
     for (uint32_t i = 0; i < nc; ++i) {
         if (!cfg->chains[i] || batched[i] || !choices[i].jit) continue;
-        const auto key = std::make_tuple(dev, i, choices[i].lds_hist);
+        const uint32_t kind = choices[i].path_hist ? 2u : (choices[i].lds_hist ? 1u : 0u);
+        const auto key = std::make_tuple(dev, i, kind);
         auto it = c->jit.find(key);
         if (it == c->jit.end() && !c->jit_failed.count(key)) {
-            // one workgroup per CU holds the LDS histogram, so it gets 1024
+            // one workgroup per CU holds an LDS histogram, so it gets 1024
             // threads (four waves per SIMD) unless that spills registers, then
             // 512; without it, 256-thread workgroups
             std::string log;
             JitKernel jk;
             bool ok = false;
-            for (uint32_t mb : choices[i].lds_hist ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
-                const JitSource src = jit_uniform_source(c->circuits[i], choices[i].lds_hist, mb);
+            for (uint32_t mb : kind ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
+                const JitSource src = jit_uniform_source(c->circuits[i], kind == 1, mb, kind == 2);
                 if (src.lds_bytes > JIT_LDS_LIMIT) {
                     log = "LDS of the specialised kernel exceeds 160 KiB";
                     break;
@@ -154,7 +186,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                 if (jk.scratch_bytes == 0) break;
             }
             if (ok) {
-                jk.lds_hist = choices[i].lds_hist;
+                jk.lds_hist = kind == 1;
+                jk.path_hist = kind == 2;
                 it = c->jit.emplace(key, jk).first;
             } else {
                 c->jit_failed[key] = log;
@@ -212,7 +245,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         soff += (uint64_t)ch * k.W;
         if (batched[i]) {
             const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
-            const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode == 0 && hb <= bt.hist_lds_max);
+            const bool lh = cfg->hist_mode == 1 || ((cfg->hist_mode == 0 || cfg->hist_mode == 3) && hb <= bt.hist_lds_max);
             const size_t lds = gibbs_lds_bytes(k.blob.data(), true, lh);
             if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
             BatchCirc bc;
@@ -401,10 +434,10 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
     std::memset(out, 0, sizeof(*out));
     out->kernel_words = k.WS;
-    if (runs_batched(c, index, cfg)) {
+    if (runs_batched(c, index, cfg, batch_specialised(c, cfg))) {
         const BatchTuning bt = tune_batch(c, cfg);
         const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
-        const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode == 0 && hb <= bt.hist_lds_max);
+        const bool lh = cfg->hist_mode == 1 || ((cfg->hist_mode == 0 || cfg->hist_mode == 3) && hb <= bt.hist_lds_max);
         out->kernel = PBIT_KERNEL_PERSISTENT;
         out->block = 256;
         out->lds_hist = lh ? 1u : 0u;
@@ -418,8 +451,9 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
         // a specialisation that failed to build on this device is replaced
         // by the generic kernels
         int dev = 0;
+        const uint32_t kind = tc.path_hist ? 2u : (tc.lds_hist ? 1u : 0u);
         if (!c->jit_failed.empty() && hipGetDevice(&dev) == hipSuccess &&
-            c->jit_failed.count(std::make_tuple(dev, index, tc.lds_hist))) {
+            c->jit_failed.count(std::make_tuple(dev, index, kind))) {
             pbit_gibbs_cfg g = *cfg;
             g.specialize = 1;
             tc = tune_choice(c, index, cfg->chains[index], total, &g);
@@ -427,10 +461,11 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     }
     out->kernel = tc.jit ? PBIT_KERNEL_SPECIALISED : (tc.pair ? PBIT_KERNEL_TWO_LANE : PBIT_KERNEL_ONE_LANE);
     out->block = tc.block;
-    out->lds_hist = tc.lds_hist ? 1u : 0u;
+    out->lds_hist = tc.jit && tc.path_hist ? 2u : (tc.lds_hist ? 1u : 0u);
     out->toggle_tables = tc.tog ? 1u : 0u;
     out->lanes_per_chain = tc.jit ? (1u << tc.lanes_log2) : (tc.pair ? 2u : 1u);
-    out->lds_bytes = (uint32_t)(tc.jit ? jit_rows_bytes(k) + (tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0)
+    out->lds_bytes = (uint32_t)(tc.jit ? jit_rows_bytes(k) + (tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0) +
+                                             (tc.path_hist ? ((size_t)4 << k.h) : 0)
                                 : tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
                                           : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
     out->sweeps_per_launch = tc.group;
@@ -445,7 +480,9 @@ extern "C" pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, u
     if (index >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
     const CompiledCircuit &k = c->circuits[index];
     if (!k.uniform) return set_error(PBIT_E_MODE_UNAVAILABLE, "circuit has conditionals other than 1/2");
-    const JitSource src = jit_uniform_source(k, lds_hist != 0, max_block);
+    if (lds_hist > 2) return set_error(PBIT_E_INVALID_ARG, "lds_hist must be 0, 1 or 2");
+    if (lds_hist == 2 && k.h > 16) return set_error(PBIT_E_TOO_LARGE, "path counts need h <= 16");
+    const JitSource src = jit_uniform_source(k, lds_hist == 1, max_block, lds_hist == 2);
     *len = src.text.size() + 1;
     if (buf && cap) {
         const size_t m = std::min(cap - 1, src.text.size());

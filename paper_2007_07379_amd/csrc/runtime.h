@@ -65,8 +65,10 @@ struct pbit_circuit_s {
     pbit::TunedBatch tuned_batch;
     uint64_t tune_epoch = 0;
     // circuit-specialised kernels, keyed by (device, circuit, LDS histogram)
-    std::map<std::tuple<int, uint32_t, bool>, pbit::JitKernel> jit;
-    std::map<std::tuple<int, uint32_t, bool>, std::string> jit_failed;
+    // specialised kernels by (device, circuit, histogram kind: 0 global
+    // atomics, 1 LDS bins, 2 LDS path counts)
+    std::map<std::tuple<int, uint32_t, uint32_t>, pbit::JitKernel> jit;
+    std::map<std::tuple<int, uint32_t, uint32_t>, std::string> jit_failed;
     ~pbit_circuit_s();
 };
 

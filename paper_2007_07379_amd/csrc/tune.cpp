@@ -80,8 +80,17 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
         t.tog = true;
         const size_t hist_b = ((size_t)1 << (k.n + k.K)) * 4;
         const size_t rows_b = jit_rows_bytes(k);
-        t.lds_hist = cfg->hist_mode == 1 || (cfg->hist_mode == 0 && rows_b + hist_b <= LDS_MAX);
-        t.block = t.lds_hist ? 1024 : 256;
+        t.lds_hist = cfg->hist_mode == 1 || ((cfg->hist_mode == 0 || cfg->hist_mode == 3) && rows_b + hist_b <= LDS_MAX);
+        // counts per path when the paths are few next to the samples of a
+        // workgroup (at least 16 per path): a sweep then skips the lattice,
+        // phase and bin, and the histogram sees one atomic per path that
+        // occurred instead of one per sample
+        const bool path_fits = k.h <= 16 && rows_b + ((size_t)4 << k.h) <= LDS_MAX;
+        const uint64_t per_wg = (uint64_t)1024 * t.group >> t.lanes_log2;
+        t.path_hist = path_fits &&
+                      (cfg->hist_mode == 3 || (cfg->hist_mode == 0 && k.h <= 14 && per_wg >= (16ull << k.h)));
+        if (t.path_hist) t.lds_hist = false;
+        t.block = t.lds_hist || t.path_hist ? 1024 : 256;
         if (cfg->block_size) t.block = cfg->block_size;
     }
     return t;

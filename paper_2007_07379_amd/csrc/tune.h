@@ -16,6 +16,7 @@ struct TuneChoice {
     bool pair = false;        // two lanes per chain (uniform circuits)
     bool jit = false;         // circuit-specialised kernel (uniform circuits)
     uint32_t lanes_log2 = 0;  // specialised kernel: log2(lanes per chain)
+    bool path_hist = false;   // specialised kernel: LDS counts per path, binned at the end
 };
 
 // Explicit cfg fields win; unset ones come from the autotuned table of the

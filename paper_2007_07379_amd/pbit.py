@@ -238,12 +238,12 @@ class CircuitSet:
     def specialised_source(self, idx=0, lds_hist=True, max_block=None):
         """HIP source of the circuit-specialised sweep kernel of circuit idx."""
         if max_block is None:
-            max_block = 1024 if lds_hist else 256
+            max_block = 1024 if lds_hist else 256  # lds_hist: 0/False, 1/True bins, 2 path counts
         L = lib()
         L.pbit_specialised_source.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_char_p,
                                               C.c_size_t, C.POINTER(C.c_size_t)]
         n = C.c_size_t(0)
-        lh = 1 if lds_hist else 0
+        lh = int(lds_hist)
         _check(L.pbit_specialised_source(self.handle, idx, lh, max_block, None, 0, C.byref(n)))
         buf = C.create_string_buffer(n.value)
         _check(L.pbit_specialised_source(self.handle, idx, lh, max_block, buf, n.value, C.byref(n)))

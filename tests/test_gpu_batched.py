@@ -103,6 +103,25 @@ def test_persistent_groups_graph_and_grid_shapes(env):
             assert np.array_equal(h, h_ref), (kw, rep)
 
 
+def test_specialised_members_of_a_batch(env):
+    """specialize=2 takes the heaviest circuits out of the persistent launch
+    into their own circuit-specialised launches; states and counts are those
+    of the plain persistent run, bit for bit."""
+    torch, pbit = env
+    circs, chains = small_set()
+    _, st_ref, h_ref = run_set(env, circs, chains, 3, 17, persistent=1)
+    s = pbit.CircuitSet(circs)
+    kinds = [s.launch_shape(chains, 3, 17, idx=i, persistent=1, specialize=2)["kernel"] for i in range(len(circs))]
+    say("kernels", kinds)
+    assert pbit.KERNEL_SPECIALISED in kinds and pbit.KERNEL_PERSISTENT in kinds
+    for kw in [dict(persistent=1, specialize=2), dict(persistent=1, specialize=2, sweeps_per_launch=5),
+               dict(persistent=1, specialize=2, hist_mode=3)]:
+        say("batch", kw)
+        _, st, h = run_set(env, circs, chains, 3, 17, **kw)
+        assert np.array_equal(st, st_ref), kw
+        assert np.array_equal(h, h_ref), kw
+
+
 def test_autotune_cache_and_identical_results(env):
     torch, pbit = env
     circs, chains = small_set()

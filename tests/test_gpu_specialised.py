@@ -1,9 +1,10 @@
 """GPU parity of the circuit-specialised sweep kernel (generated per circuit,
 compiled at run time with hipRTC): for circuits whose conditionals are all
 1/2, final lattice words and uint32 counts equal the CPU oracle's bit for
-bit with 1, 2, 4 and 8 lanes per chain, LDS or HBM histograms, sweep groups
-that do not divide the lane count, hipGraph replay, and runs resumed across
-the generic and the specialised kernels."""
+bit with 1, 2, 4 and 8 lanes per chain, LDS or HBM histograms, path counts
+in LDS (circuits with few free bits), sweep groups that do not divide the
+lane count, hipGraph replay, and runs resumed across the generic and the
+specialised kernels."""
 import os
 import sys
 
@@ -41,6 +42,7 @@ CASES = [
     ("hchain_odd", lambda: wc.hadamard_chain(33, K=1), 300, 5, 50, 0),
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 21, 0),
     ("rasym", lambda: wc.random_asymmetric(6, 10, 3, K=3), 777, 10, 41, 5),
+    ("rct_shallow", lambda: wc.random_clifford_t(16, 4, 24, K=3), 2000, 7, 300, 11),
 ]
 
 _oracle_cache = {}
@@ -79,7 +81,11 @@ def test_specialised_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb
     sh = s.launch_shape([chains], burn, sweeps, specialize=2, lanes_per_chain=lanes)
     assert sh["kernel"] == pbit.KERNEL_SPECIALISED and sh["lanes_per_chain"] == lanes
     st_o, h_o = oracle(name, c, chains, burn, sweeps, seed, cb)
-    for hm in [0, 2]:
+    modes = [0, 2] + ([3] if s.info(0)["h"] <= 14 else [])
+    if 3 in modes:
+        assert s.launch_shape([chains], burn, sweeps, specialize=2, lanes_per_chain=lanes,
+                              hist_mode=3)["lds_hist"] == 2
+    for hm in modes:
         say("case", name, chains, burn, sweeps, cb, "lanes", lanes, "hist_mode", hm)
         st, h = run(env, s, chains, burn, sweeps, seed, cb, specialize=2, lanes_per_chain=lanes, hist_mode=hm)
         assert np.array_equal(st, st_o), hm
@@ -128,3 +134,45 @@ def test_specialised_groups_graph_and_resume(env):
         h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
         assert np.array_equal(st, st_o)
         assert np.array_equal(h, h_o)
+
+
+def test_path_counts_groups_graph_and_resume(env):
+    """Path counts in LDS with sweep groups (burn-in ending inside a group),
+    graph replay and a resume from the generic kernel."""
+    torch, pbit = env
+    c = wc.random_clifford_t(16, 4, 24, K=3)
+    chains, burn, sweeps, seed = 1500, 13, 90, 99
+    st_o, h_o = oracle("rct_shallow", c, chains, burn, sweeps, seed, 0)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    for kw in [dict(sweeps_per_launch=7, lanes_per_chain=4), dict(sweeps_per_launch=1, lanes_per_chain=1),
+               dict(sweeps_per_launch=40, lanes_per_chain=8)]:
+        say("path counts, groups", kw)
+        st, h = run(env, s, chains, burn, sweeps, seed, 0, specialize=2, hist_mode=3, **kw)
+        assert np.array_equal(st, st_o), kw
+        assert np.array_equal(h, h_o), kw
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        say("path counts, graph replay", rep)
+        hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+        state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        s.gibbs_run([chains], burn, sweeps, hist, state, seed=seed, sweeps_per_launch=25, use_graph=True,
+                    specialize=2, hist_mode=3, lanes_per_chain=2, stream=side)
+        side.synchronize()
+        st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+        h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+        assert np.array_equal(st, st_o), rep
+        assert np.array_equal(h, h_o), rep
+        _ = torch.ones(1000, device="cuda").sum().item()
+    say("path counts, resume from the generic kernel")
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([chains], burn, 30, hist, state, seed=seed, specialize=1)
+    s.gibbs_run([chains], 0, sweeps - 30, hist, state, seed=seed, sweep_offset=burn + 30, resume=True,
+                specialize=2, hist_mode=3, lanes_per_chain=4)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+    assert np.array_equal(st, st_o)
+    assert np.array_equal(h, h_o)

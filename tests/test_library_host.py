@@ -270,6 +270,18 @@ def test_launch_shape_rules(pb):
     assert m.launch_shape([100, 100], 0, 10, idx=0, persistent=2)["kernel"] != pb.KERNEL_PERSISTENT
     with pytest.raises(pb.PbitError):
         m.launch_shape([100, 100], 0, 10, idx=2)
+    # few free bits next to the samples of a workgroup: path counts in LDS
+    sc = pb.CircuitSet(wc.random_clifford_t(16, 4, 24, K=3))
+    h = sc.info(0)["h"]
+    assert h <= 14
+    sh = sc.launch_shape([4096], 100, 20000, specialize=2)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lds_hist"] == 2 and sh["block"] == 1024
+    assert sh["lds_bytes"] >= 4 << h
+    sh = sc.launch_shape([4096], 0, 2, specialize=2)  # too few samples per path
+    assert sh["lds_hist"] != 2
+    assert sc.launch_shape([4096], 0, 2, specialize=2, hist_mode=3)["lds_hist"] == 2
+    assert sc.launch_shape([4096], 100, 20000, specialize=2, hist_mode=1)["lds_hist"] == 1
+    assert sc.launch_shape([4096], 100, 20000, specialize=1, hist_mode=3)["kernel"] != pb.KERNEL_SPECIALISED
 
 
 SPEC_CIRCUITS = [
@@ -279,6 +291,7 @@ SPEC_CIRCUITS = [
     ("brick16", lambda: wc.workload_circuit("brick16")),
     ("hchain_odd", lambda: wc.hadamard_chain(33, K=1)),
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3)),
+    ("rct_shallow", lambda: wc.random_clifford_t(16, 4, 24, K=3)),
 ]
 
 
@@ -287,10 +300,13 @@ def test_specialised_source_compiles_for_gfx950(pb, name, mk, tmp_path):
     """The generated kernel of every uniform test circuit compiles offline for
     gfx950 without register spills: with the LDS histogram (where it fits) at
     1024 threads per workgroup (128 VGPRs) or else at 512 (256 VGPRs), the
-    run-time fallback; without it at 256."""
+    run-time fallback; without it at 256.  Circuits with h <= 14 also with the
+    path counts in LDS, at 1024 or 512."""
     s = pb.CircuitSet(mk())
     info = s.info(0)
     modes = [(False, (256,))] + ([(True, (1024, 512))] if info["hist_bins"] * 4 <= 128 * 1024 else [])
+    if info["h"] <= 14:
+        modes.append((2, (1024, 512)))
     for lds, blocks in modes:
         for mb in blocks:
             vg, sc = _offline_compile(s, name, lds, mb, tmp_path)
@@ -302,7 +318,7 @@ def test_specialised_source_compiles_for_gfx950(pb, name, mk, tmp_path):
 def _offline_compile(s, name, lds, mb, tmp_path):
     src = s.specialised_source(0, lds_hist=lds, max_block=mb)
     assert "pbit_uniform_sweep" in src
-    f = tmp_path / ("%s_%d_%d.hip" % (name, lds, mb))
+    f = tmp_path / ("%s_%d_%d.hip" % (name, int(lds), mb))
     f.write_text(src)
     cmd = ["/opt/rocm/bin/hipcc", "-include", "hip/hip_runtime.h", "--offload-arch=gfx950", "-O3",
            "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
