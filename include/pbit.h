@@ -136,7 +136,16 @@ typedef struct {
                                    counts: circuits on the specialised kernel whose 2^h path
                                    table (4 bytes a path) fits in LDS beside the toggle rows count
                                    each sweep's free bits in LDS and bin every path that occurred
-                                   once at the end (the same histogram); other circuits take 0 */
+                                   once at the end (the same histogram); 4 = keys: circuits on the
+                                   specialised kernel with n + K <= 22 and at most 2^24 chains
+                                   store each sample's bin
+                                   as a 32-bit key (at most 2^28 keys a launch, in a buffer the
+                                   handle holds) and a second kernel counts them through LDS,
+                                   2^15 bins at a time.  Other circuits take 0 for 3 and 4.  Auto
+                                   picks 3 for h <= 14 when each path gets >= 16 samples a
+                                   workgroup, else LDS bins when they fit, else 4 up to 2^20
+                                   bins when HBM atomics would bound the sweep (few free bits
+                                   for the histogram's size), else 2. */
     uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
     uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
     uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */
@@ -149,9 +158,9 @@ typedef struct {
                                    1 = never, 2 = always for such circuits (MODE_UNAVAILABLE if
                                    the run-time compile fails): a kernel generated for the circuit
                                    and compiled with hipRTC on first use (cached in the handle).
-                                   In a persistent batch, 2 takes the heaviest circuits (chains x
-                                   free bits; as many as cover 90 % of the work, at most 64) out of
-                                   the batch into launches of their own specialised kernels. */
+                                   In a persistent batch, 2 takes the circuits with at least 1,024
+                                   chains (at most 256, heaviest by chains x free bits first) out
+                                   of the batch into launches of their own specialised kernels. */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its
@@ -280,7 +289,8 @@ pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char 
 /* Launch shape that pbit_gibbs_run would use for circuit `index` under
  * cfg (after the handle's autotuned choices and cfg's explicit fields):
  * which kernel, threads per workgroup, histogram privatisation (lds_hist:
- * 0 global atomics, 1 bins in LDS, 2 path counts in LDS), toggle tables, the
+ * 0 global atomics, 1 bins in LDS, 2 path counts in LDS, 3 bins stored as
+ * keys and counted by a second kernel), toggle tables, the
  * kernel's lattice width in words, LDS bytes and sweeps per launch.  Host
  * only; enqueues nothing. */
 enum {
@@ -305,8 +315,9 @@ pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uin
 
 /* HIP source of the specialised sweep kernel of circuit `index` (whose
  * conditionals must all be 1/2, else MODE_UNAVAILABLE), with the histogram
- * in global memory (lds_hist 0), its bins privatised in LDS (1) or path
- * counts in LDS (2; h <= 16, else TOO_LARGE), compiled for workgroups of at most
+ * in global memory (lds_hist 0), its bins privatised in LDS (1), path counts
+ * in LDS (2; h <= 16, else TOO_LARGE) or bins stored as keys (3), compiled
+ * for workgroups of at most
  * max_block threads (256, 512 or 1024).  Copies at most cap bytes
  * (NUL-terminated) into buf; *len receives the full length + 1.  Host only,
  * for inspection and offline compile checks. */

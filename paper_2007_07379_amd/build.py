@@ -40,6 +40,7 @@ SOURCES = [
     ("made.hip", "hip"),
     ("mh.hip", "hip"),
     ("batched.hip", "hip"),
+    ("keyhist.hip", "hip"),
 ]
 
 

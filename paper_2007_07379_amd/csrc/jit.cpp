@@ -116,14 +116,15 @@ size_t jit_rows_bytes(const CompiledCircuit &k) {
     return rows.size() * sizeof(uint32_t);
 }
 
-JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool path_hist) {
+JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint32_t max_block) {
+    const bool lds_hist = hist_kind == JIT_HIST_LDS, path_hist = hist_kind == JIT_HIST_PATHS;
+    const bool keys = hist_kind == JIT_HIST_KEYS;
     const uint32_t *B = k.blob.data();
     const uint32_t W = B[H_W], WS = B[H_WS], K = B[H_K], n = B[H_N], h = B[H_H];
     const uint32_t nblk = B[H_NBLK];
     const uint32_t *cw = B + B[H_OFF_CONST];
     JitSource out;
     out.max_block = max_block;
-    if (path_hist) lds_hist = false;
 
     std::vector<Blk> blks;
     std::vector<uint32_t> rows;
@@ -285,6 +286,8 @@ JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
         emit_bin(o, "                ");
         if (lds_hist)
             o << "                atomicAdd(&lds_h[bin], 1u);\n";
+        else if (keys)
+            o << "                hist[(u64)(s - bin_from) * n_chains + lc] = bin;\n";
         else
             o << "                atomicAdd(&hist[bin], 1u);\n";
         o << "            }\n";

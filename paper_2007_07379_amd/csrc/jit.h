@@ -29,11 +29,21 @@ struct JitSource {
 // histogram of 2^(n+K) bins is privatised in LDS.  max_block (256, 512 or
 // 1024) is the largest workgroup the kernel is compiled for: 1024 threads
 // leave 128 VGPRs per lane, 512 leave 256.
-// With path_hist (h <= 16) a sweep only draws the free bits and counts the
-// path (bit b = free bit b) in an LDS table of 2^h words; the lattice, phase
-// and bin of every path that occurred are evaluated once per workgroup at
-// the end, so the counts are the same as binning every sample.
-JitSource jit_uniform_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool path_hist = false);
+// How the generated kernel bins its samples.
+enum JitHist : uint32_t {
+    JIT_HIST_GLOBAL = 0,  // atomics into the HBM histogram
+    JIT_HIST_LDS = 1,     // histogram privatised in LDS, flushed at the end
+    // a sweep only draws the free bits and counts the path (bit b = free bit
+    // b) in an LDS table of 2^h words (h <= 16); the lattice, phase and bin of
+    // every path that occurred are evaluated once per workgroup at the end,
+    // so the counts are the same as binning every sample
+    JIT_HIST_PATHS = 2,
+    // each binned sample's bin is stored as a key: the `hist` argument is then
+    // the key buffer, key (s - bin_from) * n_chains + chain for sweep s, with
+    // bin_from no earlier than the launch's first sweep (keyhist.h bins them)
+    JIT_HIST_KEYS = 3,
+};
+JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint32_t max_block);
 
 // LDS bytes of the compacted toggle rows (without the histogram).
 size_t jit_rows_bytes(const CompiledCircuit &k);
@@ -42,8 +52,7 @@ size_t jit_rows_bytes(const CompiledCircuit &k);
 struct JitKernel {
     hipModule_t module = nullptr;
     hipFunction_t fn = nullptr;
-    bool lds_hist = false;
-    bool path_hist = false;
+    uint32_t hist_kind = JIT_HIST_GLOBAL;
     uint32_t lds_bytes = 0;
     uint32_t max_block = 256;
     int scratch_bytes = 0;  // per-lane scratch of the compiled kernel (register spills)

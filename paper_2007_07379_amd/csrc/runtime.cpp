@@ -9,6 +9,7 @@
 #include "batched.h"
 #include "blob.h"
 #include "gibbs.h"
+#include "keyhist.h"
 #include "tune.h"
 
 pbit_circuit_s::~pbit_circuit_s() {
@@ -16,11 +17,18 @@ pbit_circuit_s::~pbit_circuit_s() {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
-    for (auto *m : {&blobs, &scratch, &work})
+    for (auto *m : {&blobs, &scratch, &work, &keys, &keypart})
         for (auto &kv : *m)
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     for (auto &kv : jit)
         if (kv.second.module) (void)hipModuleUnload(kv.second.module);
+    for (auto &kv : side) {
+        for (int k = 0; k < pbit::SIDE_STREAMS; ++k) {
+            if (kv.second.s[k]) (void)hipStreamDestroy(kv.second.s[k]);
+            if (kv.second.join[k]) (void)hipEventDestroy(kv.second.join[k]);
+        }
+        if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
+    }
 }
 
 namespace pbit {
@@ -28,6 +36,24 @@ namespace pbit {
 namespace {
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
+// keys of one launch of a specialised kernel that stores its bins as keys
+// (1 GiB of key buffer)
+constexpr uint64_t KEYS_MAX = 1ull << 28;
+
+pbit_status ensure_side(std::map<int, SideStreams> &m, int dev, SideStreams **out) {
+    SideStreams &ss = m[dev];
+    if (!ss.fork) {
+        for (int k = 0; k < SIDE_STREAMS; ++k) {
+            hipError_t e = hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_error(e, "side stream creation");
+        }
+        hipError_t e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_error(e, "side stream creation");
+    }
+    *out = &ss;
+    return PBIT_OK;
+}
 
 pbit_status ensure_buf(std::map<int, DevBuf> &m, int dev, size_t bytes, void **out) {
     DevBuf &b = m[dev];
@@ -78,29 +104,25 @@ bool batchable(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
            cfg->toggle_mode != 2;
 }
 
-// With specialize == 2 the heaviest circuits of a persistent batch (by
-// chains x free bits; every circuit runs the same sweeps) leave the batch for
-// launches of their own circuit-specialised kernel: as many as cover 90 % of
-// the batch's work, at most 64, since each costs a run-time compile.
+// With specialize == 2 the circuits of a persistent batch with at least
+// BATCH_SPEC_CHAINS chains leave the batch for launches of their own
+// circuit-specialised kernel (each costs a run-time compile, at most
+// BATCH_SPEC_MAX of them, the heaviest by chains x free bits first); the
+// persistent launch keeps the many small circuits.
+constexpr uint32_t BATCH_SPEC_CHAINS = 1024;
+constexpr size_t BATCH_SPEC_MAX = 256;
 std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
     const uint32_t nc = (uint32_t)c->circuits.size();
     std::vector<bool> out(nc, false);
     if (cfg->specialize != 2) return out;
     std::vector<std::pair<uint64_t, uint32_t>> cand;
-    uint64_t total = 0;
     for (uint32_t i = 0; i < nc; ++i) {
-        if (!cfg->chains[i] || !batchable(c, i, cfg)) continue;
-        const uint64_t w = (uint64_t)cfg->chains[i] * c->circuits[i].h;
-        cand.push_back({w, i});
-        total += w;
+        if (cfg->chains[i] < BATCH_SPEC_CHAINS || !batchable(c, i, cfg)) continue;
+        cand.push_back({(uint64_t)cfg->chains[i] * c->circuits[i].h, i});
     }
     std::stable_sort(cand.begin(), cand.end(), [](const std::pair<uint64_t, uint32_t> &a,
                                                   const std::pair<uint64_t, uint32_t> &b) { return a.first > b.first; });
-    uint64_t cum = 0;
-    for (size_t r = 0; r < cand.size() && r < 64 && (double)cum < 0.9 * (double)total; ++r) {
-        out[cand[r].second] = true;
-        cum += cand[r].first;
-    }
+    for (size_t r = 0; r < cand.size() && r < BATCH_SPEC_MAX; ++r) out[cand[r].second] = true;
     return out;
 }
 
@@ -115,7 +137,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (cfg->init != PBIT_INIT_ZERO && cfg->init != PBIT_INIT_RESUME)
         return set_error(PBIT_E_INVALID_ARG, "bad init mode");
     if (cfg->init == PBIT_INIT_RESUME && !d_state) return set_error(PBIT_E_INVALID_ARG, "RESUME needs d_state");
-    if (cfg->hist_mode > 3) return set_error(PBIT_E_INVALID_ARG, "bad hist_mode");
+    if (cfg->hist_mode > 4) return set_error(PBIT_E_INVALID_ARG, "bad hist_mode");
     if (cfg->toggle_mode > 2) return set_error(PBIT_E_INVALID_ARG, "bad toggle_mode");
     if (cfg->persistent > 2) return set_error(PBIT_E_INVALID_ARG, "bad persistent mode");
     if (cfg->wg_per_cu > 16) return set_error(PBIT_E_INVALID_ARG, "wg_per_cu must be <= 16");
@@ -163,7 +185,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     std::vector<const JitKernel *> jits(nc, nullptr);
     for (uint32_t i = 0; i < nc; ++i) {
         if (!cfg->chains[i] || batched[i] || !choices[i].jit) continue;
-        const uint32_t kind = choices[i].path_hist ? 2u : (choices[i].lds_hist ? 1u : 0u);
+        const uint32_t kind = jit_hist_kind(choices[i]);
         const auto key = std::make_tuple(dev, i, kind);
         auto it = c->jit.find(key);
         if (it == c->jit.end() && !c->jit_failed.count(key)) {
@@ -173,8 +195,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             std::string log;
             JitKernel jk;
             bool ok = false;
-            for (uint32_t mb : kind ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
-                const JitSource src = jit_uniform_source(c->circuits[i], kind == 1, mb, kind == 2);
+            const bool lds = kind == JIT_HIST_LDS || kind == JIT_HIST_PATHS;
+            for (uint32_t mb : lds ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
+                const JitSource src = jit_uniform_source(c->circuits[i], kind, mb);
                 if (src.lds_bytes > JIT_LDS_LIMIT) {
                     log = "LDS of the specialised kernel exceeds 160 KiB";
                     break;
@@ -186,8 +209,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                 if (jk.scratch_bytes == 0) break;
             }
             if (ok) {
-                jk.lds_hist = kind == 1;
-                jk.path_hist = kind == 2;
+                jk.hist_kind = kind;
                 it = c->jit.emplace(key, jk).first;
             } else {
                 c->jit_failed[key] = log;
@@ -209,7 +231,10 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     if (cfg->sweeps_per_launch) group = std::min<uint64_t>(cfg->sweeps_per_launch, total);
     bool multi_group = group < total;
     for (uint32_t i = 0; i < nc; ++i)
-        if (cfg->chains[i] && !batched[i] && choices[i].group < total) multi_group = true;
+        if (cfg->chains[i] && !batched[i] &&
+            (choices[i].group < total || (choices[i].jit && jits[i]->hist_kind == JIT_HIST_KEYS &&
+                                          (uint64_t)cfg->chains[i] * cfg->sweeps > KEYS_MAX)))
+            multi_group = true;
     uint32_t *state_base = d_state;
     if (!d_state && multi_group) {
         void *p = nullptr;
@@ -228,8 +253,15 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         uint32_t lanes_log2;
         uint32_t block;
         size_t lds;
+        // bins stored as keys: counted into hist_out afterwards
+        uint32_t *hist_out;
+        uint64_t keys_n;
+        uint32_t bits;
+        int lane;  // 0: the caller's stream, k > 0: side stream k - 1
     };
     std::vector<Plan> plans;
+    uint64_t keys_words = 0;
+    size_t part_bytes = 0;
     // persistent classes
     std::vector<BatchCirc> bcirc;
     std::vector<std::vector<BatchTile>> btiles(3);
@@ -245,7 +277,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         soff += (uint64_t)ch * k.W;
         if (batched[i]) {
             const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
-            const bool lh = cfg->hist_mode == 1 || ((cfg->hist_mode == 0 || cfg->hist_mode == 3) && hb <= bt.hist_lds_max);
+            const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode != 2 && hb <= bt.hist_lds_max);
             const size_t lds = gibbs_lds_bytes(k.blob.data(), true, lh);
             if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
             BatchCirc bc;
@@ -272,7 +304,15 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                                   : (tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
                                              : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
         if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
-        for (uint64_t done = 0; done < total; done += tc.group) {
+        const bool keys = tc.jit && jits[i]->hist_kind == JIT_HIST_KEYS;
+        for (uint64_t done = 0, g = 0; done < total; done += g) {
+            g = std::min<uint64_t>(tc.group, total - done);
+            const uint64_t bin0 = std::max<uint64_t>(done, cfg->burn_in);  // first binned sweep, relative
+            if (keys && done + g > bin0) {
+                // at most KEYS_MAX keys per launch
+                const uint64_t per = std::max<uint64_t>(1, KEYS_MAX / ch);
+                if (done + g - bin0 > per) g = bin0 - done + per;
+            }
             Plan p;
             std::memset(&p.a, 0, sizeof(p.a));
             p.a.blob = dblob + c->blob_off[i];
@@ -283,8 +323,20 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.a.seed_lo = (uint32_t)cfg->seed;
             p.a.seed_hi = (uint32_t)(cfg->seed >> 32);
             p.a.sweep_begin = (uint32_t)(cfg->sweep_offset + done);
-            p.a.n_sweeps = (uint32_t)std::min<uint64_t>(tc.group, total - done);
+            p.a.n_sweeps = (uint32_t)g;
             p.a.bin_from = cfg->sweep_offset + cfg->burn_in;
+            p.hist_out = nullptr;
+            p.keys_n = 0;
+            p.bits = k.n + k.K;
+            if (keys) {
+                // the kernel indexes keys from its first binned sweep
+                p.a.bin_from = (uint32_t)(cfg->sweep_offset + bin0);
+                p.hist_out = p.a.hist;
+                p.a.hist = nullptr;  // the key buffer, set below
+                p.keys_n = done + g > bin0 ? (uint64_t)ch * (done + g - bin0) : 0;
+                keys_words = std::max(keys_words, p.keys_n);
+                part_bytes = std::max(part_bytes, keyhist_shape(p.keys_n, p.bits).part_bytes);
+            }
             p.a.resume = done > 0 ? 1u : (cfg->init == PBIT_INIT_RESUME ? 1u : 0u);
             p.a.lds_hist = tc.lds_hist ? 1u : 0u;
             p.Wk = k.WS;
@@ -295,8 +347,64 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.lanes_log2 = tc.lanes_log2;
             p.block = tc.jit ? std::min<uint32_t>(tc.block, jits[i]->max_block) : tc.block;
             p.lds = lds;
+            p.lane = 0;
             plans.push_back(p);
         }
+    }
+    // Independent circuits run concurrently: launches that share the key
+    // buffer stay on the caller's stream, every other circuit's launches
+    // (and the persistent launch) go, whole, to the side stream with the
+    // least work so far, so small launches that leave CUs idle overlap.
+    int batched_lane = 0;
+    bool fork = false;
+    {
+        std::vector<uint32_t> units;  // circuits with launches of their own
+        for (const Plan &p : plans)
+            if (units.empty() || units.back() != (uint32_t)(p.a.blob - dblob)) units.push_back((uint32_t)(p.a.blob - dblob));
+        fork = units.size() + (bcirc.empty() ? 0 : 1) > 1;
+        if (fork) {
+            double load[SIDE_STREAMS] = {0.0, 0.0, 0.0};
+            auto pick = [&](double w) {
+                int best = 0;
+                for (int k = 1; k < SIDE_STREAMS; ++k)
+                    if (load[k] < load[best]) best = k;
+                load[best] += w;
+                return best + 1;
+            };
+            if (!bcirc.empty()) {
+                double w = 0.0;
+                for (uint32_t i = 0; i < nc; ++i)
+                    if (batched[i] && cfg->chains[i]) w += (double)cfg->chains[i] * c->circuits[i].h;
+                batched_lane = pick(w);
+            }
+            int lane = 0;
+            const uint32_t *prev = nullptr;
+            for (Plan &p : plans) {
+                if (p.a.blob != prev) {
+                    prev = p.a.blob;
+                    lane = 0;
+                    if (!p.hist_out) {
+                        const uint32_t i = (uint32_t)std::distance(
+                            c->blob_off.begin(),
+                            std::find(c->blob_off.begin(), c->blob_off.end(), (uint64_t)(p.a.blob - dblob)));
+                        lane = pick((double)cfg->chains[i] * c->circuits[i].h);
+                    }
+                }
+                p.lane = lane;
+            }
+        }
+    }
+    SideStreams *side = nullptr;
+    if (fork && (st = ensure_side(c->side, dev, &side)) != PBIT_OK) return st;
+
+    // key buffer and partial rows of the key histogram (shared by the plans,
+    // which run in stream order)
+    void *d_keys = nullptr, *d_part = nullptr;
+    if (keys_words) {
+        if ((st = ensure_buf(c->keys, dev, keys_words * sizeof(uint32_t), &d_keys)) != PBIT_OK) return st;
+        if ((st = ensure_buf(c->keypart, dev, part_bytes, &d_part)) != PBIT_OK) return st;
+        for (Plan &p : plans)
+            if (p.hist_out) p.a.hist = (uint32_t *)d_keys;
     }
     // tiles in decreasing cost order (longest first), 256 chains each
     uint32_t tiles_total = 0;
@@ -348,14 +456,21 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
-    auto enqueue = [&]() -> pbit_status {
+    auto lane_stream = [&](int lane) { return lane == 0 ? stream : side->s[lane - 1]; };
+    auto enqueue_work = [&]() -> pbit_status {
         for (const Plan &p : plans) {
-            hipError_t le = p.jit ? jit_launch(*p.jit, p.a, p.lanes_log2, p.block, stream)
-                            : p.pair ? launch_gibbs_pair(p.Wk, p.a, p.block, p.lds, stream)
-                                     : launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, stream);
+            const hipStream_t ps = lane_stream(p.lane);
+            hipError_t le = p.jit ? jit_launch(*p.jit, p.a, p.lanes_log2, p.block, ps)
+                            : p.pair ? launch_gibbs_pair(p.Wk, p.a, p.block, p.lds, ps)
+                                     : launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, ps);
             if (le != hipSuccess) return hip_error(le, "gibbs kernel launch");
+            if (p.hist_out && p.keys_n) {
+                le = launch_keyhist(p.a.hist, p.keys_n, p.bits, (uint32_t *)d_part, p.hist_out, ps);
+                if (le != hipSuccess) return hip_error(le, "key histogram launch");
+            }
         }
         if (bcirc.empty()) return PBIT_OK;
+        const hipStream_t bs = lane_stream(batched_lane);
         for (uint64_t done = 0; done < total; done += group) {
             for (int cls = 0; cls < 3; ++cls) {
                 if (btiles[cls].empty()) continue;
@@ -375,10 +490,26 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                 uint32_t wg = cfg->wg_per_cu ? cfg->wg_per_cu : bt.wg_per_cu[cls];
                 if (blds[cls]) wg = std::min<uint32_t>(wg, std::max<uint32_t>(1, (uint32_t)(LDS_LIMIT / blds[cls])));
                 const uint32_t grid = std::min<uint32_t>(a.ntiles, (uint32_t)cus * std::max<uint32_t>(wg, 1));
-                hipError_t le = launch_batched(cls, a, grid, blds[cls], stream);
+                hipError_t le = launch_batched(cls, a, grid, blds[cls], bs);
                 if (le != hipSuccess) return hip_error(le, "batched kernel launch");
             }
         }
+        return PBIT_OK;
+    };
+    // fork the side streams from the caller's stream, enqueue, join them back
+    // (also after an error, so no side stream is left behind a capture)
+    auto enqueue = [&]() -> pbit_status {
+        if (!fork) return enqueue_work();
+        hipError_t fe = hipEventRecord(side->fork, stream);
+        for (int k = 0; k < SIDE_STREAMS && fe == hipSuccess; ++k) fe = hipStreamWaitEvent(side->s[k], side->fork, 0);
+        if (fe != hipSuccess) return hip_error(fe, "side stream fork");
+        const pbit_status ws = enqueue_work();
+        for (int k = 0; k < SIDE_STREAMS && fe == hipSuccess; ++k) {
+            fe = hipEventRecord(side->join[k], side->s[k]);
+            if (fe == hipSuccess) fe = hipStreamWaitEvent(stream, side->join[k], 0);
+        }
+        if (ws != PBIT_OK) return ws;
+        if (fe != hipSuccess) return hip_error(fe, "side stream join");
         return PBIT_OK;
     };
 
@@ -387,7 +518,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     // graph replay keyed by everything that shapes the captured launches
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)stream, (uint64_t)(uintptr_t)d_state,
                                  (uint64_t)(uintptr_t)d_hist, (uint64_t)(uintptr_t)state_base,
-                                 (uint64_t)(uintptr_t)d_bcirc, cfg->chain_begin, cfg->burn_in, cfg->sweeps,
+                                 (uint64_t)(uintptr_t)d_bcirc, (uint64_t)(uintptr_t)d_keys,
+                                 (uint64_t)(uintptr_t)d_part, cfg->chain_begin, cfg->burn_in, cfg->sweeps,
                                  cfg->seed, cfg->sweep_offset, cfg->init, cfg->sweeps_per_launch, cfg->block_size,
                                  cfg->hist_mode, cfg->toggle_mode, cfg->persistent, cfg->wg_per_cu,
                                  cfg->lanes_per_chain, cfg->specialize, c->tune_epoch};
@@ -437,7 +569,7 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     if (runs_batched(c, index, cfg, batch_specialised(c, cfg))) {
         const BatchTuning bt = tune_batch(c, cfg);
         const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
-        const bool lh = cfg->hist_mode == 1 || ((cfg->hist_mode == 0 || cfg->hist_mode == 3) && hb <= bt.hist_lds_max);
+        const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode != 2 && hb <= bt.hist_lds_max);
         out->kernel = PBIT_KERNEL_PERSISTENT;
         out->block = 256;
         out->lds_hist = lh ? 1u : 0u;
@@ -451,7 +583,7 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
         // a specialisation that failed to build on this device is replaced
         // by the generic kernels
         int dev = 0;
-        const uint32_t kind = tc.path_hist ? 2u : (tc.lds_hist ? 1u : 0u);
+        const uint32_t kind = jit_hist_kind(tc);
         if (!c->jit_failed.empty() && hipGetDevice(&dev) == hipSuccess &&
             c->jit_failed.count(std::make_tuple(dev, index, kind))) {
             pbit_gibbs_cfg g = *cfg;
@@ -461,7 +593,7 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     }
     out->kernel = tc.jit ? PBIT_KERNEL_SPECIALISED : (tc.pair ? PBIT_KERNEL_TWO_LANE : PBIT_KERNEL_ONE_LANE);
     out->block = tc.block;
-    out->lds_hist = tc.jit && tc.path_hist ? 2u : (tc.lds_hist ? 1u : 0u);
+    out->lds_hist = tc.jit ? jit_hist_kind(tc) : (tc.lds_hist ? 1u : 0u);
     out->toggle_tables = tc.tog ? 1u : 0u;
     out->lanes_per_chain = tc.jit ? (1u << tc.lanes_log2) : (tc.pair ? 2u : 1u);
     out->lds_bytes = (uint32_t)(tc.jit ? jit_rows_bytes(k) + (tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0) +
@@ -480,9 +612,9 @@ extern "C" pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, u
     if (index >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
     const CompiledCircuit &k = c->circuits[index];
     if (!k.uniform) return set_error(PBIT_E_MODE_UNAVAILABLE, "circuit has conditionals other than 1/2");
-    if (lds_hist > 2) return set_error(PBIT_E_INVALID_ARG, "lds_hist must be 0, 1 or 2");
-    if (lds_hist == 2 && k.h > 16) return set_error(PBIT_E_TOO_LARGE, "path counts need h <= 16");
-    const JitSource src = jit_uniform_source(k, lds_hist == 1, max_block, lds_hist == 2);
+    if (lds_hist > 3) return set_error(PBIT_E_INVALID_ARG, "lds_hist must be 0, 1, 2 or 3");
+    if (lds_hist == JIT_HIST_PATHS && k.h > 16) return set_error(PBIT_E_TOO_LARGE, "path counts need h <= 16");
+    const JitSource src = jit_uniform_source(k, lds_hist, max_block);
     *len = src.text.size() + 1;
     if (buf && cap) {
         const size_t m = std::min(cap - 1, src.text.size());

@@ -23,6 +23,16 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Streams beside the caller's on which independent circuits of one run are
+// enqueued, forked from and joined back to the caller's stream with events
+// (default priority, non-blocking).
+constexpr int SIDE_STREAMS = 3;
+struct SideStreams {
+    hipStream_t s[SIDE_STREAMS] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[SIDE_STREAMS] = {nullptr, nullptr, nullptr};
+};
+
 // Autotuned shape of one circuit's single-circuit launches.
 struct TunedSingle {
     uint32_t block = 256;
@@ -64,9 +74,11 @@ struct pbit_circuit_s {
     bool tuned_batch_valid = false;
     pbit::TunedBatch tuned_batch;
     uint64_t tune_epoch = 0;
-    // circuit-specialised kernels, keyed by (device, circuit, LDS histogram)
-    // specialised kernels by (device, circuit, histogram kind: 0 global
-    // atomics, 1 LDS bins, 2 LDS path counts)
+    // key buffer and partial rows of the key histogram
+    std::map<int, pbit::DevBuf> keys;
+    std::map<int, pbit::DevBuf> keypart;
+    std::map<int, pbit::SideStreams> side;
+    // circuit-specialised kernels by (device, circuit, histogram kind JitHist)
     std::map<std::tuple<int, uint32_t, uint32_t>, pbit::JitKernel> jit;
     std::map<std::tuple<int, uint32_t, uint32_t>, std::string> jit_failed;
     ~pbit_circuit_s();

@@ -7,6 +7,7 @@
 #include "blob.h"
 #include "gibbs.h"
 #include "jit.h"
+#include "keyhist.h"
 
 namespace pbit {
 
@@ -80,16 +81,37 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
         t.tog = true;
         const size_t hist_b = ((size_t)1 << (k.n + k.K)) * 4;
         const size_t rows_b = jit_rows_bytes(k);
-        t.lds_hist = cfg->hist_mode == 1 || ((cfg->hist_mode == 0 || cfg->hist_mode == 3) && rows_b + hist_b <= LDS_MAX);
-        // counts per path when the paths are few next to the samples of a
-        // workgroup (at least 16 per path): a sweep then skips the lattice,
-        // phase and bin, and the histogram sees one atomic per path that
-        // occurred instead of one per sample
+        const bool lds_fits = rows_b + hist_b <= LDS_MAX;
         const bool path_fits = k.h <= 16 && rows_b + ((size_t)4 << k.h) <= LDS_MAX;
+        const uint32_t bits = k.n + k.K;
+        const bool keys_ok = bits <= KEYHIST_MAX_BITS && chains <= (1u << 24);
         const uint64_t per_wg = (uint64_t)1024 * t.group >> t.lanes_log2;
-        t.path_hist = path_fits &&
-                      (cfg->hist_mode == 3 || (cfg->hist_mode == 0 && k.h <= 14 && per_wg >= (16ull << k.h)));
-        if (t.path_hist) t.lds_hist = false;
+        // Keys pay when HBM atomics would bound the sweep: the chip retires
+        // about 27e9 of them a second when the bins are spread (fewer when
+        // they are not), i.e. 37 ps a sample, while a sample costs about
+        // (34 + 6) lane-ops per Philox block and 8 per lattice word at 39.3e12
+        // lane-ops/s, plus about 0.6 ps of key histogram per 2^15-bin bucket.
+        const double ps_sample = (40.0 * ((k.h + 3) / 4) + 8.0 * k.W) / 39.3;
+        const double ps_keys = 0.6 * (double)(1u << (bits > 15 ? bits - 15 : 0));
+        const bool keys_pay = bits <= 20 && ps_sample + ps_keys < 37.0;
+        // automatic choice, in this order: counts per path when the paths are
+        // few next to the samples of a workgroup (at least 16 per path: a
+        // sweep then skips the lattice, phase and bin, and the histogram sees
+        // one atomic per path that occurred); the histogram in LDS when it
+        // fits; bins stored as keys when that pays; else HBM atomics
+        t.lds_hist = t.path_hist = t.keys = false;
+        if (k.h <= 14 && path_fits && per_wg >= (16ull << k.h))
+            t.path_hist = true;
+        else if (lds_fits)
+            t.lds_hist = true;
+        else if (keys_ok && keys_pay)
+            t.keys = true;
+        if (cfg->hist_mode == 1 || cfg->hist_mode == 2 || (cfg->hist_mode == 3 && path_fits) ||
+            (cfg->hist_mode == 4 && keys_ok)) {
+            t.lds_hist = cfg->hist_mode == 1;
+            t.path_hist = cfg->hist_mode == 3;
+            t.keys = cfg->hist_mode == 4;
+        }
         t.block = t.lds_hist || t.path_hist ? 1024 : 256;
         if (cfg->block_size) t.block = cfg->block_size;
     }

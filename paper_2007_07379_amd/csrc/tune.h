@@ -17,7 +17,13 @@ struct TuneChoice {
     bool jit = false;         // circuit-specialised kernel (uniform circuits)
     uint32_t lanes_log2 = 0;  // specialised kernel: log2(lanes per chain)
     bool path_hist = false;   // specialised kernel: LDS counts per path, binned at the end
+    bool keys = false;        // specialised kernel: bins stored as keys, counted by the key histogram
 };
+
+// Histogram kind of the specialised kernel (JitHist in jit.h).
+inline uint32_t jit_hist_kind(const TuneChoice &t) {
+    return t.path_hist ? 2u : (t.keys ? 3u : (t.lds_hist ? 1u : 0u));
+}
 
 // Explicit cfg fields win; unset ones come from the autotuned table of the
 // handle (if pbit_autotune ran or loaded a cache) or from the static rules.

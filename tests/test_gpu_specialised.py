@@ -2,9 +2,9 @@
 compiled at run time with hipRTC): for circuits whose conditionals are all
 1/2, final lattice words and uint32 counts equal the CPU oracle's bit for
 bit with 1, 2, 4 and 8 lanes per chain, LDS or HBM histograms, path counts
-in LDS (circuits with few free bits), sweep groups that do not divide the
-lane count, hipGraph replay, and runs resumed across the generic and the
-specialised kernels."""
+in LDS (circuits with few free bits), bins stored as keys and counted by the
+key histogram, sweep groups that do not divide the lane count, hipGraph
+replay, and runs resumed across the generic and the specialised kernels."""
 import os
 import sys
 
@@ -81,7 +81,8 @@ def test_specialised_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb
     sh = s.launch_shape([chains], burn, sweeps, specialize=2, lanes_per_chain=lanes)
     assert sh["kernel"] == pbit.KERNEL_SPECIALISED and sh["lanes_per_chain"] == lanes
     st_o, h_o = oracle(name, c, chains, burn, sweeps, seed, cb)
-    modes = [0, 2] + ([3] if s.info(0)["h"] <= 14 else [])
+    info = s.info(0)
+    modes = [0, 2] + ([3] if info["h"] <= 14 else []) + ([4] if info["n"] + info["K"] <= 22 else [])
     if 3 in modes:
         assert s.launch_shape([chains], burn, sweeps, specialize=2, lanes_per_chain=lanes,
                               hist_mode=3)["lds_hist"] == 2
@@ -176,3 +177,70 @@ def test_path_counts_groups_graph_and_resume(env):
     h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
     assert np.array_equal(st, st_o)
     assert np.array_equal(h, h_o)
+
+
+def test_keys_groups_graph_and_resume(env):
+    """Bins stored as keys (n + K = 19: 16 buckets of 2^15 bins) with sweep
+    groups, burn-in ending inside a group, graph replay and a resume."""
+    torch, pbit = env
+    c = wc.workload_circuit("brick16")
+    chains, burn, sweeps, seed = 600, 11, 37, 5
+    st_o, h_o = oracle("brick16", c, chains, burn, sweeps, seed, 0)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    assert s.launch_shape([chains], burn, sweeps, specialize=2, hist_mode=4)["lds_hist"] == 3
+    for kw in [dict(sweeps_per_launch=7, lanes_per_chain=4), dict(sweeps_per_launch=1, lanes_per_chain=1),
+               dict(lanes_per_chain=8)]:
+        say("keys, groups", kw)
+        st, h = run(env, s, chains, burn, sweeps, seed, 0, specialize=2, hist_mode=4, **kw)
+        assert np.array_equal(st, st_o), kw
+        assert np.array_equal(h, h_o), kw
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        say("keys, graph replay", rep)
+        hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+        state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        s.gibbs_run([chains], burn, sweeps, hist, state, seed=seed, sweeps_per_launch=9, use_graph=True,
+                    specialize=2, hist_mode=4, lanes_per_chain=2, stream=side)
+        side.synchronize()
+        st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+        h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+        assert np.array_equal(st, st_o), rep
+        assert np.array_equal(h, h_o), rep
+        _ = torch.ones(1000, device="cuda").sum().item()
+    say("keys, resume from the generic kernel")
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([chains], burn, 20, hist, state, seed=seed, specialize=1)
+    s.gibbs_run([chains], 0, sweeps - 20, hist, state, seed=seed, sweep_offset=burn + 20, resume=True,
+                specialize=2, hist_mode=4)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+    assert np.array_equal(st, st_o)
+    assert np.array_equal(h, h_o)
+
+
+def test_keys_split_over_launches_at_full_size(env):
+    """131,072 chains x 2,100 binned sweeps store more than the 2^28 keys one
+    launch holds, so the run is split; states and counts equal those of HBM
+    atomics (bit-exact against the oracle in the cases above), and chains
+    sampled from the run replay exactly on the oracle."""
+    torch, pbit = env
+    c = wc.workload_circuit("brick16")
+    chains, burn, sweeps, seed = 131072, 100, 2100, 17
+    s = pbit.CircuitSet(c)
+    assert chains * sweeps > (1 << 28)
+    res = {}
+    for hm in [2, 4]:
+        say("brick16 full, hist_mode", hm)
+        res[hm] = run(env, s, chains, burn, sweeps, seed, 0, specialize=2, hist_mode=hm)
+    assert np.array_equal(res[2][0], res[4][0])
+    assert np.array_equal(res[2][1], res[4][1])
+    assert int(res[4][1].sum()) == chains * sweeps
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    for ch in [0, 77777, chains - 1]:
+        say("oracle replay of chain", ch)
+        st_o, _ = och.gibbs(comp, 1, burn, sweeps, seed=seed, chain_begin=ch, threads=1)
+        assert np.array_equal(res[4][0][ch], st_o[0]), ch

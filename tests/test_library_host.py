@@ -282,6 +282,22 @@ def test_launch_shape_rules(pb):
     assert sc.launch_shape([4096], 0, 2, specialize=2, hist_mode=3)["lds_hist"] == 2
     assert sc.launch_shape([4096], 100, 20000, specialize=2, hist_mode=1)["lds_hist"] == 1
     assert sc.launch_shape([4096], 100, 20000, specialize=1, hist_mode=3)["kernel"] != pb.KERNEL_SPECIALISED
+    # histograms beyond LDS, up to 2^20 bins, and sweeps short enough that
+    # HBM atomics would bound them: bins stored as keys
+    sw = pb.CircuitSet(wc.random_clifford_t(16, 17, 500, K=3))
+    assert sw.info(0)["h"] <= 60
+    sh = sw.launch_shape([122112], 200, 2000)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lds_hist"] == 3 and sh["block"] == 256
+    assert sw.launch_shape([122112], 200, 2000, hist_mode=2)["lds_hist"] == 0
+    # long sweeps (h = 102) hide the atomics
+    b16 = pb.CircuitSet(wc.workload_circuit("brick16"))
+    sh = b16.launch_shape([131072], 200, 2000)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lds_hist"] == 0
+    assert b16.launch_shape([131072], 200, 2000, hist_mode=4)["lds_hist"] == 3
+    assert s.launch_shape([65536], 200, 10000, hist_mode=4)["lds_hist"] == 3  # rct12, forced
+    b20 = pb.CircuitSet(wc.workload_circuit("brick20"))
+    assert b20.launch_shape([262144], 200, 2000)["lds_hist"] == 0  # 2^24 bins: HBM atomics
+    assert b20.launch_shape([262144], 200, 2000, hist_mode=4)["lds_hist"] == 0  # beyond the key histogram
 
 
 SPEC_CIRCUITS = [
@@ -307,6 +323,7 @@ def test_specialised_source_compiles_for_gfx950(pb, name, mk, tmp_path):
     modes = [(False, (256,))] + ([(True, (1024, 512))] if info["hist_bins"] * 4 <= 128 * 1024 else [])
     if info["h"] <= 14:
         modes.append((2, (1024, 512)))
+    modes.append((3, (256,)))
     for lds, blocks in modes:
         for mb in blocks:
             vg, sc = _offline_compile(s, name, lds, mb, tmp_path)
