@@ -442,8 +442,8 @@ def batch_mode(args):
         "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tslot-op/s", "frac": ops / kernel_s / VALU_PEAK, "traffic": None,
                      "kernel": ("batched_kernel (width classes)" if not n_spec else
-                                "pbit_uniform_sweep for the %d circuits with >= 1024 chains + batched_kernel for "
-                                "the rest" % n_spec),
+                                "pbit_uniform_sweep for %d circuits on launches of their own + batched_kernel "
+                                "for the rest" % n_spec),
                      "kernel_ms": kernel_s * 1e3},
         "warmup_s": t_warm,
     }

@@ -160,7 +160,8 @@ typedef struct {
                                    and compiled with hipRTC on first use (cached in the handle).
                                    In a persistent batch, 2 takes the circuits with at least 1,024
                                    chains (at most 256, heaviest by chains x free bits first) out
-                                   of the batch into launches of their own specialised kernels. */
+                                   of the batch into launches of their own specialised kernels;
+                                   0 takes those among them with 2^33 updates or more. */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its

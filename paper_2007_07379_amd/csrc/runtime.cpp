@@ -108,16 +108,20 @@ bool batchable(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
 // BATCH_SPEC_CHAINS chains leave the batch for launches of their own
 // circuit-specialised kernel (each costs a run-time compile, at most
 // BATCH_SPEC_MAX of them, the heaviest by chains x free bits first); the
-// persistent launch keeps the many small circuits.
+// persistent launch keeps the many small circuits.  With specialize == 0
+// (auto) only those whose run alone pays for the compile (2^33 updates or
+// more, the single-circuit rule) leave.
 constexpr uint32_t BATCH_SPEC_CHAINS = 1024;
 constexpr size_t BATCH_SPEC_MAX = 256;
 std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
     const uint32_t nc = (uint32_t)c->circuits.size();
     std::vector<bool> out(nc, false);
-    if (cfg->specialize != 2) return out;
+    if (cfg->specialize == 1 || (cfg->specialize == 0 && cfg->toggle_mode != 0)) return out;
+    const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
     std::vector<std::pair<uint64_t, uint32_t>> cand;
     for (uint32_t i = 0; i < nc; ++i) {
         if (cfg->chains[i] < BATCH_SPEC_CHAINS || !batchable(c, i, cfg)) continue;
+        if (cfg->specialize == 0 && (uint64_t)cfg->chains[i] * total * c->circuits[i].h < (1ull << 33)) continue;
         cand.push_back({(uint64_t)cfg->chains[i] * c->circuits[i].h, i});
     }
     std::stable_sort(cand.begin(), cand.end(), [](const std::pair<uint64_t, uint32_t> &a,
@@ -257,7 +261,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         uint32_t *hist_out;
         uint64_t keys_n;
         uint32_t bits;
-        int lane;  // 0: the caller's stream, k > 0: side stream k - 1
+        uint32_t *part;  // partial rows of the key histogram
+        uint32_t circ;
+        int lane;        // 0: the caller's stream, k > 0: side stream k - 1
     };
     std::vector<Plan> plans;
     uint64_t keys_words = 0;
@@ -348,63 +354,65 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             p.block = tc.jit ? std::min<uint32_t>(tc.block, jits[i]->max_block) : tc.block;
             p.lds = lds;
             p.lane = 0;
+            p.part = nullptr;
+            p.circ = i;
             plans.push_back(p);
         }
     }
-    // Independent circuits run concurrently: launches that share the key
-    // buffer stay on the caller's stream, every other circuit's launches
-    // (and the persistent launch) go, whole, to the side stream with the
-    // least work so far, so small launches that leave CUs idle overlap.
+    // Independent circuits run concurrently: each circuit's launches go,
+    // whole and in order, to one of the caller's stream and the side
+    // streams, the heaviest circuit first to the stream with the least work
+    // so far (the persistent launch counts as one circuit), so small launches
+    // that leave CUs idle overlap, and key histograms (bound by HBM) overlap
+    // sweeps (bound by the VALU).  Each stream has its own key buffer.
+    constexpr int LANES = 1 + SIDE_STREAMS;
     int batched_lane = 0;
     bool fork = false;
     {
-        std::vector<uint32_t> units;  // circuits with launches of their own
-        for (const Plan &p : plans)
-            if (units.empty() || units.back() != (uint32_t)(p.a.blob - dblob)) units.push_back((uint32_t)(p.a.blob - dblob));
+        std::vector<std::pair<double, uint32_t>> units;  // (work, circuit) of circuits with launches of their own
+        std::vector<int> lane_of(nc, 0);
+        for (uint32_t i = 0; i < nc; ++i)
+            if (cfg->chains[i] && !batched[i]) units.push_back({(double)cfg->chains[i] * (c->circuits[i].h + 1), i});
         fork = units.size() + (bcirc.empty() ? 0 : 1) > 1;
         if (fork) {
-            double load[SIDE_STREAMS] = {0.0, 0.0, 0.0};
+            double load[LANES] = {0.0, 0.0, 0.0, 0.0};
             auto pick = [&](double w) {
                 int best = 0;
-                for (int k = 1; k < SIDE_STREAMS; ++k)
+                for (int k = 1; k < LANES; ++k)
                     if (load[k] < load[best]) best = k;
                 load[best] += w;
-                return best + 1;
+                return best;
             };
             if (!bcirc.empty()) {
                 double w = 0.0;
                 for (uint32_t i = 0; i < nc; ++i)
-                    if (batched[i] && cfg->chains[i]) w += (double)cfg->chains[i] * c->circuits[i].h;
+                    if (batched[i] && cfg->chains[i]) w += (double)cfg->chains[i] * (c->circuits[i].h + 1);
                 batched_lane = pick(w);
             }
-            int lane = 0;
-            const uint32_t *prev = nullptr;
-            for (Plan &p : plans) {
-                if (p.a.blob != prev) {
-                    prev = p.a.blob;
-                    lane = 0;
-                    if (!p.hist_out) {
-                        const uint32_t i = (uint32_t)std::distance(
-                            c->blob_off.begin(),
-                            std::find(c->blob_off.begin(), c->blob_off.end(), (uint64_t)(p.a.blob - dblob)));
-                        lane = pick((double)cfg->chains[i] * c->circuits[i].h);
-                    }
-                }
-                p.lane = lane;
-            }
+            std::stable_sort(units.begin(), units.end(),
+                             [](const std::pair<double, uint32_t> &a, const std::pair<double, uint32_t> &b) {
+                                 return a.first > b.first;
+                             });
+            for (const auto &u : units) lane_of[u.second] = pick(u.first);
+            for (Plan &p : plans) p.lane = lane_of[p.circ];
         }
     }
     SideStreams *side = nullptr;
     if (fork && (st = ensure_side(c->side, dev, &side)) != PBIT_OK) return st;
 
-    // key buffer and partial rows of the key histogram (shared by the plans,
-    // which run in stream order)
+    // key buffers and partial rows of the key histogram, one of each per
+    // stream (the plans of one stream run in order)
     void *d_keys = nullptr, *d_part = nullptr;
+    const size_t part_stride = (part_bytes + 255) & ~(size_t)255;
     if (keys_words) {
-        if ((st = ensure_buf(c->keys, dev, keys_words * sizeof(uint32_t), &d_keys)) != PBIT_OK) return st;
-        if ((st = ensure_buf(c->keypart, dev, part_bytes, &d_part)) != PBIT_OK) return st;
+        const int nl = fork ? LANES : 1;
+        if ((st = ensure_buf(c->keys, dev, keys_words * sizeof(uint32_t) * nl, &d_keys)) != PBIT_OK) return st;
+        if ((st = ensure_buf(c->keypart, dev, part_stride * nl, &d_part)) != PBIT_OK) return st;
         for (Plan &p : plans)
-            if (p.hist_out) p.a.hist = (uint32_t *)d_keys;
+            if (p.hist_out) {
+                p.a.hist = (uint32_t *)d_keys + keys_words * p.lane;
+                p.part = (uint32_t *)((unsigned char *)d_part + part_stride * p.lane);
+            }
     }
     // tiles in decreasing cost order (longest first), 256 chains each
     uint32_t tiles_total = 0;
@@ -465,7 +473,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                                      : launch_gibbs(p.Wk, p.uniform, p.tog, p.a, p.block, p.lds, ps);
             if (le != hipSuccess) return hip_error(le, "gibbs kernel launch");
             if (p.hist_out && p.keys_n) {
-                le = launch_keyhist(p.a.hist, p.keys_n, p.bits, (uint32_t *)d_part, p.hist_out, ps);
+                le = launch_keyhist(p.a.hist, p.keys_n, p.bits, p.part, p.hist_out, ps);
                 if (le != hipSuccess) return hip_error(le, "key histogram launch");
             }
         }

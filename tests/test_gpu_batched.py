@@ -148,11 +148,14 @@ def test_autotune_cache_and_identical_results(env):
         assert np.array_equal(hist.cpu().numpy().view(np.uint32), h_ref)
 
 
-def test_full_batch256(env):
+@pytest.mark.parametrize("specialize", [1, 0])
+def test_full_batch256(env, specialize):
     """256 random Clifford+T circuits (n 4..16, d 4..32), 2^22 chains in
-    total, 200 + 2000 sweeps in one persistent launch per width class:
-    pooled 4-sigma rule over every amplitude of every circuit, TV_path per
-    circuit, and sampled chains replayed by the oracle."""
+    total, 200 + 2000 sweeps: in one persistent launch per width class
+    (specialize=1), or with the circuits of 2^33 updates or more on their own
+    specialised launches (auto): pooled 4-sigma rule over every amplitude of
+    every circuit, TV_path per circuit, and sampled chains replayed by the
+    oracle."""
     torch, pbit = env
     data = json.load(open(os.path.join(wc.DATA_DIR, "batch256.json")))
     circs, chains = data["circuits"], data["chains"]
@@ -161,7 +164,11 @@ def test_full_batch256(env):
     words = s.state_words(chains)
     hist = torch.zeros(s.hist_bins(), dtype=torch.int32, device="cuda")
     state = torch.zeros(words, dtype=torch.int32, device="cuda")
-    s.gibbs_run(chains, 200, 2000, hist, state, seed=0, persistent=1)
+    kinds = [s.launch_shape(chains, 200, 2000, idx=i, persistent=1, specialize=specialize)["kernel"]
+             for i in range(len(circs))]
+    say("specialised launches", sum(k == pbit.KERNEL_SPECIALISED for k in kinds))
+    assert (pbit.KERNEL_SPECIALISED in kinds) == (specialize == 0)
+    s.gibbs_run(chains, 200, 2000, hist, state, seed=0, persistent=1, specialize=specialize)
     torch.cuda.synchronize()
     res = per_circuit(s, chains, state.cpu().numpy().view(np.uint32), hist.cpu().numpy().view(np.uint32))
     amps, sres, sims, psis = [], [], [], []
