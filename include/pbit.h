@@ -137,15 +137,15 @@ typedef struct {
                                    table (4 bytes a path) fits in LDS beside the toggle rows count
                                    each sweep's free bits in LDS and bin every path that occurred
                                    once at the end (the same histogram); 4 = keys: circuits on the
-                                   specialised kernel with n + K <= 22 and at most 2^24 chains
+                                   specialised kernel with n + K <= 24 and at most 2^24 chains
                                    store each sample's bin
                                    as a 32-bit key (at most 2^28 keys a launch, in a buffer the
-                                   handle holds) and a second kernel counts them through LDS,
-                                   2^15 bins at a time.  Other circuits take 0 for 3 and 4.  Auto
+                                   handle holds), partitioned by 2^15-bin bucket and counted
+                                   through LDS.  Other circuits take 0 for 3 and 4.  Auto
                                    picks 3 for h <= 14 when each path gets >= 16 samples a
-                                   workgroup, else LDS bins when they fit, else 4 up to 2^20
-                                   bins when HBM atomics would bound the sweep (few free bits
-                                   for the histogram's size), else 2. */
+                                   workgroup, else LDS bins when they fit, else 4 when HBM
+                                   atomics would bound the sweep (few free bits and lattice
+                                   words), else 2. */
     uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
     uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
     uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */

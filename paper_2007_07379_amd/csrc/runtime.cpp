@@ -261,7 +261,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         uint32_t *hist_out;
         uint64_t keys_n;
         uint32_t bits;
-        uint32_t *part;  // partial rows of the key histogram
+        void *part;      // scratch of the key histogram
         uint32_t circ;
         int lane;        // 0: the caller's stream, k > 0: side stream k - 1
     };
@@ -341,7 +341,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                 p.a.hist = nullptr;  // the key buffer, set below
                 p.keys_n = done + g > bin0 ? (uint64_t)ch * (done + g - bin0) : 0;
                 keys_words = std::max(keys_words, p.keys_n);
-                part_bytes = std::max(part_bytes, keyhist_shape(p.keys_n, p.bits).part_bytes);
+                part_bytes = std::max(part_bytes, keyhist_scratch_bytes(p.keys_n, p.bits));
             }
             p.a.resume = done > 0 ? 1u : (cfg->init == PBIT_INIT_RESUME ? 1u : 0u);
             p.a.lds_hist = tc.lds_hist ? 1u : 0u;
@@ -404,6 +404,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     // stream (the plans of one stream run in order)
     void *d_keys = nullptr, *d_part = nullptr;
     const size_t part_stride = (part_bytes + 255) & ~(size_t)255;
+    keys_words = (keys_words + 63) & ~63ull;  // each stream's keys start 256-byte aligned
     if (keys_words) {
         const int nl = fork ? LANES : 1;
         if ((st = ensure_buf(c->keys, dev, keys_words * sizeof(uint32_t) * nl, &d_keys)) != PBIT_OK) return st;
@@ -411,7 +412,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         for (Plan &p : plans)
             if (p.hist_out) {
                 p.a.hist = (uint32_t *)d_keys + keys_words * p.lane;
-                p.part = (uint32_t *)((unsigned char *)d_part + part_stride * p.lane);
+                p.part = (unsigned char *)d_part + part_stride * p.lane;
             }
     }
     // tiles in decreasing cost order (longest first), 256 chains each

@@ -89,11 +89,11 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
         // Keys pay when HBM atomics would bound the sweep: the chip retires
         // about 27e9 of them a second when the bins are spread (fewer when
         // they are not), i.e. 37 ps a sample, while a sample costs about
-        // (34 + 6) lane-ops per Philox block and 8 per lattice word at 39.3e12
-        // lane-ops/s, plus about 0.6 ps of key histogram per 2^15-bin bucket.
-        const double ps_sample = (40.0 * ((k.h + 3) / 4) + 8.0 * k.W) / 39.3;
-        const double ps_keys = 0.6 * (double)(1u << (bits > 15 ? bits - 15 : 0));
-        const bool keys_pay = bits <= 20 && ps_sample + ps_keys < 37.0;
+        // (34 + 6) lane-ops per Philox block and 8 per lattice word, at 85 %
+        // of 39.3e12 lane-ops/s, plus about 4 ps of key histogram (16 bytes
+        // of HBM traffic a key and the partial rows).
+        const double ps_sample = (40.0 * ((k.h + 3) / 4) + 8.0 * k.W) / (39.3 * 0.85);
+        const bool keys_pay = ps_sample + 4.0 < 37.0;
         // automatic choice, in this order: counts per path when the paths are
         // few next to the samples of a workgroup (at least 16 per path: a
         // sweep then skips the lattice, phase and bin, and the histogram sees

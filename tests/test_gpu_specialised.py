@@ -82,7 +82,7 @@ def test_specialised_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb
     assert sh["kernel"] == pbit.KERNEL_SPECIALISED and sh["lanes_per_chain"] == lanes
     st_o, h_o = oracle(name, c, chains, burn, sweeps, seed, cb)
     info = s.info(0)
-    modes = [0, 2] + ([3] if info["h"] <= 14 else []) + ([4] if info["n"] + info["K"] <= 22 else [])
+    modes = [0, 2] + ([3] if info["h"] <= 14 else []) + ([4] if info["n"] + info["K"] <= 24 else [])
     if 3 in modes:
         assert s.launch_shape([chains], burn, sweeps, specialize=2, lanes_per_chain=lanes,
                               hist_mode=3)["lds_hist"] == 2

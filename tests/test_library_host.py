@@ -296,8 +296,10 @@ def test_launch_shape_rules(pb):
     assert b16.launch_shape([131072], 200, 2000, hist_mode=4)["lds_hist"] == 3
     assert s.launch_shape([65536], 200, 10000, hist_mode=4)["lds_hist"] == 3  # rct12, forced
     b20 = pb.CircuitSet(wc.workload_circuit("brick20"))
-    assert b20.launch_shape([262144], 200, 2000)["lds_hist"] == 0  # 2^24 bins: HBM atomics
-    assert b20.launch_shape([262144], 200, 2000, hist_mode=4)["lds_hist"] == 0  # beyond the key histogram
+    assert b20.launch_shape([262144], 200, 2000)["lds_hist"] == 0  # long sweeps: HBM atomics
+    assert b20.launch_shape([262144], 200, 2000, hist_mode=4)["lds_hist"] == 3  # 2^24 bins, 512 buckets
+    big = pb.CircuitSet(wc.brickwork(22, 4, 1, K=4, kmax=3))  # 2^26 bins: beyond the key histogram
+    assert big.launch_shape([1024], 0, 100, specialize=2, hist_mode=4)["lds_hist"] == 0
 
 
 SPEC_CIRCUITS = [
