@@ -461,6 +461,8 @@ def main():
     ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train"])
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--specialize", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--hist-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
+                    help="histogram placement (pbit_gibbs_cfg.hist_mode), gibbs mode")
     ap.add_argument("--gibbs-per-mh", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args()
@@ -513,14 +515,15 @@ def main():
 
     def run_parts():
         for (b, n, off), hh in zip(parts, hists):
-            s.gibbs_run([chains], b, n, hh, state, seed=0, sweep_offset=off, resume=off > 0, stream=stream)
+            s.gibbs_run([chains], b, n, hh, state, seed=0, sweep_offset=off, resume=off > 0, stream=stream,
+                        hist_mode=args.hist_mode)
 
     def step():
         for hh in hists:
             hh.zero_()
         run_parts()
 
-    shape = s.launch_shape([chains], parts[0][0], parts[0][1])
+    shape = s.launch_shape([chains], parts[0][0], parts[0][1], hist_mode=args.hist_mode)
     kname = {pbit.KERNEL_ONE_LANE: "gibbs_kernel<%d,%s>" % (shape["kernel_words"],
                                                           "true" if info["uniform"] else "false"),
              pbit.KERNEL_TWO_LANE: "gibbs_pair_kernel<%d>" % shape["kernel_words"],

@@ -137,20 +137,69 @@ __global__ void __launch_bounds__(64) base_kernel(Layout L, unsigned char *__res
 
 // Each key's low bits go to its bucket's region, at the tile's offset there
 // plus its rank within the tile (the order inside a bucket is immaterial).
+// The tile is first sorted by bucket in LDS (rank by LDS atomic, bucket
+// starts by a scan), so consecutive threads then write consecutive 16-bit
+// words of each bucket's run.
 __global__ void __launch_bounds__(TILE_THREADS) scatter_kernel(const uint32_t *__restrict__ keys, uint64_t M,
                                                               Layout L, unsigned char *__restrict__ ws) {
-    __shared__ uint32_t off[KEYHIST_MAX_BUCKETS];
+    constexpr uint32_t PER = TILE / TILE_THREADS;  // keys per thread
+    __shared__ uint32_t rank[KEYHIST_MAX_BUCKETS];
+    __shared__ uint32_t start[KEYHIST_MAX_BUCKETS];
+    __shared__ uint32_t goff[KEYHIST_MAX_BUCKETS];
+    __shared__ uint32_t sorted[TILE];
     const uint32_t *cnt = (const uint32_t *)(ws + L.cnt_off);
     const uint32_t *base = (const uint32_t *)(ws + L.base_off);
-    for (uint32_t b = threadIdx.x; b < L.NB; b += TILE_THREADS)
-        off[b] = base[b] + cnt[(uint64_t)b * L.T + blockIdx.x];
+    for (uint32_t b = threadIdx.x; b < L.NB; b += TILE_THREADS) {
+        rank[b] = 0u;
+        goff[b] = base[b] + cnt[(uint64_t)b * L.T + blockIdx.x];
+    }
     __syncthreads();
+    const uint64_t k0 = (uint64_t)blockIdx.x * TILE;
+    const uint64_t k1 = k0 + TILE < M ? k0 + TILE : M;
+    uint32_t key[PER], r[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER / 4; ++j) {
+        const uint64_t k = k0 + 4ull * (threadIdx.x + j * TILE_THREADS);
+        if (k + 4 <= k1) {
+            const u32x4 q = *(const u32x4 *)(keys + k);
+            key[4 * j] = q.x;
+            key[4 * j + 1] = q.y;
+            key[4 * j + 2] = q.z;
+            key[4 * j + 3] = q.w;
+        } else {
+#pragma unroll
+            for (uint32_t e = 0; e < 4; ++e) key[4 * j + e] = k + e < k1 ? keys[k + e] : 0xFFFFFFFFu;
+        }
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < PER; ++e) {
+        const uint32_t b = key[e] >> L.lb;
+        r[e] = b < L.NB ? atomicAdd(&rank[b], 1u) : 0u;
+    }
+    __syncthreads();
+    // exclusive prefix of the tile's bucket counts
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t b = 0; b < L.NB; ++b) {
+            start[b] = run;
+            run += rank[b];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t e = 0; e < PER; ++e) {
+        const uint32_t b = key[e] >> L.lb;
+        if (b < L.NB) sorted[start[b] + r[e]] = key[e];
+    }
+    __syncthreads();
+    const uint32_t n = start[L.NB - 1] + rank[L.NB - 1];  // keys of this tile below 2^bits
     uint16_t *out = (uint16_t *)(ws + L.out_off);
     const uint32_t mask = (1u << L.lb) - 1u;
-    tile_keys(keys, M, blockIdx.x, [&](uint32_t k) {
+    for (uint32_t i = threadIdx.x; i < n; i += TILE_THREADS) {
+        const uint32_t k = sorted[i];
         const uint32_t b = k >> L.lb;
-        if (b < L.NB) out[atomicAdd(&off[b], 1u)] = (uint16_t)(k & mask);
-    });
+        out[goff[b] + (i - start[b])] = (uint16_t)(k & mask);
+    }
 }
 
 // Workgroup w = c * NB + b: chunk c of bucket b's keys counted in LDS and
