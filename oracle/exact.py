@@ -17,6 +17,7 @@ Everything is FP64.
 from __future__ import annotations
 
 import itertools
+import math
 
 import numpy as np
 
@@ -115,3 +116,27 @@ def path_sum(circ, return_paths=False):
     if return_paths:
         return amp, paths
     return amp
+
+
+def prefactor(circ, alpha, weighted):
+    """std({W_C},{p_C}) of Eq. (U30) over the paths of Eq. (U343) that end
+    in output alpha, the quantity Fig. 5 plots for a chain of rotated
+    Hadamards: W_C = psi_C / p_C (Eq. (U344)) and U = sum of psi_C over those
+    paths; p_C is uniform over all 2^(n(d-1)) intermediate sequences ending
+    in alpha (weighted=False; paths of weight zero included) or
+    proportional to |psi_C| among them (weighted=True, Eq. (weightedS)).
+    |W - U|^2 is used for complex weights.  Explicit enumeration: tiny
+    circuits only."""
+    _, paths = path_sum(circ, return_paths=True)
+    mine = [w for states, w in paths if states[-1] == alpha]
+    U = complex(sum(mine))
+    if weighted:
+        Za = float(sum(abs(w) for w in mine))
+        if Za == 0.0:
+            return 0.0
+        var = sum((abs(w) / Za) * abs(w / (abs(w) / Za) - U) ** 2 for w in mine)
+    else:
+        N = 2 ** (circ.n * (circ.d - 1))
+        var = sum((1.0 / N) * abs(w * N - U) ** 2 for w in mine)
+        var += (N - len(mine)) * (1.0 / N) * abs(U) ** 2  # the paths of weight zero
+    return math.sqrt(max(var, 0.0))

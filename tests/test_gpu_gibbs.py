@@ -243,3 +243,28 @@ def test_full_tiny_born_tv(env):
     assert oest.tv_born(amp, psi) < 0.01
     ok, info = oest.z_gate(amp, sre, sim, psi)
     assert ok, info
+
+
+@pytest.mark.parametrize("theta", [math.pi / 4, math.pi / 8, math.pi / 16, 3 * math.pi / 8])
+def test_rotated_hadamard_prefactor_fig5(env, theta):
+    """Fig. 5: d = 10 rotated Hadamards (Eq. (HadT)), weighted sampling.
+    From the GPU counts, the samples that reach output alpha carry W = Z_alpha
+    times their sign, so their spread is Z_alpha sqrt(1 - mean sign^2); it
+    must match the exact Eq. (U30) prefactor of the oracle within 1 % of
+    Z_alpha on both outputs."""
+    c = wc.rotated_hadamard_chain(10, theta, K=1)
+    chains, burn, sweeps = 65536, 100, 1000
+    say("fig5 theta", theta)
+    st, h, s = run_gpu(env, c, chains, burn, sweeps, seed=7)
+    circ = oc.from_dict(c)
+    _, Z = exact.magnitude_marginal(circ)
+    T = chains * sweeps
+    assert int(h.sum()) == T
+    for a in (0, 1):
+        na = float(h[a].sum())
+        Za = Z * na / T
+        m = (float(h[a, 0]) - float(h[a, 1])) / na
+        est = Za * math.sqrt(max(1.0 - m * m, 0.0))
+        want = exact.prefactor(circ, a, True)
+        say("  output", a, "measured", est, "exact", want, "Z_alpha", Za)
+        assert abs(est - want) <= 0.01 * Za, (a, est, want)

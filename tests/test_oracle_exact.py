@@ -320,3 +320,49 @@ def test_repeated_cnot_cancels_in_the_lattice():
     comp = ocomp.compile_circuit(c)
     assert comp.h == 1
     assert np.allclose(compiled_amplitudes(comp), want, atol=1e-12)
+
+
+@pytest.mark.parametrize("theta", [math.pi / 4, math.pi / 8, math.pi / 16, 3 * math.pi / 8, 0.3])
+def test_prefactor_two_rotated_hadamards_closed_form(theta):
+    """Eq. (U30) for d = 2 rotated Hadamards (Eq. (HadT)) worked by hand:
+    to |0> the two paths weigh cos^2 and sin^2 (U = 1), so uniform sampling
+    (p = 1/2, W = 2 psi) gives |cos 2 theta| and weighted sampling gives W = 1
+    on both, std 0; to |1> they weigh +-sin cos (U = 0), both samplings give
+    W = +-sin 2 theta, std |sin 2 theta|."""
+    c = _circ(wc.rotated_hadamard_chain(2, theta, K=1))
+    assert exact.prefactor(c, 0, False) == pytest.approx(abs(math.cos(2 * theta)), abs=1e-13)
+    assert exact.prefactor(c, 0, True) == pytest.approx(0.0, abs=1e-7)
+    assert exact.prefactor(c, 1, False) == pytest.approx(abs(math.sin(2 * theta)), abs=1e-13)
+    assert exact.prefactor(c, 1, True) == pytest.approx(abs(math.sin(2 * theta)), abs=1e-13)
+
+
+def test_prefactor_hadamard_chain_is_eq_stdT():
+    """Fig. 5 at theta = pi/4 (the Hadamard gate): on the wrong output of
+    d = 10 the prefactor is the 2^(d/2) / 2 of Eq. (stdT) (std(T) times the
+    root of the T/2 samples that reach it), and weighted sampling equals
+    uniform sampling on both outputs (all paths weigh the same)."""
+    c = _circ(wc.rotated_hadamard_chain(10, math.pi / 4, K=1))
+    assert exact.prefactor(c, 1, False) == pytest.approx(2.0 ** 5 / 2, rel=1e-12)
+    for a in (0, 1):
+        assert exact.prefactor(c, a, True) == pytest.approx(exact.prefactor(c, a, False), rel=1e-12)
+
+
+@pytest.mark.parametrize("theta", [math.pi / 32, math.pi / 8, 0.5, math.pi / 3, 0.45 * math.pi])
+def test_prefactor_weighted_closed_form_and_ordering(theta):
+    """Weighted sampling (p_C = |psi_C| / Z_alpha over the paths to alpha)
+    makes W_C = Z_alpha times a phase, so Eq. (U30) is sqrt(Z_alpha^2 -
+    |U_alpha|^2): checked against Z_alpha from the magnitude circuit and
+    U_alpha from the statevector (independent routines).  By Cauchy-Schwarz
+    it never exceeds uniform sampling (Fig. 5's point), and at theta = pi/2
+    (a classical NOT) it is zero."""
+    c = _circ(wc.rotated_hadamard_chain(10, theta, K=1))
+    pm, Z = exact.magnitude_marginal(c)
+    psi = exact.statevector(c)
+    for a in (0, 1):
+        Za = pm[a] * Z
+        want = math.sqrt(max(Za * Za - abs(psi[a]) ** 2, 0.0))
+        assert exact.prefactor(c, a, True) == pytest.approx(want, rel=1e-9, abs=1e-12)
+        assert exact.prefactor(c, a, True) <= exact.prefactor(c, a, False) + 1e-12
+    cx = _circ(wc.rotated_hadamard_chain(10, math.pi / 2, K=1))
+    assert exact.prefactor(cx, 0, True) == pytest.approx(0.0, abs=1e-12)
+    assert exact.prefactor(cx, 0, False) > 1.0
