@@ -19,6 +19,8 @@ the passage of the paper it follows:
   estimator.py  Eqs. (U343), (U23), (U26), (U30): amplitudes, sigma, TV
   ancestral.py  an independent exact sampler of p_C (layer-by-layer)
   made.py       FP64 MADE forward / backward / Adam (the learned proposal)
+  shor.py       period finding by column sampling (Sec. 5, Fig. 7) and the
+                circuit of Fig. 6 built from matrices
 
 Pins that tie each part to the paper rather than to itself live in
 tests/test_oracle_*.py.  Parity unpinned: none of the functions above is

@@ -10,10 +10,12 @@ from oracle import compile as ocomp
 from oracle import estimator as oest
 from oracle import exact
 from oracle import made as omade
+from oracle import shor as oshor
 
 import test_oracle_chain as tchain  # tests/ is on sys.path under pytest
 import test_oracle_exact as texact
 import test_oracle_made as tmade
+import test_oracle_shor as tshor
 
 
 def caught(*pins):
@@ -161,7 +163,22 @@ def test_wrong_sign_in_loss_gradient_is_caught(monkeypatch):
     assert caught(*MADE_PINS)
 
 
-@pytest.mark.parametrize("pin", EXACT_PINS[:4] + CHAIN_PINS + MADE_PINS,
+SHOR_PINS = [tshor.test_n15_a7_closed_form, tshor.test_peaks_at_multiples_of_2n_over_r] + [
+    (tshor.test_all_columns_once_equals_circuit, args) for args in [(15, 7, 4), (21, 2, 5)]]
+
+
+def test_columns_grouped_by_x_instead_of_f_is_caught(monkeypatch):
+    monkeypatch.setattr(oshor, "groups", lambda N, a, xs: {x: [x] for x in xs})
+    assert caught(*SHOR_PINS)
+
+
+def test_inverse_qft_without_normalisation_is_caught(monkeypatch):
+    orig = oshor.register_distribution
+    monkeypatch.setattr(oshor, "register_distribution", lambda N, a, n: orig(N, a, n) * 2 ** n)
+    assert caught(*SHOR_PINS)
+
+
+@pytest.mark.parametrize("pin", EXACT_PINS[:4] + CHAIN_PINS + MADE_PINS + SHOR_PINS,
                          ids=lambda p: getattr(p, "__name__", str(p)))
 def test_pins_pass_on_the_unmodified_oracle(pin):
     """Control: the same pins pass when nothing is planted."""
