@@ -325,6 +325,38 @@ pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uin
 pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, uint32_t lds_hist, uint32_t max_block,
                                     char *buf, size_t cap, size_t *len);
 
+/* ------------------------------------------------------------------------
+ * Period finding by column sampling (Sec. 5, Figs. 6-7): the first register
+ * of the order-finding circuit is n p-bits.  A sample is a configuration x,
+ * drawn uniformly (word i mod 4 of Philox4x32-10 at counter (i / 4, 0, 0,
+ * 3 << 16) under key seed, its low n bits); f(x) = a^x mod N is the second
+ * register; the inverse-QFT column of x, 2^(-n/2) exp(-2 pi i k x / 2^n)
+ * over k, is added to column f(x) of psi, and the output law is the row sum
+ * of |psi|^2.  With T samples
+ *     P[k] = 2^(-n) / T * sum over values f of
+ *            |sum over sampled x with f(x) = f of exp(-2 pi i k x / 2^n)|^2,
+ * which sums to 1 when no x is drawn twice; its r largest peaks sit near
+ * j 2^n / r for the order r of a mod N.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t N;    /* modulus, 3 <= N < 2^31 */
+    uint64_t a;    /* base, 1 < a < N (gcd(a, N) = 1 is the caller's concern) */
+    uint32_t n;    /* p-bits of the first register, 1 <= n <= 30 */
+    uint32_t T;    /* column samples, 1 <= T <= 2^20 */
+    uint64_t seed; /* Philox key */
+} pbit_shor_cfg;
+
+/* Bytes of device workspace pbit_shor_run needs for cfg (8 x T rounded up
+ * to a power of two, at least 32).  Host only. */
+pbit_status pbit_shor_work_bytes(const pbit_shor_cfg *cfg, size_t *bytes);
+
+/* Runs the sampler on hip_stream: d_P (caller-owned device buffer of 2^n
+ * floats) receives P; d_work (caller-owned device workspace of
+ * pbit_shor_work_bytes bytes, 8-byte aligned) holds on return the T samples
+ * as uint64 keys (f << 32 | x), sorted by f and then x.  INVALID_ARG for
+ * parameters out of range or NULL buffers (before anything is enqueued). */
+pbit_status pbit_shor_run(const pbit_shor_cfg *cfg, float *d_P, void *d_work, void *hip_stream);
+
 const char *pbit_last_error(void);
 
 /* Blocks until all work the library enqueued on hip_stream is done; returns

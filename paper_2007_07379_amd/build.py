@@ -41,6 +41,7 @@ SOURCES = [
     ("mh.hip", "hip"),
     ("batched.hip", "hip"),
     ("keyhist.hip", "hip"),
+    ("shor.hip", "hip"),
 ]
 
 

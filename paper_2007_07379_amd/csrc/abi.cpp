@@ -17,6 +17,7 @@
 #include "compile.h"
 #include "gibbs.h"
 #include "runtime.h"
+#include "shor.h"
 
 namespace pbit {
 
@@ -38,6 +39,34 @@ using namespace pbit;
 extern "C" {
 
 const char *pbit_last_error(void) { return g_last_error.c_str(); }
+
+static pbit_status shor_check(const pbit_shor_cfg *cfg) {
+    if (!cfg) return set_error(PBIT_E_INVALID_ARG, "NULL cfg");
+    if (cfg->N < 3 || cfg->N >= (1ull << 31)) return set_error(PBIT_E_INVALID_ARG, "N must be in [3, 2^31)");
+    if (cfg->a < 2 || cfg->a >= cfg->N) return set_error(PBIT_E_INVALID_ARG, "a must be in (1, N)");
+    if (cfg->n < 1 || cfg->n > 30) return set_error(PBIT_E_INVALID_ARG, "n must be in [1, 30]");
+    if (cfg->T < 1 || cfg->T > (1u << 20)) return set_error(PBIT_E_INVALID_ARG, "T must be in [1, 2^20]");
+    return PBIT_OK;
+}
+
+pbit_status pbit_shor_work_bytes(const pbit_shor_cfg *cfg, size_t *bytes) {
+    const pbit_status st = shor_check(cfg);
+    if (st != PBIT_OK) return st;
+    if (!bytes) return set_error(PBIT_E_INVALID_ARG, "NULL bytes");
+    *bytes = (size_t)shor_pad(cfg->T) * sizeof(uint64_t);
+    return PBIT_OK;
+}
+
+pbit_status pbit_shor_run(const pbit_shor_cfg *cfg, float *d_P, void *d_work, void *hip_stream) {
+    const pbit_status st = shor_check(cfg);
+    if (st != PBIT_OK) return st;
+    if (!d_P || !d_work) return set_error(PBIT_E_INVALID_ARG, "NULL d_P or d_work");
+    if ((uintptr_t)d_work % 8) return set_error(PBIT_E_INVALID_ARG, "d_work must be 8-byte aligned");
+    const hipError_t e = launch_shor(cfg->N, cfg->a, cfg->n, cfg->T, cfg->seed, d_P, (uint64_t *)d_work,
+                                     (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_error(e, "column sampling launch");
+    return PBIT_OK;
+}
 
 pbit_status pbit_compile_circuit(const pbit_circuit_desc *descs, uint32_t n_circuits, pbit_circuit *out) {
     if (!out) return set_error(PBIT_E_INVALID_ARG, "out is NULL");

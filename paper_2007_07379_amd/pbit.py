@@ -374,3 +374,32 @@ def mh_run(cset, proposal, chains, cycles, d_state, d_hist, d_accepts=None, gibb
     _made_sigs(L)
     _check(L.pbit_mh_run(cset.handle, proposal.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                          _ptr(d_accepts), _stream(stream)))
+
+
+class ShorCfg(C.Structure):
+    _fields_ = [("N", C.c_uint64), ("a", C.c_uint64), ("n", C.c_uint32), ("T", C.c_uint32),
+                ("seed", C.c_uint64)]
+
+
+def _shor_sigs(L):
+    L.pbit_shor_work_bytes.argtypes = [C.POINTER(ShorCfg), C.POINTER(C.c_size_t)]
+    L.pbit_shor_run.argtypes = [C.POINTER(ShorCfg), C.c_void_p, C.c_void_p, C.c_void_p]
+
+
+def shor_work_bytes(N, a, n, T, seed=0):
+    """Device workspace bytes of shor_run."""
+    L = lib()
+    _shor_sigs(L)
+    cfg = ShorCfg(N, a, n, T, seed)
+    b = C.c_size_t(0)
+    _check(L.pbit_shor_work_bytes(C.byref(cfg), C.byref(b)))
+    return b.value
+
+
+def shor_run(N, a, n, T, d_P, d_work, seed=0, stream=None):
+    """Column sampling for the order of a mod N (pbit_shor_run): d_P gets
+    2^n floats, d_work the T samples as (f << 32 | x) sorted by f, then x."""
+    L = lib()
+    _shor_sigs(L)
+    cfg = ShorCfg(N, a, n, T, seed)
+    _check(L.pbit_shor_run(C.byref(cfg), _ptr(d_P), _ptr(d_work), _stream(stream)))

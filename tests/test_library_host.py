@@ -354,3 +354,25 @@ def test_specialised_source_rejects_nonuniform(pb):
     with pytest.raises(pb.PbitError) as e:
         r.specialised_source(0)
     assert e.value.name == "MODE_UNAVAILABLE"
+
+
+def test_shor_argument_errors_before_device(pb):
+    """Column sampling: workspace size and every argument error are host
+    checks (nothing is enqueued, no device needed)."""
+    assert pb.shor_work_bytes(15, 7, 4, 1) == 32
+    assert pb.shor_work_bytes(15, 7, 4, 250) == 8 * 256
+    assert pb.shor_work_bytes(98743069, 10424, 27, 250) == 8 * 256
+    for args in [(2, 1, 4, 10), (15, 1, 4, 10), (15, 15, 4, 10), (15, 7, 0, 10), (15, 7, 31, 10),
+                 (15, 7, 4, 0), (15, 7, 4, (1 << 20) + 1), (1 << 31, 7, 4, 10)]:
+        with pytest.raises(pb.PbitError) as e:
+            pb.shor_work_bytes(*args)
+        assert e.value.name == "INVALID_ARG", args
+        with pytest.raises(pb.PbitError) as e:
+            pb.shor_run(*args, d_P=1 << 20, d_work=1 << 20)
+        assert e.value.name == "INVALID_ARG", args
+    with pytest.raises(pb.PbitError) as e:
+        pb.shor_run(15, 7, 4, 10, d_P=None, d_work=1 << 20)
+    assert e.value.name == "INVALID_ARG"
+    with pytest.raises(pb.PbitError) as e:
+        pb.shor_run(15, 7, 4, 10, d_P=1 << 20, d_work=(1 << 20) + 4)
+    assert e.value.name == "INVALID_ARG"
