@@ -343,6 +343,67 @@ def train_mode(args):
     }))
 
 
+# Period finding by column sampling (Sec. 5): the paper's 27-bit example
+SHOR = dict(N=98743069, a=10424, n=27, T=250)
+SHOR_PAPER_SECONDS = 5923.0  # the same workload on one laptop core in MATLAB (Sec. 5, Table 1)
+# VALU instructions of one term exp(-2 pi i k x / 2^n) in shor_column_kernel:
+# 32-bit multiply, conversion, scale, hardware cosine and sine, two adds; each
+# issues at full rate on gfx950 (the kernel sustains more than 4 terms per
+# SIMD per 4 cycles' worth of these, so none can be quarter rate)
+SHOR_SLOTS_PER_TERM = 7
+
+
+def shor_mode(args):
+    """Column sampling for the order of 10424 mod 98743069 (n = 27, 250
+    samples): one pbit_shor_run per step, P over all 2^27 outputs."""
+    import torch
+    from paper_2007_07379_amd import pbit
+    N, a, n, T = SHOR["N"], SHOR["a"], SHOR["n"], SHOR["T"]
+    stream = torch.cuda.current_stream()
+    P = torch.empty(1 << n, dtype=torch.float32, device="cuda")
+    work = torch.empty(pbit.shor_work_bytes(N, a, n, T) // 8, dtype=torch.int64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        pbit.shor_run(N, a, n, T, P, work, seed=0, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        pbit.shor_run(N, a, n, T, P, work, seed=i, stream=stream)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    kernel_s = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev])) / 1e3
+    terms = T * float(1 << n)
+    slots = terms * SHOR_SLOTS_PER_TERM
+    out = {
+        "metric": "column-sampling wall time (Sec. 5 27-bit example)", "value": wall, "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": wall / SHOR_PAPER_SECONDS,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "period finding by column sampling: N=98743069, a=10424 (order 78), n=27 "
+                               "first-register p-bits, 250 column samples, P over all 2^27 outputs"},
+        "terms_per_s": terms / kernel_s,
+        "roofline": {"bound": "alu", "achieved": slots / kernel_s / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tslot-op/s", "frac": slots / kernel_s / VALU_PEAK, "traffic": None,
+                     "kernel": "shor_column_kernel (+ shor_prepare_kernel)", "kernel_ms": kernel_s * 1e3,
+                     "slots_per_term": SHOR_SLOTS_PER_TERM},
+        "baseline_note": "vs_baseline divides by the paper's ~5923 s for the same workload on one laptop "
+                         "core in MATLAB (other hardware and software: context)",
+    }
+    if not args.no_cpu:
+        from oracle import shor as oshor
+        xs = oshor.draws(n, T, 0)
+        ks = list(range(0, 1 << n, (1 << n) // 32768))
+        t0 = time.perf_counter()
+        oshor.column_probs(N, a, n, xs, ks=ks)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": dt * (1 << n) / len(ks), "unit": "s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of the 2^27 outputs (x 250 samples) in %.1f s, scaled to all"
+                                         % (len(ks), dt)}
+    print(json.dumps(out))
+
+
 def copy_mode(args):
     """One plain device-to-device copy of known size, the reference point that
     scales the FETCH_SIZE / WRITE_SIZE hardware counters to bytes."""
@@ -458,7 +519,7 @@ def main():
     ap.add_argument("--workload", default="rct12")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=8192)
-    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train"])
+    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train", "shor"])
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--specialize", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--hist-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
@@ -476,6 +537,9 @@ def main():
         return
     if args.mode == "train":
         train_mode(args)
+        return
+    if args.mode == "shor":
+        shor_mode(args)
         return
     if args.mode == "mh":
         if args.workload == "rct12":

@@ -12,8 +12,8 @@
 // memory at the samples plus one output row, instead of 2^n x 2^n);
 // shor_column_kernel gives every lane one output k and walks the sorted
 // samples, whose loads are uniform across the wave (scalar loads), so each
-// term costs the lane one multiply, one mask, one conversion and a
-// hardware sine and cosine.
+// term costs the lane one multiply, one conversion, one scale, a hardware
+// cosine and sine and two adds.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -77,16 +77,16 @@ __global__ void __launch_bounds__(PREP_THREADS) shor_prepare_kernel(uint64_t N, 
     }
 }
 
-__device__ __forceinline__ void add_term(uint32_t k, uint32_t x, uint32_t mask, float scale, float &sr, float &si) {
-    // phase k x mod 2^n in revolutions; the hardware sine and cosine take
-    // revolutions
-    const float u = (float)((k * x) & mask) * scale;
+// ks = k << (32 - n): the 32-bit product ks x is (k x mod 2^n) << (32 - n),
+// so 2^-32 times it is the phase k x / 2^n mod 1 in revolutions, the unit of
+// the hardware sine and cosine.
+__device__ __forceinline__ void add_term(uint32_t ks, uint32_t x, float &sr, float &si) {
+    const float u = (float)(ks * x) * 0x1p-32f;
     sr += __builtin_amdgcn_cosf(u);
     si -= __builtin_amdgcn_sinf(u);
 }
 
-__device__ __forceinline__ void step(uint64_t key, uint32_t k, uint32_t mask, float scale, uint32_t &fprev,
-                                     double &acc, float &sr, float &si) {
+__device__ __forceinline__ void step(uint64_t key, uint32_t ks, uint32_t &fprev, double &acc, float &sr, float &si) {
     const uint32_t f = (uint32_t)(key >> 32);
     if (f != fprev) {  // wave-uniform: the keys are the same for every lane
         acc += (double)sr * sr + (double)si * si;
@@ -94,14 +94,15 @@ __device__ __forceinline__ void step(uint64_t key, uint32_t k, uint32_t mask, fl
         si = 0.0f;
         fprev = f;
     }
-    add_term(k, (uint32_t)key, mask, scale, sr, si);
+    add_term(ks, (uint32_t)key, sr, si);
 }
 
 __global__ void __launch_bounds__(COL_THREADS) shor_column_kernel(const uint64_t *__restrict__ keys, uint32_t n,
-                                                                 uint32_t T, double inv_T, float *__restrict__ P) {
+                                                                 uint32_t T, double inv_T, double inv_2n,
+                                                                 float *__restrict__ P) {
     const uint32_t k = blockIdx.x * COL_THREADS + threadIdx.x;
     const uint32_t mask = (1u << n) - 1u;
-    const float scale = 1.0f / (float)(1u << n);
+    const uint32_t ks = k << (32 - n);
     double acc = 0.0;
     float sr = 0.0f, si = 0.0f;
     uint32_t fprev = (uint32_t)(keys[0] >> 32);
@@ -112,11 +113,11 @@ __global__ void __launch_bounds__(COL_THREADS) shor_column_kernel(const uint64_t
 #pragma unroll
         for (int e = 0; e < 8; ++e) kk[e] = keys[i + e];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) step(kk[e], k, mask, scale, fprev, acc, sr, si);
+        for (int e = 0; e < 8; ++e) step(kk[e], ks, fprev, acc, sr, si);
     }
-    for (; i < T; ++i) step(keys[i], k, mask, scale, fprev, acc, sr, si);
+    for (; i < T; ++i) step(keys[i], ks, fprev, acc, sr, si);
     acc += (double)sr * sr + (double)si * si;
-    if (k <= mask) P[k] = (float)(acc * (double)scale * inv_T);
+    if (k <= mask) P[k] = (float)(acc * inv_2n * inv_T);
 }
 
 }  // namespace
@@ -136,7 +137,7 @@ hipError_t launch_shor(uint64_t N, uint64_t a, uint32_t n, uint32_t T, uint64_t 
     if (e != hipSuccess) return e;
     const uint32_t grid = (uint32_t)(((1ull << n) + COL_THREADS - 1) / COL_THREADS);
     hipLaunchKernelGGL(shor_column_kernel, dim3(grid), dim3(COL_THREADS), 0, s, (const uint64_t *)keys, n, T,
-                       1.0 / (double)T, P);
+                       1.0 / (double)T, 1.0 / (double)(1ull << n), P);
     return hipGetLastError();
 }
 
