@@ -344,8 +344,12 @@ def train_mode(args):
 
 
 # Period finding by column sampling (Sec. 5): the paper's 27-bit example
-SHOR = dict(N=98743069, a=10424, n=27, T=250)
-SHOR_PAPER_SECONDS = 5923.0  # the same workload on one laptop core in MATLAB (Sec. 5, Table 1)
+# (250 column samples) and Table 1's 20-bit case (order 479,568; T = 2 r
+# samples), with the paper's wall times on one laptop core in MATLAB
+SHOR_WORKLOADS = {
+    "shor27": dict(N=98743069, a=10424, n=27, T=250, paper_s=5923.0, paper="about 5,923 s"),
+    "shor20": dict(N=961307, a=5, n=20, T=2 * 479568, paper_s=32 * 3600.0, paper="32 hours"),
+}
 # VALU instructions of one term exp(-2 pi i k x / 2^n) in shor_column_kernel:
 # 32-bit multiply, conversion, scale, hardware cosine and sine, two adds; each
 # issues at full rate on gfx950 (the kernel sustains more than 4 terms per
@@ -354,11 +358,13 @@ SHOR_SLOTS_PER_TERM = 7
 
 
 def shor_mode(args):
-    """Column sampling for the order of 10424 mod 98743069 (n = 27, 250
-    samples): one pbit_shor_run per step, P over all 2^27 outputs."""
+    """Column sampling for the order of a mod N (shor27: 10424 mod 98743069,
+    n = 27, 250 samples; shor20: 5 mod 961307, n = 20, T = 2 r): one
+    pbit_shor_run per step, P over all 2^n outputs."""
     import torch
     from paper_2007_07379_amd import pbit
-    N, a, n, T = SHOR["N"], SHOR["a"], SHOR["n"], SHOR["T"]
+    w = SHOR_WORKLOADS[args.workload]
+    N, a, n, T = w["N"], w["a"], w["n"], w["T"]
     stream = torch.cuda.current_stream()
     P = torch.empty(1 << n, dtype=torch.float32, device="cuda")
     work = torch.empty(pbit.shor_work_bytes(N, a, n, T) // 8, dtype=torch.int64, device="cuda")
@@ -377,30 +383,30 @@ def shor_mode(args):
     terms = T * float(1 << n)
     slots = terms * SHOR_SLOTS_PER_TERM
     out = {
-        "metric": "column-sampling wall time (Sec. 5 27-bit example)", "value": wall, "unit": "s",
+        "metric": "column-sampling wall time (Sec. 5)", "value": wall, "unit": "s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3,
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": wall / SHOR_PAPER_SECONDS,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": wall / w["paper_s"],
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "period finding by column sampling: N=98743069, a=10424 (order 78), n=27 "
-                               "first-register p-bits, 250 column samples, P over all 2^27 outputs"},
+        "config": {"workload": "%s: period finding by column sampling, N=%d, a=%d, n=%d first-register p-bits, "
+                               "%d column samples, P over all 2^%d outputs" % (args.workload, N, a, n, T, n)},
         "terms_per_s": terms / kernel_s,
         "roofline": {"bound": "alu", "achieved": slots / kernel_s / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tslot-op/s", "frac": slots / kernel_s / VALU_PEAK, "traffic": None,
                      "kernel": "shor_column_kernel (+ shor_prepare_kernel)", "kernel_ms": kernel_s * 1e3,
                      "slots_per_term": SHOR_SLOTS_PER_TERM},
-        "baseline_note": "vs_baseline divides by the paper's ~5923 s for the same workload on one laptop "
-                         "core in MATLAB (other hardware and software: context)",
+        "baseline_note": "vs_baseline divides by the paper's %s for the same workload on one laptop "
+                         "core in MATLAB (other hardware and software: context)" % w["paper"],
     }
     if not args.no_cpu:
         from oracle import shor as oshor
         xs = oshor.draws(n, T, 0)
-        ks = list(range(0, 1 << n, (1 << n) // 32768))
+        ks = list(range(0, 1 << n, (1 << n) // max(1, min(1 << n, (1 << 23) // T))))
         t0 = time.perf_counter()
         oshor.column_probs(N, a, n, xs, ks=ks)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": dt * (1 << n) / len(ks), "unit": "s", "cores": 1, "kind": "oracle",
-                               "sample": "%d of the 2^27 outputs (x 250 samples) in %.1f s, scaled to all"
-                                         % (len(ks), dt)}
+                               "sample": "%d of the 2^%d outputs (x %d samples) in %.1f s, scaled to all"
+                                         % (len(ks), n, T, dt)}
     print(json.dumps(out))
 
 
@@ -539,6 +545,8 @@ def main():
         train_mode(args)
         return
     if args.mode == "shor":
+        if args.workload not in SHOR_WORKLOADS:
+            args.workload = "shor27"
         shor_mode(args)
         return
     if args.mode == "mh":

@@ -342,7 +342,7 @@ typedef struct {
     uint64_t N;    /* modulus, 3 <= N < 2^31 */
     uint64_t a;    /* base, 1 < a < N (gcd(a, N) = 1 is the caller's concern) */
     uint32_t n;    /* p-bits of the first register, 1 <= n <= 30 */
-    uint32_t T;    /* column samples, 1 <= T <= 2^20 */
+    uint32_t T;    /* column samples, 1 <= T <= 2^22 */
     uint64_t seed; /* Philox key */
 } pbit_shor_cfg;
 

@@ -45,7 +45,7 @@ static pbit_status shor_check(const pbit_shor_cfg *cfg) {
     if (cfg->N < 3 || cfg->N >= (1ull << 31)) return set_error(PBIT_E_INVALID_ARG, "N must be in [3, 2^31)");
     if (cfg->a < 2 || cfg->a >= cfg->N) return set_error(PBIT_E_INVALID_ARG, "a must be in (1, N)");
     if (cfg->n < 1 || cfg->n > 30) return set_error(PBIT_E_INVALID_ARG, "n must be in [1, 30]");
-    if (cfg->T < 1 || cfg->T > (1u << 20)) return set_error(PBIT_E_INVALID_ARG, "T must be in [1, 2^20]");
+    if (cfg->T < 1 || cfg->T > (1u << 22)) return set_error(PBIT_E_INVALID_ARG, "T must be in [1, 2^22]");
     return PBIT_OK;
 }
 

@@ -28,6 +28,7 @@ namespace {
 constexpr uint32_t PREP_THREADS = 1024;
 constexpr uint32_t COL_THREADS = 256;
 constexpr uint32_t TAG_SHOR = 3;
+constexpr uint32_t SMALL_SORT = 1u << 16;  // keys one workgroup sorts
 
 __device__ __forceinline__ uint64_t powmod(uint64_t a, uint64_t e, uint64_t N) {
     uint64_t r = 1 % N, b = a % N;  // N < 2^31: every product below 2^62
@@ -39,13 +40,13 @@ __device__ __forceinline__ uint64_t powmod(uint64_t a, uint64_t e, uint64_t N) {
     return r;
 }
 
-// Draws, f, then a bitonic sort of the Tpad keys (f << 32 | x, padding all
-// ones) in place: one workgroup, a barrier between steps.
-__global__ void __launch_bounds__(PREP_THREADS) shor_prepare_kernel(uint64_t N, uint64_t a, uint32_t n, uint32_t T,
-                                                                   uint32_t Tpad, uint32_t seed_lo, uint32_t seed_hi,
-                                                                   uint64_t *__restrict__ keys) {
-    const uint32_t mask = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
-    for (uint32_t b = threadIdx.x; b < Tpad / 4; b += PREP_THREADS) {
+// Keys of Philox blocks b0, b0 + step, ... below Tpad / 4: (f << 32 | x),
+// padding all ones.
+__device__ __forceinline__ void draw_keys(uint64_t N, uint64_t a, uint32_t n, uint32_t T, uint32_t Tpad,
+                                          uint32_t seed_lo, uint32_t seed_hi, uint64_t *__restrict__ keys,
+                                          uint32_t b0, uint32_t step) {
+    const uint32_t mask = (1u << n) - 1u;
+    for (uint32_t b = b0; b < Tpad / 4; b += step) {
         const U4 u = philox4x32_10(b, 0u, 0u, TAG_SHOR << 16, seed_lo, seed_hi);
         const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
@@ -59,22 +60,48 @@ __global__ void __launch_bounds__(PREP_THREADS) shor_prepare_kernel(uint64_t N, 
             keys[i] = key;
         }
     }
+}
+
+// One compare-exchange of the bitonic network (sequence size `size`,
+// distance `stride`) for pair index i < Tpad / 2.
+__device__ __forceinline__ void bitonic_pair(uint64_t *__restrict__ keys, uint32_t i, uint32_t size,
+                                             uint32_t stride) {
+    const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
+    const uint32_t hi = lo + stride;
+    const bool up = (lo & size) == 0;
+    const uint64_t p = keys[lo], q = keys[hi];
+    if ((p > q) == up) {
+        keys[lo] = q;
+        keys[hi] = p;
+    }
+}
+
+// Small T: draws, f and the whole sort in one workgroup, a barrier between
+// the steps of the network.
+__global__ void __launch_bounds__(PREP_THREADS) shor_prepare_kernel(uint64_t N, uint64_t a, uint32_t n, uint32_t T,
+                                                                   uint32_t Tpad, uint32_t seed_lo, uint32_t seed_hi,
+                                                                   uint64_t *__restrict__ keys) {
+    draw_keys(N, a, n, T, Tpad, seed_lo, seed_hi, keys, threadIdx.x, PREP_THREADS);
     __syncthreads();
     for (uint32_t size = 2; size <= Tpad; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = threadIdx.x; i < Tpad / 2; i += PREP_THREADS) {
-                const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
-                const uint32_t hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t p = keys[lo], q = keys[hi];
-                if ((p > q) == up) {
-                    keys[lo] = q;
-                    keys[hi] = p;
-                }
-            }
+            for (uint32_t i = threadIdx.x; i < Tpad / 2; i += PREP_THREADS) bitonic_pair(keys, i, size, stride);
             __syncthreads();
         }
     }
+}
+
+// Large T: the draws over the whole grid, then one launch per step.
+__global__ void __launch_bounds__(256) shor_draw_kernel(uint64_t N, uint64_t a, uint32_t n, uint32_t T,
+                                                       uint32_t Tpad, uint32_t seed_lo, uint32_t seed_hi,
+                                                       uint64_t *__restrict__ keys) {
+    draw_keys(N, a, n, T, Tpad, seed_lo, seed_hi, keys, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
+}
+
+__global__ void __launch_bounds__(256) shor_bitonic_kernel(uint64_t *__restrict__ keys, uint32_t Tpad,
+                                                          uint32_t size, uint32_t stride) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < Tpad / 2) bitonic_pair(keys, i, size, stride);
 }
 
 // ks = k << (32 - n): the 32-bit product ks x is (k x mod 2^n) << (32 - n),
@@ -131,10 +158,22 @@ uint32_t shor_pad(uint32_t T) {
 hipError_t launch_shor(uint64_t N, uint64_t a, uint32_t n, uint32_t T, uint64_t seed, float *P, uint64_t *keys,
                        hipStream_t s) {
     const uint32_t Tpad = shor_pad(T);
-    hipLaunchKernelGGL(shor_prepare_kernel, dim3(1), dim3(PREP_THREADS), 0, s, N, a, n, T, Tpad, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), keys);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (Tpad <= SMALL_SORT) {
+        hipLaunchKernelGGL(shor_prepare_kernel, dim3(1), dim3(PREP_THREADS), 0, s, N, a, n, T, Tpad, (uint32_t)seed,
+                           (uint32_t)(seed >> 32), keys);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        const uint32_t g = (Tpad / 2 + 255) / 256;
+        hipLaunchKernelGGL(shor_draw_kernel, dim3((Tpad / 4 + 255) / 256), dim3(256), 0, s, N, a, n, T, Tpad,
+                           (uint32_t)seed, (uint32_t)(seed >> 32), keys);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (uint32_t size = 2; size <= Tpad; size <<= 1)
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                hipLaunchKernelGGL(shor_bitonic_kernel, dim3(g), dim3(256), 0, s, keys, Tpad, size, stride);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+    }
     const uint32_t grid = (uint32_t)(((1ull << n) + COL_THREADS - 1) / COL_THREADS);
     hipLaunchKernelGGL(shor_column_kernel, dim3(grid), dim3(COL_THREADS), 0, s, (const uint64_t *)keys, n, T,
                        1.0 / (double)T, 1.0 / (double)(1ull << n), P);

@@ -132,3 +132,30 @@ def test_paper_27_bit_example(env):
     say("27-bit: median", med, "clusters above 2 x median:", len(centres))
     assert len(centres) == r
     assert all(min(abs(c - p) for p in peaks + [2 ** n]) <= 2 for c in centres)
+
+
+def test_table1_20_bit_example(env):
+    """Table 1's 20-bit case: N = 961,307, a = 5 (order 479,568), n = 20,
+    T = 2 r column samples (more than 2^16 keys: the multi-launch sort).
+    Keys bit-exact; P at 8 random k within the FP32 bound; the local maxima
+    of P above its median are exactly the r outputs nearest j 2^n / r, so
+    counting peaks gives the order."""
+    N, a, n = 961307, 5, 20
+    r = shor.order(N, a)
+    assert r == 479568
+    T = 2 * r
+    P, keys = run(env, N, a, n, T, 0)
+    xs, want = oracle_keys(N, a, n, T, 0)
+    assert np.array_equal(keys, want)
+    p = P.cpu().numpy().astype(np.float64)
+    ks = np.random.default_rng(2).integers(0, 1 << n, 8)
+    ref = shor.column_probs(N, a, n, xs, ks=ks.tolist())
+    tol_abs, pmax = bound(N, a, n, xs)
+    err = np.abs(p[ks] - ref)
+    say("20-bit: max |dP|", err.max(), "bound", tol_abs + 2.0 ** -23 * pmax)
+    assert (err <= tol_abs + 2.0 ** -23 * np.maximum(ref, pmax * 1e-3)).all()
+    lm = (p > np.roll(p, 1)) & (p >= np.roll(p, -1)) & (p > np.median(p))
+    peaks = np.zeros(1 << n, dtype=bool)
+    peaks[[int(round(j * 2 ** n / r)) % 2 ** n for j in range(r)]] = True
+    say("20-bit: peaks counted", int(lm.sum()), "order", r)
+    assert np.array_equal(lm, peaks)

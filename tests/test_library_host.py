@@ -363,7 +363,7 @@ def test_shor_argument_errors_before_device(pb):
     assert pb.shor_work_bytes(15, 7, 4, 250) == 8 * 256
     assert pb.shor_work_bytes(98743069, 10424, 27, 250) == 8 * 256
     for args in [(2, 1, 4, 10), (15, 1, 4, 10), (15, 15, 4, 10), (15, 7, 0, 10), (15, 7, 31, 10),
-                 (15, 7, 4, 0), (15, 7, 4, (1 << 20) + 1), (1 << 31, 7, 4, 10)]:
+                 (15, 7, 4, 0), (15, 7, 4, (1 << 22) + 1), (1 << 31, 7, 4, 10)]:
         with pytest.raises(pb.PbitError) as e:
             pb.shor_work_bytes(*args)
         assert e.value.name == "INVALID_ARG", args
