@@ -13,9 +13,12 @@ the passage of the paper it follows:
                 Eq. (path), the magnitude circuit and Z of Eq. (weightedS)
   compile.py    gate energies Eq. (UE) as magnitude / phase-bin tables,
                 the Appendix's exact elimination of zero entries (copy / XOR
-                / NOT), free p-bits, cones, real-energy factors, colouring
+                / NOT / CCNOT), free p-bits, cones, real-energy factors,
+                colouring; the lattice of a free-bit assignment evaluated
+                gate by gate (three-qubit permutation gates)
   chain.c       Philox4x32-10 and the Gibbs chain of Fig. 2 steps 1-3,
-  chain.py      replayed chain by chain (plain C, loaded through ctypes)
+  chain.py      replayed chain by chain (plain C, loaded through ctypes;
+                circuits with non-affine gates in plain Python)
   estimator.py  Eqs. (U343), (U23), (U26), (U30): amplitudes, sigma, TV
   ancestral.py  an independent exact sampler of p_C (layer-by-layer)
   made.py       FP64 MADE forward / backward / Adam (the learned proposal)

@@ -135,6 +135,9 @@ def gibbs(comp, chains, burn_in, sweeps, seed=0, circuit_id=0, chain_begin=0,
           sweep_offset=0, init_state=None, threads=1, tag=TAG_GIBBS, tables=None):
     """Replay `chains` chains (global indices chain_begin...).  Returns
     (final lattice words uint32[chains, W], histogram uint64[2^n, 2^K])."""
+    if comp.nonlinear:
+        return gibbs_forward(comp, chains, burn_in, sweeps, seed, circuit_id, chain_begin, sweep_offset,
+                             init_state, tag)
     t = tables if tables is not None else Tables(comp)
     W = comp.W
     hist = np.zeros(1 << (comp.n + comp.K), dtype=np.uint64)
@@ -164,3 +167,33 @@ def gibbs(comp, chains, burn_in, sweeps, seed=0, circuit_id=0, chain_begin=0,
     if rc != 0:
         raise RuntimeError("oracle_gibbs_run failed")
     return out, hist.reshape(1 << comp.n, 1 << comp.K)
+
+
+def gibbs_forward(comp, chains, burn_in, sweeps, seed=0, circuit_id=0, chain_begin=0, sweep_offset=0,
+                  init_state=None, tag=TAG_GIBBS):
+    """The chain of Fig. 2 steps 1-3 for circuits with non-affine gates
+    (whose magnitudes are all constant, so every conditional is 1/2): a
+    sweep redraws each free bit b as u < 2^31 from word b mod 4 of the
+    Philox block at counter (sweep, b / 4, chain, circuit_id | tag << 16),
+    the lattice of the new free bits is evaluated gate by gate, and each
+    post-burn-in sweep bins (alpha, phase).  Plain Python."""
+    from . import compile as ocomp
+    W, h, K = comp.W, comp.h, comp.K
+    hist = np.zeros(1 << (comp.n + K), dtype=np.uint64)
+    out = np.zeros((chains, W), dtype=np.uint32)
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    for lc in range(chains):
+        chain = chain_begin + lc
+        words = None if init_state is None else np.asarray(init_state, dtype=np.uint32).reshape(chains, W)[lc]
+        for it in range(burn_in + sweeps):
+            s = sweep_offset + it
+            f = []
+            for blk in range((h + 3) // 4):
+                f.extend(int(u < (1 << 31)) for u in philox((s, blk, chain, circuit_id | (tag << 16)), key))
+            x = ocomp.forward_lattice(comp, f[:h])
+            if it >= burn_in:
+                _, k = ocomp.path_weight(comp, x)
+                hist[(ocomp.alpha_of(comp, x) << K) | k] += 1
+            words = ocomp.pack_words(x, W)
+        out[lc] = words if words is not None else ocomp.pack_words(comp.const, W)
+    return out, hist.reshape(1 << comp.n, 1 << K)

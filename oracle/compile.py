@@ -17,10 +17,16 @@ Paper passages followed:
     with hard zeros eliminated every assignment of the free p-bits is a
     valid path.
 
-The lattice bit of layer l (0..d) and qubit q has index l*n + q.  Every
-lattice bit is an affine GF(2) form of the free bits: a constant XOR a set
-of free bits.  The cone of free bit b is the set of lattice bits whose form
-contains b; flipping b flips exactly its cone.
+  * Appendix CCNOT: a three-qubit permutation gate is also deterministic
+    (s_1 XOR (s_2 AND s_3) for the Toffoli), but not affine.
+
+The lattice bit of layer l (0..d) and qubit q has index l*n + q.  Without
+three-qubit gates every lattice bit is an affine GF(2) form of the free
+bits: a constant XOR a set of free bits.  The cone of free bit b is the set
+of lattice bits whose form contains b; flipping b flips exactly its cone.
+With a non-affine permutation gate the circuit is `nonlinear`: the lattice
+of a free-bit assignment is then found by evaluating the gates layer by
+layer (`forward_lattice`), which is the definition in every case.
 """
 from __future__ import annotations
 
@@ -68,6 +74,8 @@ class OGate:
         if nz.all():
             self.kind = "branch"
             self.perm = None
+            if self.a > 2:
+                raise CompileError("three-qubit gates must be permutations")
         elif (nz.sum(axis=0) == 1).all() and (nz.sum(axis=1) == 1).all():
             self.perm = [int(np.nonzero(nz[:, i])[0][0]) for i in range(dim)]
             self.kind = "copy" if self.perm == list(range(dim)) else "derived"
@@ -102,7 +110,9 @@ def compile_circuit(circ):
     L = n * (d + 1)
     gates = [OGate(g, n, K) for g in circ.gates]
 
-    # affine forms (constant bit, frozenset of free bits) per lattice bit
+    # affine forms (constant bit, frozenset of free bits) per lattice bit;
+    # None once a bit depends on a non-affine gate
+    nonlinear = False
     forms = [None] * L
     for q in range(n):
         forms[q] = ((circ.input >> q) & 1, frozenset())
@@ -133,31 +143,39 @@ def compile_circuit(circ):
             for j in range(g.a):
                 c = (g.perm[0] >> j) & 1
                 A = [((g.perm[1 << t] >> j) & 1) ^ c for t in range(g.a)]
+                affine = True
                 for i in range(dim):
                     want = (g.perm[i] >> j) & 1
                     got = c
                     for t in range(g.a):
                         got ^= A[t] & ((i >> t) & 1)
                     if want != got:
-                        raise CompileError("non-affine permutation")
+                        affine = False
                 f = (c, frozenset())
                 for t in range(g.a):
-                    if A[t]:
-                        f = _xor(f, ins[t])
+                    if A[t] and f is not None:
+                        f = None if ins[t] is None else _xor(f, ins[t])
+                if not affine:
+                    nonlinear = True
+                    f = None
                 forms[g.out_bits[j]] = f
     h = len(free_pos)
     cone = [set() for _ in range(h)]
-    for p, (_, s) in enumerate(forms):
-        for b in s:
-            cone[b].add(p)
-    const = np.array([forms[p][0] for p in range(L)], dtype=np.uint8)
+    if nonlinear:
+        if not all(g.const_mag for g in gates):
+            raise CompileError("non-affine gates need every gate magnitude constant")
+        cone = None
+    else:
+        for p, (_, s) in enumerate(forms):
+            for b in s:
+                cone[b].add(p)
 
     # real-energy factors of each free bit: gates whose magnitude is not
     # constant and whose scope meets the cone, in gate order
     factors = []
     for b in range(h):
         factors.append([gi for gi, g in enumerate(gates)
-                        if not g.const_mag and g.scope & cone[b]])
+                        if not g.const_mag and g.scope & cone[b]] if cone is not None else [])
     fscope = [set().union(*[gates[gi].scope for gi in factors[b]]) if factors[b] else set()
               for b in range(h)]
 
@@ -166,7 +184,7 @@ def compile_circuit(circ):
     for b in range(h):
         used = set()
         for b2 in range(b):
-            if (cone[b2] & fscope[b]) or (cone[b] & fscope[b2]):
+            if cone is not None and ((cone[b2] & fscope[b]) or (cone[b] & fscope[b2])):
                 used.add(colour[b2])
         c = 0
         while c in used:
@@ -183,6 +201,8 @@ def compile_circuit(circ):
         Z *= g.col_sum
 
     out = Compiled()
+    out.nonlinear = nonlinear
+    out.circuit = circ
     out.n, out.d, out.K, out.L = n, d, K, L
     out.W = (L + 31) // 32
     out.gates = gates
@@ -190,7 +210,8 @@ def compile_circuit(circ):
     out.free_pos = free_pos
     out.h = h
     out.cone = cone
-    out.const = const
+    out.const = forward_lattice(out, [0] * h) if nonlinear else \
+        np.array([forms[p][0] for p in range(L)], dtype=np.uint8)
     out.factors = factors
     out.colour = colour
     out.ncolours = ncol
@@ -200,8 +221,40 @@ def compile_circuit(circ):
     return out
 
 
+def forward_lattice(comp, f):
+    """Lattice bits for the free-bit assignment f, gate by gate in layer
+    order: layer 0 is the input state, an idle qubit copies its bit, a gate
+    without zero entries takes its outputs from the free bits (numbered by
+    ascending lattice index), and a permutation gate maps its input bits to
+    the output of its one nonzero entry (Appendix)."""
+    n, d = comp.n, comp.d
+    x = np.zeros(comp.L, dtype=np.uint8)
+    for q in range(n):
+        x[q] = (comp.circuit.input >> q) & 1
+    slot = {p: b for b, p in enumerate(comp.free_pos)}
+    for layer in range(1, d + 1):
+        for q in range(n):
+            x[layer * n + q] = x[(layer - 1) * n + q]
+        for g in comp.gates:
+            if g.layer != layer:
+                continue
+            if g.kind == "branch":
+                for p in g.out_bits:
+                    x[p] = f[slot[p]]
+            else:
+                i = sum(int(x[p]) << j for j, p in enumerate(g.in_bits))
+                o = g.perm[i]
+                for j, p in enumerate(g.out_bits):
+                    x[p] = (o >> j) & 1
+    return x
+
+
 def lattice_from_free(comp, f):
-    """Lattice bits for the free-bit assignment f (sequence of 0/1)."""
+    """Lattice bits for the free-bit assignment f (sequence of 0/1): the
+    constant lattice with the cones of the set free bits flipped (affine
+    circuits), else `forward_lattice`."""
+    if comp.nonlinear:
+        return forward_lattice(comp, f)
     x = comp.const.copy()
     for b in range(comp.h):
         if f[b]:

@@ -16,6 +16,7 @@ import test_oracle_chain as tchain  # tests/ is on sys.path under pytest
 import test_oracle_exact as texact
 import test_oracle_made as tmade
 import test_oracle_shor as tshor
+import test_oracle_nonlinear as tnl
 
 
 def caught(*pins):
@@ -163,6 +164,26 @@ def test_wrong_sign_in_loss_gradient_is_caught(monkeypatch):
     assert caught(*MADE_PINS)
 
 
+NONLINEAR_PINS = [tnl.test_toffoli_truth_table] + [
+    (tnl.test_compiled_paths_with_toffoli_reproduce_statevector, (s,)) for s in range(8)]
+
+
+def test_inverted_permutation_in_forward_lattice_is_caught(monkeypatch):
+    orig = ocomp.forward_lattice
+
+    def forward_lattice(comp, f):
+        saved = [(g, g.perm) for g in comp.gates if g.perm is not None]
+        try:
+            for g, p in saved:
+                g.perm = [p.index(i) for i in range(len(p))]
+            return orig(comp, f)
+        finally:
+            for g, p in saved:
+                g.perm = p
+    monkeypatch.setattr(ocomp, "forward_lattice", forward_lattice)
+    assert caught(*NONLINEAR_PINS)
+
+
 SHOR_PINS = [tshor.test_n15_a7_closed_form, tshor.test_peaks_at_multiples_of_2n_over_r] + [
     (tshor.test_all_columns_once_equals_circuit, args) for args in [(15, 7, 4), (21, 2, 5)]]
 
@@ -178,7 +199,7 @@ def test_inverse_qft_without_normalisation_is_caught(monkeypatch):
     assert caught(*SHOR_PINS)
 
 
-@pytest.mark.parametrize("pin", EXACT_PINS[:4] + CHAIN_PINS + MADE_PINS + SHOR_PINS,
+@pytest.mark.parametrize("pin", EXACT_PINS[:4] + CHAIN_PINS + MADE_PINS + SHOR_PINS + NONLINEAR_PINS[:2],
                          ids=lambda p: getattr(p, "__name__", str(p)))
 def test_pins_pass_on_the_unmodified_oracle(pin):
     """Control: the same pins pass when nothing is planted."""

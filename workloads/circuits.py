@@ -363,3 +363,63 @@ def random_asymmetric(n, d, seed, K=3):
             used.add(q)
             used.add(p)
     return circuit(f"rasym_n{n}_d{d}_s{seed}", n, d, K, gates, 0)
+
+
+def mat_perm3(perm):
+    """Three-qubit permutation gate: input index i (s_{q0} + 2 s_{q1} +
+    4 s_{q2}) goes to output perm[i]."""
+    U = [[0] * 8 for _ in range(8)]
+    for i in range(8):
+        U[perm[i]][i] = 1
+    return _mat(U)
+
+
+# Toffoli on qubits (target, c1, c2): s_t XOR (s_c1 AND s_c2), the Appendix's
+# CCNOT; Peres = Toffoli then CNOT(c1 -> c2), a permutation that is not its
+# own inverse (so a transposed matrix changes the result)
+TOFFOLI_PERM = [i ^ ((i >> 1) & (i >> 2) & 1) for i in range(8)]
+PERES_PERM = [(lambda j: j ^ (((j >> 1) & 1) << 2))(i ^ ((i >> 1) & (i >> 2) & 1)) for i in range(8)]
+
+
+def toffoli(layer, target, c1, c2):
+    re, im = mat_perm3(TOFFOLI_PERM)
+    return {"layer": layer, "qubits": [target, c1, c2], "kind": "CCNOT", "re": re, "im": im}
+
+
+def peres(layer, target, c1, c2):
+    re, im = mat_perm3(PERES_PERM)
+    return {"layer": layer, "qubits": [target, c1, c2], "kind": "PERES", "re": re, "im": im}
+
+
+def random_clifford_t_toffoli(n, d, seed, K=3, p1=0.5, p3=0.25, name=None):
+    """Random Clifford+T layers with three-qubit permutation gates: per layer
+    each unused qubit gets, with probability p1, a gate from {H, S, T};
+    otherwise, with probability p3 and two unused partners, a Toffoli or a
+    Peres gate (itself as target), else CNOT or CZ with one partner."""
+    rng = random.Random(seed)
+    gates = []
+    for layer in range(1, d + 1):
+        order = list(range(n))
+        rng.shuffle(order)
+        used = set()
+        for q in order:
+            if q in used:
+                continue
+            free = [p for p in range(n) if p not in used and p != q]
+            if rng.random() < p1 or not free:
+                gates.append(gate1(layer, q, rng.choice(["H", "S", "T"])))
+                used.add(q)
+                continue
+            if len(free) >= 2 and rng.random() < p3:
+                c1, c2 = rng.sample(free, 2)
+                gates.append((toffoli if rng.random() < 0.5 else peres)(layer, q, c1, c2))
+                used.update([q, c1, c2])
+                continue
+            p = rng.choice(free)
+            if rng.random() < 0.5:
+                gates.append(cnot(layer, q, p))
+            else:
+                gates.append(cz(layer, min(q, p), max(q, p)))
+            used.add(q)
+            used.add(p)
+    return circuit(name or "rctt_n%d_d%d_s%d" % (n, d, seed), n, d, K, gates, 0)
