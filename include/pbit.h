@@ -67,14 +67,20 @@ typedef struct pbit_circuit_s *pbit_circuit;
 typedef struct pbit_proposal_s *pbit_proposal;
 
 /* One gate.  layer in 1..d; gates of one layer act on disjoint qubits; an
- * idle qubit carries the identity.  re/im hold U[out][in] row-major
- * (2x2 uses the first 4 entries). */
+ * idle qubit carries the identity.  re/im hold U[out][in] row-major, the
+ * state index s_{q[0]} + 2 s_{q[1]} + 4 s_{q[2]} (2x2 uses the first 4
+ * entries, 4x4 the first 16).  One- and two-qubit gates: any zero-free,
+ * diagonal or permutation matrix with phases on the 2 pi / 2^K grid.
+ * Three-qubit gates: permutation matrices with every nonzero entry 1 (the
+ * Appendix's CCNOT and the like: deterministic, their outputs of degree 2
+ * in the inputs); a circuit with one whose outputs are not affine needs
+ * every other gate's magnitude constant, else UNSUPPORTED_GATE. */
 typedef struct {
     uint32_t layer;
-    uint32_t arity; /* 1 or 2 */
-    uint32_t q[2];
-    double re[16];
-    double im[16];
+    uint32_t arity; /* 1, 2 or 3 */
+    uint32_t q[3];
+    double re[64];
+    double im[64];
 } pbit_gate;
 
 /* One circuit.  input_state is beta (bit q = qubit q).  zero_tol: an entry
@@ -146,12 +152,15 @@ typedef struct {
                                    workgroup, else LDS bins when they fit, else 4 when HBM
                                    atomics would bound the sweep (few free bits and lattice
                                    words), else 2. */
-    uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles */
+    uint32_t toggle_mode;       /* 0 = auto, 1 = LDS toggle tables, 2 = per-bit cone toggles
+                                   (MODE_UNAVAILABLE for circuits with three-qubit products,
+                                   which rebuild the lattice each sweep from the tables) */
     uint32_t persistent;        /* 0 = auto (sets of more than one circuit), 1 = always, 2 = never */
     uint32_t wg_per_cu;         /* persistent grid: workgroups per CU; 0 = autotuned */
     uint32_t lanes_per_chain;   /* 0 = auto, 1, 2, 4 or 8.  Circuits whose conditionals are all
                                    1/2, single-circuit launches only: 2 with the generic kernel
-                                   splits a chain's lattice words over two lanes; with the
+                                   splits a chain's lattice words over two lanes (one lane for
+                                   circuits with three-qubit products); with the
                                    specialised kernel L lanes split a chain's sweeps (lane r runs
                                    sweeps r, r + L, ...).  4 and 8 need the specialised kernel. */
     uint32_t specialize;        /* 0 = auto (large runs of circuits whose conditionals are all 1/2),

@@ -52,6 +52,8 @@ enum Header : uint32_t {
     H_OFF_QG,     // NQG group records
     H_NRE,        // gates with non-constant magnitude (real-energy records)
     H_OFF_RE,     // NRE records of RE_STRIDE words
+    H_NY,         // derived AND variables of three-qubit permutation gates
+    H_OFF_Y,      // NY records of Y_STRIDE words, in layer order
     H_COUNT = 48  // header words (must exceed every index above)
 };
 
@@ -70,6 +72,9 @@ constexpr int THR_STRIDE = 2 + MAX_SCOPE;
 // at index out * 2^a + in (0 where the entry is zero).
 constexpr int RE_STRIDE = 8 + 32;
 constexpr inline uint32_t qd_stride(uint32_t K, uint32_t W) { return 2 + K * W; }
+// derived AND variable: [0], [1] = lattice bits (previous layer) whose AND it
+// is, then WS words: the lattice bits whose form contains it
+constexpr inline uint32_t y_stride(uint32_t WS) { return 2 + WS; }
 // quadratic record: [0] = offset delta (1..63), [1] = mask of nonzero planes,
 // then K planes of WS words: bit i of plane t set if bit t of the coefficient
 // of x_i x_{i+delta} is set.

@@ -7,7 +7,14 @@
 //   |U| entries -> magnitudes (exp(-Re E)), arg U -> integer phase bins
 //   k with U/|U| = exp(2 pi i k / 2^K) (exp(-i Im E)).
 // Lattice: every bit is an affine GF(2) form of the free bits; the cone of
-// free bit b is every lattice bit whose form contains b.
+// free bit b is every lattice bit whose form contains b.  A three-qubit
+// permutation gate (the Appendix's CCNOT) has outputs of degree 2 in its
+// inputs: each product of two input bits becomes a derived variable y
+// (the AND of two lattice bits of the previous layer), so every bit is an
+// affine form of the free bits and the y's, and the lattice of a sweep is
+// the free bits' part followed by the y's in layer order, each y read off
+// the lattice so far and its cone XORed in when it is 1.  Such circuits
+// must have every conditional 1/2.
 // Conditionals (Eq. (weightedS) restricted to one free bit): the factors of
 // b are the gates with non-constant magnitude whose scope meets its cone;
 // the threshold table over the factors' scope bits holds
@@ -41,21 +48,23 @@ namespace {
 struct Form {
     uint32_t c = 0;
     std::array<uint64_t, MAX_FW / 2> s{};  // 256 free bits
+    uint64_t y = 0;                          // derived AND variables
     void xor_with(const Form &o) {
         c ^= o.c;
         for (size_t i = 0; i < s.size(); ++i) s[i] ^= o.s[i];
+        y ^= o.y;
     }
     bool has(uint32_t b) const { return (s[b >> 6] >> (b & 63)) & 1u; }
 };
 
 struct GateC {
     uint32_t layer, a;
-    uint32_t q[2];
-    uint32_t in_bits[2], out_bits[2];
-    double mag[16];
-    int32_t ph[16];  // -1 where the entry is zero
+    uint32_t q[3];
+    uint32_t in_bits[3], out_bits[3];
+    double mag[64];
+    int32_t ph[64];  // -1 where the entry is zero
     int kind;        // 0 branching, 1 copy, 2 derived
-    uint32_t perm[4];
+    uint32_t perm[8];
     bool const_mag;
     bool has_col_sum;
     double col_sum;
@@ -96,11 +105,13 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     std::vector<int> owner((size_t)(d + 1) * n, -1);
     for (uint32_t gi = 0; gi < D.n_gates; ++gi) {
         const pbit_gate &g = D.gates[gi];
-        if (g.arity != 1 && g.arity != 2) return fail(err, PBIT_E_INVALID_ARG, "gate arity must be 1 or 2");
+        if (g.arity < 1 || g.arity > 3) return fail(err, PBIT_E_INVALID_ARG, "gate arity must be 1, 2 or 3");
         if (g.layer < 1 || g.layer > d) return fail(err, PBIT_E_INVALID_ARG, "gate layer out of 1..d");
         for (uint32_t j = 0; j < g.arity; ++j)
             if (g.q[j] >= n) return fail(err, PBIT_E_INVALID_ARG, "gate qubit >= n");
-        if (g.arity == 2 && g.q[0] == g.q[1]) return fail(err, PBIT_E_INVALID_ARG, "two-qubit gate on one qubit");
+        for (uint32_t j = 0; j < g.arity; ++j)
+            for (uint32_t t = 0; t < j; ++t)
+                if (g.q[j] == g.q[t]) return fail(err, PBIT_E_INVALID_ARG, "gate acts twice on one qubit");
         for (uint32_t j = 0; j < g.arity; ++j) {
             int &o = owner[(size_t)g.layer * n + g.q[j]];
             if (o >= 0) return fail(err, PBIT_E_INVALID_ARG, "gates of one layer overlap");
@@ -109,11 +120,10 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
         GateC &c = gates[gi];
         c.layer = g.layer;
         c.a = g.arity;
-        c.q[0] = g.q[0];
-        c.q[1] = g.arity == 2 ? g.q[1] : 0;
+        for (uint32_t j = 0; j < 3; ++j) c.q[j] = j < g.arity ? g.q[j] : 0;
         const uint32_t dim = 1u << c.a;
         bool any_zero = false;
-        int row_nz[4] = {0, 0, 0, 0}, col_nz[4] = {0, 0, 0, 0};
+        int row_nz[8] = {0, 0, 0, 0, 0, 0, 0, 0}, col_nz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (uint32_t o = 0; o < dim; ++o)
             for (uint32_t i = 0; i < dim; ++i) {
                 const double re = g.re[o * dim + i], im = g.im[o * dim + i];
@@ -135,6 +145,7 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
                 col_nz[i]++;
             }
         if (!any_zero) {
+            if (c.a == 3) return fail(err, PBIT_E_UNSUPPORTED_GATE, "three-qubit gates must be permutations");
             c.kind = KIND_BRANCH;
         } else {
             bool mono = true;
@@ -148,6 +159,11 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
                 ident = ident && c.perm[i] == i;
             }
             c.kind = ident ? KIND_COPY : KIND_DERIVED;
+            if (c.a == 3)
+                for (uint32_t t = 0; t < dim * dim; ++t)
+                    if (c.ph[t] > 0 || (c.ph[t] == 0 && std::fabs(c.mag[t] - 1.0) > 1e-9))
+                        return fail(err, PBIT_E_UNSUPPORTED_GATE,
+                                    "three-qubit permutation gates must have entries exactly 1");
         }
         double mx = 0, mn = 1e300;
         for (uint32_t t = 0; t < dim * dim; ++t)
@@ -172,14 +188,16 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     }
     // gate order: layer, then lowest qubit
     std::stable_sort(gates.begin(), gates.end(), [](const GateC &x, const GateC &y) {
-        uint32_t mx = x.a == 2 ? std::min(x.q[0], x.q[1]) : x.q[0];
-        uint32_t my = y.a == 2 ? std::min(y.q[0], y.q[1]) : y.q[0];
+        uint32_t mx = x.q[0], my = y.q[0];
+        for (uint32_t j = 1; j < x.a; ++j) mx = std::min(mx, x.q[j]);
+        for (uint32_t j = 1; j < y.a; ++j) my = std::min(my, y.q[j]);
         return x.layer != y.layer ? x.layer < y.layer : mx < my;
     });
     const uint32_t G = (uint32_t)gates.size();
 
-    // ---- affine forms over the free bits ----------------------------------
+    // ---- affine forms over the free bits and the derived AND variables -----
     std::vector<Form> form(L);
+    std::vector<std::array<uint32_t, 2>> yvar;  // lattice bits whose AND each y is
     for (uint32_t q = 0; q < n; ++q) form[q].c = (uint32_t)((D.input_state >> q) & 1u);
     std::vector<uint32_t> fpos;
     {
@@ -203,24 +221,41 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
             for (uint32_t gi = 0; gi < G; ++gi) {
                 const GateC &g = gates[gi];
                 if (g.layer != l || g.kind == KIND_BRANCH) continue;
-                // out_j(in) = c_j ^ sum_t A_jt in_t (every permutation of <= 2
-                // bits is affine over GF(2))
+                // out_j as a polynomial over GF(2) in the inputs (Moebius
+                // transform of its truth table): every permutation of <= 2
+                // bits is affine; of 3 bits, each output is balanced, so of
+                // degree <= 2, and a product in_t in_u becomes a y variable
                 const uint32_t dim = 1u << g.a;
-                Form nf[2];
+                Form nf[3];
+                uint32_t ypair[3][3];
+                for (auto &r : ypair)
+                    for (auto &v : r) v = ~0u;
                 for (uint32_t j = 0; j < g.a; ++j) {
-                    const uint32_t cj = (g.perm[0] >> j) & 1u;
-                    uint32_t A[2] = {0, 0};
-                    for (uint32_t t = 0; t < g.a; ++t) A[t] = ((g.perm[1u << t] >> j) & 1u) ^ cj;
-                    for (uint32_t i = 0; i < dim; ++i) {
-                        uint32_t v = cj;
-                        for (uint32_t t = 0; t < g.a; ++t) v ^= A[t] & ((i >> t) & 1u);
-                        if (v != ((g.perm[i] >> j) & 1u))
-                            return fail(err, PBIT_E_UNSUPPORTED_GATE, "non-affine permutation gate");
-                    }
-                    nf[j] = Form();
-                    nf[j].c = cj;
+                    uint32_t anf[8];
+                    for (uint32_t i = 0; i < dim; ++i) anf[i] = (g.perm[i] >> j) & 1u;
                     for (uint32_t t = 0; t < g.a; ++t)
-                        if (A[t]) nf[j].xor_with(form[g.in_bits[t]]);
+                        for (uint32_t i = 0; i < dim; ++i)
+                            if (i & (1u << t)) anf[i] ^= anf[i ^ (1u << t)];
+                    nf[j] = Form();
+                    nf[j].c = anf[0];
+                    for (uint32_t m = 1; m < dim; ++m) {
+                        if (!anf[m]) continue;
+                        const int deg = __builtin_popcount(m);
+                        if (deg == 1) {
+                            nf[j].xor_with(form[g.in_bits[__builtin_ctz(m)]]);
+                        } else if (deg == 2) {
+                            const uint32_t t = __builtin_ctz(m), u = 31 - __builtin_clz(m);
+                            if (ypair[t][u] == ~0u) {
+                                if (yvar.size() >= 64)
+                                    return fail(err, PBIT_E_TOO_LARGE, "more than 64 products in permutation gates");
+                                ypair[t][u] = (uint32_t)yvar.size();
+                                yvar.push_back({g.in_bits[t], g.in_bits[u]});
+                            }
+                            nf[j].y ^= 1ull << ypair[t][u];
+                        } else {
+                            return fail(err, PBIT_E_UNSUPPORTED_GATE, "permutation gate output of degree 3");
+                        }
+                    }
                 }
                 for (uint32_t j = 0; j < g.a; ++j) form[g.out_bits[j]] = nf[j];
             }
@@ -237,6 +272,11 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     std::vector<uint32_t> constw(W, 0);
     for (uint32_t p = 0; p < L; ++p)
         if (form[p].c) constw[p >> 5] |= 1u << (p & 31);
+    const uint32_t ny = (uint32_t)yvar.size();
+    std::vector<std::vector<uint32_t>> ycone(ny, std::vector<uint32_t>(W, 0));
+    for (uint32_t p = 0; p < L; ++p)
+        for (uint32_t j = 0; j < ny; ++j)
+            if ((form[p].y >> j) & 1u) ycone[j][p >> 5] |= 1u << (p & 31);
 
     // ---- factors, threshold tables, colouring -----------------------------
     auto gate_scope_meets = [&](const GateC &g, const std::vector<uint32_t> &mask) {
@@ -260,6 +300,9 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
         }
         if (!factors[b].empty()) uniform = false;
     }
+    if (ny && !uniform)
+        return fail(err, PBIT_E_UNSUPPORTED_GATE,
+                    "three-qubit gates with products need every gate magnitude constant (all conditionals 1/2)");
     std::vector<uint32_t> colour(h, 0);
     uint32_t ncol = h ? 1 : 0;
     for (uint32_t b = 0; b < h; ++b) {
@@ -543,6 +586,20 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
         blob[H_TOGW] = TW;
         blob[H_OFF_TOG] = append(tog);
     }
+    {
+        // derived AND variables in layer order: the two lattice bits, then
+        // the cone (WS words)
+        std::vector<uint32_t> yr;
+        for (uint32_t j = 0; j < ny; ++j) {
+            yr.push_back(yvar[j][0]);
+            yr.push_back(yvar[j][1]);
+            std::vector<uint32_t> c = ycone[j];
+            c.resize(WS, 0u);
+            yr.insert(yr.end(), c.begin(), c.end());
+        }
+        blob[H_NY] = ny;
+        blob[H_OFF_Y] = append(yr);
+    }
     blob[H_THR_TOTAL] = (uint32_t)thrtab.size();
     blob[H_HBITS] = n + K;
     // pad so that kernels may read a few words past any array
@@ -557,6 +614,7 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
     out.WS = WS;
     out.L = L;
     out.h = h;
+    out.ny = ny;
     out.ncol = ncol;
     out.uniform = uniform;
     out.n_gates = G;

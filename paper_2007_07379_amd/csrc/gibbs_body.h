@@ -138,6 +138,18 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
                         if (4 * q + 3 < W) x[4 * q + 3] ^= r[q].w;
                     }
                 }
+                // three-qubit permutation gates: each derived AND variable,
+                // in layer order, read off the lattice so far
+                const uint32_t ny = B[H_NY];
+                const uint32_t *yr = B + B[H_OFF_Y];
+                const uint32_t ys = y_stride(B[H_WS]);
+                for (uint32_t j = 0; j < ny; ++j) {
+                    const uint32_t p = yr[j * ys], q = yr[j * ys + 1];
+                    const uint32_t y = (select_word<W>(x, p >> 5) >> (p & 31)) & (select_word<W>(x, q >> 5) >> (q & 31));
+                    const uint32_t m = 0u - (y & 1u);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) x[w] ^= m & yr[j * ys + 2 + w];
+                }
             } else
             for (uint32_t c = 0; c < ncol; ++c) {
 #pragma unroll

@@ -135,6 +135,23 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
     const uint32_t npaths = path_hist ? 1u << h : 0u;
     out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0) + npaths * 4;
 
+    // three-qubit permutation gates: each derived AND variable in layer
+    // order, read off the lattice so far, its cone XORed in when 1
+    auto emit_y = [&](std::ostringstream &o, const std::string &ind) {
+        const uint32_t ny = B[H_NY];
+        const uint32_t *yr = B + B[H_OFF_Y];
+        const uint32_t ys = y_stride(WS);
+        for (uint32_t j = 0; j < ny; ++j) {
+            const uint32_t p = yr[j * ys], q = yr[j * ys + 1];
+            o << ind << "{\n" << ind << "    const u32 m = 0u - ((x[" << (p >> 5) << "] >> " << (p & 31) << "u) & (x["
+              << (q >> 5) << "] >> " << (q & 31) << "u) & 1u);\n";
+            for (uint32_t w = 0; w < W; ++w) {
+                const uint32_t mk = yr[j * ys + 2 + w];
+                if (mk) o << ind << "    x[" << w << "] ^= m & " << hx(mk) << ";\n";
+            }
+            o << ind << "}\n";
+        }
+    };
     // lattice = const ^ rows of every block, p_j given by an expression
     auto emit_build = [&](std::ostringstream &o, const std::string &ind, auto pexpr) {
         for (uint32_t w = 0; w < W; ++w) o << ind << "x[" << w << "] = " << hx(cw[w]) << ";\n";
@@ -162,6 +179,7 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
             }
             o << ind << "}\n";
         }
+        emit_y(o, ind);
     };
     // phase polynomial and bin of the lattice in x: declares `bin`
     auto emit_bin = [&](std::ostringstream &o, const std::string &ind) {
@@ -282,6 +300,7 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
             }
             o << "            }\n";
         }
+        emit_y(o, "            ");
         o << "            if (s >= bin_from) {\n";
         emit_bin(o, "                ");
         if (lds_hist)

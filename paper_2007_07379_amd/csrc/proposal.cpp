@@ -319,6 +319,9 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
     const uint32_t H = cfg && cfg->hidden ? cfg->hidden : 1024;
     if (H % 64 || H > 4096) return set_error(PBIT_E_INVALID_ARG, "hidden must be a multiple of 64, <= 4096");
     if (k.h == 0) return set_error(PBIT_E_INVALID_ARG, "circuit has no free p-bit");
+    if (k.ny)
+        return set_error(PBIT_E_MODE_UNAVAILABLE,
+                         "the proposal builds paths through cones; three-qubit products are not affine");
     auto *q = new pbit_proposal_s();
     q->circ = c;
     q->idx = idx;

@@ -156,6 +156,10 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         return set_error(PBIT_E_INVALID_ARG, "sweep counter would wrap");
     if (cfg->use_graph && !stream) return set_error(PBIT_E_INVALID_ARG, "graph replay needs a non-null stream");
     const uint32_t nc = (uint32_t)c->circuits.size();
+    for (uint32_t i = 0; i < nc; ++i)
+        if (cfg->chains[i] && c->circuits[i].ny && cfg->toggle_mode == 2)
+            return set_error(PBIT_E_MODE_UNAVAILABLE,
+                             "per-bit cone toggles cannot follow three-qubit products: toggle_mode 2");
     uint64_t state_words = 0;
     for (uint32_t i = 0; i < nc; ++i) {
         const uint64_t ch = cfg->chains[i];

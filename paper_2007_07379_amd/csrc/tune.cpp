@@ -37,6 +37,12 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     }
     if (cfg->lanes_per_chain == 1) t.pair = false;
     if (cfg->lanes_per_chain == 2) t.pair = k.uniform;
+    // three-qubit products need the whole lattice in one lane, rebuilt each
+    // sweep from the toggle tables
+    if (k.ny) {
+        t.pair = false;
+        t.tog = true;
+    }
     if (cfg->toggle_mode == 1) t.tog = true;
     if (cfg->toggle_mode == 2) t.tog = false;
     if (cfg->hist_mode == 1) t.lds_hist = true;

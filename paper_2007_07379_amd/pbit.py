@@ -32,8 +32,8 @@ class PbitError(RuntimeError):
 
 
 class Gate(C.Structure):
-    _fields_ = [("layer", C.c_uint32), ("arity", C.c_uint32), ("q", C.c_uint32 * 2),
-                ("re", C.c_double * 16), ("im", C.c_double * 16)]
+    _fields_ = [("layer", C.c_uint32), ("arity", C.c_uint32), ("q", C.c_uint32 * 3),
+                ("re", C.c_double * 64), ("im", C.c_double * 64)]
 
 
 class CircuitDesc(C.Structure):
@@ -124,8 +124,8 @@ def _gates_of(c):
         G = Gate()
         G.layer = g["layer"]
         G.arity = len(g["qubits"])
-        G.q[0] = g["qubits"][0]
-        G.q[1] = g["qubits"][1] if len(g["qubits"]) > 1 else 0
+        for j, q in enumerate(g["qubits"]):
+            G.q[j] = q
         for i, v in enumerate(re):
             G.re[i] = v
         for i, v in enumerate(im):

@@ -44,7 +44,8 @@ def test_every_declared_symbol_is_exported(pb):
 H = dict(MAGIC=0, N=1, D=2, K=3, W=4, H=5, L=6, CID=7, NCOL=8, UNIFORM=9, AWORD=10, ASHIFT=11,
          PCONST=12, LINMASK=13, NQD=14, FW=15, OFF_CONST=16, OFF_FPOS=17, OFF_CONE=18, OFF_LIN=19,
          OFF_QD=20, OFF_COLIDX=21, OFF_COLENT=22, OFF_THRINFO=23, OFF_THRTAB=24, THR_TOTAL=25,
-         HBITS=26, TOTAL=27, WS=28, NBLK=29, TOGW=30, OFF_TOG=31, NQG=32, OFF_QG=33)
+         HBITS=26, TOTAL=27, WS=28, NBLK=29, TOGW=30, OFF_TOG=31, NQG=32, OFF_QG=33, NRE=34, OFF_RE=35,
+         NY=36, OFF_Y=37)
 MAX_FW = 8
 THR_STRIDE = 14
 
@@ -182,6 +183,62 @@ def test_library_compile_equals_oracle(pb, name, c):
             assert blob.threshold(b, xw) == och.threshold(comp, b, xw, tables), (trial, b)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_library_compile_with_toffoli_equals_oracle(pb, seed):
+    """Circuits with Toffoli and Peres gates: the image's lattice of a free-bit
+    assignment — constant words, the cones of the set free bits, then each
+    derived AND variable in order, read off the lattice so far and its cone
+    XORed in when 1 — equals the oracle's gate-by-gate lattice, and the
+    image's phase polynomial gives the oracle's phase bin."""
+    c = wc.random_clifford_t_toffoli(6, 8, 900 + seed, K=3, p3=0.5)
+    lib_set = pb.CircuitSet(c)
+    b = lib_set.export(0)
+    blob = Blob(b)
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    assert comp.nonlinear and blob.uniform == 1
+    assert (blob.h, blob.fpos) == (comp.h, list(comp.free_pos))
+    ny, oy = int(b[H["NY"]]), int(b[H["OFF_Y"]])
+    assert ny > 0
+    st = 2 + blob.WS
+    rng = np.random.default_rng(seed)
+    for trial in range(60):
+        f = rng.integers(0, 2, size=comp.h)
+        x = np.array(blob.const, dtype=np.uint32)
+        for bb in range(comp.h):
+            if f[bb]:
+                x ^= blob.cone[bb]
+        for j in range(ny):
+            p, q = int(b[oy + j * st]), int(b[oy + j * st + 1])
+            if (x[p >> 5] >> (p & 31)) & (x[q >> 5] >> (q & 31)) & 1:
+                x ^= b[oy + j * st + 2:oy + j * st + 2 + blob.W]
+        want = ocomp.forward_lattice(comp, f)
+        assert np.array_equal(x, ocomp.pack_words(want, comp.W)), trial
+        assert blob.phase(x) == ocomp.path_weight(comp, want)[1], trial
+
+
+def test_toffoli_rejections(pb):
+    """A zero-free three-qubit gate, a permutation with a phase, and a
+    Toffoli beside a gate of non-constant magnitude are refused."""
+    U = np.ones((8, 8)) / math.sqrt(8)
+    g = {"layer": 1, "qubits": [0, 1, 2], "kind": "F3", "re": U.tolist(), "im": np.zeros((8, 8)).tolist()}
+    assert _err(pb, wc.circuit("f3", 3, 1, 3, [g], 0)) == "UNSUPPORTED_GATE"
+    re, im = wc.mat_perm3(wc.TOFFOLI_PERM)
+    im = np.array(im)
+    re = np.array(re)
+    re[7, 6], im[7, 6] = 0.0, 1.0  # i instead of 1
+    g = {"layer": 1, "qubits": [0, 1, 2], "kind": "T3", "re": re.tolist(), "im": im.tolist()}
+    assert _err(pb, wc.circuit("t3", 3, 1, 2, [g], 0)) == "UNSUPPORTED_GATE"
+    gs = [wc.gate1(1, 1, "RH", wc.mat_rh(math.pi / 8)), wc.toffoli(2, 0, 1, 2)]
+    assert _err(pb, wc.circuit("nu", 3, 2, 1, gs, 0)) == "UNSUPPORTED_GATE"
+    # an affine three-qubit permutation (a cyclic shift of the qubits) is fine
+    # anywhere
+    shift = [((i << 1) | (i >> 2)) & 7 for i in range(8)]
+    re, im = wc.mat_perm3(shift)
+    g = {"layer": 2, "qubits": [0, 1, 2], "kind": "ROT", "re": re, "im": im}
+    s = pb.CircuitSet(wc.circuit("rot", 3, 2, 1, [wc.gate1(1, 1, "RH", wc.mat_rh(math.pi / 8)), g], 0))
+    assert s.info(0)["uniform"] == 0
+
+
 def _err(pb, c):
     with pytest.raises(pb.PbitError) as e:
         pb.CircuitSet(c)
@@ -282,6 +339,13 @@ def test_launch_shape_rules(pb):
     assert sc.launch_shape([4096], 0, 2, specialize=2, hist_mode=3)["lds_hist"] == 2
     assert sc.launch_shape([4096], 100, 20000, specialize=2, hist_mode=1)["lds_hist"] == 1
     assert sc.launch_shape([4096], 100, 20000, specialize=1, hist_mode=3)["kernel"] != pb.KERNEL_SPECIALISED
+    # three-qubit products: one lane, toggle tables; the specialised kernel
+    # splits sweeps over lanes as usual
+    tt = pb.CircuitSet(wc.random_clifford_t_toffoli(12, 30, 13, K=3))
+    sh = tt.launch_shape([65536], 0, 100, specialize=1)
+    assert sh["kernel"] == pb.KERNEL_ONE_LANE and sh["toggle_tables"] == 1
+    assert tt.launch_shape([65536], 0, 100, specialize=1, lanes_per_chain=2)["kernel"] == pb.KERNEL_ONE_LANE
+    assert tt.launch_shape([4096], 0, 100, specialize=2, lanes_per_chain=4)["lanes_per_chain"] == 4
     # histograms beyond LDS, up to 2^20 bins, and sweeps short enough that
     # HBM atomics would bound them: bins stored as keys
     sw = pb.CircuitSet(wc.random_clifford_t(16, 17, 500, K=3))
@@ -310,6 +374,7 @@ SPEC_CIRCUITS = [
     ("hchain_odd", lambda: wc.hadamard_chain(33, K=1)),
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3)),
     ("rct_shallow", lambda: wc.random_clifford_t(16, 4, 24, K=3)),
+    ("rctt", lambda: wc.random_clifford_t_toffoli(12, 30, 13, K=3)),
 ]
 
 
