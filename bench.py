@@ -37,7 +37,7 @@ PHILOX_SLOTS_PER_SWEEP = 5
 UPDATE_FIXED_SLOTS = 1  # the threshold compare u < T
 
 HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19, OFF_QD=20, WS=28,
-           NQG=32, OFF_QG=33)
+           NQG=32, OFF_QG=33, NY=36, OFF_Y=37)
 
 
 def algorithmic_ops(blob):
@@ -49,7 +49,9 @@ def algorithmic_ops(blob):
     cone word for the expected half of the updates that flip; per sample two
     slots (AND, popcount) per nonzero linear phase-plane word, two (funnel
     shift, AND/OR) per nonzero quadratic mask word plus two per word of each
-    quadratic popcount, and three for the output index and the bin."""
+    quadratic popcount, and three for the output index and the bin; per
+    derived AND variable of a three-qubit gate, four plus one per nonzero
+    word of its cone, per sweep."""
     g = lambda k: int(blob[HDR[k]])
     h, W, WS, K = g("H"), g("W"), g("WS"), g("K")
     cone = blob[g("OFF_CONE"):g("OFF_CONE") + h * WS].reshape(h, WS)[:, :W]
@@ -76,6 +78,13 @@ def algorithmic_ops(blob):
             o += 1 + WS
         per_sample += 2 * int(np.count_nonzero(union))
     per_sample += 3  # alpha funnel shift + mask, histogram index
+    # three-qubit products: per derived variable, two shifts, a three-input
+    # AND with 1 and the negation to a mask (4), then one three-input
+    # AND-XOR per nonzero word of its cone
+    ny, oy = g("NY"), g("OFF_Y")
+    for j in range(ny):
+        rec = blob[oy + j * (2 + WS):oy + (j + 1) * (2 + WS)]
+        per_sweep += 4 + int(np.count_nonzero(rec[2:2 + W]))
     return per_sweep, per_sample, nnz
 
 
@@ -85,6 +94,11 @@ def cpu_baseline(c, h, burn, sweeps, chains_sample):
     from oracle import compile as ocomp
     comp = ocomp.compile_circuit(oc.from_dict(c))
     threads = os.cpu_count() or 1
+    if comp.nonlinear:
+        # the gate-by-gate replay is plain Python on one core: a few chains
+        threads = 1
+        chains_sample = 2
+        sweeps = min(sweeps, 2000)
     t0 = time.perf_counter()
     och.gibbs(comp, chains_sample, burn, sweeps, seed=0, threads=threads)
     dt = time.perf_counter() - t0

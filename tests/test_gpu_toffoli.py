@@ -146,3 +146,29 @@ def test_toffoli_amplitudes_4_sigma(env):
     assert ok, info
     T = chains * sweeps
     assert oest.tv_path(h, pm) < 3 * oest.expected_iid_tv(pm, T)
+
+
+def test_full_rctt12_sampled_chains_and_amplitudes(env):
+    """The benchmark's launch (rctt12: 65,536 chains x (200 + 10,000)
+    sweeps, automatic shape): three chains replayed by the oracle end in the
+    same lattice words; amplitudes pass the 4-sigma rule against the 2^12
+    statevector; TV_path at the i.i.d. level."""
+    torch, pbit = env
+    w = wc.WORKLOADS["rctt12"]
+    c = wc.workload_circuit("rctt12")
+    chains, burn, sweeps = w["chains"], w["burn_in"], w["sweeps"]
+    s = pbit.CircuitSet(c)
+    say("rctt12 full run", s.launch_shape([chains], burn, sweeps))
+    st, h = run(env, s, chains, burn, sweeps, 0, 0)
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    for ch in (0, 31337, chains - 1):
+        say("oracle replay of chain", ch)
+        st_o, _ = och.gibbs(comp, 1, burn, sweeps, seed=0, chain_begin=ch)
+        assert np.array_equal(st[ch], st_o[0]), ch
+    circ = oc.from_dict(c)
+    psi = exact.statevector(circ)
+    pm, _ = exact.magnitude_marginal(circ)
+    amp, sre, sim = s.amplitudes(h)
+    ok, info = oest.z_gate(amp, sre, sim, psi)
+    assert ok, info
+    assert oest.tv_path(h, pm) < 3 * oest.expected_iid_tv(pm, chains * sweeps)

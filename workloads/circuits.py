@@ -300,6 +300,9 @@ WORKLOADS = {
                                            one_q=("H", "S", "T", "SX"),
                                            kmax=1),
                     chains=131072, burn_in=200, sweeps=2000),
+    # rct12's shape with Toffoli and Peres gates (three-qubit products)
+    "rctt12": dict(make=lambda: random_clifford_t_toffoli(12, 40, 1, K=3),
+                   chains=65536, burn_in=200, sweeps=10000),
 }
 
 
