@@ -13,7 +13,8 @@ the passage of the paper it follows:
                 Eq. (path), the magnitude circuit and Z of Eq. (weightedS)
   compile.py    gate energies Eq. (UE) as magnitude / phase-bin tables,
                 the Appendix's exact elimination of zero entries (copy / XOR
-                / NOT / CCNOT), free p-bits, cones, real-energy factors,
+                / NOT / CCNOT) or e^(-J) soft zeros, free p-bits, cones,
+                real-energy factors,
                 colouring; the lattice of a free-bit assignment evaluated
                 gate by gate (three-qubit permutation gates)
   chain.c       Philox4x32-10 and the Gibbs chain of Fig. 2 steps 1-3,

@@ -7,7 +7,10 @@
  *   step 1/2  each free p-bit is redrawn from its exact conditional
  *             (heat bath / Glauber: no rejection), colour by colour;
  *   step 3    after each post-burn-in sweep the path's output state alpha
- *             and phase exp(-i Im E) = exp(2 pi i k / 2^K) are binned.
+ *             and phase exp(-i Im E) = exp(2 pi i k / 2^K) are binned,
+ *             unless the path meets a soft zero (a zero entry replaced by
+ *             e^(-J) for sampling, Appendix): then it is not a path of the
+ *             circuit and is not binned.
  *
  * The conditional of free bit b is evaluated directly on the lattice:
  *   w_v = product over its real-energy factors (ascending gate order) of
@@ -129,7 +132,11 @@ static void sample(const oracle_run *R, const uint32_t *x, uint64_t *hist) {
     uint32_t alpha = 0;
     for (int q = 0; q < n; ++q) alpha |= (uint32_t)getbit(x, d * n + q) << q;
     int64_t k = 0;
-    for (int g = 0; g < R->G; ++g) k += R->ph[16 * g + gate_index(R, g, x)];
+    for (int g = 0; g < R->G; ++g) {
+        const int e = R->ph[16 * g + gate_index(R, g, x)];
+        if (e < 0) return; /* a soft zero: not a path of the circuit, not binned */
+        k += e;
+    }
     uint32_t phi = (uint32_t)(k & ((1 << K) - 1));
     hist[((uint64_t)alpha << K) | phi] += 1;
 }

@@ -92,8 +92,10 @@ class Tables:
             self.in_bits[gi, :g.a] = g.in_bits
             self.out_bits[gi, :g.a] = g.out_bits
             m = len(g.mag)
-            self.mag[gi, :m] = g.mag
-            self.ph[gi, :m] = np.where(g.ph >= 0, g.ph, 0)
+            # the chain samples with e^(-J) at soft zeros; a soft zero's
+            # phase entry is -1, which the replay reads as "do not bin"
+            self.mag[gi, :m] = g.mag_s
+            self.ph[gi, :m] = np.where(g.ph >= 0, g.ph, np.where(g.soft, -1, 0))
         off = [0]
         ids = []
         for b in range(h):

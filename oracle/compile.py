@@ -19,6 +19,13 @@ Paper passages followed:
 
   * Appendix CCNOT: a three-qubit permutation gate is also deterministic
     (s_1 XOR (s_2 AND s_3) for the Toffoli), but not affine.
+  * Appendix, general zero elements: a gate whose zeros are neither absent
+    nor a permutation pattern (controlled-H, controlled rotations) gets
+    e^(-J) in place of each zero for sampling (soft_J); such a gate then
+    creates free p-bits like a gate without zeros.  The chain samples the
+    law with e^(-J) weights and bins only paths that avoid every soft zero,
+    which are exactly the paths of the circuit with their weights |psi_C|
+    (conditioning), whatever J.
 
 The lattice bit of layer l (0..d) and qubit q has index l*n + q.  Without
 three-qubit gates every lattice bit is an affine GF(2) form of the free
@@ -46,7 +53,7 @@ class CompileError(ValueError):
 class OGate:
     """One gate with its magnitude / phase tables indexed out * 2^a + in."""
 
-    def __init__(self, g, n, K):
+    def __init__(self, g, n, K, soft_J=None):
         self.layer = g.layer
         self.qubits = list(g.qubits)
         self.a = len(g.qubits)
@@ -79,9 +86,18 @@ class OGate:
         elif (nz.sum(axis=0) == 1).all() and (nz.sum(axis=1) == 1).all():
             self.perm = [int(np.nonzero(nz[:, i])[0][0]) for i in range(dim)]
             self.kind = "copy" if self.perm == list(range(dim)) else "derived"
+        elif soft_J is not None and self.a <= 2:
+            self.kind = "branch"
+            self.perm = None
         else:
             raise CompileError("gate with partial zero pattern")
-        mags = self.mag[self.mag > 0]
+        # sampling magnitudes: e^(-J) at the soft zeros of a gate that has
+        # both zero and nonzero entries but no permutation pattern
+        self.soft = np.zeros(dim * dim, dtype=bool)
+        if self.kind == "branch" and not nz.all():
+            self.soft = ~nz.ravel()
+        self.mag_s = np.where(self.soft, math.exp(-soft_J) if soft_J is not None else 0.0, self.mag)
+        mags = self.mag_s[self.mag_s > 0]
         self.const_mag = bool(mags.max() - mags.min() <= MAG_RTOL * mags.max())
         cols = [sum(self.mag[o * dim + i] for o in range(dim)) for i in range(dim)]
         self.col_sum = cols[0] if max(cols) - min(cols) <= MAG_RTOL * max(cols) else None
@@ -105,10 +121,10 @@ class Compiled:
     pass
 
 
-def compile_circuit(circ):
+def compile_circuit(circ, soft_J=None):
     n, d, K = circ.n, circ.d, circ.K
     L = n * (d + 1)
-    gates = [OGate(g, n, K) for g in circ.gates]
+    gates = [OGate(g, n, K, soft_J) for g in circ.gates]
 
     # affine forms (constant bit, frozenset of free bits) per lattice bit;
     # None once a bit depends on a non-affine gate
@@ -275,6 +291,19 @@ def path_weight(comp, x):
         m *= g.mag[idx]
         k += int(g.ph[idx])
     return m, k % (2 ** comp.K)
+
+
+def violates(comp, x):
+    """True if the path given as lattice bits meets a soft zero of a gate."""
+    return any(g.soft[g.index(x)] for g in comp.gates)
+
+
+def sampling_weight(comp, x):
+    """Product of the sampling magnitudes (e^(-J) at soft zeros)."""
+    m = 1.0
+    for g in comp.gates:
+        m *= g.mag_s[g.index(x)]
+    return m
 
 
 def alpha_of(comp, x):

@@ -426,3 +426,59 @@ def random_clifford_t_toffoli(n, d, seed, K=3, p1=0.5, p3=0.25, name=None):
             used.add(q)
             used.add(p)
     return circuit(name or "rctt_n%d_d%d_s%d" % (n, d, seed), n, d, K, gates, 0)
+
+
+def mat_ch_tc():
+    """Controlled Hadamard on qubits (target, control): H on the target when
+    the control (second listed qubit) is 1; zeros neither absent nor a
+    permutation pattern."""
+    r = 1.0 / math.sqrt(2.0)
+    return _mat([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, r, r], [0, 0, r, -r]])
+
+
+def mat_cry_tc(theta):
+    """Controlled rotated Hadamard of Eq. (HadT) on (target, control)."""
+    c, s = math.cos(theta), math.sin(theta)
+    return _mat([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, c, s], [0, 0, s, -c]])
+
+
+def ch(layer, control, target):
+    re, im = mat_ch_tc()
+    return {"layer": layer, "qubits": [target, control], "kind": "CH", "re": re, "im": im}
+
+
+def crh(layer, control, target, theta, kind="CRH"):
+    re, im = mat_cry_tc(theta)
+    return {"layer": layer, "qubits": [target, control], "kind": kind, "re": re, "im": im}
+
+
+def random_clifford_t_ch(n, d, seed, K=3, p1=0.55, p_ch=0.4, name=None):
+    """Random Clifford+T layers with controlled-Hadamard gates: per layer
+    each unused qubit gets, with probability p1, a gate from {H, S, T},
+    otherwise a partner and, with probability p_ch, a controlled Hadamard
+    (itself as control), else CNOT or CZ."""
+    rng = random.Random(seed)
+    gates = []
+    for layer in range(1, d + 1):
+        order = list(range(n))
+        rng.shuffle(order)
+        used = set()
+        for q in order:
+            if q in used:
+                continue
+            free = [p for p in range(n) if p not in used and p != q]
+            if rng.random() < p1 or not free:
+                gates.append(gate1(layer, q, rng.choice(["H", "S", "T"])))
+                used.add(q)
+                continue
+            p = rng.choice(free)
+            r = rng.random()
+            if r < p_ch:
+                gates.append(ch(layer, q, p))
+            elif r < p_ch + (1 - p_ch) / 2:
+                gates.append(cnot(layer, q, p))
+            else:
+                gates.append(cz(layer, min(q, p), max(q, p)))
+            used.add(q)
+            used.add(p)
+    return circuit(name or "rctch_n%d_d%d_s%d" % (n, d, seed), n, d, K, gates, 0)
