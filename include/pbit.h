@@ -95,6 +95,13 @@ typedef struct {
     uint32_t K; /* 1..8 */
     double zero_tol, phase_tol;
     uint32_t circuit_id;
+    double soft_zero_J; /* 0: a one- or two-qubit gate whose zeros are neither absent nor a
+                           permutation pattern is UNSUPPORTED_GATE.  J > 0: soft zeros (Appendix):
+                           such a gate samples with e^(-J) in place of its zeros and creates free
+                           p-bits; a path that meets one of those entries is not a path of the
+                           circuit and is not binned, so the binned law is exact for any J (J only
+                           sets how often chains pass through such paths).  Counts then total
+                           fewer than chains x sweeps: pass their sum as T to pbit_amplitudes. */
 } pbit_circuit_desc;
 
 typedef struct {

@@ -54,6 +54,8 @@ enum Header : uint32_t {
     H_OFF_RE,     // NRE records of RE_STRIDE words
     H_NY,         // derived AND variables of three-qubit permutation gates
     H_OFF_Y,      // NY records of Y_STRIDE words, in layer order
+    H_NSOFT,      // gates with soft zeros
+    H_OFF_SOFT,   // NSOFT records of SOFT_STRIDE words
     H_COUNT = 48  // header words (must exceed every index above)
 };
 
@@ -75,6 +77,11 @@ constexpr inline uint32_t qd_stride(uint32_t K, uint32_t W) { return 2 + K * W; 
 // derived AND variable: [0], [1] = lattice bits (previous layer) whose AND it
 // is, then WS words: the lattice bits whose form contains it
 constexpr inline uint32_t y_stride(uint32_t WS) { return 2 + WS; }
+// gate with soft zeros: [0], [1] input lattice bits, [2], [3] output lattice
+// bits, [4] mask: bit o * 4 + i set where the entry (out o, in i) is a soft
+// zero (one-qubit gates use bits 0 and 2 as i0 and o0; the others never
+// set); a sample whose lattice meets one is not binned
+constexpr uint32_t SOFT_STRIDE = 5;
 // quadratic record: [0] = offset delta (1..63), [1] = mask of nonzero planes,
 // then K planes of WS words: bit i of plane t set if bit t of the coefficient
 // of x_i x_{i+delta} is set.

@@ -22,6 +22,14 @@
 //   w_v = product over factors (ascending gate order) of |U_g| at bit b = v.
 // Colouring: free bits whose cones touch each other's factor scopes
 // conflict; greedy colouring in ascending free-bit order.
+// Soft zeros (Appendix, general zero elements; desc.soft_zero_J > 0): a
+// one- or two-qubit gate whose zeros are neither absent nor a permutation
+// pattern (controlled Hadamard, controlled rotations) gets e^(-J) in place
+// of each zero for sampling and creates free p-bits like a gate without
+// zeros; a path that meets one of these entries is not a path of the
+// circuit and is not binned, so the binned law is the circuit's exactly.
+// The phases at soft entries never reach a binned sample: they are chosen
+// (mod 2^K) so that the gate's phase polynomial keeps degree <= 2.
 // Phase polynomial: each gate's phase table is expanded as a multilinear
 // polynomial over Z_{2^K} in its lattice bits (Moebius transform); the sum
 // is stored as bit planes (linear terms per lattice bit, quadratic terms per
@@ -59,6 +67,7 @@ struct Form {
 
 struct GateC {
     uint32_t layer, a;
+    bool soft[16];  // soft zeros (two-qubit tables at most)
     uint32_t q[3];
     uint32_t in_bits[3], out_bits[3];
     double mag[64];
@@ -78,6 +87,76 @@ inline void setb(std::vector<uint32_t> &x, uint32_t p) { x[p >> 5] |= 1u << (p &
 pbit_status fail(std::string &err, pbit_status st, const std::string &msg) {
     err = msg;
     return st;
+}
+
+// Values at the soft entries of a two-qubit phase table (index o * 4 + i,
+// which is also its Moebius index over the bits i0 i1 o0 o1) that make the
+// coefficients of degree 3 and 4 vanish mod 2^K: five linear equations
+// with coefficients +-1 over Z_(2^K), solved by elimination on odd (unit)
+// pivots, free unknowns 0.  False if that finds no solution.
+bool complete_soft_phases(int32_t ph[16], const bool soft[16], uint32_t K) {
+    const int64_t M = (int64_t)1 << K, MK = M - 1;
+    std::vector<uint32_t> unk;
+    for (uint32_t t = 0; t < 16; ++t)
+        if (soft[t]) unk.push_back(t);
+    const uint32_t S_list[5] = {7, 11, 13, 14, 15};
+    const size_t nu = unk.size();
+    std::vector<std::vector<int64_t>> A(5, std::vector<int64_t>(nu, 0));
+    std::vector<int64_t> rhs(5, 0);
+    for (int r = 0; r < 5; ++r) {
+        const uint32_t S = S_list[r];
+        for (uint32_t T = 0; T < 16; ++T) {
+            if ((T & S) != T) continue;
+            const int64_t sg = (__builtin_popcount(S ^ T) & 1) ? -1 : 1;
+            if (soft[T]) {
+                for (size_t u = 0; u < nu; ++u)
+                    if (unk[u] == T) A[r][u] = (A[r][u] + sg) & MK;
+            } else {
+                rhs[r] = (rhs[r] - sg * ph[T]) & MK;
+            }
+        }
+    }
+    std::vector<int> pivot_col(5, -1);
+    std::vector<bool> used(nu, false);
+    for (int r = 0; r < 5; ++r) {
+        int c = -1;
+        for (size_t u = 0; u < nu && c < 0; ++u)
+            if (!used[u] && (A[r][u] & 1)) c = (int)u;
+        if (c < 0) continue;
+        // scale the row by the inverse of its odd pivot (Newton iteration)
+        int64_t inv = 1;
+        for (int it = 0; it < 6; ++it) inv = (inv * (2 - A[r][c] * inv)) & MK;
+        for (size_t u = 0; u < nu; ++u) A[r][u] = (A[r][u] * inv) & MK;
+        rhs[r] = (rhs[r] * inv) & MK;
+        for (int r2 = 0; r2 < 5; ++r2) {
+            if (r2 == r || !A[r2][c]) continue;
+            const int64_t f = A[r2][c];
+            for (size_t u = 0; u < nu; ++u) A[r2][u] = (A[r2][u] - f * A[r][u]) & MK;
+            rhs[r2] = (rhs[r2] - f * rhs[r]) & MK;
+        }
+        used[c] = true;
+        pivot_col[r] = c;
+    }
+    std::vector<int64_t> val(nu, 0);
+    for (int r = 0; r < 5; ++r) {
+        if (pivot_col[r] >= 0) {
+            val[pivot_col[r]] = rhs[r];
+        } else {
+            for (size_t u = 0; u < nu; ++u)
+                if (A[r][u]) return false;
+            if (rhs[r]) return false;
+        }
+    }
+    for (size_t u = 0; u < nu; ++u) ph[unk[u]] = (int32_t)val[u];
+    // check: no term of degree 3 or 4 is left
+    int64_t f[16];
+    for (uint32_t t = 0; t < 16; ++t) f[t] = ph[t];
+    for (uint32_t j = 0; j < 4; ++j)
+        for (uint32_t a = 0; a < 16; ++a)
+            if (a & (1u << j)) f[a] -= f[a ^ (1u << j)];
+    for (uint32_t a = 0; a < 16; ++a)
+        if (__builtin_popcount(a) >= 3 && (f[a] & MK)) return false;
+    return true;
 }
 
 }  // namespace
@@ -120,6 +199,7 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
         GateC &c = gates[gi];
         c.layer = g.layer;
         c.a = g.arity;
+        for (bool &v : c.soft) v = false;
         for (uint32_t j = 0; j < 3; ++j) c.q[j] = j < g.arity ? g.q[j] : 0;
         const uint32_t dim = 1u << c.a;
         bool any_zero = false;
@@ -144,12 +224,23 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
                 row_nz[o]++;
                 col_nz[i]++;
             }
+        bool mono = true;
+        for (uint32_t t = 0; t < dim; ++t) mono = mono && row_nz[t] == 1 && col_nz[t] == 1;
         if (!any_zero) {
             if (c.a == 3) return fail(err, PBIT_E_UNSUPPORTED_GATE, "three-qubit gates must be permutations");
             c.kind = KIND_BRANCH;
+        } else if (!mono && D.soft_zero_J > 0.0 && c.a <= 2) {
+            // soft zeros: e^(-J) for sampling (below), phases completed
+            for (uint32_t t = 0; t < dim * dim; ++t)
+                if (c.ph[t] < 0) {
+                    c.soft[t] = true;
+                    c.ph[t] = 0;
+                }
+            if (c.a == 2 && !complete_soft_phases(c.ph, c.soft, K))
+                return fail(err, PBIT_E_UNSUPPORTED_GATE,
+                            "soft-zero gate: no phase polynomial of degree <= 2 fits its nonzero entries");
+            c.kind = KIND_BRANCH;
         } else {
-            bool mono = true;
-            for (uint32_t t = 0; t < dim; ++t) mono = mono && row_nz[t] == 1 && col_nz[t] == 1;
             if (!mono) return fail(err, PBIT_E_UNSUPPORTED_GATE,
                                    "gate zero pattern is neither zero-free, diagonal nor a permutation");
             bool ident = true;
@@ -165,13 +256,7 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
                         return fail(err, PBIT_E_UNSUPPORTED_GATE,
                                     "three-qubit permutation gates must have entries exactly 1");
         }
-        double mx = 0, mn = 1e300;
-        for (uint32_t t = 0; t < dim * dim; ++t)
-            if (c.ph[t] >= 0) {
-                mx = std::max(mx, c.mag[t]);
-                mn = std::min(mn, c.mag[t]);
-            }
-        c.const_mag = (mx - mn) <= 1e-9 * mx;
+        // column sums of |U| (exact normalisation), soft zeros counted as 0
         double cmx = 0, cmn = 1e300;
         for (uint32_t i = 0; i < dim; ++i) {
             double s = 0;
@@ -181,6 +266,16 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
         }
         c.has_col_sum = (cmx - cmn) <= 1e-9 * cmx;
         c.col_sum = cmx;
+        // sampling magnitudes
+        for (uint32_t t = 0; t < dim * dim; ++t)
+            if (c.soft[t]) c.mag[t] = std::exp(-D.soft_zero_J);
+        double mx = 0, mn = 1e300;
+        for (uint32_t t = 0; t < dim * dim; ++t)
+            if (c.ph[t] >= 0) {
+                mx = std::max(mx, c.mag[t]);
+                mn = std::min(mn, c.mag[t]);
+            }
+        c.const_mag = (mx - mn) <= 1e-9 * mx;
         for (uint32_t j = 0; j < c.a; ++j) {
             c.in_bits[j] = (c.layer - 1) * n + c.q[j];
             c.out_bits[j] = c.layer * n + c.q[j];
@@ -599,6 +694,31 @@ pbit_status compile_one(const pbit_circuit_desc &D, CompiledCircuit &out, std::s
         }
         blob[H_NY] = ny;
         blob[H_OFF_Y] = append(yr);
+    }
+    {
+        // soft zeros: the four lattice bits of the gate (a one-qubit gate
+        // repeats its bits: index bits 1 and 3 then copy bits 0 and 2, and
+        // the mask is spread to the 4-bit index)
+        std::vector<uint32_t> sr;
+        uint32_t nsoft = 0;
+        for (const GateC &g : gates) {
+            bool any = false;
+            for (bool v : g.soft) any = any || v;
+            if (!any) continue;
+            const uint32_t i1 = g.a == 2 ? g.in_bits[1] : g.in_bits[0];
+            const uint32_t o1 = g.a == 2 ? g.out_bits[1] : g.out_bits[0];
+            uint32_t mask = 0;
+            for (uint32_t idx = 0; idx < 16; ++idx) {
+                const uint32_t i = idx & 3u, o = idx >> 2;
+                if (g.a == 1 && (((i ^ (i >> 1)) & 1u) || ((o ^ (o >> 1)) & 1u))) continue;
+                const uint32_t t = g.a == 2 ? (o * 4 + i) : ((o & 1u) * 2 + (i & 1u));
+                if (g.soft[t]) mask |= 1u << idx;
+            }
+            sr.insert(sr.end(), {g.in_bits[0], i1, g.out_bits[0], o1, mask});
+            ++nsoft;
+        }
+        blob[H_NSOFT] = nsoft;
+        blob[H_OFF_SOFT] = append(sr);
     }
     blob[H_THR_TOTAL] = (uint32_t)thrtab.size();
     blob[H_HBITS] = n + K;

@@ -202,7 +202,7 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
                     }
                 }
             }
-            if (s >= a.bin_from) {
+            if (s >= a.bin_from && !meets_soft_zero<W>(B, x)) {
                 const uint32_t bin = phase_and_bin<W>(B, x, K, n);
                 if (a.lds_hist)
                     atomicAdd(&lds_h[bin], 1u);

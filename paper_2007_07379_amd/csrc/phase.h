@@ -19,6 +19,25 @@ __device__ __forceinline__ uint32_t select_word(const uint32_t (&x)[W + 2], uint
     return r;
 }
 
+// True if the lattice meets a soft zero of a gate (an entry replaced by
+// e^(-J) for sampling): such a path is not one of the circuit's, and the
+// sample is not binned.
+template <int W>
+__device__ __forceinline__ bool meets_soft_zero(const uint32_t *__restrict__ B, const uint32_t (&x)[W + 2]) {
+    const uint32_t ns = B[H_NSOFT];
+    const uint32_t *r = B + B[H_OFF_SOFT];
+    for (uint32_t g = 0; g < ns; ++g, r += SOFT_STRIDE) {
+        uint32_t idx = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t p = r[j];
+            idx |= ((select_word<W>(x, p >> 5) >> (p & 31)) & 1u) << j;
+        }
+        if ((r[4] >> idx) & 1u) return true;
+    }
+    return false;
+}
+
 template <int W>
 __device__ __forceinline__ uint32_t threshold_of(const uint32_t *__restrict__ B, uint32_t b,
                                                  const uint32_t (&x)[W + 2], const uint32_t *lds_thr) {

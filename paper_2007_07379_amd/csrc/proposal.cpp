@@ -322,6 +322,8 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
     if (k.ny)
         return set_error(PBIT_E_MODE_UNAVAILABLE,
                          "the proposal builds paths through cones; three-qubit products are not affine");
+    if (k.blob[H_NSOFT])
+        return set_error(PBIT_E_MODE_UNAVAILABLE, "soft zeros: the MH chain would bin paths that meet them");
     auto *q = new pbit_proposal_s();
     q->circ = c;
     q->idx = idx;

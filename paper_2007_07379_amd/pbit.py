@@ -39,7 +39,8 @@ class Gate(C.Structure):
 class CircuitDesc(C.Structure):
     _fields_ = [("n", C.c_uint32), ("d", C.c_uint32), ("gates", C.POINTER(Gate)),
                 ("n_gates", C.c_uint32), ("input_state", C.c_uint64), ("K", C.c_uint32),
-                ("zero_tol", C.c_double), ("phase_tol", C.c_double), ("circuit_id", C.c_uint32)]
+                ("zero_tol", C.c_double), ("phase_tol", C.c_double), ("circuit_id", C.c_uint32),
+                ("soft_zero_J", C.c_double)]
 
 
 class CircuitInfo(C.Structure):
@@ -137,7 +138,7 @@ def _gates_of(c):
 class CircuitSet:
     """A compiled handle (pbit_circuit) over one or more circuits."""
 
-    def __init__(self, circuits, circuit_ids=None, zero_tol=0.0, phase_tol=0.0):
+    def __init__(self, circuits, circuit_ids=None, zero_tol=0.0, phase_tol=0.0, soft_zero_J=0.0):
         if isinstance(circuits, dict):
             circuits = [circuits]
         self.circuits = list(circuits)
@@ -158,6 +159,7 @@ class CircuitSet:
             descs[i].zero_tol = zero_tol
             descs[i].phase_tol = phase_tol
             descs[i].circuit_id = ids[i]
+            descs[i].soft_zero_J = soft_zero_J
         h = C.c_void_p()
         _check(lib().pbit_compile_circuit(descs, n, C.byref(h)))
         self.handle = h

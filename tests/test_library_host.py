@@ -45,7 +45,7 @@ H = dict(MAGIC=0, N=1, D=2, K=3, W=4, H=5, L=6, CID=7, NCOL=8, UNIFORM=9, AWORD=
          PCONST=12, LINMASK=13, NQD=14, FW=15, OFF_CONST=16, OFF_FPOS=17, OFF_CONE=18, OFF_LIN=19,
          OFF_QD=20, OFF_COLIDX=21, OFF_COLENT=22, OFF_THRINFO=23, OFF_THRTAB=24, THR_TOTAL=25,
          HBITS=26, TOTAL=27, WS=28, NBLK=29, TOGW=30, OFF_TOG=31, NQG=32, OFF_QG=33, NRE=34, OFF_RE=35,
-         NY=36, OFF_Y=37)
+         NY=36, OFF_Y=37, NSOFT=38, OFF_SOFT=39)
 MAX_FW = 8
 THR_STRIDE = 14
 
@@ -214,6 +214,47 @@ def test_library_compile_with_toffoli_equals_oracle(pb, seed):
         want = ocomp.forward_lattice(comp, f)
         assert np.array_equal(x, ocomp.pack_words(want, comp.W)), trial
         assert blob.phase(x) == ocomp.path_weight(comp, want)[1], trial
+
+
+@pytest.mark.parametrize("seed", [0, 2, 4, 6, 8])
+def test_library_compile_with_soft_zeros_equals_oracle(pb, seed):
+    """Controlled Hadamards as soft zeros (J = 2): free bits, cones,
+    colouring and every threshold (the e^(-J) sampling law) equal the
+    oracle's; the image's soft-zero records flag exactly the lattices the
+    oracle calls violating, and on the others its phase polynomial (with
+    the completed phases at the soft entries) gives the oracle's phase."""
+    c = wc.random_clifford_t_ch(5, 7, 400 + seed, K=3)
+    lib_set = pb.CircuitSet(c, soft_zero_J=2.0)
+    b = lib_set.export(0)
+    blob = Blob(b)
+    comp = ocomp.compile_circuit(oc.from_dict(c), soft_J=2.0)
+    assert (blob.h, blob.fpos, blob.colour) == (comp.h, list(comp.free_pos), list(comp.colour))
+    assert blob.uniform == 0
+    tables = och.Tables(comp)
+    assert np.array_equal(blob.cone, tables.cone[:comp.h])
+    ns, os_ = int(b[H["NSOFT"]]), int(b[H["OFF_SOFT"]])
+    assert ns == sum(1 for g in comp.gates if g.soft.any())
+    rng = np.random.default_rng(seed)
+    seen = [0, 0]
+    for trial in range(400):
+        f = rng.integers(0, 2, size=comp.h)
+        x = ocomp.lattice_from_free(comp, f)
+        xw = ocomp.pack_words(x, comp.W)
+        meets = False
+        for g in range(ns):
+            r = b[os_ + 5 * g:os_ + 5 * g + 5]
+            idx = sum(int(x[int(r[j])]) << j for j in range(4))
+            meets = meets or bool((int(r[4]) >> idx) & 1)
+        v = ocomp.violates(comp, x)
+        assert meets == v, trial
+        seen[v] += 1
+        if not v:
+            assert blob.phase(xw) == ocomp.path_weight(comp, x)[1], trial
+        for bb in range(comp.h):
+            assert blob.threshold(bb, xw) == och.threshold(comp, bb, xw, tables), (trial, bb)
+    assert seen[0] and seen[1]
+    with pytest.raises(pb.PbitError):
+        pb.CircuitSet(c)  # no soft_zero_J: refused
 
 
 def test_toffoli_rejections(pb):
