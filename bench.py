@@ -37,7 +37,7 @@ PHILOX_SLOTS_PER_SWEEP = 5
 UPDATE_FIXED_SLOTS = 1  # the threshold compare u < T
 
 HDR = dict(N=1, D=2, K=3, W=4, H=5, LINMASK=13, NQD=14, OFF_CONE=18, OFF_LIN=19, OFF_QD=20, WS=28,
-           NQG=32, OFF_QG=33, NY=36, OFF_Y=37)
+           NQG=32, OFF_QG=33, NY=36, OFF_Y=37, UNIFORM=9, OFF_THRINFO=23)
 
 
 def algorithmic_ops(blob):
@@ -51,7 +51,9 @@ def algorithmic_ops(blob):
     shift, AND/OR) per nonzero quadratic mask word plus two per word of each
     quadratic popcount, and three for the output index and the bin; per
     derived AND variable of a three-qubit gate, four plus one per nonzero
-    word of its cone, per sweep."""
+    word of its cone, per sweep; per update of a circuit with conditionals
+    other than 1/2, two per scope bit of its threshold table (extract and
+    place) and one for the table read."""
     g = lambda k: int(blob[HDR[k]])
     h, W, WS, K = g("H"), g("W"), g("WS"), g("K")
     cone = blob[g("OFF_CONE"):g("OFF_CONE") + h * WS].reshape(h, WS)[:, :W]
@@ -78,6 +80,10 @@ def algorithmic_ops(blob):
             o += 1 + WS
         per_sample += 2 * int(np.count_nonzero(union))
     per_sample += 3  # alpha funnel shift + mask, histogram index
+    if not g("UNIFORM"):
+        ot = g("OFF_THRINFO")
+        for b in range(h):
+            per_sweep += 2 * int(blob[ot + b * 14 + 1]) + 1
     # three-qubit products: per derived variable, two shifts, a three-input
     # AND with 1 and the negation to a mask (4), then one three-input
     # AND-XOR per nonzero word of its cone
@@ -88,11 +94,11 @@ def algorithmic_ops(blob):
     return per_sweep, per_sample, nnz
 
 
-def cpu_baseline(c, h, burn, sweeps, chains_sample):
+def cpu_baseline(c, h, burn, sweeps, chains_sample, soft_J=None):
     from oracle import chain as och
     from oracle import circuit as oc
     from oracle import compile as ocomp
-    comp = ocomp.compile_circuit(oc.from_dict(c))
+    comp = ocomp.compile_circuit(oc.from_dict(c), soft_J=soft_J)
     threads = os.cpu_count() or 1
     if comp.nonlinear:
         # the gate-by-gate replay is plain Python on one core: a few chains
@@ -579,7 +585,8 @@ def main():
     w = wc.WORKLOADS[args.workload]
     c = wc.workload_circuit(args.workload)
     chains, burn, sweeps = w["chains"], w["burn_in"], w["sweeps"]
-    s = pbit.CircuitSet(c)
+    soft_J = w.get("soft_J", 0.0)
+    s = pbit.CircuitSet(c, soft_zero_J=soft_J)
     info = s.info(0)
     h = info["h"]
     blob = s.export(0)
@@ -614,8 +621,9 @@ def main():
                                                           "true" if info["uniform"] else "false"),
              pbit.KERNEL_TWO_LANE: "gibbs_pair_kernel<%d>" % shape["kernel_words"],
              pbit.KERNEL_PERSISTENT: "batched_kernel",
-             pbit.KERNEL_SPECIALISED: "pbit_uniform_sweep (generated for the circuit, %d lanes per chain)"
-                                      % shape["lanes_per_chain"]}[shape["kernel"]]
+             pbit.KERNEL_SPECIALISED: ("pbit_uniform_sweep (generated for the circuit, %d lanes per chain)"
+                                       % shape["lanes_per_chain"]) if info["uniform"] else
+                                      "pbit_general_sweep (generated for the circuit, one lane per chain)"}[shape["kernel"]]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -628,6 +636,10 @@ def main():
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # samples binned by one run (fewer than chains x sweeps with soft zeros)
+    step()
+    torch.cuda.synchronize()
+    binned = float(sum(int(hh.to(torch.int64).sum().item()) & 0xFFFFFFFFFFFF for hh in hists))
     kms = [a.elapsed_time(b) for a, b in ev]
     kernel_s = float(np.mean(kms)) / 1e3
     ms_per_step = wall / args.steps * 1e3
@@ -653,8 +665,10 @@ def main():
                         % (args.workload, c.get("name", ""), info["n"], info["d"], info["K"], chains,
                            burn, sweeps, h),
             "chains": chains, "sweeps": sweeps, "burn_in": burn, "free_bits": h,
+            "soft_zero_J": soft_J,
         },
         "samples_per_s": chains * sweeps / (ms_per_step / 1e3),
+        "binned_samples_per_s": binned / (ms_per_step / 1e3),
         "lattice_bit_updates_per_s": value * info["L"] / max(h, 1),
         "roofline": {
             "bound": "alu",
@@ -673,7 +687,7 @@ def main():
         },
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(c, h, burn, sweeps, min(args.cpu_chains, chains))
+        out["cpu_baseline"] = cpu_baseline(c, h, burn, sweeps, min(args.cpu_chains, chains), soft_J or None)
     print(json.dumps(out))
 
 

@@ -170,10 +170,11 @@ typedef struct {
                                    circuits with three-qubit products); with the
                                    specialised kernel L lanes split a chain's sweeps (lane r runs
                                    sweeps r, r + L, ...).  4 and 8 need the specialised kernel. */
-    uint32_t specialize;        /* 0 = auto (large runs of circuits whose conditionals are all 1/2),
-                                   1 = never, 2 = always for such circuits (MODE_UNAVAILABLE if
-                                   the run-time compile fails): a kernel generated for the circuit
-                                   and compiled with hipRTC on first use (cached in the handle).
+    uint32_t specialize;        /* 0 = auto (runs of 2^33 updates or more), 1 = never, 2 = always
+                                   (MODE_UNAVAILABLE if the run-time compile fails): a kernel
+                                   generated for the circuit and compiled with hipRTC on first use
+                                   (cached in the handle); circuits with conditionals other than
+                                   1/2 get one lane per chain and the colour schedule unrolled.
                                    In a persistent batch, 2 takes the circuits with at least 1,024
                                    chains (at most 256, heaviest by chains x free bits first) out
                                    of the batch into launches of their own specialised kernels;
@@ -330,8 +331,10 @@ typedef struct {
 pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t index,
                                   pbit_launch_shape *out);
 
-/* HIP source of the specialised sweep kernel of circuit `index` (whose
- * conditionals must all be 1/2, else MODE_UNAVAILABLE), with the histogram
+/* HIP source of the specialised sweep kernel of circuit `index`
+ * (`pbit_uniform_sweep` when every conditional is 1/2, else
+ * `pbit_general_sweep`: one lane per chain, the colour schedule unrolled,
+ * lds_hist 0 or 1 only, else MODE_UNAVAILABLE), with the histogram
  * in global memory (lds_hist 0), its bins privatised in LDS (1), path counts
  * in LDS (2; h <= 16, else TOO_LARGE) or bins stored as keys (3), compiled
  * for workgroups of at most

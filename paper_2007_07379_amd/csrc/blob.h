@@ -69,6 +69,9 @@ constexpr inline uint32_t kernel_words(uint32_t W) {
 }
 
 constexpr int THR_STRIDE = 2 + MAX_SCOPE;
+// threshold tables up to this many words are staged in LDS; larger ones are
+// read from the image in device memory
+constexpr uint32_t THR_LDS_MAX_WORDS = 16384;
 // real-energy record: [0] arity a, [1..2] input lattice bits, [3..4] output
 // lattice bits, [5..7] unused, then 16 doubles (as 32 words): ln |U[out][in]|
 // at index out * 2^a + in (0 where the entry is zero).

@@ -20,7 +20,7 @@ size_t gibbs_lds_bytes(const uint32_t *hb, bool tog, bool lds_hist) {
     const uint32_t TW = (WS + 3) & ~3u;
     size_t words = 0;
     if (tog) words += (size_t)hb[H_NBLK] * 16 * TW;
-    words += hb[H_UNIFORM] ? 0 : hb[H_THR_TOTAL];
+    words += hb[H_UNIFORM] || hb[H_THR_TOTAL] > THR_LDS_MAX_WORDS ? 0 : hb[H_THR_TOTAL];
     if (lds_hist) words += (size_t)1 << hb[H_HBITS];
     return words * sizeof(uint32_t);
 }

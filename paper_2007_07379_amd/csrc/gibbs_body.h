@@ -53,12 +53,15 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
     const uint32_t cid = B[H_CID];
     const bool uniform = UNIFORM || B[H_UNIFORM] != 0u;
     const uint32_t tog_words = TOG ? B[H_NBLK] * 16u * TW : 0u;
-    const uint32_t thr_total = uniform ? 0u : B[H_THR_TOTAL];
+    // threshold tables in LDS, or read from the image when too large
+    const bool thr_glob = !uniform && B[H_THR_TOTAL] > THR_LDS_MAX_WORDS;
+    const uint32_t thr_total = uniform || thr_glob ? 0u : B[H_THR_TOTAL];
     const uint32_t nbins = 1u << B[H_HBITS];
     const uint32_t nblk = B[H_NBLK];
     uint32_t *lds_tog = lds;
     uint32_t *lds_thr = lds + tog_words;
     uint32_t *lds_h = lds_thr + thr_total;
+    const uint32_t *thr = thr_glob ? B + B[H_OFF_THRTAB] : lds_thr;
     const uint32_t tid = threadIdx.x;
     const uint32_t lc = lc0 + tid;
     const bool active = lc < a.n_chains;
@@ -171,7 +174,7 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
 #pragma unroll
                                 for (int t = 0; t < 4; ++t)
                                     if (m & (1u << t)) {
-                                        const uint32_t T = threshold_of<W>(B, 4 * j + t, x, lds_thr);
+                                        const uint32_t T = threshold_of<W>(B, 4 * j + t, x, thr);
                                         nb |= (uu[t] < T ? 1u : 0u) << t;
                                     }
                             }

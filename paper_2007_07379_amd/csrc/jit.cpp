@@ -107,6 +107,75 @@ __device__ __attribute__((always_inline)) inline void philox(u32 c0, u32 c1, u32
 }
 )";
 
+// The phase polynomial and output state of the lattice in x, masks as
+// immediates: declares `bin` = alpha 2^K + phase.
+void emit_bin_code(std::ostringstream &o, const std::string &ind, const uint32_t *B) {
+    const uint32_t W = B[H_W], WS = B[H_WS], K = B[H_K], n = B[H_N];
+    for (uint32_t t = 0; t < K; ++t) o << ind << "u32 c" << t << " = 0u;\n";
+    const uint32_t linmask = B[H_LINMASK];
+    const uint32_t *lin = B + B[H_OFF_LIN];
+    for (uint32_t t = 0; t < K; ++t) {
+        if (!((linmask >> t) & 1u)) continue;
+        for (uint32_t w = 0; w < W; ++w) {
+            const uint32_t m = lin[t * WS + w];
+            if (m) o << ind << "c" << t << " += __builtin_popcount(x[" << w << "] & " << hx(m) << ");\n";
+        }
+    }
+    const uint32_t *qrec = B + B[H_OFF_QD];
+    for (uint32_t q = 0; q < B[H_NQD]; ++q) {
+        const uint32_t delta = qrec[0], pm = qrec[1];
+        for (uint32_t w = 0; w < W; ++w) {
+            bool any = false;
+            for (uint32_t t = 0; t < K; ++t)
+                if (((pm >> t) & 1u) && qrec[2 + t * WS + w]) any = true;
+            if (!any) continue;
+            o << ind << "{\n" << ind << "    const u32 y = x[" << w << "] & " << funnel(w, delta, W) << ";\n";
+            for (uint32_t t = 0; t < K; ++t) {
+                const uint32_t m = qrec[2 + t * WS + w];
+                if (((pm >> t) & 1u) && m) o << ind << "    c" << t << " += __builtin_popcount(y & " << hx(m) << ");\n";
+            }
+            o << ind << "}\n";
+        }
+        qrec += qd_stride(K, WS);
+    }
+    const uint32_t *grec = B + B[H_OFF_QG];
+    for (uint32_t g = 0; g < B[H_NQG]; ++g) {
+        const uint32_t t = grec[0], m = grec[1];
+        for (uint32_t w = 0; w < W; ++w) {
+            std::string z;
+            for (uint32_t e = 0; e < m; ++e) {
+                const uint32_t delta = grec[2 + e * qg_entry_stride(WS)];
+                const uint32_t mk = grec[2 + e * qg_entry_stride(WS) + 1 + w];
+                if (!mk) continue;
+                if (!z.empty()) z += " | ";
+                z += "(" + funnel(w, delta, W) + " & " + hx(mk) + ")";
+            }
+            if (!z.empty()) o << ind << "c" << t << " += __builtin_popcount(x[" << w << "] & (" << z << "));\n";
+        }
+        grec += 2 + m * qg_entry_stride(WS);
+    }
+    o << ind << "const u32 ph = (" << B[H_PCONST] << "u";
+    for (uint32_t t = 0; t < K; ++t) o << " + (c" << t << " << " << t << ")";
+    o << ") & " << ((1u << K) - 1u) << "u;\n";
+    const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
+    o << ind << "const u32 alpha = __builtin_amdgcn_alignbit(" << xw(aw + 1, W) << ", " << xw(aw, W) << ", "
+      << ash << "u) & " << hx(n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u) << ";\n";
+    o << ind << "const u32 bin = (alpha << " << K << ") | ph;\n";
+}
+
+// True when the lattice in x meets a soft zero (declares `soft_hit`).
+void emit_soft_code(std::ostringstream &o, const std::string &ind, const uint32_t *B) {
+    const uint32_t ns = B[H_NSOFT];
+    const uint32_t *r = B + B[H_OFF_SOFT];
+    o << ind << "bool soft_hit = false;\n";
+    for (uint32_t g = 0; g < ns; ++g, r += SOFT_STRIDE) {
+        o << ind << "soft_hit |= ((" << hx(r[4]) << " >> (";
+        for (uint32_t j = 0; j < 4; ++j)
+            o << (j ? " | " : "") << "(((x[" << (r[j] >> 5) << "] >> " << (r[j] & 31) << "u) & 1u) << " << j << ")";
+        o << ")) & 1u) != 0u;\n";
+    }
+}
+
 }  // namespace
 
 size_t jit_rows_bytes(const CompiledCircuit &k) {
@@ -117,6 +186,7 @@ size_t jit_rows_bytes(const CompiledCircuit &k) {
 }
 
 JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint32_t max_block) {
+    if (!k.uniform) return jit_general_source(k, hist_kind == JIT_HIST_LDS, max_block);
     const bool lds_hist = hist_kind == JIT_HIST_LDS, path_hist = hist_kind == JIT_HIST_PATHS;
     const bool keys = hist_kind == JIT_HIST_KEYS;
     const uint32_t *B = k.blob.data();
@@ -182,58 +252,7 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
         emit_y(o, ind);
     };
     // phase polynomial and bin of the lattice in x: declares `bin`
-    auto emit_bin = [&](std::ostringstream &o, const std::string &ind) {
-        for (uint32_t t = 0; t < K; ++t) o << ind << "u32 c" << t << " = 0u;\n";
-        const uint32_t linmask = B[H_LINMASK];
-        const uint32_t *lin = B + B[H_OFF_LIN];
-        for (uint32_t t = 0; t < K; ++t) {
-            if (!((linmask >> t) & 1u)) continue;
-            for (uint32_t w = 0; w < W; ++w) {
-                const uint32_t m = lin[t * WS + w];
-                if (m) o << ind << "c" << t << " += __builtin_popcount(x[" << w << "] & " << hx(m) << ");\n";
-            }
-        }
-        const uint32_t *qrec = B + B[H_OFF_QD];
-        for (uint32_t q = 0; q < B[H_NQD]; ++q) {
-            const uint32_t delta = qrec[0], pm = qrec[1];
-            for (uint32_t w = 0; w < W; ++w) {
-                bool any = false;
-                for (uint32_t t = 0; t < K; ++t)
-                    if (((pm >> t) & 1u) && qrec[2 + t * WS + w]) any = true;
-                if (!any) continue;
-                o << ind << "{\n" << ind << "    const u32 y = x[" << w << "] & " << funnel(w, delta, W) << ";\n";
-                for (uint32_t t = 0; t < K; ++t) {
-                    const uint32_t m = qrec[2 + t * WS + w];
-                    if (((pm >> t) & 1u) && m) o << ind << "    c" << t << " += __builtin_popcount(y & " << hx(m) << ");\n";
-                }
-                o << ind << "}\n";
-            }
-            qrec += qd_stride(K, WS);
-        }
-        const uint32_t *grec = B + B[H_OFF_QG];
-        for (uint32_t g = 0; g < B[H_NQG]; ++g) {
-            const uint32_t t = grec[0], m = grec[1];
-            for (uint32_t w = 0; w < W; ++w) {
-                std::string z;
-                for (uint32_t e = 0; e < m; ++e) {
-                    const uint32_t delta = grec[2 + e * qg_entry_stride(WS)];
-                    const uint32_t mk = grec[2 + e * qg_entry_stride(WS) + 1 + w];
-                    if (!mk) continue;
-                    if (!z.empty()) z += " | ";
-                    z += "(" + funnel(w, delta, W) + " & " + hx(mk) + ")";
-                }
-                if (!z.empty()) o << ind << "c" << t << " += __builtin_popcount(x[" << w << "] & (" << z << "));\n";
-            }
-            grec += 2 + m * qg_entry_stride(WS);
-        }
-        o << ind << "const u32 ph = (" << B[H_PCONST] << "u";
-        for (uint32_t t = 0; t < K; ++t) o << " + (c" << t << " << " << t << ")";
-        o << ") & " << ((1u << K) - 1u) << "u;\n";
-        const uint32_t aw = B[H_AWORD], ash = B[H_ASHIFT];
-        o << ind << "const u32 alpha = __builtin_amdgcn_alignbit(" << xw(aw + 1, W) << ", " << xw(aw, W) << ", "
-          << ash << "u) & " << hx(n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u) << ";\n";
-        o << ind << "const u32 bin = (alpha << " << K << ") | ph;\n";
-    };
+    auto emit_bin = [&](std::ostringstream &o, const std::string &ind) { emit_bin_code(o, ind, B); };
     const uint32_t ctag = B[H_CID];  // tag 0: Gibbs updates
     auto from_philox = [&](std::ostringstream &o, const std::string &ind, uint32_t j) {
         o << ind << "u32 u0, u1, u2, u3;\n"
@@ -255,7 +274,7 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
     o << "extern \"C\" __global__ void __attribute__((amdgpu_flat_work_group_size(1, " << max_block
       << "))) pbit_uniform_sweep(\n"
          "    u32 *__restrict__ state, u32 *__restrict__ hist, u32 n_chains, u32 lanes_log2, u32 chain_begin,\n"
-         "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from) {\n";
+         "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from, u32 resume) {\n";
     o << "    __shared__ __attribute__((aligned(16))) u32 lds_rows[" << out.rows_words << "];\n";
     if (lds_hist) o << "    __shared__ u32 lds_h[" << nbins << "];\n";
     if (path_hist) o << "    __shared__ u32 lds_p[" << npaths << "];\n";
@@ -362,6 +381,124 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
     return out;
 }
 
+// Circuits with conditionals other than 1/2: one lane per chain (a chain's
+// sweeps depend on each other), the colour schedule unrolled.  Per colour,
+// every Philox block the colour needs is drawn first, then every bit's
+// neighbourhood index (its scope bits at immediate positions), threshold
+// (from the LDS copy of the tables) and flip are computed, and then the
+// flipped bits' cones are XORed in: bits of one colour touch no scope of
+// another, so this equals flipping them one after the other.
+JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block) {
+    const uint32_t *B = k.blob.data();
+    const uint32_t W = B[H_W], WS = B[H_WS], h = B[H_H], ncol = B[H_NCOL];
+    const uint32_t *cw = B + B[H_OFF_CONST];
+    const uint32_t *fpos = B + B[H_OFF_FPOS];
+    const uint32_t *cone = B + B[H_OFF_CONE];
+    const uint32_t *thrinfo = B + B[H_OFF_THRINFO];
+    const uint32_t *thrtab = B + B[H_OFF_THRTAB];
+    const uint32_t total = B[H_THR_TOTAL];
+    const uint32_t *colidx = B + B[H_OFF_COLIDX];
+    const uint32_t *colent = B + B[H_OFF_COLENT];
+    const uint32_t nbins = 1u << B[H_HBITS];
+    const uint32_t ctag = B[H_CID];
+    JitSource out;
+    out.entry = "pbit_general_sweep";
+    out.max_block = max_block;
+    const bool thr_lds = (size_t)total * 4 + (lds_hist ? (size_t)nbins * 4 : 0) <= JIT_LDS_LIMIT;
+    out.rows_words = thr_lds ? total : 0;
+    out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0);
+
+    std::ostringstream o;
+    o << PRELUDE;
+    o << "\n// circuit: n=" << B[H_N] << " d=" << B[H_D] << " K=" << B[H_K] << " W=" << W << " h=" << h
+      << " colours=" << ncol << " id=" << B[H_CID] << "\n";
+    o << "static __device__ const u32 thr_init[" << std::max<uint32_t>(total, 1) << "] = {";
+    for (uint32_t i = 0; i < std::max<uint32_t>(total, 1); ++i)
+        o << (i % 8 ? " " : "\n    ") << hx(i < total ? thrtab[i] : 0u) << ",";
+    o << "\n};\n\n";
+    o << "extern \"C\" __global__ void __attribute__((amdgpu_flat_work_group_size(1, " << max_block
+      << "))) pbit_general_sweep(\n"
+         "    u32 *__restrict__ state, u32 *__restrict__ hist, u32 n_chains, u32 lanes_log2, u32 chain_begin,\n"
+         "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from, u32 resume) {\n";
+    if (thr_lds) o << "    __shared__ u32 lds_t[" << std::max<uint32_t>(total, 1) << "];\n";
+    if (lds_hist) o << "    __shared__ u32 lds_h[" << nbins << "];\n";
+    if (thr_lds) o << "    for (u32 e = threadIdx.x; e < " << total << "u; e += blockDim.x) lds_t[e] = thr_init[e];\n";
+    if (lds_hist) o << "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) lds_h[e] = 0u;\n";
+    o << "    __syncthreads();\n";
+    o << "    const u32 *tab = " << (thr_lds ? "lds_t" : "thr_init") << ";\n";
+    o << "    const u32 lc = blockIdx.x * blockDim.x + threadIdx.x;\n"
+         "    if (lc < n_chains) {\n"
+         "        const u32 chain = chain_begin + lc;\n"
+         "        u32 x[" << W << "];\n"
+         "        if (resume) {\n";
+    for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = state[(u64)" << w << " * n_chains + lc];\n";
+    o << "        } else {\n";
+    for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = " << hx(cw[w]) << ";\n";
+    o << "        }\n"
+         "        for (u32 it = 0; it < n_sweeps; ++it) {\n"
+         "            const u32 s = sweep_begin + it;\n";
+    for (uint32_t c = 0; c < ncol; ++c) {
+        std::vector<std::pair<uint32_t, uint32_t>> ents;  // (block, mask)
+        for (uint32_t kk = 0; kk < (uint32_t)MAX_FW; ++kk) {
+            const uint32_t off = colidx[(c * MAX_FW + kk) * 2], cnt = colidx[(c * MAX_FW + kk) * 2 + 1];
+            for (uint32_t e = 0; e < cnt; ++e) ents.push_back({colent[off + e] >> 4, colent[off + e] & 15u});
+        }
+        o << "            {  // colour " << c << "\n";
+        for (auto &en : ents)
+            o << "                u32 u" << en.first << "_0, u" << en.first << "_1, u" << en.first << "_2, u" << en.first
+              << "_3;\n                philox(s, " << en.first << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u"
+              << en.first << "_0, u" << en.first << "_1, u" << en.first << "_2, u" << en.first << "_3);\n";
+        std::vector<uint32_t> bits;
+        for (auto &en : ents)
+            for (uint32_t t = 0; t < 4; ++t)
+                if ((en.second >> t) & 1u) bits.push_back(4 * en.first + t);
+        for (uint32_t b : bits) {
+            const uint32_t *rec = thrinfo + b * THR_STRIDE;
+            const uint32_t toff = rec[0], ns = rec[1];
+            o << "                const u32 i" << b << " = 0u";
+            for (uint32_t j = 0; j < ns; ++j)
+                o << " | (((x[" << (rec[2 + j] >> 5) << "] >> " << (rec[2 + j] & 31) << "u) & 1u) << " << j << ")";
+            o << ";\n";
+            const uint32_t p = fpos[b];
+            o << "                const u32 f" << b << " = (u" << (b >> 2) << "_" << (b & 3) << " < tab[" << toff << "u + i"
+              << b << "] ? 1u : 0u) ^ ((x[" << (p >> 5) << "] >> " << (p & 31) << "u) & 1u);\n";
+        }
+        for (uint32_t b : bits) {
+            o << "                {\n                    const u32 m = 0u - f" << b << ";\n";
+            for (uint32_t w = 0; w < W; ++w) {
+                const uint32_t mk = cone[(size_t)b * WS + w];
+                if (mk) o << "                    x[" << w << "] ^= m & " << hx(mk) << ";\n";
+            }
+            o << "                }\n";
+        }
+        o << "            }\n";
+    }
+    o << "            if (s >= bin_from) {\n";
+    emit_soft_code(o, "                ", B);
+    o << "                if (!soft_hit) {\n";
+    emit_bin_code(o, "                    ", B);
+    if (lds_hist)
+        o << "                    atomicAdd(&lds_h[bin], 1u);\n";
+    else
+        o << "                    atomicAdd(&hist[bin], 1u);\n";
+    o << "                }\n"
+         "            }\n"
+         "        }\n"
+         "        if (state && n_sweeps) {\n";
+    for (uint32_t w = 0; w < W; ++w) o << "            state[(u64)" << w << " * n_chains + lc] = x[" << w << "];\n";
+    o << "        }\n"
+         "    }\n";
+    if (lds_hist)
+        o << "    __syncthreads();\n"
+             "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) {\n"
+             "        const u32 v = lds_h[e];\n"
+             "        if (v) atomicAdd(&hist[e], v);\n"
+             "    }\n";
+    o << "}\n";
+    out.text = o.str();
+    return out;
+}
+
 bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -370,7 +507,7 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
         return false;
     }
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.text.c_str(), "pbit_uniform_sweep.hip", 0, nullptr, nullptr) !=
+    if (hiprtcCreateProgram(&prog, src.text.c_str(), (src.entry + ".hip").c_str(), 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS) {
         *log = "hiprtcCreateProgram failed";
         return false;
@@ -400,7 +537,7 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
         return false;
     }
     hipFunction_t fn = nullptr;
-    e = hipModuleGetFunction(&fn, mod, "pbit_uniform_sweep");
+    e = hipModuleGetFunction(&fn, mod, src.entry.c_str());
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);
         *log = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
@@ -427,8 +564,8 @@ hipError_t jit_launch(const JitKernel &k, const GibbsLaunch &a, uint32_t lanes_l
     if (grid * block > 0xFFFFFFFFull || a.n_sweeps > 0xFFFFFF00u) return hipErrorInvalidValue;
     uint32_t *state = a.state, *hist = a.hist;
     uint32_t n_chains = a.n_chains, ll = lanes_log2, cb = a.chain_begin, slo = a.seed_lo, shi = a.seed_hi;
-    uint32_t sb = a.sweep_begin, ns = a.n_sweeps, bf = a.bin_from;
-    void *args[] = {&state, &hist, &n_chains, &ll, &cb, &slo, &shi, &sb, &ns, &bf};
+    uint32_t sb = a.sweep_begin, ns = a.n_sweeps, bf = a.bin_from, rs = a.resume;
+    void *args[] = {&state, &hist, &n_chains, &ll, &cb, &slo, &shi, &sb, &ns, &bf, &rs};
     return hipModuleLaunchKernel(k.fn, (uint32_t)grid, 1, 1, block, 1, 1, 0, stream, args, nullptr);
 }
 

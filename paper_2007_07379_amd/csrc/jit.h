@@ -18,7 +18,8 @@ namespace pbit {
 constexpr size_t JIT_LDS_LIMIT = 160 * 1024;
 
 struct JitSource {
-    std::string text;        // HIP source of kernel `pbit_uniform_sweep`
+    std::string text;        // HIP source of the kernel `entry`
+    std::string entry = "pbit_uniform_sweep";
     uint32_t rows_words = 0; // LDS words of the compacted toggle rows
     uint32_t lds_bytes = 0;  // static LDS of the kernel
     uint32_t xor_words = 0;  // lattice words XORed per sweep (sum of block supports)
@@ -43,7 +44,10 @@ enum JitHist : uint32_t {
     // bin_from no earlier than the launch's first sweep (keyhist.h bins them)
     JIT_HIST_KEYS = 3,
 };
+// Circuits with other conditionals get the kernel of jit_general_source
+// (`pbit_general_sweep`: one lane per chain, LDS or HBM histogram only).
 JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint32_t max_block);
+JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block);
 
 // LDS bytes of the compacted toggle rows (without the histogram).
 size_t jit_rows_bytes(const CompiledCircuit &k);

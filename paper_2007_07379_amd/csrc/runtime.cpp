@@ -203,7 +203,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             std::string log;
             JitKernel jk;
             bool ok = false;
-            const bool lds = kind == JIT_HIST_LDS || kind == JIT_HIST_PATHS;
+            const bool lds = c->circuits[i].uniform && (kind == JIT_HIST_LDS || kind == JIT_HIST_PATHS);
             for (uint32_t mb : lds ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
                 const JitSource src = jit_uniform_source(c->circuits[i], kind, mb);
                 if (src.lds_bytes > JIT_LDS_LIMIT) {
@@ -308,8 +308,6 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             continue;
         }
         const TuneChoice &tc = choices[i];
-        const size_t thr_bytes = k.uniform ? 0 : (size_t)k.blob[H_THR_TOTAL] * sizeof(uint32_t);
-        if (thr_bytes > 64 * 1024) return set_error(PBIT_E_TOO_LARGE, "threshold tables exceed 64 KiB of LDS");
         const size_t lds = tc.jit ? jits[i]->lds_bytes
                                   : (tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
                                              : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
@@ -609,8 +607,10 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     out->lds_hist = tc.jit ? jit_hist_kind(tc) : (tc.lds_hist ? 1u : 0u);
     out->toggle_tables = tc.tog ? 1u : 0u;
     out->lanes_per_chain = tc.jit ? (1u << tc.lanes_log2) : (tc.pair ? 2u : 1u);
-    out->lds_bytes = (uint32_t)(tc.jit ? jit_rows_bytes(k) + (tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0) +
-                                             (tc.path_hist ? ((size_t)4 << k.h) : 0)
+    const size_t thr_b = (size_t)k.blob[H_THR_TOTAL] * 4;
+    const size_t hist_lb = tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0;
+    out->lds_bytes = (uint32_t)(tc.jit && !k.uniform ? (thr_b + hist_lb <= JIT_LDS_LIMIT ? thr_b : 0) + hist_lb
+                                : tc.jit ? jit_rows_bytes(k) + hist_lb + (tc.path_hist ? ((size_t)4 << k.h) : 0)
                                 : tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
                                           : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
     out->sweeps_per_launch = tc.group;
@@ -624,8 +624,9 @@ extern "C" pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, u
         return set_error(PBIT_E_INVALID_ARG, "max_block must be 256, 512 or 1024");
     if (index >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
     const CompiledCircuit &k = c->circuits[index];
-    if (!k.uniform) return set_error(PBIT_E_MODE_UNAVAILABLE, "circuit has conditionals other than 1/2");
     if (lds_hist > 3) return set_error(PBIT_E_INVALID_ARG, "lds_hist must be 0, 1, 2 or 3");
+    if (!k.uniform && lds_hist > 1)
+        return set_error(PBIT_E_MODE_UNAVAILABLE, "path counts and keys need every conditional 1/2");
     if (lds_hist == JIT_HIST_PATHS && k.h > 16) return set_error(PBIT_E_TOO_LARGE, "path counts need h <= 16");
     const JitSource src = jit_uniform_source(k, lds_hist, max_block);
     *len = src.text.size() + 1;

@@ -73,9 +73,19 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     // compile takes about a second), unless the caller asks for a generic
     // toggle mode
     const uint64_t work = (uint64_t)chains * total_sweeps * k.h;
-    t.jit = k.uniform && (cfg->specialize == 2 || (cfg->specialize == 0 && cfg->toggle_mode == 0 &&
-                                                   work >= (1ull << 33)));
-    if (t.jit) {
+    t.jit = cfg->specialize == 2 || (cfg->specialize == 0 && cfg->toggle_mode == 0 && work >= (1ull << 33));
+    if (t.jit && !k.uniform) {
+        // other conditionals: one lane per chain (sweeps depend on each
+        // other), threshold tables and the histogram in LDS when they fit
+        t.lanes_log2 = 0;
+        t.pair = false;
+        t.tog = true;
+        t.path_hist = t.keys = false;
+        const size_t thr_b = (size_t)k.blob[H_THR_TOTAL] * 4;
+        const size_t hist_b = ((size_t)1 << (k.n + k.K)) * 4;
+        t.lds_hist = cfg->hist_mode == 1 || (cfg->hist_mode != 2 && thr_b + hist_b <= LDS_MAX);
+        t.block = cfg->block_size ? cfg->block_size : 256;
+    } else if (t.jit) {
         uint32_t L = cfg->lanes_per_chain;
         if (!L) {
             // enough lanes for four waves per SIMD, each lane keeping >= 16 sweeps

@@ -78,6 +78,10 @@ MODES = {
     # others run one lane per chain whatever is asked)
     "pair": dict(lanes_per_chain=2),
     "pair_ghist": dict(lanes_per_chain=2, hist_mode=2),
+    # the circuit-specialised kernel (pbit_general_sweep for the circuits
+    # with other conditionals), histogram in LDS or HBM, sweep groups
+    "spec": dict(specialize=2, lanes_per_chain=1),
+    "spec_ghist_groups": dict(specialize=2, lanes_per_chain=1, hist_mode=2, sweeps_per_launch=7),
 }
 
 
@@ -268,3 +272,26 @@ def test_rotated_hadamard_prefactor_fig5(env, theta):
         want = exact.prefactor(circ, a, True)
         say("  output", a, "measured", est, "exact", want, "Z_alpha", Za)
         assert abs(est - want) <= 0.01 * Za, (a, est, want)
+
+
+@pytest.mark.parametrize("first,second", [(1, 2), (2, 1)])
+def test_general_kernel_resume_across_kernels(env, first, second):
+    """A rotated-brickwork run (conditionals other than 1/2) resumed from
+    the generic kernel into the specialised one and back equals the
+    uninterrupted oracle run."""
+    torch, pbit = env
+    c = wc.rotated_brickwork(5, 8, 3, math.pi / 7, K=3)
+    ch, burn, sweeps = 640, 7, 60
+    st_o, h_o, _ = oracle_run(c, ch, burn, sweeps, seed=31)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    state = torch.zeros(ch * info["W"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([ch], burn, 25, hist, state, seed=31, specialize=first)
+    s.gibbs_run([ch], 0, sweeps - 25, hist, state, seed=31, sweep_offset=burn + 25, resume=True,
+                specialize=second)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], ch).T
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
+    assert np.array_equal(st, st_o)
+    assert np.array_equal(h, h_o)

@@ -44,10 +44,13 @@ CASES = [
                                                       wc.gate1(3, 1, "H"), wc.crh(4, 1, 0, math.pi / 3, "CRH3"),
                                                       wc.gate1(5, 0, "H"), wc.ch(6, 0, 1)], 0),
      2.0, 600, 10, 50, 0),
+    # threshold tables beyond 64 KiB: read from the image in device memory
+    ("rctch12", lambda: wc.workload_circuit("rctch12"), 4.0, 300, 10, 25, 9),
 ]
 
-MODES = [dict(toggle_mode=1), dict(toggle_mode=2), dict(toggle_mode=1, hist_mode=2),
-         dict(toggle_mode=1, sweeps_per_launch=7), dict(toggle_mode=1, block_size=64)]
+MODES = [dict(toggle_mode=1, specialize=1), dict(toggle_mode=2), dict(toggle_mode=1, hist_mode=2, specialize=1),
+         dict(toggle_mode=1, sweeps_per_launch=7, specialize=1), dict(toggle_mode=1, block_size=64, specialize=1),
+         dict(specialize=2), dict(specialize=2, hist_mode=2, sweeps_per_launch=9)]
 
 
 def run(env, s, chains, burn, sweeps, seed, cb, **kw):

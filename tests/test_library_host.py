@@ -361,7 +361,9 @@ def test_launch_shape_rules(pb):
     assert sh["kernel"] == pb.KERNEL_TWO_LANE and sh["block"] == 128 and sh["sweeps_per_launch"] == 7
     r = pb.CircuitSet(wc.rotated_hadamard_chain(10, math.pi / 8, K=1))
     assert r.launch_shape([1000], 0, 10, lanes_per_chain=2)["kernel"] == pb.KERNEL_ONE_LANE
-    assert r.launch_shape([1000], 0, 10, specialize=2)["kernel"] == pb.KERNEL_ONE_LANE
+    sh = r.launch_shape([1000], 0, 10, specialize=2)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lanes_per_chain"] == 1 and sh["lds_hist"] in (0, 1)
+    assert r.launch_shape([1000], 0, 10, specialize=1)["kernel"] == pb.KERNEL_ONE_LANE
     m = pb.CircuitSet([wc.tiny_ghz_t(), wc.rotated_hadamard_chain(6, math.pi / 8, K=1)])
     assert m.launch_shape([100, 100], 0, 10, idx=0)["kernel"] == pb.KERNEL_PERSISTENT
     assert m.launch_shape([100, 100], 0, 10, idx=1)["kernel"] == pb.KERNEL_ONE_LANE
@@ -455,11 +457,39 @@ def _offline_compile(s, name, lds, mb, tmp_path):
     return vg, sc
 
 
-def test_specialised_source_rejects_nonuniform(pb):
-    r = pb.CircuitSet(wc.rotated_hadamard_chain(10, math.pi / 8, K=1))
-    with pytest.raises(pb.PbitError) as e:
-        r.specialised_source(0)
-    assert e.value.name == "MODE_UNAVAILABLE"
+GENERAL_CIRCUITS = [
+    ("rhchain", lambda: pb_circ(wc.rotated_hadamard_chain(10, math.pi / 8, K=1)), 0.0),
+    ("rbrick", lambda: pb_circ(wc.rotated_brickwork(4, 6, 5, math.pi / 8, K=3)), 0.0),
+    ("rctch12", lambda: pb_circ(wc.workload_circuit("rctch12")), 4.0),
+]
+
+
+def pb_circ(c):
+    return c
+
+
+@pytest.mark.parametrize("name,mk,J", GENERAL_CIRCUITS, ids=[c[0] for c in GENERAL_CIRCUITS])
+def test_general_source_compiles_for_gfx950(pb, name, mk, J, tmp_path):
+    """Circuits with conditionals other than 1/2 get `pbit_general_sweep`
+    (one lane per chain, colours unrolled); it compiles offline for gfx950
+    without register spills, with the histogram in LDS or HBM; path counts
+    and keys are refused."""
+    s = pb.CircuitSet(mk(), soft_zero_J=J)
+    for lds in (False, True):
+        src = s.specialised_source(0, lds_hist=lds, max_block=256)
+        assert "pbit_general_sweep" in src
+        f = tmp_path / ("%s_%d.hip" % (name, int(lds)))
+        f.write_text(src)
+        cmd = ["/opt/rocm/bin/hipcc", "-include", "hip/hip_runtime.h", "--offload-arch=gfx950", "-O3",
+               "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
+               "-c", str(f), "-o", str(f) + ".o", "-Rpass-analysis=kernel-resource-usage"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-2000:]
+        assert int(re.search(r"ScratchSize \[bytes/lane\]: (\d+)", r.stderr).group(1)) == 0
+    for kind in (2, 3):
+        with pytest.raises(pb.PbitError) as e:
+            s.specialised_source(0, lds_hist=kind, max_block=256)
+        assert e.value.name == "MODE_UNAVAILABLE"
 
 
 def test_shor_argument_errors_before_device(pb):

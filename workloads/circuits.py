@@ -303,6 +303,9 @@ WORKLOADS = {
     # rct12's shape with Toffoli and Peres gates (three-qubit products)
     "rctt12": dict(make=lambda: random_clifford_t_toffoli(12, 40, 1, K=3),
                    chains=65536, burn_in=200, sweeps=10000),
+    # rct12's shape with controlled Hadamards as soft zeros (J = 4)
+    "rctch12": dict(make=lambda: random_clifford_t_ch(12, 40, 1, K=3, p_ch=0.15),
+                    chains=65536, burn_in=200, sweeps=2000, soft_J=4.0),
 }
 
 
