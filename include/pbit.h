@@ -272,6 +272,16 @@ pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_beg
  * batched forward GEMMs. */
 pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint32_t n, double *d_logq,
                                 void *hip_stream);
+/* pbit_proposal_sample (n proposals into d_out, d_logq) and
+ * pbit_proposal_score of the n word-major paths d_cur (into d_logq_cur) in
+ * one call: the MH step's two passes over the network.  For networks of
+ * width <= 256 on lattices of <= 256 bits it is one kernel that carries both
+ * paths of a chain through the same weight tiles; otherwise the two calls
+ * run in sequence.  Outputs are bit-identical to the two separate calls.
+ * d_cur must not overlap d_out. */
+pbit_status pbit_proposal_sample_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed,
+                                       uint32_t step, uint32_t *d_out, double *d_logq, const uint32_t *d_cur,
+                                       double *d_logq_cur, void *hip_stream);
 
 typedef struct {
     uint32_t chains, chain_begin;

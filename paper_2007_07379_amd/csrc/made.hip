@@ -697,8 +697,338 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// register-resident sampler for small networks
+// ---------------------------------------------------------------------------
+// The same autoregressive procedure for H <= 256 and lattices of at most 256
+// bits, with every activation kept in registers and the network in LDS.
+// Each product is taken transposed: the weight rows of 16 units are the
+// MFMA's A operand and the wave's 16 chains its B operand, so the outputs of
+// a unit land in the lanes of their chain (lane & 15) and feed the next
+// product as its B operand directly.  Half t of K-chunk cc is the tile of
+// units 32 cc + 8 r + 4 t + e (row group r, e = 0..3): lane group g then
+// receives units 32 cc + 8 g + 4 t + e, which are elements 4 t + e of the
+// 8-element B slice it supplies for that chunk, so no lane exchange is
+// needed.  A tile is computed when it holds a unit whose degree falls in the
+// current phase (the host lists them per free bit; see layer_tiles for why
+// writing all 16 of its units is safe).  Each lane of a chain draws the same
+// bits, so the four
+// copies of a chain's lattice stay equal; the four lanes share the
+// logarithms of log q instead, one per lane every fourth position.
+//
+// A wave carries NP paths per chain through the same tiles: NP = 1 samples
+// (or, with `score`, scores) one path; NP = 2 samples the proposal (path 0)
+// and scores the chain's current path (path 1, from `score`) in one pass, the
+// weight rows and tile decisions shared.  Every path's arithmetic is the one
+// the single-path kernel performs, so the results are the same bits.
+
+__device__ __forceinline__ bf16x8 bits_to_bf16x8(uint32_t b) {
+    // element s is 1.0 (0x3f80) when bit s of b is set, else 0
+    u32x4v d;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        d[j] = ((b >> (2 * j)) & 1u) * 0x3f80u | ((b >> (2 * j + 1)) & 1u) * 0x3f800000u;
+    return __builtin_bit_cast(bf16x8, d);
+}
+
+template <int N>
+__device__ __forceinline__ uint32_t pick_word(const uint32_t (&v)[N], int i) {
+    uint32_t r = 0u;
+#pragma unroll
+    for (int w = 0; w < N; ++w) r = (w == i) ? v[w] : r;
+    return r;
+}
+
+// this lane's 8-element slices of chunks k < nk of one weight row (LDS)
+template <int N>
+__device__ __forceinline__ void load_rows(bf16x8 (&av)[N], const bf16 *__restrict__ wrow, int nk) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k < nk) av[k] = *reinterpret_cast<const bf16x8 *>(wrow + 32 * k);
+}
+
+// sum over chunks k < nk (ascending, from zero) of A = av[k] times B = ops[k]
+// (8 bf16 per lane, as bf16x8 or as four dwords)
+template <int N, class Op>
+__device__ __forceinline__ f32x4 mfma_ops(const bf16x8 (&av)[N], const Op (&ops)[N], int nk) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k < nk)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], __builtin_bit_cast(bf16x8, ops[k]), acc, 0, 0, 0);
+    return acc;
+}
+
+typedef bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
+
+// two floats as a dword of two bf16 (element 0 in the low half)
+__device__ __forceinline__ uint32_t pack_bf16(float x, float y) {
+    const f32x2 v = {x, y};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// one layer's phase for NP paths: the half tiles flagged in `tiles` (bit
+// 2 cc + t; the host sets those that hold a unit whose degree falls in this
+// phase) from ops (nk chunks) and the rows of WT (row stride rs), bias, ReLU,
+// written into act (chunk cc: four dwords, element s of the lane's 8-element
+// slice in the half s & 1 of dword s >> 1).  All 16 units of a tile are
+// written.  The new ones are what they must be; the earlier ones come out
+// with the bits they already had (their inputs are final and the extra K
+// chunks add exact zeros); the later ones are provisional until their own
+// phase recomputes them, and until then they only meet weights the degree
+// masks keep at exactly zero (a ReLU output is finite and >= 0, so each such
+// product is +0).  The chunk loop is unrolled so every write goes to a fixed
+// register.
+template <int NP, int NO, int NA, class Op>
+__device__ __forceinline__ void layer_tiles(u32x4v (&act)[NP][NA], const Op (&ops)[NP][NO],
+                                            const bf16 *__restrict__ WT, int rs, const float *__restrict__ bias,
+                                            uint32_t tiles, int nk, int g, int rrow) {
+#pragma unroll
+    for (int cc = 0; cc < NA; ++cc) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (!(tiles & (1u << (2 * cc + t)))) continue;
+            bf16x8 av[NO];
+            load_rows<NO>(av, WT + (int64_t)(32 * cc + rrow + 4 * t) * rs + 8 * g, nk);
+            const float4 bb = *reinterpret_cast<const float4 *>(bias + 32 * cc + 8 * g + 4 * t);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const f32x4 acc = mfma_ops<NO>(av, ops[q], nk);
+                act[q][cc][2 * t] = pack_bf16(relu(acc[0] + bb.x), relu(acc[1] + bb.y));
+                act[q][cc][2 * t + 1] = pack_bf16(relu(acc[2] + bb.z), relu(acc[3] + bb.w));
+            }
+        }
+    }
+}
+
+// LDS image of the network for the register-resident sampler: the table of
+// 8-bit input slices as bf16x8 (256 x 16 bytes), W1T (H rows of DP), W2T (H
+// rows of H), VT (D rows of H) as bf16, each row padded by 8 elements so the
+// 16 rows a half tile reads at once fall on different LDS banks, then b1, b2
+// (H each) and c (D) as FP32.
+constexpr int REG_PAD = 8;
+
+struct RegLayout {
+    size_t lut, w1, w2, v, b1, b2, c, total;
+};
+
+__host__ __device__ inline RegLayout reg_layout(int D, int DP, int H) {
+    RegLayout L;
+    L.lut = 0;
+    L.w1 = 256 * 16;
+    L.w2 = L.w1 + (size_t)H * (DP + REG_PAD) * 2;
+    L.v = L.w2 + (size_t)H * (H + REG_PAD) * 2;
+    L.b1 = (L.v + (size_t)D * (H + REG_PAD) * 2 + 15) & ~(size_t)15;
+    L.b2 = L.b1 + (size_t)H * 4;
+    L.c = L.b2 + (size_t)H * 4;
+    L.total = (L.c + (size_t)D * 4 + 15) & ~(size_t)15;
+    return L;
+}
+
+// copies n bytes (a multiple of 16, both ends 16-byte aligned) into LDS
+__device__ __forceinline__ void stage16(unsigned char *dst, const void *src, size_t n) {
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    for (size_t i = threadIdx.x; i < n / 16; i += blockDim.x) d4[i] = s4[i];
+}
+
+// copies `rows` bf16 rows of `len` elements (a multiple of 8) into LDS rows
+// of len + REG_PAD elements; eight loads per thread are in flight at once, so
+// a small workgroup is not held up by one memory latency per piece
+__device__ __forceinline__ void stage_rows(unsigned char *dst, const bf16 *src, int rows, int len) {
+    const int q = len / 8;  // 16-byte pieces per row
+    const int n = rows * q;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < n) v[u] = s4[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < n) *reinterpret_cast<uint4 *>(dst + ((size_t)(i / q) * (len + REG_PAD) + 8 * (i % q)) * 2) = v[u];
+        }
+    }
+}
+
+template <int NX, int NH, int NP>
+__global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int h = a.h, W = a.W, DP = a.DP, H = a.H, D = a.D;
+    const RegLayout L = reg_layout(D, DP, H);
+    // the whole network goes to LDS once per workgroup; after this barrier
+    // every wave runs on its own
+    stage_rows(smem + L.w1, a.W1T, H, DP);
+    stage_rows(smem + L.w2, a.W2T, H, H);
+    stage_rows(smem + L.v, a.VT, D, H);
+    stage16(smem + L.b1, a.b1, (size_t)H * 4);
+    stage16(smem + L.b2, a.b2, (size_t)H * 4);
+    {
+        float *cl = reinterpret_cast<float *>(smem + L.c);
+        for (int i = threadIdx.x; i < D; i += blockDim.x) cl[i] = a.c[i];
+        bf16x8 *lut = reinterpret_cast<bf16x8 *>(smem + L.lut);
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) lut[i] = bits_to_bf16x8((uint32_t)i);
+    }
+    __syncthreads();
+    const bf16x8 *lut = reinterpret_cast<const bf16x8 *>(smem + L.lut);
+    const bf16 *W1s = reinterpret_cast<const bf16 *>(smem + L.w1);
+    const bf16 *W2s = reinterpret_cast<const bf16 *>(smem + L.w2);
+    const bf16 *Vs = reinterpret_cast<const bf16 *>(smem + L.v);
+    const float *b1s = reinterpret_cast<const float *>(smem + L.b1);
+    const float *b2s = reinterpret_cast<const float *>(smem + L.b2);
+    const float *cs = reinterpret_cast<const float *>(smem + L.c);
+
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15, g = lane >> 4;
+    const int chain = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 + c;
+    if (__builtin_amdgcn_readfirstlane(chain - c) >= a.n) return;  // the wave has no chain
+    const bool valid = chain < a.n;
+    const uint32_t *B = a.blob;
+    const uint32_t *cw = B + B[H_OFF_CONST];
+    const uint32_t cid = B[H_CID];
+    // path q < NP draws its bits unless it is the scored one (the last path
+    // when `score` is given)
+    const int qs = a.score ? NP - 1 : NP;  // first scored path (NP: none)
+
+    uint32_t lat[NP][NX], path[NX];
+    u32x4v act1[NP][NH], act2[NP][NH];
+    // of the last <= 4 positions, the threshold and bit whose logarithm this
+    // lane group takes (position f with f % 4 == g)
+    uint32_t tg[NP], bg[NP];
+    double lq[NP];
+#pragma unroll
+    for (int w = 0; w < NX; ++w) path[w] = (a.score && valid && w < W) ? a.score[(int64_t)w * a.n + chain] : 0u;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int w = 0; w < NX; ++w) lat[q][w] = w < W ? cw[w] : 0u;
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            act1[q][k] = u32x4v{0u, 0u, 0u, 0u};
+            act2[q][k] = u32x4v{0u, 0u, 0u, 0u};
+        }
+        tg[q] = bg[q] = 0u;
+        lq[q] = 0.0;
+    }
+    const int rrow = 8 * (c >> 2) + (c & 3);  // this lane's A row within a half tile
+    U4 u4 = {0u, 0u, 0u, 0u};
+    for (int f = 0; f < h; ++f) {
+        const uint32_t *rec = a.sched + (size_t)f * 16;  // wave-uniform: one scalar load
+        const uint32_t t1 = rec[4] & 0xffffu, t2 = rec[5] & 0xffffu;
+        const int nk1 = (int)(rec[4] >> 16), nk2 = (int)(rec[5] >> 16), nk3 = (int)rec[6], p = (int)rec[7];
+        if (t1) {
+            bf16x8 xop[NP][NX];
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int k = 0; k < NX; ++k)
+                    if (k < nk1) xop[q][k] = lut[(lat[q][k] >> (8 * g)) & 0xffu];
+            layer_tiles<NP, NX, NH>(act1, xop, W1s, DP + REG_PAD, b1s, t1, nk1, g, rrow);
+        }
+        if (t2) layer_tiles<NP, NH, NH>(act2, act1, W2s, H + REG_PAD, b2s, t2, nk2, g, rrow);
+        // logit of position p: every A row is row p of V, so all four
+        // accumulator elements hold it
+        if (qs > 0 && (f & 3) == 0)  // some path draws its bits
+            u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + (uint32_t)chain, cid | (1u << 16),
+                               a.seed_lo, a.seed_hi);
+        const uint32_t ud = (f & 3) == 0 ? u4.x : ((f & 3) == 1 ? u4.y : ((f & 3) == 2 ? u4.z : u4.w));
+        const uint32_t pbit = (pick_word(path, p >> 5) >> (p & 31)) & 1u;
+        bf16x8 vv[NH];
+        load_rows<NH>(vv, Vs + (int64_t)p * (H + REG_PAD) + 8 * g, nk3);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const f32x4 lacc = mfma_ops<NH>(vv, act2[q], nk3);
+            const uint32_t T = made_threshold(lacc[0] + cs[p]);
+            const uint32_t bit = q < qs ? (ud < T ? 1u : 0u) : pbit;
+            tg[q] = (g == (f & 3)) ? T : tg[q];
+            bg[q] = (g == (f & 3)) ? bit : bg[q];
+            // the lattice bit at p is the free bit itself: flip its cone when
+            // the new value differs from the current one
+            const uint32_t m = 0u - (((pick_word(lat[q], p >> 5) >> (p & 31)) & 1u) ^ bit);
+#pragma unroll
+            for (int w = 0; w < NX; ++w) lat[q][w] ^= m & rec[8 + w];  // cone words, zero beyond W
+        }
+        // log q in free-bit order, as the batched scorer sums it: after every
+        // fourth position lane group j evaluates the logarithm of the j-th of
+        // them and the four are added in order in every lane
+        if ((f & 3) == 3 || f == h - 1) {
+            const int cnt = (f & 3) + 1;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const double lg = g < cnt ? made_log_prob(tg[q], bg[q]) : 0.0;
+                const int64_t lb = __builtin_bit_cast(int64_t, lg);
+                for (int j = 0; j < cnt; ++j) {
+                    const int src = (c + 16 * j) << 2;
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)lb);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(lb >> 32));
+                    lq[q] += __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+                }
+            }
+        }
+    }
+    if (g == 0 && valid) {
+        if (a.out && qs > 0)
+#pragma unroll
+            for (int w = 0; w < NX; ++w)
+                if (w < W) a.out[(int64_t)w * a.n + chain] = lat[0][w];
+        a.logq[chain] = lq[0];
+        if (NP == 2) a.logq_cur[chain] = lq[NP - 1];
+    }
+}
+
+template <int NX, int NH, int NP>
+hipError_t launch_reg(const SampleArgs &a, size_t lds, hipStream_t s) {
+    // enough waves per workgroup to share the staged network, few enough to
+    // spread small runs over every CU
+    const int waves = (a.n + 15) / 16;
+    const int per_wg = std::min(8, std::max(1, waves / 512));
+    const int grid = (waves + per_wg - 1) / per_wg;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)made_sample_reg_kernel<NX, NH, NP>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((made_sample_reg_kernel<NX, NH, NP>), dim3(grid), dim3(64 * per_wg), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int NX, int NP>
+hipError_t launch_reg_h(const SampleArgs &a, size_t lds, hipStream_t s) {
+    if (a.H <= 64) return launch_reg<NX, 2, NP>(a, lds, s);
+    if (NP == 2 || a.H <= 128) return launch_reg<NX, 4, NP>(a, lds, s);  // dual: H <= 128
+    return launch_reg<NX, (NP == 1 ? 8 : 4), NP>(a, lds, s);
+}
+
+template <int NP>
+hipError_t launch_reg_w(const SampleArgs &a, size_t lds, hipStream_t s) {
+    if (a.W <= 2) return launch_reg_h<2, NP>(a, lds, s);
+    if (NP == 2 || a.W <= 4) return launch_reg_h<4, NP>(a, lds, s);  // dual: W <= 4
+    return launch_reg_h<(NP == 1 ? 8 : 4), NP>(a, lds, s);
+}
+
+bool made_sample_dual_ok(const SampleArgs &a) {
+    // two paths of 256-wide activations, or of 8-word lattices beside 128-wide
+    // ones, would not fit in registers
+    return a.H <= 128 && a.W <= 4 && reg_layout(a.D, a.DP, a.H).total <= 160 * 1024;
+}
+
+hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    return launch_reg_w<2>(a, reg_layout(a.D, a.DP, a.H).total, s);
+}
+
 hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
     SampleArgs a = a0;
+    if (a.n <= 0) return hipSuccess;
+    // small networks and lattices: the register-resident kernel
+    if (made_sample_dual_ok(a)) return launch_reg_w<1>(a, reg_layout(a.D, a.DP, a.H).total, s);
     const int grid = (a.n + 15) / 16;
     const size_t base = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
     // small networks defer the log-probabilities to the end and keep the cones

@@ -11,18 +11,23 @@ namespace pbit {
 // The proposal's probability of a 1 at a free position, as the uint32
 // threshold the sampler compares its Philox draw with: P(1) = T / 2^32
 // exactly, whatever rounding produced T.  The sigmoid is evaluated in FP32
-// (the logit is FP32 already); scaling by 2^32 is exact and the conversion
+// (the logit is FP32 already) with the hardware exponential and reciprocal
+// (each within about one ulp); scaling by 2^32 is exact and the conversion
 // truncates.  T is kept in [1, 2^32 - 1] (a NaN logit gives 1) so every path
-// has q > 0.  The sampler and the scorer call this same function, so both
-// see the same T.
+// has q > 0.  The samplers and the scorers call this same function, so all
+// of them see the same T.
 __device__ __forceinline__ uint32_t made_threshold(float logit) {
-    const float p = 1.0f / (1.0f + __expf(-logit));
+    const float p = __builtin_amdgcn_rcpf(1.0f + __expf(-logit));
     const float t = p * 4294967296.0f;
     return t >= 4294967296.0f ? 0xFFFFFFFFu : (t >= 1.0f ? (uint32_t)t : 1u);
 }
 
+// log of the probability of `bit` under threshold T: log(T / 2^32) for a 1,
+// log((2^32 - T) / 2^32) for a 0.  The argument is selected first, so a wave
+// whose lanes hold both values evaluates one logarithm, not two.
 __device__ __forceinline__ double made_log_prob(uint32_t T, uint32_t bit) {
-    return bit ? log((double)T / 4294967296.0) : log((4294967296.0 - (double)T) / 4294967296.0);
+    const double v = bit ? (double)T : 4294967296.0 - (double)T;
+    return log(v / 4294967296.0);
 }
 
 struct SampleArgs {
@@ -31,15 +36,22 @@ struct SampleArgs {
     const float *b1, *b2, *c;
     const int4 *phase;    // per free bit: first-layer unit range, second-layer unit range
     const int4 *phase_k;  // per free bit: K ends of the three products, lattice position
+    const uint32_t *sched;  // per free bit: 16 words (unit ranges, half tiles, K chunks, position, cone)
     int n, h, W, D, DP, H;
     uint32_t chain_begin, step, seed_lo, seed_hi;
     uint32_t *out;        // word-major lattice words of the proposals (may be NULL)
-    double *logq;         // log q of each proposal
+    double *logq;         // log q of each proposal (score mode: of each scored path)
+    double *logq_cur;     // dual mode: log q of the scored current paths
     const uint32_t *score;  // score mode: word-major paths whose bits are read instead of drawn
     int defer;            // set by the launcher: 0 logs in the loop, 1/2 deferred (2: over the activations)
 };
 
 hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s);
+// One pass that draws proposals (out, logq) and scores the paths in `score`
+// (logq_cur) with the arithmetic of the two separate calls; only for the
+// networks made_sample_dual_ok accepts (H <= 256, lattices <= 256 bits).
+bool made_sample_dual_ok(const SampleArgs &a);
+hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s);
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
 // G and the batch-mean loss, written to *loss (per-workgroup partials in
 // `part`, ceil(n D / 256) floats, summed in a fixed order).

@@ -55,6 +55,12 @@ struct pbit_proposal_s {
     uint64_t oW1, ob1, oW2, ob2, oV, oc;
     std::vector<int> deg_in, deg1, deg2, deg_out, fpos, freem;
     std::vector<int4> phase, phase_k;
+    // per free bit, 16 words for the register-resident sampler: the unit
+    // ranges {lo1, hi1, lo2, hi2} of its phase, the half tiles of each layer
+    // that hold a unit of the phase (bit 2 cc + t) with the layer's K chunk
+    // count in the high half, the logit's K chunk count, the lattice
+    // position, then the free bit's cone words (W <= 8)
+    std::vector<uint32_t> sched;
     int dev = -1;
     DeviceArena arena;
     // device
@@ -64,6 +70,7 @@ struct pbit_proposal_s {
         *d_fpos = nullptr;
     int *k1end = nullptr, *k2end = nullptr, *k3end = nullptr, *g2beg = nullptr, *g1beg = nullptr;
     int4 *d_phase = nullptr, *d_phase_k = nullptr;
+    uint32_t *d_sched = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
     float *L = nullptr;
     float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / 256) x max(D, H)
@@ -145,8 +152,11 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     up(q->g1beg, b1);
     q->d_phase = A.alloc<int4>(q->phase.size() + 1);
     q->d_phase_k = A.alloc<int4>(q->phase_k.size() + 1);
-    if (!q->theta || !q->L || !q->colpart || !q->part || !q->lpart || !q->d_phase || !q->d_phase_k || !q->g1beg)
+    q->d_sched = A.alloc<uint32_t>(q->sched.size() + 16);
+    if (!q->theta || !q->L || !q->colpart || !q->part || !q->lpart || !q->d_phase || !q->d_phase_k || !q->g1beg ||
+        !q->d_sched)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
+    (void)hipMemcpy(q->d_sched, q->sched.data(), q->sched.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     (void)hipMemcpy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4), hipMemcpyHostToDevice);
     (void)hipMemcpy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4), hipMemcpyHostToDevice);
     (void)hipMemcpy(q->theta, q->host_params.data(), q->P * sizeof(float), hipMemcpyHostToDevice);
@@ -275,7 +285,8 @@ pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
 pbit_status unpack_range(pbit_proposal q, const uint32_t *states, uint64_t stride, uint64_t b0, int n,
                          hipStream_t s);
 pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed, uint32_t step,
-                            uint32_t *d_out, double *d_logq, const uint32_t *score, hipStream_t hip_stream);
+                            uint32_t *d_out, double *d_logq, const uint32_t *score, hipStream_t hip_stream,
+                            double *d_logq_cur = nullptr);
 
 }  // namespace
 
@@ -365,6 +376,16 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
         q->phase.push_back(int4{u1a, u1b, u2a, u2b});
         q->phase_k.push_back(int4{k1, k2, k3, p});
         prev = p;
+        uint32_t m1 = 0, m2 = 0;  // half tile t of chunk cc holds the units with (u >> 2) & 1 == t
+        for (int u = u1a; u < u1b; ++u) m1 |= 1u << (2 * (u >> 5) + ((u >> 2) & 1));
+        for (int u = u2a; u < u2b; ++u) m2 |= 1u << (2 * (u >> 5) + ((u >> 2) & 1));
+        const uint32_t rec[8] = {(uint32_t)u1a, (uint32_t)u1b, (uint32_t)u2a, (uint32_t)u2b,
+                                 (m1 & 0xffffu) | ((uint32_t)((k1 + 31) / 32) << 16),
+                                 (m2 & 0xffffu) | ((uint32_t)((k2 + 31) / 32) << 16), (uint32_t)((k3 + 31) / 32),
+                                 (uint32_t)p};
+        for (uint32_t r : rec) q->sched.push_back(r);
+        const uint32_t *cn = k.blob.data() + k.blob[H_OFF_CONE] + (size_t)b * k.WS;
+        for (uint32_t w = 0; w < 8; ++w) q->sched.push_back(w < k.W ? cn[w] : 0u);
     }
     // initial parameters
     q->host_params.assign(q->P, 0.f);
@@ -520,7 +541,8 @@ namespace {
 // The fused autoregressive kernel: draws paths (score == NULL) or reads
 // their bits from `score` and returns log q with the same arithmetic.
 pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed, uint32_t step,
-                            uint32_t *d_out, double *d_logq, const uint32_t *score, hipStream_t hip_stream) {
+                            uint32_t *d_out, double *d_logq, const uint32_t *score, hipStream_t hip_stream,
+                            double *d_logq_cur) {
     if ((uint64_t)chain_begin + n > 0x100000000ull) return set_error(PBIT_E_INVALID_ARG, "chain index overflow");
     hipStream_t s = (hipStream_t)hip_stream;
     pbit_status st = upload(q, s);
@@ -542,6 +564,7 @@ pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, u
     a.c = q->theta + q->oc;
     a.phase = q->d_phase;
     a.phase_k = q->d_phase_k;
+    a.sched = q->d_sched;
     a.n = (int)n;
     a.h = q->h;
     a.W = q->W;
@@ -555,6 +578,12 @@ pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, u
     a.out = d_out;
     a.logq = d_logq;
     a.score = score;
+    a.logq_cur = d_logq_cur;
+    if (d_logq_cur) {
+        hipError_t e = launch_made_sample_dual(a, s);
+        if (e != hipSuccess) return hip_error(e, "made sampler (sample and score)");
+        return PBIT_OK;
+    }
     hipError_t e = launch_made_sample(a, s);
     if (e != hipSuccess) return hip_error(e, "made sampler");
     return PBIT_OK;
@@ -582,6 +611,25 @@ pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint3
         if (e != hipSuccess) return hip_error(e, "logq");
     }
     return PBIT_OK;
+}
+
+pbit_status pbit_proposal_sample_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, uint64_t seed,
+                                       uint32_t step, uint32_t *d_out, double *d_logq, const uint32_t *d_cur,
+                                       double *d_logq_cur, void *hip_stream) {
+    if (!q || !d_out || !d_logq || !d_cur || !d_logq_cur) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    if (n == 0) return PBIT_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    SampleArgs probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.H = q->H;
+    probe.W = q->W;
+    probe.D = q->D;
+    probe.DP = q->DP;
+    if (made_sample_dual_ok(probe))
+        return sample_or_score(q, n, chain_begin, seed, step, d_out, d_logq, d_cur, s, d_logq_cur);
+    pbit_status st = pbit_proposal_sample(q, n, chain_begin, seed, step, d_out, d_logq, s);
+    if (st != PBIT_OK) return st;
+    return pbit_proposal_score(q, d_cur, n, d_logq_cur, s);
 }
 
 pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
@@ -627,10 +675,9 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
     uint32_t *hist_c = d_hist;  // this circuit's histogram (offset applied below for MH bins)
     for (uint32_t cy = 0; cy < cfg->cycles; ++cy) {
         const uint32_t step = cfg->step_offset + cy;
-        if ((st = pbit_proposal_sample(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, q->prop, q->lq_prop, s)) !=
-            PBIT_OK)
+            if ((st = pbit_proposal_sample_score(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, q->prop, q->lq_prop,
+                                             d_state, q->lq_cur, s)) != PBIT_OK)
             return st;
-        if ((st = pbit_proposal_score(q, d_state, (uint32_t)n, q->lq_cur, s)) != PBIT_OK) return st;
         MhArgs a;
         std::memset(&a, 0, sizeof(a));
         a.blob = blob;

@@ -309,6 +309,7 @@ def _made_sigs(L):
     L.pbit_proposal_grad.argtypes = [V, V, C.c_uint32, V, C.POINTER(C.c_float), V]
     L.pbit_proposal_train.argtypes = [V, V, P, C.POINTER(TrainCfg), V, V]
     L.pbit_proposal_sample.argtypes = [V, C.c_uint32, C.c_uint32, P, C.c_uint32, V, V, V]
+    L.pbit_proposal_sample_score.argtypes = [V, C.c_uint32, C.c_uint32, P, C.c_uint32, V, V, V, V, V]
     L.pbit_proposal_score.argtypes = [V, V, C.c_uint32, V, V]
     L.pbit_mh_run.argtypes = [V, V, C.POINTER(MhCfg), V, V, V, V]
 
@@ -366,6 +367,12 @@ class Proposal:
 
     def score(self, d_states, n, d_logq, stream=None):
         _check(lib().pbit_proposal_score(self.handle, _ptr(d_states), n, _ptr(d_logq), _stream(stream)))
+
+    def sample_score(self, n, d_out, d_logq, d_cur, d_logq_cur, seed=0, step=0, chain_begin=0, stream=None):
+        """sample() into d_out / d_logq and score() of d_cur into d_logq_cur
+        in one call (one pass over the network for small networks)."""
+        _check(lib().pbit_proposal_sample_score(self.handle, n, chain_begin, seed, step, _ptr(d_out),
+                                                _ptr(d_logq), _ptr(d_cur), _ptr(d_logq_cur), _stream(stream)))
 
 
 def mh_run(cset, proposal, chains, cycles, d_state, d_hist, d_accepts=None, gibbs_per_mh=4, seed=0,

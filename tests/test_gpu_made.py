@@ -202,6 +202,38 @@ def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
 
 
+@pytest.mark.parametrize("which,H,n", [("small", 64, 3001), ("rh48", 128, 4099), ("small", 256, 2000),
+                                        ("brick16", 1024, 1000)])
+def test_sample_score_equals_separate_calls(env, which, H, n):
+    """The MH step's fused pass (proposals drawn and the current paths scored
+    in one kernel for small networks; the two calls in sequence otherwise)
+    gives the separate calls' proposals and log q bit for bit, on a ragged
+    chain count with a chain offset."""
+    torch, pbit = env
+    if which == "small":
+        c = SMALL()
+    elif which == "rh48":
+        c = wc.rotated_hadamard_chain(48, math.pi / 64, K=1)
+    else:
+        c = wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    q = pbit.Proposal(s, hidden=H)
+    q.set_params(random_params(q.D, H, 7, scale=2.0))
+    W = s.info(0)["W"]
+    d_cur, _ = _sample(env, q, n, seed=5, step=9)  # valid current paths
+    z = lambda k, dt: torch.zeros(k, dtype=dt, device="cuda")
+    d_out, d_lq, d_lqc = z(n * W, torch.int32), z(n, torch.float64), z(n, torch.float64)
+    q.sample_score(n, d_out, d_lq, d_cur, d_lqc, seed=3, step=2, chain_begin=11)
+    d_out2, d_lq2, d_lqc2 = z(n * W, torch.int32), z(n, torch.float64), z(n, torch.float64)
+    q.sample(n, d_out2, d_lq2, seed=3, step=2, chain_begin=11)
+    q.score(d_cur, n, d_lqc2)
+    torch.cuda.synchronize()
+    assert torch.equal(d_out, d_out2)
+    assert np.array_equal(d_lq.cpu().numpy().view(np.uint64), d_lq2.cpu().numpy().view(np.uint64))
+    assert np.array_equal(d_lqc.cpu().numpy().view(np.uint64), d_lqc2.cpu().numpy().view(np.uint64))
+    assert np.isfinite(d_lqc.cpu().numpy()).all() and (d_lqc.cpu().numpy() < 0).all()
+
+
 def test_sampler_distribution_is_q(env):
     torch, pbit = env
     c = wc.rotated_hadamard_chain(7, math.pi / 5, K=1)
