@@ -147,7 +147,7 @@ MH_WORKLOADS = {
     "rhchain48": dict(circuit=_rh(PI / 64), chains=131072, burn_in=2000, hidden=128, train=1 << 18,
                       train_steps=1500, batch=4096, long_cycles=200, tau_chains=4096),
 }
-for _k in (16, 32, 128, 256):
+for _k in (16, 32, 128, 256, 512):
     MH_WORKLOADS["rhchain48_pi%d" % _k] = dict(MH_WORKLOADS["rhchain48"], circuit=_rh(PI / _k),
                                                 burn_in=max(2000, _k * _k // 2))
 
@@ -204,7 +204,7 @@ def mh_mode(args):
     from workloads import circuits as wc
 
     cfg = MH_WORKLOADS[args.workload]
-    chains, burn, hidden = cfg["chains"], cfg["burn_in"], cfg["hidden"]
+    chains, burn, hidden = cfg["chains"], cfg["burn_in"], args.hidden or cfg["hidden"]
     long_cycles, tc = cfg["long_cycles"], cfg["tau_chains"]
     G = args.gibbs_per_mh
     c = cfg["circuit"](wc)
@@ -552,6 +552,7 @@ def main():
                     help="histogram placement (pbit_gibbs_cfg.hist_mode), gibbs mode")
     ap.add_argument("--gibbs-per-mh", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--hidden", type=int, default=0, help="mh mode: MADE width (0: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: chains are independent, so N GPUs would each run "

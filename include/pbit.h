@@ -170,7 +170,9 @@ typedef struct {
                                    circuits with three-qubit products); with the
                                    specialised kernel L lanes split a chain's sweeps (lane r runs
                                    sweeps r, r + L, ...).  4 and 8 need the specialised kernel. */
-    uint32_t specialize;        /* 0 = auto (runs of 2^33 updates or more), 1 = never, 2 = always
+    uint32_t specialize;        /* 0 = auto (runs of 2^33 updates or more, and any run of a circuit
+                                   whose kernel of the needed kind is already compiled in the
+                                   handle), 1 = never, 2 = always
                                    (MODE_UNAVAILABLE if the run-time compile fails): a kernel
                                    generated for the circuit and compiled with hipRTC on first use
                                    (cached in the handle); circuits with conditionals other than

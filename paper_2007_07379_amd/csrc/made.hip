@@ -782,10 +782,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float x, float y) {
 // masks keep at exactly zero (a ReLU output is finite and >= 0, so each such
 // product is +0).  The chunk loop is unrolled so every write goes to a fixed
 // register.
-template <int NP, int NO, int NA, class Op>
-__device__ __forceinline__ void layer_tiles(u32x4v (&act)[NP][NA], const Op (&ops)[NP][NO],
-                                            const bf16 *__restrict__ WT, int rs, const float *__restrict__ bias,
-                                            uint32_t tiles, int nk, int g, int rrow) {
+template <int NP, int NO, int NA, class OpFn>
+__device__ __forceinline__ void layer_tiles(u32x4v (&act)[NP][NA], OpFn op, const bf16 *__restrict__ WT, int rs,
+                                            const float *__restrict__ bias, uint32_t tiles, int nk, int g, int rrow) {
 #pragma unroll
     for (int cc = 0; cc < NA; ++cc) {
 #pragma unroll
@@ -796,7 +795,12 @@ __device__ __forceinline__ void layer_tiles(u32x4v (&act)[NP][NA], const Op (&op
             const float4 bb = *reinterpret_cast<const float4 *>(bias + 32 * cc + 8 * g + 4 * t);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const f32x4 acc = mfma_ops<NO>(av, ops[q], nk);
+                // sum over chunks k < nk (ascending, from zero) of av[k] times
+                // the B slice op(q, k) of path q
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < NO; ++k)
+                    if (k < nk) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], op(q, k), acc, 0, 0, 0);
                 act[q][cc][2 * t] = pack_bf16(relu(acc[0] + bb.x), relu(acc[1] + bb.y));
                 act[q][cc][2 * t + 1] = pack_bf16(relu(acc[2] + bb.z), relu(acc[3] + bb.w));
             }
@@ -858,8 +862,18 @@ __device__ __forceinline__ void stage_rows(unsigned char *dst, const bf16 *src, 
     }
 }
 
-template <int NX, int NH, int NP>
+// A wave carries S = NB x NP slots of 16 chains: NB blocks of chains, each
+// with NP paths (path 0 drawn, or scored when only `score` is given; with
+// NP = 2 path 1 is the scored current path).  Slot s = q NB + j holds path q
+// of chains 16 j + c (c = lane & 15) of the wave.  Every lane keeps the
+// activations and lattices of all S slots for its c, so each slot's products
+// take the same weight rows; the per-chain work of a position (threshold,
+// draw or read of the bit, logarithm) is done by lane group g for slot
+// g % S, and one ballot hands every slot's bits to all lanes.  With S = 4
+// each lane does one chain-path, so nothing is repeated.
+template <int NX, int NH, int NB, int NP>
 __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
+    constexpr int S = NB * NP;
     extern __shared__ __align__(16) unsigned char smem[];
     const int h = a.h, W = a.W, DP = a.DP, H = a.H, D = a.D;
     const RegLayout L = reg_layout(D, DP, H);
@@ -887,26 +901,27 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
 
     const int lane = threadIdx.x & 63;
     const int c = lane & 15, g = lane >> 4;
-    const int chain = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 + c;
-    if (__builtin_amdgcn_readfirstlane(chain - c) >= a.n) return;  // the wave has no chain
-    const bool valid = chain < a.n;
+    const int base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16 * NB;  // first chain of the wave
+    if (__builtin_amdgcn_readfirstlane(base) >= a.n) return;  // the wave has no chain
+    // this lane's slot for the per-chain work
+    const int my_s = g % S, my_q = my_s / NB;
+    const int my_chain = base + 16 * (my_s % NB) + c;
+    const bool my_valid = my_chain < a.n;
+    // path q draws its bits unless it is the scored one (the last path when
+    // `score` is given)
+    const int qs = a.score ? NP - 1 : NP;  // first scored path (NP: none)
+    const bool my_draws = my_q < qs;
     const uint32_t *B = a.blob;
     const uint32_t *cw = B + B[H_OFF_CONST];
     const uint32_t cid = B[H_CID];
-    // path q < NP draws its bits unless it is the scored one (the last path
-    // when `score` is given)
-    const int qs = a.score ? NP - 1 : NP;  // first scored path (NP: none)
 
-    uint32_t lat[NP][NX], path[NX];
-    u32x4v act1[NP][NH], act2[NP][NH];
-    // of the last <= 4 positions, the threshold and bit whose logarithm this
-    // lane group takes (position f with f % 4 == g)
-    uint32_t tg[NP], bg[NP];
-    double lq[NP];
+    uint32_t lat[S][NX], path[NX];
+    u32x4v act1[S][NH], act2[S][NH];
 #pragma unroll
-    for (int w = 0; w < NX; ++w) path[w] = (a.score && valid && w < W) ? a.score[(int64_t)w * a.n + chain] : 0u;
+    for (int w = 0; w < NX; ++w)
+        path[w] = (!my_draws && my_valid && w < W) ? a.score[(int64_t)w * a.n + my_chain] : 0u;
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
+    for (int q = 0; q < S; ++q) {
 #pragma unroll
         for (int w = 0; w < NX; ++w) lat[q][w] = w < W ? cw[w] : 0u;
 #pragma unroll
@@ -914,103 +929,120 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
             act1[q][k] = u32x4v{0u, 0u, 0u, 0u};
             act2[q][k] = u32x4v{0u, 0u, 0u, 0u};
         }
-        tg[q] = bg[q] = 0u;
-        lq[q] = 0.0;
     }
+    double lq = 0.0;
     const int rrow = 8 * (c >> 2) + (c & 3);  // this lane's A row within a half tile
     U4 u4 = {0u, 0u, 0u, 0u};
     for (int f = 0; f < h; ++f) {
         const uint32_t *rec = a.sched + (size_t)f * 16;  // wave-uniform: one scalar load
         const uint32_t t1 = rec[4] & 0xffffu, t2 = rec[5] & 0xffffu;
         const int nk1 = (int)(rec[4] >> 16), nk2 = (int)(rec[5] >> 16), nk3 = (int)rec[6], p = (int)rec[7];
-        if (t1) {
-            bf16x8 xop[NP][NX];
-#pragma unroll
-            for (int q = 0; q < NP; ++q)
-#pragma unroll
-                for (int k = 0; k < NX; ++k)
-                    if (k < nk1) xop[q][k] = lut[(lat[q][k] >> (8 * g)) & 0xffu];
-            layer_tiles<NP, NX, NH>(act1, xop, W1s, DP + REG_PAD, b1s, t1, nk1, g, rrow);
-        }
-        if (t2) layer_tiles<NP, NH, NH>(act2, act1, W2s, H + REG_PAD, b2s, t2, nk2, g, rrow);
-        // logit of position p: every A row is row p of V, so all four
-        // accumulator elements hold it
-        if (qs > 0 && (f & 3) == 0)  // some path draws its bits
-            u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + (uint32_t)chain, cid | (1u << 16),
-                               a.seed_lo, a.seed_hi);
-        const uint32_t ud = (f & 3) == 0 ? u4.x : ((f & 3) == 1 ? u4.y : ((f & 3) == 2 ? u4.z : u4.w));
-        const uint32_t pbit = (pick_word(path, p >> 5) >> (p & 31)) & 1u;
+        // layer 1 reads its input slices (8 lattice bits as bf16) from the
+        // table as it goes; layer 2 reads the layer-1 activations
+        if (t1)
+            layer_tiles<S, NX, NH>(
+                act1, [&](int q, int k) { return lut[(lat[q][k] >> (8 * g)) & 0xffu]; }, W1s, DP + REG_PAD, b1s, t1,
+                nk1, g, rrow);
+        if (t2)
+            layer_tiles<S, NH, NH>(
+                act2, [&](int q, int k) { return __builtin_bit_cast(bf16x8, act1[q][k]); }, W2s, H + REG_PAD, b2s,
+                t2, nk2, g, rrow);
+        // logits of position p: every A row is row p of V, so all four
+        // accumulator elements of a slot hold its chains' logits
         bf16x8 vv[NH];
         load_rows<NH>(vv, Vs + (int64_t)p * (H + REG_PAD) + 8 * g, nk3);
+        float lg = 0.f;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
+        for (int q = 0; q < S; ++q) {
             const f32x4 lacc = mfma_ops<NH>(vv, act2[q], nk3);
-            const uint32_t T = made_threshold(lacc[0] + cs[p]);
-            const uint32_t bit = q < qs ? (ud < T ? 1u : 0u) : pbit;
-            tg[q] = (g == (f & 3)) ? T : tg[q];
-            bg[q] = (g == (f & 3)) ? bit : bg[q];
+            lg = (q == my_s) ? lacc[0] : lg;
+        }
+        const uint32_t T = made_threshold(lg + cs[p]);
+        uint32_t bit;
+        if (my_draws) {
+            if ((f & 3) == 0)
+                u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + (uint32_t)my_chain, cid | (1u << 16),
+                                   a.seed_lo, a.seed_hi);
+            const uint32_t u = (f & 3) == 0 ? u4.x : ((f & 3) == 1 ? u4.y : ((f & 3) == 2 ? u4.z : u4.w));
+            bit = u < T ? 1u : 0u;
+        } else {
+            bit = (pick_word(path, p >> 5) >> (p & 31)) & 1u;
+        }
+        // log q in free-bit order, as the batched scorer sums it
+        lq += made_log_prob(T, bit);
+        // every slot's bit for chain c: lane 16 s + c holds slot s's
+        const uint64_t bits = __ballot(bit != 0u);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint32_t bq = (uint32_t)(bits >> (16 * q + c)) & 1u;
             // the lattice bit at p is the free bit itself: flip its cone when
             // the new value differs from the current one
-            const uint32_t m = 0u - (((pick_word(lat[q], p >> 5) >> (p & 31)) & 1u) ^ bit);
+            const uint32_t m = 0u - (((pick_word(lat[q], p >> 5) >> (p & 31)) & 1u) ^ bq);
 #pragma unroll
             for (int w = 0; w < NX; ++w) lat[q][w] ^= m & rec[8 + w];  // cone words, zero beyond W
         }
-        // log q in free-bit order, as the batched scorer sums it: after every
-        // fourth position lane group j evaluates the logarithm of the j-th of
-        // them and the four are added in order in every lane
-        if ((f & 3) == 3 || f == h - 1) {
-            const int cnt = (f & 3) + 1;
+    }
+    if (g < S && my_valid) {
+        if (my_q == 0) {
+            if (a.out && qs > 0) {
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const double lg = g < cnt ? made_log_prob(tg[q], bg[q]) : 0.0;
-                const int64_t lb = __builtin_bit_cast(int64_t, lg);
-                for (int j = 0; j < cnt; ++j) {
-                    const int src = (c + 16 * j) << 2;
-                    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)lb);
-                    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(lb >> 32));
-                    lq[q] += __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+                for (int w = 0; w < NX; ++w) {
+                    uint32_t v = 0u;
+#pragma unroll
+                    for (int q = 0; q < S; ++q) v = (q == my_s) ? lat[q][w] : v;
+                    if (w < W) a.out[(int64_t)w * a.n + my_chain] = v;
                 }
             }
+            a.logq[my_chain] = lq;
+        } else {
+            a.logq_cur[my_chain] = lq;
         }
-    }
-    if (g == 0 && valid) {
-        if (a.out && qs > 0)
-#pragma unroll
-            for (int w = 0; w < NX; ++w)
-                if (w < W) a.out[(int64_t)w * a.n + chain] = lat[0][w];
-        a.logq[chain] = lq[0];
-        if (NP == 2) a.logq_cur[chain] = lq[NP - 1];
     }
 }
 
-template <int NX, int NH, int NP>
+template <int NX, int NH, int NB, int NP>
 hipError_t launch_reg(const SampleArgs &a, size_t lds, hipStream_t s) {
     // enough waves per workgroup to share the staged network, few enough to
     // spread small runs over every CU
-    const int waves = (a.n + 15) / 16;
+    const int waves = (a.n + 16 * NB - 1) / (16 * NB);
     const int per_wg = std::min(8, std::max(1, waves / 512));
     const int grid = (waves + per_wg - 1) / per_wg;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)made_sample_reg_kernel<NX, NH, NP>,
+        hipError_t e = hipFuncSetAttribute((const void *)made_sample_reg_kernel<NX, NH, NB, NP>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((made_sample_reg_kernel<NX, NH, NP>), dim3(grid), dim3(64 * per_wg), lds, s, a);
+    hipLaunchKernelGGL((made_sample_reg_kernel<NX, NH, NB, NP>), dim3(grid), dim3(64 * per_wg), lds, s, a);
     return hipGetLastError();
+}
+
+// chain blocks per wave: four slots (one chain-path per lane) where the
+// activations and lattices of four slots fit in registers without spilling,
+// fewer for wider networks or lattices
+template <int NX, int NH, int NP>
+constexpr int reg_blocks() {
+    if (NH <= 2) return 4 / NP;
+    if (NH <= 4) return NX <= 2 ? 4 / NP : (NP == 1 ? 2 : 1);
+    return 1;
+}
+
+template <int NX, int NH, int NP>
+hipError_t launch_reg_nb(const SampleArgs &a, size_t lds, hipStream_t s) {
+    return launch_reg<NX, NH, reg_blocks<NX, NH, NP>(), NP>(a, lds, s);
 }
 
 template <int NX, int NP>
 hipError_t launch_reg_h(const SampleArgs &a, size_t lds, hipStream_t s) {
-    if (a.H <= 64) return launch_reg<NX, 2, NP>(a, lds, s);
-    if (NP == 2 || a.H <= 128) return launch_reg<NX, 4, NP>(a, lds, s);  // dual: H <= 128
-    return launch_reg<NX, (NP == 1 ? 8 : 4), NP>(a, lds, s);
+    if (a.H <= 64) return launch_reg_nb<NX, 2, NP>(a, lds, s);
+    if (NP == 2 || a.H <= 128) return launch_reg_nb<NX, 4, NP>(a, lds, s);  // dual: H <= 128
+    return launch_reg_nb<NX, 8, 1>(a, lds, s);
 }
 
 template <int NP>
 hipError_t launch_reg_w(const SampleArgs &a, size_t lds, hipStream_t s) {
     if (a.W <= 2) return launch_reg_h<2, NP>(a, lds, s);
     if (NP == 2 || a.W <= 4) return launch_reg_h<4, NP>(a, lds, s);  // dual: W <= 4
-    return launch_reg_h<(NP == 1 ? 8 : 4), NP>(a, lds, s);
+    return launch_reg_h<8, 1>(a, lds, s);
 }
 
 bool made_sample_dual_ok(const SampleArgs &a) {

@@ -16,25 +16,33 @@
 
 namespace pbit {
 
+// ln|psi| of two paths x and y at once: the sum, in gate order, of ln|U_g|
+// over the real-energy records (`rec`, nre records of RE_STRIDE words; the
+// tables are read with a per-lane index, so the caller passes a copy in LDS
+// when it has one)
 template <int W>
-__device__ __forceinline__ double log_weight(const uint32_t *__restrict__ B, const uint32_t (&x)[W + 2]) {
-    const uint32_t nre = B[H_NRE];
-    const uint32_t *rec = B + B[H_OFF_RE];
-    double s = 0.0;
+__device__ __forceinline__ void log_weights(const uint32_t *rec, uint32_t nre, const uint32_t (&x)[W + 2],
+                                            const uint32_t (&y)[W + 2], double &sx, double &sy) {
+    sx = 0.0;
+    sy = 0.0;
     for (uint32_t r = 0; r < nre; ++r, rec += RE_STRIDE) {
         const uint32_t a = rec[0];
-        uint32_t i = 0, o = 0;
+        uint32_t ix = 0, ox = 0, iy = 0, oy = 0;
         for (uint32_t j = 0; j < a; ++j) {
             const uint32_t pi = rec[1 + j], po = rec[3 + j];
-            i |= ((select_word<W>(x, pi >> 5) >> (pi & 31)) & 1u) << j;
-            o |= ((select_word<W>(x, po >> 5) >> (po & 31)) & 1u) << j;
+            ix |= ((select_word<W>(x, pi >> 5) >> (pi & 31)) & 1u) << j;
+            ox |= ((select_word<W>(x, po >> 5) >> (po & 31)) & 1u) << j;
+            iy |= ((select_word<W>(y, pi >> 5) >> (pi & 31)) & 1u) << j;
+            oy |= ((select_word<W>(y, po >> 5) >> (po & 31)) & 1u) << j;
         }
-        const uint32_t t = o * (1u << a) + i;
-        const uint64_t bits = (uint64_t)rec[8 + 2 * t] | ((uint64_t)rec[9 + 2 * t] << 32);
-        s += __longlong_as_double((long long)bits);
+        const uint32_t tx = ox * (1u << a) + ix, ty = oy * (1u << a) + iy;
+        sx += __longlong_as_double((long long)((uint64_t)rec[8 + 2 * tx] | ((uint64_t)rec[9 + 2 * tx] << 32)));
+        sy += __longlong_as_double((long long)((uint64_t)rec[8 + 2 * ty] | ((uint64_t)rec[9 + 2 * ty] << 32)));
     }
-    return s;
 }
+
+// real-energy records staged in LDS when they take at most this many words
+constexpr uint32_t MH_LDS_RE_WORDS = 8192;
 
 // Histograms of at most this many bins are privatised in LDS per workgroup
 // (every chain adds one count per transition, and circuits with few output
@@ -42,7 +50,7 @@ __device__ __forceinline__ double log_weight(const uint32_t *__restrict__ B, con
 constexpr uint32_t MH_LDS_BINS = 8192;
 
 template <int W>
-__device__ __forceinline__ void mh_accept_body(const MhArgs &a, uint32_t *lds_h) {
+__device__ __forceinline__ void mh_accept_body(const MhArgs &a, uint32_t *lds_h, const uint32_t *re) {
     const uint32_t *__restrict__ B = a.blob;
     const int lc = blockIdx.x * blockDim.x + threadIdx.x;
     if (lc >= a.n) return;
@@ -55,7 +63,11 @@ __device__ __forceinline__ void mh_accept_body(const MhArgs &a, uint32_t *lds_h)
         y[w] = (uint32_t)w < Wc ? a.prop[(int64_t)w * a.n + lc] : 0u;
     }
     double lr = a.logq_cur[lc] - a.logq_prop[lc];
-    if (B[H_NRE]) lr += log_weight<W>(B, y) - log_weight<W>(B, x);
+    if (B[H_NRE]) {
+        double wx, wy;
+        log_weights<W>(re, B[H_NRE], x, y, wx, wy);
+        lr += wy - wx;
+    }
     const double acc = lr >= 0.0 ? 1.0 : exp(lr);
     const uint32_t cid = B[H_CID];
     const U4 u = philox4x32_10(a.step, 0u, a.chain_begin + (uint32_t)lc, cid | (2u << 16), a.seed_lo, a.seed_hi);
@@ -81,11 +93,18 @@ template <int W>
 __global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
     extern __shared__ uint32_t lds_h[];
     const bool priv = a.hist && a.hist_bins <= MH_LDS_BINS;
-    if (priv) {
-        for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) lds_h[i] = 0u;
-        __syncthreads();
+    // LDS: the privatised histogram, then the real-energy records
+    const uint32_t nre_w = a.blob[H_NRE] * (uint32_t)RE_STRIDE;
+    const bool re_lds = nre_w <= MH_LDS_RE_WORDS;
+    uint32_t *re_s = lds_h + (priv ? a.hist_bins : 0u);
+    if (re_lds) {
+        const uint32_t *re_g = a.blob + a.blob[H_OFF_RE];
+        for (uint32_t i = threadIdx.x; i < nre_w; i += blockDim.x) re_s[i] = re_g[i];
     }
-    mh_accept_body<W>(a, priv ? lds_h : nullptr);
+    if (priv)
+        for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) lds_h[i] = 0u;
+    __syncthreads();
+    mh_accept_body<W>(a, priv ? lds_h : nullptr, re_lds ? re_s : a.blob + a.blob[H_OFF_RE]);
     if (priv) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) {
@@ -100,7 +119,10 @@ __global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
 hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s) {
     const int grid = (a.n + 255) / 256;
     if (grid == 0) return hipSuccess;
-    const size_t lds = (a.hist && a.hist_bins <= MH_LDS_BINS) ? (size_t)a.hist_bins * 4 : 0;
+    size_t lds = (a.hist && a.hist_bins <= MH_LDS_BINS) ? (size_t)a.hist_bins * 4 : 0;
+    // the records are staged when they fit (the kernel reads their count from
+    // the image; the launch reserves the largest staged size)
+    lds += (size_t)MH_LDS_RE_WORDS * 4;
 #define PBIT_LAUNCH(V)                                                                  \
     if (Wk == V) {                                                                      \
         hipLaunchKernelGGL((mh_accept_kernel<V>), dim3(grid), dim3(256), lds, s, a);    \

@@ -70,10 +70,13 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     if (cfg->sweeps_per_launch) t.group = std::min<uint64_t>(cfg->sweeps_per_launch, total_sweeps);
 
     // circuit-specialised kernel: runs of 2^33 updates or more (the run-time
-    // compile takes about a second), unless the caller asks for a generic
-    // toggle mode
+    // compile takes about a second), or any run once the kernel it needs is
+    // already compiled in the handle (an earlier long run paid for it),
+    // unless the caller asks for a generic toggle mode
     const uint64_t work = (uint64_t)chains * total_sweeps * k.h;
-    t.jit = cfg->specialize == 2 || (cfg->specialize == 0 && cfg->toggle_mode == 0 && work >= (1ull << 33));
+    const bool auto_rule = cfg->specialize == 0 && cfg->toggle_mode == 0;
+    const bool short_run = work < (1ull << 33);
+    t.jit = cfg->specialize == 2 || (auto_rule && (!short_run || jit_compiled_any(c, i)));
     if (t.jit && !k.uniform) {
         // other conditionals: one lane per chain (sweeps depend on each
         // other), threshold tables and the histogram in LDS when they fit
@@ -131,7 +134,27 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
         t.block = t.lds_hist || t.path_hist ? 1024 : 256;
         if (cfg->block_size) t.block = cfg->block_size;
     }
+    if (t.jit && auto_rule && short_run && !jit_compiled(c, i, jit_hist_kind(t))) {
+        // a short run does not pay for compiling another kind: generic kernels
+        pbit_gibbs_cfg g = *cfg;
+        g.specialize = 1;
+        return tune_choice(c, i, chains, total_sweeps, &g);
+    }
     return t;
+}
+
+bool jit_compiled(pbit_circuit c, uint32_t i, uint32_t kind) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    return c->jit.count(std::make_tuple(dev, i, kind)) != 0;
+}
+
+bool jit_compiled_any(pbit_circuit c, uint32_t i) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    for (uint32_t kind = 0; kind < 4; ++kind)
+        if (c->jit.count(std::make_tuple(dev, i, kind))) return true;
+    return false;
 }
 
 BatchTuning tune_batch(pbit_circuit c, const pbit_gibbs_cfg *cfg) {

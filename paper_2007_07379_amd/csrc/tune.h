@@ -25,6 +25,12 @@ inline uint32_t jit_hist_kind(const TuneChoice &t) {
     return t.path_hist ? 2u : (t.keys ? 3u : (t.lds_hist ? 1u : 0u));
 }
 
+// Is a circuit-specialised kernel of this histogram kind (any kind) for
+// circuit i compiled in the handle for the current device?  The handle's
+// mutex must be held.
+bool jit_compiled(pbit_circuit c, uint32_t i, uint32_t kind);
+bool jit_compiled_any(pbit_circuit c, uint32_t i);
+
 // Explicit cfg fields win; unset ones come from the autotuned table of the
 // handle (if pbit_autotune ran or loaded a cache) or from the static rules.
 TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t total_sweeps,
