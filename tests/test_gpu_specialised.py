@@ -94,6 +94,29 @@ def test_specialised_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb
         assert int(h.sum()) == chains * sweeps
 
 
+@pytest.mark.parametrize("name", ["rct12", "rotated"])
+def test_auto_rule_reuses_a_compiled_kernel(env, name):
+    """A short run under the automatic rule takes the generic kernels until
+    the handle holds a specialised kernel of the kind it needs (here compiled
+    by a specialize=2 run), then that kernel; the counts and states are the
+    generic kernels' bit for bit either way."""
+    torch, pbit = env
+    import math
+    c = wc.workload_circuit("rct12") if name == "rct12" else wc.rotated_brickwork(6, 8, 3, math.pi / 7, K=3)
+    s = pbit.CircuitSet(c)
+    chains, burn, sweeps, seed = 3000, 5, 37, 99
+    assert s.launch_shape([chains], burn, sweeps)["kernel"] != pbit.KERNEL_SPECIALISED
+    st_g, h_g = run(env, s, chains, burn, sweeps, seed, 0, specialize=1)
+    st_a, h_a = run(env, s, chains, burn, sweeps, seed, 0)  # auto, nothing compiled yet
+    assert np.array_equal(st_a, st_g) and np.array_equal(h_a, h_g)
+    run(env, s, chains, burn, sweeps, seed, 0, specialize=2)  # compiles the kernel
+    sh = s.launch_shape([chains], burn, sweeps)
+    say("auto after compile", name, sh)
+    assert sh["kernel"] == pbit.KERNEL_SPECIALISED
+    st_s, h_s = run(env, s, chains, burn, sweeps, seed, 0)
+    assert np.array_equal(st_s, st_g) and np.array_equal(h_s, h_g)
+
+
 def test_specialised_groups_graph_and_resume(env):
     torch, pbit = env
     c = wc.workload_circuit("rct12")
