@@ -40,6 +40,26 @@ namespace pbit {
 // local chains lc0 .. lc0 + blockDim.x - 1 of the circuit for the launch's
 // sweeps, flush the private histogram.  Shared by the single-circuit kernel
 // and the persistent batched kernel (batched.hip).
+// dst[i] = src[i] for i < n by the whole workgroup, eight loads per thread
+// issued before their stores
+template <class T>
+__device__ __forceinline__ void stage_lds(T *dst, const T *__restrict__ src, uint32_t n) {
+    constexpr uint32_t U = 8;
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        T v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * blockDim.x;
+            if (i < n) v[u] = src[i];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * blockDim.x;
+            if (i < n) dst[i] = v[u];
+        }
+    }
+}
+
 template <int W, bool UNIFORM, bool TOG>
 __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint32_t *__restrict__ state,
                                             uint32_t *__restrict__ hist, const GibbsArgs &a, uint32_t lc0,
@@ -66,15 +86,11 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
     const uint32_t lc = lc0 + tid;
     const bool active = lc < a.n_chains;
 
-    if (TOG) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(B + B[H_OFF_TOG]);
-        uint4 *dst = reinterpret_cast<uint4 *>(lds_tog);
-        for (uint32_t i = tid; i < tog_words / 4; i += blockDim.x) dst[i] = src[i];
-    }
-    if (!uniform) {
-        const uint32_t *tab = B + B[H_OFF_THRTAB];
-        for (uint32_t i = tid; i < thr_total; i += blockDim.x) lds_thr[i] = tab[i];
-    }
+    // staging: eight loads per thread in flight before their stores, so a
+    // small workgroup does not wait one memory latency per piece
+    if (TOG) stage_lds<uint4>(reinterpret_cast<uint4 *>(lds_tog), reinterpret_cast<const uint4 *>(B + B[H_OFF_TOG]),
+                              tog_words / 4);
+    if (!uniform) stage_lds<uint32_t>(lds_thr, B + B[H_OFF_THRTAB], thr_total);
     if (a.lds_hist)
         for (uint32_t i = tid; i < nbins; i += blockDim.x) lds_h[i] = 0u;
     __syncthreads();
