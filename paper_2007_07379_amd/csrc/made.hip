@@ -871,7 +871,12 @@ __device__ __forceinline__ void stage_rows(unsigned char *dst, const bf16 *src, 
 // draw or read of the bit, logarithm) is done by lane group g for slot
 // g % S, and one ballot hands every slot's bits to all lanes.  With S = 4
 // each lane does one chain-path, so nothing is repeated.
-template <int NX, int NH, int NB, int NP>
+// FULL (rows exactly NX and NH chunks long: DP = 32 NX, H = 32 NH): every
+// product runs over all chunks of its rows instead of the phase's K range.
+// The extra chunks multiply weights the degree masks keep at exactly zero,
+// so the units a phase keeps come out with the same bits, and the products
+// need no per-chunk branches.
+template <int NX, int NH, int NB, int NP, bool FULL>
 __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
     constexpr int S = NB * NP;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -936,7 +941,8 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
     for (int f = 0; f < h; ++f) {
         const uint32_t *rec = a.sched + (size_t)f * 16;  // wave-uniform: one scalar load
         const uint32_t t1 = rec[4] & 0xffffu, t2 = rec[5] & 0xffffu;
-        const int nk1 = (int)(rec[4] >> 16), nk2 = (int)(rec[5] >> 16), nk3 = (int)rec[6], p = (int)rec[7];
+        const int nk1 = FULL ? NX : (int)(rec[4] >> 16), nk2 = FULL ? NH : (int)(rec[5] >> 16);
+        const int nk3 = FULL ? NH : (int)rec[6], p = (int)rec[7];
         // layer 1 reads its input slices (8 lattice bits as bf16) from the
         // table as it goes; layer 2 reads the layer-1 activations
         if (t1)
@@ -1000,19 +1006,19 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
     }
 }
 
-template <int NX, int NH, int NB, int NP>
-hipError_t launch_reg(const SampleArgs &a, size_t lds, hipStream_t s) {
+template <int NX, int NH, int NB, int NP, bool FULL>
+hipError_t launch_reg_k(const SampleArgs &a, size_t lds, hipStream_t s) {
     // enough waves per workgroup to share the staged network, few enough to
     // spread small runs over every CU
     const int waves = (a.n + 16 * NB - 1) / (16 * NB);
     const int per_wg = std::min(8, std::max(1, waves / 512));
     const int grid = (waves + per_wg - 1) / per_wg;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)made_sample_reg_kernel<NX, NH, NB, NP>,
+        hipError_t e = hipFuncSetAttribute((const void *)made_sample_reg_kernel<NX, NH, NB, NP, FULL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((made_sample_reg_kernel<NX, NH, NB, NP>), dim3(grid), dim3(64 * per_wg), lds, s, a);
+    hipLaunchKernelGGL((made_sample_reg_kernel<NX, NH, NB, NP, FULL>), dim3(grid), dim3(64 * per_wg), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1026,41 +1032,57 @@ constexpr int reg_blocks() {
     return 1;
 }
 
+// Rows of exactly 2, 4 or 8 chunks take the full-chunk kernel (sized for
+// them); any other shape within the limits takes one guarded kernel sized for
+// the largest (8 and 8 chunks, one slot), which keeps the number of kernels
+// compiled small.
+int reg_chunks(int len) { return len == 64 ? 2 : (len == 128 ? 4 : (len == 256 ? 8 : 0)); }
+
 template <int NX, int NH, int NP>
-hipError_t launch_reg_nb(const SampleArgs &a, size_t lds, hipStream_t s) {
-    return launch_reg<NX, NH, reg_blocks<NX, NH, NP>(), NP>(a, lds, s);
+hipError_t launch_full(const SampleArgs &a, size_t lds, hipStream_t s) {
+    return launch_reg_k<NX, NH, reg_blocks<NX, NH, NP>(), NP, true>(a, lds, s);
 }
 
 template <int NX, int NP>
-hipError_t launch_reg_h(const SampleArgs &a, size_t lds, hipStream_t s) {
-    if (a.H <= 64) return launch_reg_nb<NX, 2, NP>(a, lds, s);
-    if (NP == 2 || a.H <= 128) return launch_reg_nb<NX, 4, NP>(a, lds, s);  // dual: H <= 128
-    return launch_reg_nb<NX, 8, 1>(a, lds, s);
+hipError_t launch_full_h(const SampleArgs &a, size_t lds, hipStream_t s) {
+    if (reg_chunks(a.H) == 2) return launch_full<NX, 2, NP>(a, lds, s);
+    return launch_full<NX, 4, NP>(a, lds, s);  // H = 128 (a 256-wide network does not fit in LDS)
 }
 
 template <int NP>
-hipError_t launch_reg_w(const SampleArgs &a, size_t lds, hipStream_t s) {
-    if (a.W <= 2) return launch_reg_h<2, NP>(a, lds, s);
-    if (NP == 2 || a.W <= 4) return launch_reg_h<4, NP>(a, lds, s);  // dual: W <= 4
-    return launch_reg_h<8, 1>(a, lds, s);
+hipError_t launch_full_w(const SampleArgs &a, size_t lds, hipStream_t s) {
+    const int nx = reg_chunks(a.DP);
+    if (nx == 2) return launch_full_h<2, NP>(a, lds, s);
+    if (nx == 4) return launch_full_h<4, NP>(a, lds, s);
+    return launch_full_h<(NP == 1 ? 8 : 4), NP>(a, lds, s);  // dual: W <= 4
+}
+
+bool reg_fits(const SampleArgs &a) {
+    return a.H <= 256 && a.W <= 8 && reg_layout(a.D, a.DP, a.H).total <= 160 * 1024;
 }
 
 bool made_sample_dual_ok(const SampleArgs &a) {
     // two paths of 256-wide activations, or of 8-word lattices beside 128-wide
-    // ones, would not fit in registers
-    return a.H <= 128 && a.W <= 4 && reg_layout(a.D, a.DP, a.H).total <= 160 * 1024;
+    // ones, would not fit in registers; other shapes than whole rows of 2 or 4
+    // chunks run the two calls
+    const int nx = reg_chunks(a.DP), nh = reg_chunks(a.H);
+    return reg_fits(a) && (nx == 2 || nx == 4) && (nh == 2 || nh == 4);
 }
 
 hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    return launch_reg_w<2>(a, reg_layout(a.D, a.DP, a.H).total, s);
+    return launch_full_w<2>(a, reg_layout(a.D, a.DP, a.H).total, s);
 }
 
 hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
     SampleArgs a = a0;
     if (a.n <= 0) return hipSuccess;
     // small networks and lattices: the register-resident kernel
-    if (made_sample_dual_ok(a)) return launch_reg_w<1>(a, reg_layout(a.D, a.DP, a.H).total, s);
+    if (reg_fits(a)) {
+        const size_t lds = reg_layout(a.D, a.DP, a.H).total;
+        if (reg_chunks(a.DP) && (a.H == 64 || a.H == 128)) return launch_full_w<1>(a, lds, s);
+        return launch_reg_k<8, 8, 1, 1, false>(a, lds, s);
+    }
     const int grid = (a.n + 15) / 16;
     const size_t base = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
     // small networks defer the log-probabilities to the end and keep the cones

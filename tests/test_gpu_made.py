@@ -203,7 +203,7 @@ def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
 
 
 @pytest.mark.parametrize("which,H,n", [("small", 64, 3001), ("rh48", 128, 4099), ("small", 256, 2000),
-                                        ("brick16", 1024, 1000)])
+                                        ("w4", 128, 2000), ("w8", 64, 1500), ("brick16", 1024, 1000)])
 def test_sample_score_equals_separate_calls(env, which, H, n):
     """The MH step's fused pass (proposals drawn and the current paths scored
     in one kernel for small networks; the two calls in sequence otherwise)
@@ -214,6 +214,10 @@ def test_sample_score_equals_separate_calls(env, which, H, n):
         c = SMALL()
     elif which == "rh48":
         c = wc.rotated_hadamard_chain(48, math.pi / 64, K=1)
+    elif which == "w4":
+        c = wc.random_clifford_t(8, 12, 5, K=3)  # 104 lattice bits: 4 words
+    elif which == "w8":
+        c = wc.random_clifford_t(12, 20, 6, K=3)  # 252 lattice bits: 8 words
     else:
         c = wc.workload_circuit("brick16")
     s = pbit.CircuitSet(c)
