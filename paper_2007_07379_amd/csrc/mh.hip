@@ -49,11 +49,13 @@ constexpr uint32_t MH_LDS_RE_WORDS = 8192;
 // states would otherwise serialise on a handful of HBM addresses).
 constexpr uint32_t MH_LDS_BINS = 8192;
 
+// One chain's accept; returns the bin of its post-transition path, or -1
+// when it has none to add (no histogram, or no chain for this thread).
 template <int W>
-__device__ __forceinline__ void mh_accept_body(const MhArgs &a, uint32_t *lds_h, const uint32_t *re) {
+__device__ __forceinline__ int mh_accept_body(const MhArgs &a, const uint32_t *re) {
     const uint32_t *__restrict__ B = a.blob;
     const int lc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (lc >= a.n) return;
+    if (lc >= a.n) return -1;
     const uint32_t Wc = B[H_W];
     uint32_t x[W + 2], y[W + 2];
     x[W] = x[W + 1] = y[W] = y[W + 1] = 0u;
@@ -80,13 +82,7 @@ __device__ __forceinline__ void mh_accept_body(const MhArgs &a, uint32_t *lds_h,
         }
     }
     if (a.accepts && accept) a.accepts[lc] += 1ull;
-    if (a.hist) {
-        const uint32_t bin = phase_and_bin<W>(B, x, B[H_K], B[H_N]);
-        if (lds_h)
-            atomicAdd(&lds_h[bin], 1u);
-        else
-            atomicAdd(&a.hist[bin], 1u);
-    }
+    return a.hist ? (int)phase_and_bin<W>(B, x, B[H_K], B[H_N]) : -1;
 }
 
 template <int W>
@@ -104,7 +100,15 @@ __global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
     if (priv)
         for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) lds_h[i] = 0u;
     __syncthreads();
-    mh_accept_body<W>(a, priv ? lds_h : nullptr, re_lds ? re_s : a.blob + a.blob[H_OFF_RE]);
+    // separate calls, so the records' and the histogram's address spaces are
+    // known to the compiler (LDS reads and atomics, not generic ones)
+    const int bin = re_lds ? mh_accept_body<W>(a, re_s) : mh_accept_body<W>(a, a.blob + a.blob[H_OFF_RE]);
+    if (bin >= 0) {
+        if (priv)
+            atomicAdd(&lds_h[bin], 1u);
+        else
+            atomicAdd(&a.hist[bin], 1u);
+    }
     if (priv) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < a.hist_bins; i += blockDim.x) {
