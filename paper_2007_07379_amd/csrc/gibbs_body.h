@@ -81,7 +81,6 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
     uint32_t *lds_tog = lds;
     uint32_t *lds_thr = lds + tog_words;
     uint32_t *lds_h = lds_thr + thr_total;
-    const uint32_t *thr = thr_glob ? B + B[H_OFF_THRTAB] : lds_thr;
     const uint32_t tid = threadIdx.x;
     const uint32_t lc = lc0 + tid;
     const bool active = lc < a.n_chains;
@@ -190,7 +189,7 @@ __device__ __forceinline__ void gibbs_block(const uint32_t *__restrict__ B, uint
 #pragma unroll
                                 for (int t = 0; t < 4; ++t)
                                     if (m & (1u << t)) {
-                                        const uint32_t T = threshold_of<W>(B, 4 * j + t, x, thr);
+                                        const uint32_t T = threshold_of<W>(B, 4 * j + t, x, lds_thr, thr_glob);
                                         nb |= (uu[t] < T ? 1u : 0u) << t;
                                     }
                             }

@@ -583,8 +583,6 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     if (a.defer)
         for (int e = lane; e < h * W; e += 64) cones[e] = cone_g[(int64_t)(e / W) * WS + e % W];
     __syncthreads();
-    const uint32_t *cone = a.defer ? cones : cone_g;
-    const int cstride = a.defer ? W : (int)WS;
     double lq = 0.0;
     U4 u4 = {0u, 0u, 0u, 0u};
     const int row = lane & 15, kq = (lane >> 4) * 8;
@@ -655,9 +653,11 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
                 // when the drawn value differs from the current one
                 const uint32_t cur = (lat[lane * W + (p >> 5)] >> (p & 31)) & 1u;
                 if (bit != cur) {
-                    const uint32_t *cm = cone + (int64_t)f * cstride;
                     for (int w = 0; w < W; ++w) {
-                        uint32_t mw = cm[w];
+                        // the cone from LDS or from the image, each by its own
+                        // load (not a generic one)
+                        typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+                        uint32_t mw = a.defer ? ((lds_u32 *)cones)[f * W + w] : cone_g[(int64_t)f * WS + w];
                         lat[lane * W + w] ^= mw;
                         while (mw) {
                             const int i = 32 * w + __builtin_ctz(mw);

@@ -38,9 +38,13 @@ __device__ __forceinline__ bool meets_soft_zero(const uint32_t *__restrict__ B, 
     return false;
 }
 
+// Threshold of free bit b for the lattice x: from the tables staged in LDS
+// (lds_thr), or from the image when they did not fit (thr_glob).  The two
+// reads are separate so each is an LDS or a global load, not a generic one.
 template <int W>
 __device__ __forceinline__ uint32_t threshold_of(const uint32_t *__restrict__ B, uint32_t b,
-                                                 const uint32_t (&x)[W + 2], const uint32_t *lds_thr) {
+                                                 const uint32_t (&x)[W + 2], const uint32_t *lds_thr,
+                                                 bool thr_glob) {
     const uint32_t *rec = B + B[H_OFF_THRINFO] + b * THR_STRIDE;
     const uint32_t toff = rec[0], ns = rec[1];
     uint32_t idx = 0;
@@ -49,7 +53,10 @@ __device__ __forceinline__ uint32_t threshold_of(const uint32_t *__restrict__ B,
         const uint32_t v = select_word<W>(x, p >> 5);
         idx |= ((v >> (p & 31)) & 1u) << j;
     }
-    return lds_thr[toff + idx];
+    if (thr_glob) return B[B[H_OFF_THRTAB] + toff + idx];
+    // an LDS pointer by type, so the compiler keeps this an LDS read
+    typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+    return ((lds_u32 *)lds_thr)[toff + idx];
 }
 
 template <int W>

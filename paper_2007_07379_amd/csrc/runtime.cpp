@@ -291,9 +291,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             const size_t lds = gibbs_lds_bytes(k.blob.data(), true, lh);
             if (lds > LDS_LIMIT) return set_error(PBIT_E_INVALID_ARG, "LDS-privatised histogram does not fit");
             BatchCirc bc;
-            bc.blob = dblob + c->blob_off[i];
-            bc.state = sp;
-            bc.hist = d_hist + c->hist_off[i];
+            bc.blob_off = c->blob_off[i];
+            bc.state_off = sp ? (uint64_t)(sp - state_base) : 0;
+            bc.hist_off = c->hist_off[i];
             bc.n_chains = ch;
             bc.lds_hist = lh ? 1u : 0u;
             bc.Wk = k.WS;
@@ -501,7 +501,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
                 uint32_t wg = cfg->wg_per_cu ? cfg->wg_per_cu : bt.wg_per_cu[cls];
                 if (blds[cls]) wg = std::min<uint32_t>(wg, std::max<uint32_t>(1, (uint32_t)(LDS_LIMIT / blds[cls])));
                 const uint32_t grid = std::min<uint32_t>(a.ntiles, (uint32_t)cus * std::max<uint32_t>(wg, 1));
-                hipError_t le = launch_batched(cls, a, grid, blds[cls], bs);
+                hipError_t le = launch_batched(cls, a, dblob, state_base, d_hist, grid, blds[cls], bs);
                 if (le != hipSuccess) return hip_error(le, "batched kernel launch");
             }
         }
