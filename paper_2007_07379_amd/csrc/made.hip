@@ -706,15 +706,15 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
 // MFMA's A operand and the wave's 16 chains its B operand, so the outputs of
 // a unit land in the lanes of their chain (lane & 15) and feed the next
 // product as its B operand directly.  Half t of K-chunk cc is the tile of
-// units 32 cc + 8 r + 4 t + e (row group r, e = 0..3): lane group g then
-// receives units 32 cc + 8 g + 4 t + e, which are elements 4 t + e of the
-// 8-element B slice it supplies for that chunk, so no lane exchange is
-// needed.  A tile is computed when it holds a unit whose degree falls in the
-// current phase (the host lists them per free bit; see layer_tiles for why
-// writing all 16 of its units is safe).  Each lane of a chain draws the same
-// bits, so the four
-// copies of a chain's lattice stay equal; the four lanes share the
-// logarithms of log q instead, one per lane every fourth position.
+// the 16 consecutive units 32 cc + 16 t + r (row r): lane group g receives
+// units 32 cc + 16 t + 4 g + e (e = 0..3), and supplies them as elements
+// 4 t + e of its 8-element B slice of the chunk, so no lane exchange is
+// needed; the next product's weights are staged with the matching order of
+// K inside each 32-unit chunk (k-slot 8 g + 4 t + e holds unit 16 t + 4 g +
+// e).  Units are sorted by degree, so a phase's few new units usually sit in
+// one half tile.  A tile is computed when it holds a unit whose degree falls
+// in the current phase (the host lists them per free bit; see layer_tiles
+// for why writing all 16 of its units is safe).
 //
 // A wave carries NP paths per chain through the same tiles: NP = 1 samples
 // (or, with `score`, scores) one path; NP = 2 samples the proposal (path 0)
@@ -791,8 +791,8 @@ __device__ __forceinline__ void layer_tiles(u32x4v (&act)[NP][NA], OpFn op, cons
         for (int t = 0; t < 2; ++t) {
             if (!(tiles & (1u << (2 * cc + t)))) continue;
             bf16x8 av[NO];
-            load_rows<NO>(av, WT + (int64_t)(32 * cc + rrow + 4 * t) * rs + 8 * g, nk);
-            const float4 bb = *reinterpret_cast<const float4 *>(bias + 32 * cc + 8 * g + 4 * t);
+            load_rows<NO>(av, WT + (int64_t)(32 * cc + 16 * t + rrow) * rs + 8 * g, nk);
+            const float4 bb = *reinterpret_cast<const float4 *>(bias + 32 * cc + 16 * t + 4 * g);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
                 // sum over chunks k < nk (ascending, from zero) of av[k] times
@@ -876,6 +876,36 @@ __device__ __forceinline__ void stage_rows(unsigned char *dst, const bf16 *src, 
 // The extra chunks multiply weights the degree masks keep at exactly zero,
 // so the units a phase keeps come out with the same bits, and the products
 // need no per-chunk branches.
+// stage_rows for rows whose K runs over hidden units: inside each 32-unit
+// chunk, k-slot 8 g + 4 t + e takes unit 16 t + 4 g + e (the order in which
+// the half tiles hand their outputs to the lane groups), moved as 8-byte
+// pieces of four units
+__device__ __forceinline__ void stage_rows_k(unsigned char *dst, const bf16 *src, int rows, int len) {
+    const int q = len / 4;  // 8-byte pieces per row
+    const int n = rows * q;
+    const uint2 *s2 = reinterpret_cast<const uint2 *>(src);
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+        uint2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < n) v[u] = s2[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < n) {
+                const int r = i / q, pc = i % q;       // source piece: units 4 pc .. 4 pc + 3
+                const int cc = pc >> 3, w = pc & 7;    // chunk, piece in chunk: units 4 w .. (w = 4 t + g)
+                const int t = w >> 2, g = w & 3;
+                const int slot = 32 * cc + 8 * g + 4 * t;  // its k-slots
+                *reinterpret_cast<uint2 *>(dst + ((size_t)r * (len + REG_PAD) + slot) * 2) = v[u];
+            }
+        }
+    }
+}
+
 template <int NX, int NH, int NB, int NP, bool FULL>
 __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
     constexpr int S = NB * NP;
@@ -885,8 +915,8 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
     // the whole network goes to LDS once per workgroup; after this barrier
     // every wave runs on its own
     stage_rows(smem + L.w1, a.W1T, H, DP);
-    stage_rows(smem + L.w2, a.W2T, H, H);
-    stage_rows(smem + L.v, a.VT, D, H);
+    stage_rows_k(smem + L.w2, a.W2T, H, H);
+    stage_rows_k(smem + L.v, a.VT, D, H);
     stage16(smem + L.b1, a.b1, (size_t)H * 4);
     stage16(smem + L.b2, a.b2, (size_t)H * 4);
     {
@@ -936,7 +966,7 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
         }
     }
     double lq = 0.0;
-    const int rrow = 8 * (c >> 2) + (c & 3);  // this lane's A row within a half tile
+    const int rrow = c;  // this lane's A row within a half tile
     U4 u4 = {0u, 0u, 0u, 0u};
     for (int f = 0; f < h; ++f) {
         const uint32_t *rec = a.sched + (size_t)f * 16;  // wave-uniform: one scalar load

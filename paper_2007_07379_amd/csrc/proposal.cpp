@@ -376,9 +376,9 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
         q->phase.push_back(int4{u1a, u1b, u2a, u2b});
         q->phase_k.push_back(int4{k1, k2, k3, p});
         prev = p;
-        uint32_t m1 = 0, m2 = 0;  // half tile t of chunk cc holds the units with (u >> 2) & 1 == t
-        for (int u = u1a; u < u1b; ++u) m1 |= 1u << (2 * (u >> 5) + ((u >> 2) & 1));
-        for (int u = u2a; u < u2b; ++u) m2 |= 1u << (2 * (u >> 5) + ((u >> 2) & 1));
+        uint32_t m1 = 0, m2 = 0;  // half tile 2 cc + t holds the 16 units 32 cc + 16 t ..
+        for (int u = u1a; u < u1b; ++u) m1 |= 1u << (u >> 4);
+        for (int u = u2a; u < u2b; ++u) m2 |= 1u << (u >> 4);
         const uint32_t rec[8] = {(uint32_t)u1a, (uint32_t)u1b, (uint32_t)u2a, (uint32_t)u2b,
                                  (m1 & 0xffffu) | ((uint32_t)((k1 + 31) / 32) << 16),
                                  (m2 & 0xffffu) | ((uint32_t)((k2 + 31) / 32) << 16), (uint32_t)((k3 + 31) / 32),
