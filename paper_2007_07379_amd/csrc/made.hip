@@ -793,16 +793,25 @@ __device__ __forceinline__ void layer_tiles(u32x4v (&act)[NP][NA], OpFn op, cons
             bf16x8 av[NO];
             load_rows<NO>(av, WT + (int64_t)(32 * cc + 16 * t + rrow) * rs + 8 * g, nk);
             const float4 bb = *reinterpret_cast<const float4 *>(bias + 32 * cc + 16 * t + 4 * g);
+            // per path, the sum over chunks k < nk (ascending, from zero) of
+            // av[k] times its B slice op(q, k); one branch per chunk for all
+            // paths, and a listed tile always has nk >= 1
+            f32x4 acc[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], op(q, 0), f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int k = 1; k < NO; ++k) {
+                if (k < nk) {
+#pragma unroll
+                    for (int q = 0; q < NP; ++q)
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], op(q, k), acc[q], 0, 0, 0);
+                }
+            }
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                // sum over chunks k < nk (ascending, from zero) of av[k] times
-                // the B slice op(q, k) of path q
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int k = 0; k < NO; ++k)
-                    if (k < nk) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], op(q, k), acc, 0, 0, 0);
-                act[q][cc][2 * t] = pack_bf16(relu(acc[0] + bb.x), relu(acc[1] + bb.y));
-                act[q][cc][2 * t + 1] = pack_bf16(relu(acc[2] + bb.z), relu(acc[3] + bb.w));
+                act[q][cc][2 * t] = pack_bf16(relu(acc[q][0] + bb.x), relu(acc[q][1] + bb.y));
+                act[q][cc][2 * t + 1] = pack_bf16(relu(acc[q][2] + bb.z), relu(acc[q][3] + bb.w));
             }
         }
     }
@@ -988,10 +997,23 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
         bf16x8 vv[NH];
         load_rows<NH>(vv, Vs + (int64_t)p * (H + REG_PAD) + 8 * g, nk3);
         float lg = 0.f;
+        if (nk3 > 0) {
+            f32x4 lacc[S];
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const f32x4 lacc = mfma_ops<NH>(vv, act2[q], nk3);
-            lg = (q == my_s) ? lacc[0] : lg;
+            for (int q = 0; q < S; ++q)
+                lacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vv[0], __builtin_bit_cast(bf16x8, act2[q][0]),
+                                                                  f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int k = 1; k < NH; ++k) {
+                if (k < nk3) {
+#pragma unroll
+                    for (int q = 0; q < S; ++q)
+                        lacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vv[k], __builtin_bit_cast(bf16x8, act2[q][k]),
+                                                                          lacc[q], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < S; ++q) lg = (q == my_s) ? lacc[q][0] : lg;
         }
         const uint32_t T = made_threshold(lg + cs[p]);
         uint32_t bit;
