@@ -703,7 +703,7 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
 // The same autoregressive procedure for H <= 256 and lattices of at most 256
 // bits, with every activation kept in registers and the network in LDS.
 // Each product is taken transposed: the weight rows of 16 units are the
-// MFMA's A operand and the wave's 16 chains its B operand, so the outputs of
+// MFMA's A operand and 16 chains (one slot, below) its B operand, so the outputs of
 // a unit land in the lanes of their chain (lane & 15) and feed the next
 // product as its B operand directly.  Half t of K-chunk cc is the tile of
 // the 16 consecutive units 32 cc + 16 t + r (row r): lane group g receives
