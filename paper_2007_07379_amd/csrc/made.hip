@@ -24,12 +24,15 @@ namespace pbit {
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Workgroup tile 128 x 128 (four waves of 64 x 64, each 4 x 4 MFMA tiles of
-// 16 x 16).  K advances in stages of two 32-wide chunks staged through
-// double-buffered LDS; the global loads of a stage are issued GEMM_P stages
-// ahead into registers, so their latency hides behind the products of the
-// stages in between.
-constexpr int TM = 128, TN = 128, TK = 32, TKS = 2 * TK, LDSK = TKS + 8;
+// Workgroup tile TT x TT, TT = 128 or 64 (four waves of TT/2 x TT/2, each
+// TT/32 x TT/32 MFMA tiles of 16 x 16).  K advances in stages of two 32-wide
+// chunks staged through double-buffered LDS; the global loads of a stage are
+// issued GEMM_P stages ahead into registers, so their latency hides behind
+// the products of the stages in between.  The 128 tile reads half the LDS
+// bytes per product; the 64 tile gives a product four times the workgroups
+// (four per CU at 36 KiB of LDS each), which the small products of training
+// need to hide latency, and its own 64-column K range.
+constexpr int TK = 32, TKS = 2 * TK, LDSK = TKS + 8;
 constexpr int GEMM_P = 3;
 
 // Operands are addressed as X(r, k) = src[r sr + k sk]; everything outside
@@ -59,15 +62,17 @@ __device__ __forceinline__ u32x4v seg_mask(int rem) {
     return m;
 }
 
-template <int MODE>
+// ROWS rows x TKS k per stage: ROWS / 32 segments of 8 elements per thread
+template <int MODE, int ROWS>
 __device__ __forceinline__ void stage_load(StageRegs &st, const bf16 *__restrict__ src, int64_t sr, int64_t sk, int r0,
                                            int R, int k0, int kend) {
     const int t = threadIdx.x;
+    constexpr int NS = ROWS / 32, RB = ROWS / 8;
     if (MODE == 0) {
-        st.interior = r0 + TM <= R && k0 + TKS <= kend;
+        st.interior = r0 + ROWS <= R && k0 + TKS <= kend;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int seg = t + 256 * j;  // 128 rows x 8 segments of 8
+        for (int j = 0; j < NS; ++j) {
+            const int seg = t + 256 * j;  // ROWS rows x 8 segments of 8
             const int r = seg >> 3, kk = (seg & 7) * 8;
             const int gr = r0 + r, gk = k0 + kk;
             const int rem = st.interior ? 8 : (gr < R ? kend - gk : 0);
@@ -76,11 +81,11 @@ __device__ __forceinline__ void stage_load(StageRegs &st, const bf16 *__restrict
             st.rem[j] = rem;
         }
     } else if (MODE == 1) {
-        st.interior = r0 + TM <= R && k0 + TKS <= kend;
+        st.interior = r0 + ROWS <= R && k0 + TKS <= kend;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int blk = t + 256 * b;  // 16 row blocks of 8 x 32 k pairs
-            const int rb = (blk & 15) * 8, kp = (blk >> 4) * 2;
+        for (int b = 0; b < NS / 2; ++b) {
+            const int blk = t + 256 * b;  // RB row blocks of 8 x 32 k pairs
+            const int rb = (blk % RB) * 8, kp = (blk / RB) * 2;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int gk = k0 + kp + j, gr = r0 + rb;
@@ -93,7 +98,7 @@ __device__ __forceinline__ void stage_load(StageRegs &st, const bf16 *__restrict
     } else {
         st.interior = true;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NS; ++j) {
             const int seg = t + 256 * j;
             const int r = seg >> 3, kk = (seg & 7) * 8;
             const int gr = r0 + r, gk = k0 + kk;
@@ -106,23 +111,24 @@ __device__ __forceinline__ void stage_load(StageRegs &st, const bf16 *__restrict
     }
 }
 
-template <int MODE>
+template <int MODE, int ROWS>
 __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]) {
     const int t = threadIdx.x;
-    u32x4v v[4];
+    constexpr int NS = ROWS / 32, RB = ROWS / 8;
+    u32x4v v[NS];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = st.interior ? st.v[j] : st.v[j] & seg_mask(st.rem[j]);
+    for (int j = 0; j < NS; ++j) v[j] = st.interior ? st.v[j] : st.v[j] & seg_mask(st.rem[j]);
     if (MODE != 1) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NS; ++j) {
             const int seg = t + 256 * j;
             *reinterpret_cast<u32x4v *>(&T[seg >> 3][(seg & 7) * 8]) = v[j];
         }
     } else {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NS / 2; ++b) {
             const int blk = t + 256 * b;
-            const int rb = (blk & 15) * 8, kp = (blk >> 4) * 2;
+            const int rb = (blk % RB) * 8, kp = (blk / RB) * 2;
             const u32x4v a = v[2 * b], c = v[2 * b + 1];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -134,8 +140,9 @@ __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]
     }
 }
 
-template <int MA, int MB>
+template <int MA, int MB, int TT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    constexpr int TM = TT, TN = TT, F = TT / 32;  // F x F MFMA tiles per wave
     __shared__ __align__(16) bf16 As[2][TM][LDSK];
     __shared__ __align__(16) bf16 Bs[2][TN][LDSK];
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
@@ -149,13 +156,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int tile_m = tile / tn, tile_n = tile % tn;
     const int m0 = tile_m * TM, n0 = tile_n * TN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    // K range of the tile: the union of its two 64-column ranges
-    const int t64 = tile_n * 2;
+    const int wr = (wave >> 1) * (TT / 2), wc = (wave & 1) * (TT / 2);
+    // K range of the tile: the union of its 64-column ranges
+    const int t64 = tile_n * (TT / 64);
     const int nt64 = (g.N + 63) / 64;
+    const bool two = TT == 128 && t64 + 1 < nt64;
     int kb = 0, ke = g.K;
-    if (g.kbeg) kb = t64 + 1 < nt64 ? min(g.kbeg[t64], g.kbeg[t64 + 1]) : g.kbeg[t64];
-    if (g.kend) ke = t64 + 1 < nt64 ? max(g.kend[t64], g.kend[t64 + 1]) : g.kend[t64];
+    if (g.kbeg) kb = two ? min(g.kbeg[t64], g.kbeg[t64 + 1]) : g.kbeg[t64];
+    if (g.kend) ke = two ? max(g.kend[t64], g.kend[t64 + 1]) : g.kend[t64];
     int c_lo = kb / TK, c_hi = (ke + TK - 1) / TK;  // 32-wide chunks [c_lo, c_hi)
     // split-K: slice blockIdx.z of the chunk range
     if (g.ksplit > 1) {
@@ -168,11 +176,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         const int nlast = min(n0 + TN, g.N) - 1;
         if (g.deg_row[m0] > g.deg_col[nlast]) c_hi = c_lo;
     }
-    f32x4 acc[4][4];
+    f32x4 acc[F][F];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < F; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < F; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int S = c_hi > c_lo ? (c_hi - c_lo + 1) / 2 : 0;  // stages of two chunks
     if (S > 0) {
         // the stage's K end: the tile's, never past the slice
@@ -181,12 +189,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < GEMM_P; ++i) {
             if (i < S) {
-                stage_load<MA>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * i) * TK, kst);
-                stage_load<MB>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * i) * TK, kst);
+                stage_load<MA, TM>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * i) * TK, kst);
+                stage_load<MB, TN>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * i) * TK, kst);
             }
         }
-        stage_store<MA>(ra[0], As[0]);
-        stage_store<MB>(rb[0], Bs[0]);
+        stage_store<MA, TM>(ra[0], As[0]);
+        stage_store<MB, TN>(rb[0], Bs[0]);
         __syncthreads();
         for (int sb = 0; sb < S; sb += GEMM_P) {
 #pragma unroll
@@ -197,32 +205,32 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                     // the registers of stage st went to LDS last iteration:
                     // reuse them for stage st + P
                     if (st + GEMM_P < S) {
-                        stage_load<MA>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
-                        stage_load<MB>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
+                        stage_load<MA, TM>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
+                        stage_load<MB, TN>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
                     }
 #pragma unroll
                     for (int kk = 0; kk < 2; ++kk) {
                         if (c_lo + 2 * st + kk < c_hi) {
-                            bf16x8 af[4], bfr[4];
+                            bf16x8 af[F], bfr[F];
 #pragma unroll
-                            for (int a = 0; a < 4; ++a)
+                            for (int a = 0; a < F; ++a)
                                 af[a] = *reinterpret_cast<const bf16x8 *>(
                                     &As[buf][wr + a * 16 + (lane & 15)][kk * TK + (lane >> 4) * 8]);
 #pragma unroll
-                            for (int b = 0; b < 4; ++b)
+                            for (int b = 0; b < F; ++b)
                                 bfr[b] = *reinterpret_cast<const bf16x8 *>(
                                     &Bs[buf][wc + b * 16 + (lane & 15)][kk * TK + (lane >> 4) * 8]);
 #pragma unroll
-                            for (int a = 0; a < 4; ++a)
+                            for (int a = 0; a < F; ++a)
 #pragma unroll
-                                for (int b = 0; b < 4; ++b)
+                                for (int b = 0; b < F; ++b)
                                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0,
                                                                                         0);
                         }
                     }
                     if (st + 1 < S) {
-                        stage_store<MA>(ra[(i + 1) % GEMM_P], As[buf ^ 1]);
-                        stage_store<MB>(rb[(i + 1) % GEMM_P], Bs[buf ^ 1]);
+                        stage_store<MA, TM>(ra[(i + 1) % GEMM_P], As[buf ^ 1]);
+                        stage_store<MB, TN>(rb[(i + 1) % GEMM_P], Bs[buf ^ 1]);
                     }
                     __syncthreads();
                 }
@@ -233,9 +241,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         // raw partial sums of this slice; the reduction applies the epilogue
         float *P = g.part + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < F; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < F; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
@@ -247,18 +255,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // epilogue: every operand the epilogue reads is loaded first, without
     // branches (clamped addresses), so the loads overlap; only the stores
     // are guarded
-    float bias_j[4];
-    int dcol[4];
+    float bias_j[F];
+    int dcol[F];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < F; ++j) {
         const int n = n0 + wc + j * 16 + (lane & 15);
         const int nc = n < g.N ? n : g.N - 1;
         bias_j[j] = g.bias ? g.bias[nc] : 0.f;
         dcol[j] = g.deg_col ? g.deg_col[nc] : 0;
     }
-    int drow[4][4];
+    int drow[F][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < F; ++i)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
@@ -266,11 +274,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
     const bool masked = g.deg_row && g.deg_col;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        bf16 gv[4][4];
+    for (int i = 0; i < F; ++i) {
+        bf16 gv[F][4];
         if (g.gate) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < F; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < F; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
@@ -330,12 +338,17 @@ static int operand_mode(const bf16 *p, int64_t sr, int64_t sk, int R, int K) {
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.ksplit > 1 && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part)) return hipErrorInvalidValue;
-    const int tiles = ((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM);
-    dim3 grid(8 * ((tiles + 7) / 8), 1, g.ksplit > 1 ? g.ksplit : 1);
+    const int z = g.ksplit > 1 ? g.ksplit : 1;
+    // 128 x 128 tiles once a product has four of them per CU, else 64 x 64
+    const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
+    const int TT = t128 * z >= 1024 ? 128 : 64;
+    const int tiles = ((g.N + TT - 1) / TT) * ((g.M + TT - 1) / TT);
+    dim3 grid(8 * ((tiles + 7) / 8), 1, z);
     const int ma = operand_mode(g.A, g.sam, g.sak, g.M, g.K), mb = operand_mode(g.B, g.sbn, g.sbk, g.N, g.K);
     const void *fn = nullptr;
 #define PBIT_GEMM(A_, B_) \
-    if (ma == A_ && mb == B_) fn = (const void *)gemm_kernel<A_, B_>;
+    if (ma == A_ && mb == B_)  \
+        fn = TT == 128 ? (const void *)gemm_kernel<A_, B_, 128> : (const void *)gemm_kernel<A_, B_, 64>;
     PBIT_GEMM(0, 0) PBIT_GEMM(0, 1) PBIT_GEMM(0, 2)
     PBIT_GEMM(1, 0) PBIT_GEMM(1, 1) PBIT_GEMM(1, 2)
     PBIT_GEMM(2, 0) PBIT_GEMM(2, 1) PBIT_GEMM(2, 2)

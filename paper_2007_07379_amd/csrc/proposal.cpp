@@ -184,8 +184,9 @@ GemmArgs gemm0() {
     return g;
 }
 
-// Weight gradients reduce over the batch (K = n) into few 128 x 128 tiles:
-// split K so the launch has about 256 workgroups (one per CU), within the
+// Weight gradients reduce over the batch (K = n) into few output tiles:
+// split K so the launch has about 256 workgroups of 128 x 128 (which the GEMM
+// launch then runs as about 1,024 of 64 x 64, four per CU), within the
 // workspace.
 void splitk(pbit_proposal q, GemmArgs &g) {
     const int64_t tiles = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
