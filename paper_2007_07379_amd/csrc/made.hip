@@ -12,6 +12,7 @@
 // log q of a sampled path equals the scorer's log q of that path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "blob.h"
@@ -311,10 +312,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 }
 
 // Split-K reduction: slices added in ascending order, degree mask, fp32 out.
+// M N < 2^31 (checked at launch): 32-bit index arithmetic.
 __global__ void splitk_reduce_kernel(GemmArgs g) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)g.M * g.N) return;
-    const int m = (int)(e / g.N), n = (int)(e % g.N);
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint32_t)g.M * (uint32_t)g.N) return;
+    const int m = (int)(e / (uint32_t)g.N), n = (int)(e - (uint32_t)m * (uint32_t)g.N);
     float v = 0.f;
     for (int z = 0; z < g.ksplit; ++z) v += g.part[(int64_t)z * g.M * g.N + e];
     if (g.deg_row && g.deg_col && g.deg_row[m] > g.deg_col[n]) v = 0.f;
@@ -337,7 +339,8 @@ static int operand_mode(const bf16 *p, int64_t sr, int64_t sk, int R, int K) {
 }
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
-    if (g.ksplit > 1 && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part)) return hipErrorInvalidValue;
+    if (g.ksplit > 1 && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part || (int64_t)g.M * g.N > INT32_MAX))
+        return hipErrorInvalidValue;
     const int z = g.ksplit > 1 ? g.ksplit : 1;
     // 128 x 128 tiles once a product has four of them per CU, else 64 x 64
     const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
@@ -378,13 +381,17 @@ __global__ void unpack_kernel(const uint32_t *__restrict__ states, int n, int D,
 
 // dLoss/dL = (sigmoid(L) - x) / n on free positions; each workgroup writes
 // its share of the batch-mean binary cross-entropy to loss[blockIdx.x].
-__global__ void loss_grad_kernel(const float *__restrict__ L, const bf16 *__restrict__ X, const int *__restrict__ freem,
-                                 int n, int D, int DP, float inv_n, bf16 *__restrict__ G, float *__restrict__ loss) {
-    __shared__ float red[256];
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Grid-stride over the n D elements (a thread's elements in ascending order),
+// so a few thousand workgroups cover any batch.
+__global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict__ L, const bf16 *__restrict__ X,
+                                                        const int *__restrict__ freem, int n, int D, int DP,
+                                                        float inv_n, bf16 *__restrict__ G, float *__restrict__ loss) {
+    __shared__ float red[4];
+    // n D < 2^31 (checked at launch): 32-bit index arithmetic
+    const uint32_t tot = (uint32_t)n * (uint32_t)D, stride = gridDim.x * 256u;
     float nll = 0.f;
-    if (e < (int64_t)n * D) {
-        const int b = (int)(e / D), i = (int)(e % D);
+    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < tot; e += stride) {
+        const uint32_t b = e / (uint32_t)D, i = e - b * (uint32_t)D;
         const float z = L[e];
         const float x = (float)X[(int64_t)b * DP + i];
         float gval = 0.f;
@@ -393,23 +400,22 @@ __global__ void loss_grad_kernel(const float *__restrict__ L, const bf16 *__rest
             gval = (s - x) * inv_n;
             // softplus(-z) for x = 1, softplus(z) for x = 0
             const float zz = x > 0.5f ? -z : z;
-            nll = (zz > 0.f ? zz + log1pf(expf(-zz)) : log1pf(expf(zz))) * inv_n;
+            nll += (zz > 0.f ? zz + log1pf(expf(-zz)) : log1pf(expf(zz))) * inv_n;
         }
         G[e] = (bf16)gval;
     }
-    red[threadIdx.x] = nll;
+    // fixed-order reduction: butterfly within each wave, then the four waves
+    for (int o = 32; o > 0; o >>= 1) nll += __shfl_xor(nll, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nll;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) loss[blockIdx.x] = red[0];  // per-block partial
+    if (threadIdx.x == 0) loss[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];  // per-block partial
 }
 
 // Sums the per-block partial losses in a fixed order into *out.
 __global__ __launch_bounds__(256) void loss_sum_kernel(const float *__restrict__ part, int nb, float *__restrict__ out) {
     __shared__ float red[256];
     float v = 0.f;
+#pragma unroll 8
     for (int i = threadIdx.x; i < nb; i += 256) v += part[i];
     red[threadIdx.x] = v;
     __syncthreads();
@@ -421,18 +427,19 @@ __global__ __launch_bounds__(256) void loss_sum_kernel(const float *__restrict__
 }
 
 // Column sums of a row-major n x N bf16 matrix in two deterministic passes:
-// workgroup (column tile, row chunk) sums its 256 rows for 64 columns (four
-// row groups of 64 rows, combined in a fixed order), then each column adds
-// its chunk partials in ascending chunk order.
+// workgroup (column tile, chunk of COLSUM_ROWS rows) sums its rows for 64
+// columns (four row groups, combined in a fixed order), then each column adds
+// its chunk partials (four interleaved sets in ascending chunk order,
+// combined in a fixed order).
 __global__ __launch_bounds__(256) void colsum_part_kernel(const bf16 *__restrict__ G, int n, int N,
                                                           float *__restrict__ part) {
     __shared__ float red[4][64];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + tx;
-    const int r0 = blockIdx.y * 256 + ty * 64;
+    const int r0 = blockIdx.y * COLSUM_ROWS + ty * (COLSUM_ROWS / 4);
     float s = 0.f;
     if (j < N) {
-        const int r1 = min(r0 + 64, n);
+        const int r1 = min(r0 + COLSUM_ROWS / 4, n);
         for (int b = r0; b < r1; ++b) s += (float)G[(int64_t)b * N + j];
     }
     red[ty][tx] = s;
@@ -441,20 +448,24 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const bf16 *__restrict
 }
 
 // Vector variant for N % 8 == 0 and a 16-byte aligned G: thread (column
-// group of 8, row group of 8) adds 32 rows with one 16-byte load per row; the
-// eight row groups are combined in a fixed order.
+// group of 8, row group of 8) adds COLSUM_ROWS / 8 rows with one 16-byte load
+// per row; the eight row groups are combined in a fixed order.
 __global__ __launch_bounds__(256) void colsum_part8_kernel(const bf16 *__restrict__ G, int n, int N,
                                                            float *__restrict__ part) {
     __shared__ float red[8][256];
     const int cg = threadIdx.x & 31, rg = threadIdx.x >> 5;
     const int c0 = blockIdx.x * 256 + cg * 8;
-    const int rbase = blockIdx.y * 256;
+    const int rbase = blockIdx.y * COLSUM_ROWS;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (c0 < N) {
-        for (int r = rbase + rg; r < min(rbase + 256, n); r += 8) {
-            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(G + (int64_t)r * N + c0);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
+        for (int q = 0; q < COLSUM_ROWS / 8; ++q) {
+            const int r = rbase + rg + 8 * q;
+            if (r < n) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(G + (int64_t)r * N + c0);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
+            }
         }
     }
 #pragma unroll
@@ -469,12 +480,19 @@ __global__ __launch_bounds__(256) void colsum_part8_kernel(const bf16 *__restric
     }
 }
 
-__global__ void colsum_final_kernel(const float *__restrict__ part, int chunks, int N, float *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+__global__ __launch_bounds__(256) void colsum_final_kernel(const float *__restrict__ part, int chunks, int N,
+                                                           float *__restrict__ out) {
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + tx;
     float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * N + j];
-    out[j] = s;
+    if (j < N) {
+#pragma unroll 4
+        for (int c = ty; c < chunks; c += 4) s += part[(int64_t)c * N + j];
+    }
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && j < N) out[j] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
 }
 
 __global__ void adam_kernel(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
@@ -490,16 +508,33 @@ __global__ void adam_kernel(float *__restrict__ th, float *__restrict__ m, float
     th[i] = th[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-// bf16 shadows of one K x N weight (row-major) and its transpose N x KP
-// (row n holds the K inputs of unit n, zero-padded to KP).
-__global__ void shadow_kernel(const float *__restrict__ W, int K, int N, int KP, bf16 *__restrict__ Wb,
-                              bf16 *__restrict__ WT) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)N * KP) return;
-    const int n = (int)(e / KP), k = (int)(e % KP);
-    const float w = k < K ? W[(int64_t)k * N + n] : 0.f;
-    WT[e] = (bf16)w;
-    if (k < K) Wb[(int64_t)k * N + n] = (bf16)w;
+// bf16 shadows of up to three K x N weights (row-major) and their transposes
+// N x KP (row n holds the K inputs of unit n, zero-padded to KP), one weight
+// per blockIdx.z.  Workgroup (blockIdx.x, blockIdx.y) takes the 32 x 32 tile
+// of columns n0.. and rows k0..: rows are read and Wb written along n, the
+// tile is transposed through LDS and WT written along k.
+__global__ __launch_bounds__(256) void shadow_kernel(ShadowJobs jobs) {
+    __shared__ float t[32][33];
+    const ShadowJob &J = jobs.j[blockIdx.z];
+    const int n0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+    if (n0 >= J.N || k0 >= J.KP) return;  // whole workgroup: a smaller weight
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int r = ty; r < 32; r += 8) {
+        const int k = k0 + r, n = n0 + tx;
+        float w = 0.f;
+        if (k < J.K && n < J.N) {
+            w = J.W[(int64_t)k * J.N + n];
+            J.Wb[(int64_t)k * J.N + n] = (bf16)w;
+        }
+        t[r][tx] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < 32; r += 8) {
+        const int n = n0 + r, k = k0 + tx;
+        if (n < J.N && k < J.KP) J.WT[(int64_t)n * J.KP + k] = (bf16)t[tx][r];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,7 +1213,8 @@ hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, 
 hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
                             float *part, float *loss, hipStream_t s) {
     const int64_t tot = (int64_t)n * D;
-    const int nb = (int)((tot + 255) / 256);
+    if (tot > INT32_MAX) return hipErrorInvalidValue;
+    const int nb = (int)std::min<int64_t>((tot + 255) / 256, 2048);
     hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)nb), dim3(256), 0, s, L, X, freem, n, D, DP, 1.f / (float)n, G,
                        part);
     hipError_t e = hipGetLastError();
@@ -1188,7 +1224,7 @@ hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int
 }
 
 hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s) {
-    const int chunks = (n + 255) / 256;
+    const int chunks = (n + COLSUM_ROWS - 1) / COLSUM_ROWS;
     if (chunks == 0 || N == 0) return hipSuccess;
     if (N % 8 == 0 && (((uintptr_t)G) & 15) == 0)
         hipLaunchKernelGGL(colsum_part8_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, s, G, n, N, part);
@@ -1196,7 +1232,7 @@ hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, h
         hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, G, n, N, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, s, part, chunks, N, out);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 63) / 64), dim3(256), 0, s, part, chunks, N, out);
     return hipGetLastError();
 }
 
@@ -1207,9 +1243,15 @@ hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t P,
     return hipGetLastError();
 }
 
-hipError_t launch_shadow(const float *W, int K, int N, int KP, bf16 *Wb, bf16 *WT, hipStream_t s) {
-    const int64_t tot = (int64_t)N * KP;
-    hipLaunchKernelGGL(shadow_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, K, N, KP, Wb, WT);
+hipError_t launch_shadow(const ShadowJobs &jobs, int count, hipStream_t s) {
+    if (count < 1 || count > 3) return hipErrorInvalidValue;
+    int gx = 0, gy = 0;
+    for (int i = 0; i < count; ++i) {
+        gx = std::max(gx, (jobs.j[i].N + 31) / 32);
+        gy = std::max(gy, (jobs.j[i].KP + 31) / 32);
+    }
+    if (gx == 0 || gy == 0) return hipSuccess;
+    hipLaunchKernelGGL(shadow_kernel, dim3(gx, gy, count), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 

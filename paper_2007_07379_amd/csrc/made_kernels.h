@@ -86,15 +86,27 @@ bool made_sample_dual_ok(const SampleArgs &a);
 hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s);
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
 // G and the batch-mean loss, written to *loss (per-workgroup partials in
-// `part`, ceil(n D / 256) floats, summed in a fixed order).
+// `part`, min(ceil(n D / 256), 2048) floats, summed in a fixed order).
 hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
                             float *part, float *loss, hipStream_t s);
-// out[j] = sum_b G[b][j]: partial sums over 256-row chunks into `part`
-// (ceil(n / 256) x N floats), then over the chunks in ascending order.
+// out[j] = sum_b G[b][j]: partial sums over COLSUM_ROWS-row chunks into
+// `part` (ceil(n / COLSUM_ROWS) x N floats), then over the chunks in a fixed
+// order.
+constexpr int COLSUM_ROWS = 64;
 hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s);
 hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t P, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_shadow(const float *W, int K, int N, int KP, bf16 *Wb, bf16 *WT, hipStream_t s);
+// bf16 shadow Wb (K x N, row-major) and transpose WT (N x KP, zero-padded)
+// of an fp32 K x N weight W; one launch for `count` (1 to 3) weights.
+struct ShadowJob {
+    const float *W;
+    int K, N, KP;
+    bf16 *Wb, *WT;
+};
+struct ShadowJobs {
+    ShadowJob j[3];
+};
+hipError_t launch_shadow(const ShadowJobs &jobs, int count, hipStream_t s);
 hipError_t launch_logq(const float *L, const uint32_t *states, uint64_t stride, uint64_t b0, const int *fpos, int h,
                        int n, int D, double *out, hipStream_t s);
 

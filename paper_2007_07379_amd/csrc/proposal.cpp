@@ -73,7 +73,7 @@ struct pbit_proposal_s {
     uint32_t *d_sched = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
     float *L = nullptr;
-    float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / 256) x max(D, H)
+    float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / COLSUM_ROWS) x max(D, H)
     float *part = nullptr;     // split-K partial sums of the weight gradients
     float *lpart = nullptr;    // per-workgroup partial losses
     int64_t part_floats = 0;
@@ -114,7 +114,7 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->G2 = A.alloc<bf16>((size_t)BATCH_MAX * H);
     q->G3 = A.alloc<bf16>((size_t)BATCH_MAX * D);
     q->L = A.alloc<float>((size_t)BATCH_MAX * D);
-    q->colpart = A.alloc<float>((size_t)(BATCH_MAX / 256) * std::max(D, H));
+    q->colpart = A.alloc<float>((size_t)(BATCH_MAX / COLSUM_ROWS) * std::max(D, H));
     q->part_floats = std::min<int64_t>((int64_t)16 * std::max<int64_t>((int64_t)H * H, (int64_t)D * H),
                                        (int64_t)16 << 20);
     q->part = A.alloc<float>((size_t)q->part_floats);
@@ -171,10 +171,11 @@ pbit_status refresh(pbit_proposal q, hipStream_t s) {
     if (!q->dirty) return PBIT_OK;
     q->dirty = false;
     hipError_t e;
-    if ((e = launch_shadow(q->theta + q->oW1, q->D, q->H, q->DP, q->W1b, q->W1T, s)) != hipSuccess ||
-        (e = launch_shadow(q->theta + q->oW2, q->H, q->H, q->H, q->W2b, q->W2T, s)) != hipSuccess ||
-        (e = launch_shadow(q->theta + q->oV, q->H, q->D, q->H, q->Vb, q->VT, s)) != hipSuccess)
-        return hip_error(e, "shadow refresh");
+    ShadowJobs jobs;
+    jobs.j[0] = {q->theta + q->oW1, q->D, q->H, q->DP, q->W1b, q->W1T};
+    jobs.j[1] = {q->theta + q->oW2, q->H, q->H, q->H, q->W2b, q->W2T};
+    jobs.j[2] = {q->theta + q->oV, q->H, q->D, q->H, q->Vb, q->VT};
+    if ((e = launch_shadow(jobs, 3, s)) != hipSuccess) return hip_error(e, "shadow refresh");
     return PBIT_OK;
 }
 
