@@ -55,6 +55,12 @@ struct StageRegs {
     bool interior;  // so no load waits before the stage is stored)
 };
 
+// LDS row layout: the eight 16-byte units of a row (8 k each) are stored in
+// the order u ^ ((row >> 3) & 7).  Rows 8 apart fall on the same banks (a row
+// pitch is a multiple of 16 bytes), and the pair stores of mode 1 write rows
+// 8 apart from neighbouring lanes; the swizzle spreads them over eight units.
+__device__ __forceinline__ int lds_col(int row, int k) { return (((k >> 3) ^ ((row >> 3) & 7)) << 3) | (k & 7); }
+
 // dword d of a 16-byte segment holds elements 2d, 2d + 1; rem valid elements
 __device__ __forceinline__ u32x4v seg_mask(int rem) {
     u32x4v m;
@@ -122,8 +128,8 @@ __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]
     if (MODE != 1) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
-            const int seg = t + 256 * j;
-            *reinterpret_cast<u32x4v *>(&T[seg >> 3][(seg & 7) * 8]) = v[j];
+            const int seg = t + 256 * j, r = seg >> 3;
+            *reinterpret_cast<u32x4v *>(&T[r][lds_col(r, (seg & 7) * 8)]) = v[j];
         }
     } else {
 #pragma unroll
@@ -134,8 +140,9 @@ __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 // rows rb + 2q and rb + 2q + 1: (k, k + 1) pairs
-                *reinterpret_cast<uint32_t *>(&T[rb + 2 * q][kp]) = (a[q] & 0xFFFFu) | (c[q] << 16);
-                *reinterpret_cast<uint32_t *>(&T[rb + 2 * q + 1][kp]) = (a[q] >> 16) | (c[q] & 0xFFFF0000u);
+                const int r = rb + 2 * q;
+                *reinterpret_cast<uint32_t *>(&T[r][lds_col(r, kp)]) = (a[q] & 0xFFFFu) | (c[q] << 16);
+                *reinterpret_cast<uint32_t *>(&T[r + 1][lds_col(r + 1, kp)]) = (a[q] >> 16) | (c[q] & 0xFFFF0000u);
             }
         }
     }
@@ -214,13 +221,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         if (c_lo + 2 * st + kk < c_hi) {
                             bf16x8 af[F], bfr[F];
 #pragma unroll
-                            for (int a = 0; a < F; ++a)
+                            for (int a = 0; a < F; ++a) {
+                                const int r = wr + a * 16 + (lane & 15);
                                 af[a] = *reinterpret_cast<const bf16x8 *>(
-                                    &As[buf][wr + a * 16 + (lane & 15)][kk * TK + (lane >> 4) * 8]);
+                                    &As[buf][r][lds_col(r, kk * TK + (lane >> 4) * 8)]);
+                            }
 #pragma unroll
-                            for (int b = 0; b < F; ++b)
+                            for (int b = 0; b < F; ++b) {
+                                const int r = wc + b * 16 + (lane & 15);
                                 bfr[b] = *reinterpret_cast<const bf16x8 *>(
-                                    &Bs[buf][wc + b * 16 + (lane & 15)][kk * TK + (lane >> 4) * 8]);
+                                    &Bs[buf][r][lds_col(r, kk * TK + (lane >> 4) * 8)]);
+                            }
 #pragma unroll
                             for (int a = 0; a < F; ++a)
 #pragma unroll
