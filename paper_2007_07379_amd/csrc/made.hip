@@ -28,7 +28,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Workgroup tile TT x TT, TT = 128 or 64 (four waves of TT/2 x TT/2, each
 // TT/32 x TT/32 MFMA tiles of 16 x 16).  K advances in stages of two 32-wide
 // chunks staged through double-buffered LDS; the global loads of a stage are
-// issued GEMM_P stages ahead into registers, so their latency hides behind
+// issued P stages ahead into registers, so their latency hides behind
 // the products of the stages in between.  The 128 tile reads half the LDS
 // bytes per product; the 64 tile gives a product four times the workgroups
 // (four per CU at 36 KiB of LDS each), which the small products of training
@@ -151,6 +151,9 @@ __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]
 template <int MA, int MB, int TT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int TM = TT, TN = TT, F = TT / 32;  // F x F MFMA tiles per wave
+    // prefetch depth in stages: measured on the 64 tile (four workgroups per
+    // CU) at 1, 2, 3 and 6, 2 is best and 6 a quarter slower
+    constexpr int P = TT == 64 ? 2 : GEMM_P;
     __shared__ __align__(16) bf16 As[2][TM][LDSK];
     __shared__ __align__(16) bf16 Bs[2][TN][LDSK];
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
@@ -193,9 +196,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     if (S > 0) {
         // the stage's K end: the tile's, never past the slice
         const int kst = min(ke, c_hi * TK);
-        StageRegs ra[GEMM_P], rb[GEMM_P];
+        StageRegs ra[P], rb[P];
 #pragma unroll
-        for (int i = 0; i < GEMM_P; ++i) {
+        for (int i = 0; i < P; ++i) {
             if (i < S) {
                 stage_load<MA, TM>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * i) * TK, kst);
                 stage_load<MB, TN>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * i) * TK, kst);
@@ -204,17 +207,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         stage_store<MA, TM>(ra[0], As[0]);
         stage_store<MB, TN>(rb[0], Bs[0]);
         __syncthreads();
-        for (int sb = 0; sb < S; sb += GEMM_P) {
+        for (int sb = 0; sb < S; sb += P) {
 #pragma unroll
-            for (int i = 0; i < GEMM_P; ++i) {
+            for (int i = 0; i < P; ++i) {
                 const int st = sb + i;
                 if (st < S) {
                     const int buf = st & 1;
                     // the registers of stage st went to LDS last iteration:
                     // reuse them for stage st + P
-                    if (st + GEMM_P < S) {
-                        stage_load<MA, TM>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
-                        stage_load<MB, TN>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * (st + GEMM_P)) * TK, kst);
+                    if (st + P < S) {
+                        stage_load<MA, TM>(ra[i], g.A, g.sam, g.sak, m0, g.M, (c_lo + 2 * (st + P)) * TK, kst);
+                        stage_load<MB, TN>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * (st + P)) * TK, kst);
                     }
 #pragma unroll
                     for (int kk = 0; kk < 2; ++kk) {
@@ -241,8 +244,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         }
                     }
                     if (st + 1 < S) {
-                        stage_store<MA, TM>(ra[(i + 1) % GEMM_P], As[buf ^ 1]);
-                        stage_store<MB, TN>(rb[(i + 1) % GEMM_P], Bs[buf ^ 1]);
+                        stage_store<MA, TM>(ra[(i + 1) % P], As[buf ^ 1]);
+                        stage_store<MB, TN>(rb[(i + 1) % P], Bs[buf ^ 1]);
                     }
                     __syncthreads();
                 }
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
     if (g.ksplit > 1) {
         // raw partial sums of this slice; the reduction applies the epilogue
-        float *P = g.part + (int64_t)blockIdx.z * g.M * g.N;
+        float *part = g.part + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
         for (int i = 0; i < F; ++i)
 #pragma unroll
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 for (int e = 0; e < 4; ++e) {
                     const int m = m0 + wr + i * 16 + (lane >> 4) * 4 + e;
                     const int n = n0 + wc + j * 16 + (lane & 15);
-                    if (m < g.M && n < g.N) P[(int64_t)m * g.N + n] = acc[i][j][e];
+                    if (m < g.M && n < g.N) part[(int64_t)m * g.N + n] = acc[i][j][e];
                 }
         return;
     }
