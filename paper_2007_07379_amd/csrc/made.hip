@@ -33,8 +33,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // bytes per product; the 64 tile gives a product four times the workgroups
 // (four per CU at 36 KiB of LDS each), which the small products of training
 // need to hide latency, and its own 64-column K range.
+// Prefetch depth, measured at 1, 2, 3 and 6 stages: 1 and 2 tie, 3 is 5 %
+// (64 tile) to 60 % (128 tile) slower, 6 a quarter slower on the 64 tile.
 constexpr int TK = 32, TKS = 2 * TK, LDSK = TKS + 8;
-constexpr int GEMM_P = 3;
+constexpr int GEMM_P = 2;
 
 // Operands are addressed as X(r, k) = src[r sr + k sk]; everything outside
 // [0, R) x [0, kend) reads as zero.
@@ -151,9 +153,7 @@ __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]
 template <int MA, int MB, int TT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     constexpr int TM = TT, TN = TT, F = TT / 32;  // F x F MFMA tiles per wave
-    // prefetch depth in stages: measured on the 64 tile (four workgroups per
-    // CU) at 1, 2, 3 and 6, 2 is best and 6 a quarter slower
-    constexpr int P = TT == 64 ? 2 : GEMM_P;
+    constexpr int P = GEMM_P;
     __shared__ __align__(16) bf16 As[2][TM][LDSK];
     __shared__ __align__(16) bf16 Bs[2][TN][LDSK];
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
@@ -554,18 +554,35 @@ __global__ __launch_bounds__(256) void shadow_kernel(ShadowJobs jobs) {
 // ---------------------------------------------------------------------------
 // log q of given paths (score mode)
 // ---------------------------------------------------------------------------
-__global__ void logq_kernel(const float *__restrict__ L, const uint32_t *__restrict__ states, uint64_t stride,
-                            uint64_t b0, const int *__restrict__ fpos, int h, int n, int D, double *__restrict__ out) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
+// Workgroup of 256 threads per 64 paths.  Free positions are taken in
+// chunks of 64: all threads compute the chunk's terms log q_f (thread t: the
+// position t % 64 of paths t / 64, t / 64 + 4, ...; a wave reads 64
+// positions of one logit row), then thread c < 64 adds path c's terms in
+// ascending position order, the order of the sampler's accumulation.
+__global__ __launch_bounds__(256) void logq_kernel(const float *__restrict__ L, const uint32_t *__restrict__ states,
+                                                   uint64_t stride, uint64_t b0, const int *__restrict__ fpos, int h,
+                                                   int n, int D, double *__restrict__ out) {
+    __shared__ double term[64][65];
+    const int cb = blockIdx.x * 64, t = threadIdx.x;
     double s = 0.0;
-    for (int f = 0; f < h; ++f) {
-        const int p = fpos[f];
-        const uint32_t x = (states[(uint64_t)(p >> 5) * stride + b0 + b] >> (p & 31)) & 1u;
-        const uint32_t T = made_threshold(L[(int64_t)b * D + p]);
-        s += made_log_prob(T, x);
+    for (int f0 = 0; f0 < h; f0 += 64) {
+        const int nf = min(64, h - f0), f = t & 63;
+        if (f < nf) {
+            const int p = fpos[f0 + f];
+            for (int c = t >> 6; c < 64; c += 4) {
+                const int b = cb + c;
+                if (b < n) {
+                    const uint32_t x = (states[(uint64_t)(p >> 5) * stride + b0 + b] >> (p & 31)) & 1u;
+                    term[c][f] = made_log_prob(made_threshold(L[(int64_t)b * D + p]), x);
+                }
+            }
+        }
+        __syncthreads();
+        if (t < 64 && cb + t < n)
+            for (int j = 0; j < nf; ++j) s += term[t][j];
+        __syncthreads();
     }
-    out[b] = s;
+    if (t < 64 && cb + t < n) out[cb + t] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1271,7 +1288,8 @@ hipError_t launch_shadow(const ShadowJobs &jobs, int count, hipStream_t s) {
 
 hipError_t launch_logq(const float *L, const uint32_t *states, uint64_t stride, uint64_t b0, const int *fpos, int h,
                        int n, int D, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(logq_kernel, dim3((n + 255) / 256), dim3(256), 0, s, L, states, stride, b0, fpos, h, n, D, out);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(logq_kernel, dim3((n + 63) / 64), dim3(256), 0, s, L, states, stride, b0, fpos, h, n, D, out);
     return hipGetLastError();
 }
 
