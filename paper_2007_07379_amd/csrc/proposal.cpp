@@ -292,15 +292,29 @@ pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, u
 
 }  // namespace
 
-// unpack of a column range of a word-major state array with row stride `stride`
+// unpack of a column range of a word-major state array with row stride
+// `stride`: thread (b, g) writes X[b][8g .. 8g + 7] (positions >= D as zero)
+// with one 16-byte store, so a wave's stores run along the rows.  DP is a
+// multiple of 32 and n DP / 8 < 2^32 (checked at launch).
 __global__ void unpack_strided_kernel(const uint32_t *__restrict__ states, uint64_t stride, uint64_t b0, int n,
                                       int D, int DP, bf16 *__restrict__ X) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * DP) return;
-    const int b = (int)(e / DP), i = (int)(e % DP);
-    float v = 0.f;
-    if (i < D) v = (float)((states[(uint64_t)(i >> 5) * stride + b0 + b] >> (i & 31)) & 1u);
-    X[e] = (bf16)v;
+    const uint32_t G = (uint32_t)DP >> 3;
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint32_t)n * G) return;
+    const uint32_t b = e / G, g = e - b * G;
+    const int i0 = (int)g * 8, left = D - i0;
+    uint32_t bits = 0;
+    if (left > 0) {
+        bits = (states[(uint64_t)(i0 >> 5) * stride + b0 + b] >> (i0 & 31)) & 0xFFu;
+        if (left < 8) bits &= (1u << left) - 1u;
+    }
+    constexpr uint32_t ONE = 0x3F80u;  // bf16 1.0
+    uint4 w;
+    w.x = ((bits & 1u) ? ONE : 0u) | ((bits & 2u) ? ONE << 16 : 0u);
+    w.y = ((bits & 4u) ? ONE : 0u) | ((bits & 8u) ? ONE << 16 : 0u);
+    w.z = ((bits & 16u) ? ONE : 0u) | ((bits & 32u) ? ONE << 16 : 0u);
+    w.w = ((bits & 64u) ? ONE : 0u) | ((bits & 128u) ? ONE << 16 : 0u);
+    *reinterpret_cast<uint4 *>(X + (uint64_t)b * DP + i0) = w;
 }
 
 __global__ void fill_const_kernel(const uint32_t *__restrict__ blob, uint32_t *__restrict__ state, int n, int W) {
@@ -313,7 +327,9 @@ __global__ void fill_const_kernel(const uint32_t *__restrict__ blob, uint32_t *_
 namespace {
 pbit_status unpack_range(pbit_proposal q, const uint32_t *states, uint64_t stride, uint64_t b0, int n,
                          hipStream_t s) {
-    const int64_t tot = (int64_t)n * q->DP;
+    const int64_t tot = (int64_t)n * (q->DP / 8);
+    if (q->DP % 32 || tot > (int64_t)UINT32_MAX) return set_error(PBIT_E_INVALID_ARG, "unpack: bad row length or batch");
+    if (tot == 0) return PBIT_OK;
     hipLaunchKernelGGL(unpack_strided_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, states, stride, b0,
                        n, q->D, q->DP, q->X);
     hipError_t e = hipGetLastError();
