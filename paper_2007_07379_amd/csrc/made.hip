@@ -410,11 +410,15 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict_
         const float x = (float)X[(int64_t)b * DP + i];
         float gval = 0.f;
         if (freem[i]) {
-            const float s = 1.f / (1.f + expf(-z));
+            // one exponential t = e^-|z|: sigmoid(z) = 1 / (1 + t) for z >= 0,
+            // t / (1 + t) below; the loss is softplus(-z) for x = 1 and
+            // softplus(z) for x = 0, softplus(y) = max(y, 0) + log1p(t)
+            const float t = expf(-fabsf(z));
+            const float r = __builtin_amdgcn_rcpf(1.f + t);  // 1 + t in [1, 2]
+            const float s = z >= 0.f ? r : t * r;
             gval = (s - x) * inv_n;
-            // softplus(-z) for x = 1, softplus(z) for x = 0
             const float zz = x > 0.5f ? -z : z;
-            nll += (zz > 0.f ? zz + log1pf(expf(-zz)) : log1pf(expf(zz))) * inv_n;
+            nll += (fmaxf(zz, 0.f) + log1pf(t)) * inv_n;
         }
         G[e] = (bf16)gval;
     }
