@@ -27,8 +27,11 @@ the passage of the paper it follows:
                 circuit of Fig. 6 built from matrices
 
 Pins that tie each part to the paper rather than to itself live in
-tests/test_oracle_*.py.  Parity unpinned: none of the functions above is
-unpinned except `chain.philox` whose known-answer vectors are checked only
-against an independent host build of rocRAND's Philox4x32-10 engine when
-hipcc is present (see tests/test_oracle_philox.py).
+tests/test_oracle_*.py; none of the functions above is unpinned.  The
+estimator's exact-Z and L2 legs and its sigma are pinned at exact
+expectation against the statevector and the closed forms of Eq. (stdT)
+(tests/test_oracle_estimator.py).  `chain.philox` has no published
+known-answer vectors in reach; it is checked against an independent host
+build of rocRAND's Philox4x32-10 engine when hipcc is present
+(tests/test_oracle_chain.py).
 """

@@ -13,6 +13,7 @@ from oracle import made as omade
 from oracle import shor as oshor
 
 import test_oracle_chain as tchain  # tests/ is on sys.path under pytest
+import test_oracle_estimator as testim
 import test_oracle_exact as texact
 import test_oracle_made as tmade
 import test_oracle_shor as tshor
@@ -116,6 +117,62 @@ def test_sigma_without_factor_two_in_denominator_is_caught(monkeypatch):
     assert caught((texact.test_sigma_wrong_output_eq_stdT, (4,)), texact.test_tiny_sigma_closed_form)
 
 
+ESTIMATOR_PINS = [testim.test_tiny_at_expectation_exact_z_and_l2_give_psi,
+                  testim.test_l2_mode_is_scale_free_and_unit_norm] + [
+    (testim.test_hadamard_chain_at_expectation, (d,)) for d in (2, 4, 8)] + [
+    (testim.test_random_circuits_at_expectation_match_statevector, (s,)) for s in range(4)]
+
+
+def test_l1_norm_in_l2_mode_is_caught(monkeypatch):
+    """Fig. 2 step 4 normalises by the L2 norm; an L1 norm is a plausible slip."""
+    def amplitudes_l2(counts):
+        counts = np.asarray(counts, dtype=np.float64)
+        K = int(round(math.log2(counts.shape[1])))
+        cs, sn = oest._omega(K)
+        A = counts @ cs + 1j * (counts @ sn)
+        nrm = float(np.sum(np.abs(A)))
+        return A / nrm if nrm > 0 else A
+    monkeypatch.setattr(oest, "amplitudes_l2", amplitudes_l2)
+    assert caught(*ESTIMATOR_PINS)
+
+
+def test_missing_square_root_in_l2_mode_is_caught(monkeypatch):
+    def amplitudes_l2(counts):
+        counts = np.asarray(counts, dtype=np.float64)
+        K = int(round(math.log2(counts.shape[1])))
+        cs, sn = oest._omega(K)
+        A = counts @ cs + 1j * (counts @ sn)
+        nrm = float(np.sum(np.abs(A) ** 2))
+        return A / nrm if nrm > 0 else A
+    monkeypatch.setattr(oest, "amplitudes_l2", amplitudes_l2)
+    assert caught(*ESTIMATOR_PINS)
+
+
+def test_sigma_off_by_root_two_in_count_estimator_is_caught(monkeypatch):
+    """The sigma computed from counts (Eq. (U26)), not only exact_sigma."""
+    orig = oest.amplitudes
+
+    def amplitudes(counts, Z, T=None):
+        amp, sre, sim = orig(counts, Z, T)
+        return amp, sre / math.sqrt(2.0), sim / math.sqrt(2.0)
+    monkeypatch.setattr(oest, "amplitudes", amplitudes)
+    assert caught(*ESTIMATOR_PINS)
+
+
+def test_sigma_without_mean_subtraction_is_caught(monkeypatch):
+    """Var = E W^2 - (E W)^2; dropping the square of the mean."""
+    def amplitudes(counts, Z, T=None):
+        counts = np.asarray(counts, dtype=np.float64)
+        K = int(round(math.log2(counts.shape[1])))
+        T = float(counts.sum()) if T is None else float(T)
+        cs, sn = oest._omega(K)
+        f = counts / T
+        amp = Z * (f @ cs + 1j * (f @ sn))
+        return amp, np.sqrt(Z * Z * (f @ (cs * cs)) / T), np.sqrt(Z * Z * (f @ (sn * sn)) / T)
+    monkeypatch.setattr(oest, "amplitudes", amplitudes)
+    assert caught(*ESTIMATOR_PINS)
+
+
 MADE_PINS = [tmade.test_gradients_match_central_differences, tmade.test_autoregressive_property,
              tmade.test_log_q_normalises, tmade.test_adam_constant_gradient_closed_form,
              tmade.test_each_output_sees_its_predecessor]
@@ -199,7 +256,8 @@ def test_inverse_qft_without_normalisation_is_caught(monkeypatch):
     assert caught(*SHOR_PINS)
 
 
-@pytest.mark.parametrize("pin", EXACT_PINS[:4] + CHAIN_PINS + MADE_PINS + SHOR_PINS + NONLINEAR_PINS[:2],
+@pytest.mark.parametrize("pin", EXACT_PINS[:4] + CHAIN_PINS + ESTIMATOR_PINS + MADE_PINS + SHOR_PINS
+                         + NONLINEAR_PINS[:2],
                          ids=lambda p: getattr(p, "__name__", str(p)))
 def test_pins_pass_on_the_unmodified_oracle(pin):
     """Control: the same pins pass when nothing is planted."""
