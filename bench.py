@@ -7,7 +7,11 @@ kernel (algorithmic integer-VALU ops over the kernel time measured with HIP
 events on the launch stream), and the CPU oracle timed on the host cores on
 a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload rct12]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload brick20]
+
+With the defaults the line also carries tau_int and effective samples/s of
+plain Gibbs on the workload, and a learned-proposal comparison (MADE trained
+on the GPU, 1 MH : 4 Gibbs against plain Gibbs) on a rotated-Hadamard chain.
 """
 import argparse
 import json
@@ -114,16 +118,17 @@ def cpu_baseline(c, h, burn, sweeps, chains_sample, soft_J=None):
                       "workload), %.1f s" % (chains_sample, burn, sweeps, dt)}
 
 
-def output_parities(torch, state, info, masks):
-    """+-1 parity characters of the output state alpha of every chain."""
-    n, d, W = info["n"], info["d"], info["W"]
-    ch = state.numel() // W
-    st = state.view(W, ch).to(torch.int64) & 0xFFFFFFFF
-    lo = d * n
-    alpha = torch.zeros(ch, dtype=torch.int64, device=state.device)
-    for q in range(n):
-        p = lo + q
-        alpha |= ((st[p >> 5] >> (p & 31)) & 1) << q
+def path_observables(torch, pbit, s, state, info, chains, masks):
+    """Observables of every chain's current path for tau_int ([n_obs,
+    chains] float64): +-1 parity characters of the output alpha for each
+    mask, cos and sin of the phase 2 pi phi / 2^K, and ln|psi| (gates of
+    non-constant magnitude), from the library's pbit_path_observables."""
+    d_bin = torch.empty(chains, dtype=torch.int32, device=state.device)
+    d_lm = torch.empty(chains, dtype=torch.float64, device=state.device)
+    pbit.path_observables(s, state, chains, d_bin, d_lm, stream=torch.cuda.current_stream())
+    K, n = info["K"], info["n"]
+    b = d_bin.to(torch.int64) & 0xFFFFFFFF
+    alpha, phi = b >> K, b & ((1 << K) - 1)
     out = []
     for m in masks:
         v = alpha & m
@@ -131,7 +136,38 @@ def output_parities(torch, state, info, masks):
         for q in range(n):
             par ^= (v >> q) & 1
         out.append((1 - 2 * par).to(torch.float64))
-    return torch.stack(out)  # [n_obs, chains]
+    ang = phi.to(torch.float64) * (2.0 * 3.141592653589793 / (1 << K))
+    out += [torch.cos(ang), torch.sin(ang), d_lm]
+    return torch.stack(out)
+
+
+def observable_names(masks):
+    return ["parity(alpha & %#x)" % m for m in masks] + ["cos phi", "sin phi", "ln|psi|"]
+
+
+def magnitude_marginal(c):
+    """Exact output law of the sampled path measure (p_C proportional to
+    |psi_C|): the circuit run on beta with every gate matrix replaced by its
+    entrywise modulus, normalised.  Used only to report TV_path."""
+    n = c["n"]
+    v = np.zeros(1 << n)
+    v[c.get("input", 0)] = 1.0
+    v = v.reshape([2] * n)
+    for g in sorted(c["gates"], key=lambda g: (g["layer"], min(g["qubits"]))):
+        m = g if "re" in g else c["matrices"][g["kind"]]
+        U = np.abs(np.array(m["re"], dtype=np.float64) + 1j * np.array(m["im"], dtype=np.float64))
+        qs = list(g["qubits"])
+        a = len(qs)
+        Ut = U.reshape([2] * (2 * a))
+        axes = [n - 1 - q for q in reversed(qs)]
+        v = np.moveaxis(np.tensordot(Ut, v, axes=(list(range(a, 2 * a)), axes)), list(range(a)), axes)
+    v = v.reshape(-1)
+    return v / v.sum()
+
+
+def tv_path(hist, pm):
+    emp = hist.sum(axis=1).astype(np.float64)
+    return 0.5 * float(np.abs(emp / emp.sum() - pm).sum())
 
 
 def _rh(theta):
@@ -154,12 +190,14 @@ for _k in (16, 32, 128, 256, 512):
 
 def tau_of_series(torch, ser):
     """tau_int of a [steps, chains] series: chain-pooled autocovariance by
-    FFT, Geyer's initial positive sequence."""
+    FFT, Geyer's initial positive sequence.  None for a constant series."""
     x = ser - ser.mean()
     S = x.shape[0]
     f = torch.fft.rfft(x, n=2 * S, dim=0)
     acov = torch.fft.irfft((f * f.conj()).real.sum(dim=1), n=2 * S)[:S] / (x.shape[1] * torch.arange(
         S, 0, -1, device=x.device, dtype=x.dtype))
+    if not float(acov[0]) > 1e-12 * max(1.0, float((ser * ser).mean())):
+        return None
     rho = (acov / acov[0]).cpu().numpy()
     tau = -1.0
     k = 0
@@ -174,37 +212,36 @@ def tau_of_series(torch, ser):
 
 def adaptive_tau(torch, advance, observe, min_len=512, max_len=65536):
     """Runs `advance` (one transition of the tau population) and records
-    `observe` ([n_obs, chains]) until the series is at least 50 tau_int long
-    (or max_len); returns (tau_int, series length)."""
+    `observe` ([n_obs, chains]) until the series is at least 50 times the
+    largest tau_int over the observables long (or max_len); returns (tau_int
+    of the slowest observable, per-observable taus, series length)."""
     buf = []
-    tau = float("nan")
     L = min_len
     while True:
         while len(buf) < L:
             advance(len(buf))
             buf.append(observe().to(torch.float32))
         ser = torch.stack(buf)  # [S, n_obs, chains]
-        tau = max(tau_of_series(torch, ser[:, o, :]) for o in range(ser.shape[1]))
+        taus = [tau_of_series(torch, ser[:, o, :]) for o in range(ser.shape[1])]
+        tau = max(t for t in taus if t is not None)
         if L >= 50 * tau or L >= max_len:
-            return tau, L
+            return tau, taus, L
         L *= 2
 
 
-def mh_mode(args):
+def mh_compare(args, name, hidden=0):
     """ESS per second of plain Gibbs against the learned-proposal MH (1 MH
-    step : gibbs_per_mh Gibbs sweeps) on the same GPU.  tau_int comes from the
-    output parity series of a population of tau_chains chains, recorded
-    until it is 50 tau_int long; time per transition and TV come from long
-    runs of the full population."""
+    step : gibbs_per_mh Gibbs sweeps) on the same GPU.  tau_int is the
+    largest over the observables (output parities, cos/sin of the phase,
+    ln|psi|) of a population of tau_chains chains, recorded until it is 50
+    tau_int long; time per transition and TV_path come from long runs of the
+    full population."""
     import torch
     from paper_2007_07379_amd import pbit
-    from oracle import circuit as oc
-    from oracle import estimator as oest
-    from oracle import exact
     from workloads import circuits as wc
 
-    cfg = MH_WORKLOADS[args.workload]
-    chains, burn, hidden = cfg["chains"], cfg["burn_in"], args.hidden or cfg["hidden"]
+    cfg = MH_WORKLOADS[name]
+    chains, burn, hidden = cfg["chains"], cfg["burn_in"], hidden or cfg["hidden"]
     long_cycles, tc = cfg["long_cycles"], cfg["tau_chains"]
     G = args.gibbs_per_mh
     c = cfg["circuit"](wc)
@@ -214,11 +251,14 @@ def mh_mode(args):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     rng = np.random.default_rng(0)
-    masks = [int(m) for m in rng.integers(1, 1 << info["n"], size=16)] if info["n"] > 1 else [1]
-    pm, _ = exact.magnitude_marginal(oc.from_dict(c))
+    masks = sorted({int(m) for m in rng.integers(1, 1 << info["n"], size=16)}) if info["n"] > 1 else [1]
+    pm = magnitude_marginal(c)
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
+
+    def observe(st, n):
+        return lambda: path_observables(torch, pbit, s, st, info, n, masks)
 
     hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev)
 
@@ -226,10 +266,9 @@ def mh_mode(args):
     # tau population: burn-in, then one sweep per transition
     st_t = torch.zeros(tc * W, dtype=torch.int32, device=dev)
     s.gibbs_run([tc], burn, 0, hist, st_t, seed=11, stream=stream)
-    tau_g, len_g = adaptive_tau(
+    tau_g, taus_g, len_g = adaptive_tau(
         torch, lambda t: s.gibbs_run([tc], 0, 1, hist, st_t, seed=11, sweep_offset=burn + t, resume=True,
-                                     stream=stream),
-        lambda: output_parities(torch, st_t, info, masks))
+                                     stream=stream), observe(st_t, tc))
     # full population: burn-in, then a long timed run binned for TV
     state = torch.zeros(chains * W, dtype=torch.int32, device=dev)
     s.gibbs_run([chains], burn, 0, hist, state, seed=1, stream=stream)
@@ -249,7 +288,7 @@ def mh_mode(args):
     torch.cuda.synchronize()
     t_g = e0.elapsed_time(e1) / 1e3 / n_long  # seconds per sweep
     hist_g = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
-    tv_g = oest.tv_path(hist_g, pm)
+    tv_g = tv_path(hist_g, pm)
     ess_g = chains / (tau_g * t_g)
 
     # --- training the proposal on Gibbs samples ------------------------------
@@ -279,7 +318,7 @@ def mh_mode(args):
             s.gibbs_run([tc], 0, 1, hist, st_t, seed=12, sweep_offset=(1 << 30) + cy * G + r - 1, resume=True,
                         stream=stream)
 
-    tau_m, len_m = adaptive_tau(torch, mh_advance, lambda: output_parities(torch, st_t, info, masks))
+    tau_m, taus_m, len_m = adaptive_tau(torch, mh_advance, observe(st_t, tc))
     acc_rate = float(acc.double().mean().item()) / ((len_m + G) // (1 + G))
     state = start.clone()
     hist.zero_()
@@ -291,22 +330,54 @@ def mh_mode(args):
     torch.cuda.synchronize()
     t_m = e0.elapsed_time(e1) / 1e3 / n_long  # seconds per transition
     hist_m = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
-    tv_m = oest.tv_path(hist_m, pm)
+    tv_m = tv_path(hist_m, pm)
     ess_m = chains / (tau_m * t_m)
-    out = {
-        "metric": "effective samples/s (TV<=0.01), Gibbs vs learned-proposal MH",
+    names = observable_names(masks)
+    return {
         "workload": "%s: n=%d d=%d, h=%d free p-bits, %d chains, MADE hidden %d, 1 MH : %d Gibbs"
-                    % (args.workload, info["n"], info["d"], h, chains, hidden, G),
-        "gibbs": {"tau_int_sweeps": tau_g, "tau_series": len_g, "s_per_sweep": t_g, "ess_per_s": ess_g,
-                  "tv_path": tv_g, "tv_samples": chains * n_long},
-        "mh": {"tau_int_transitions": tau_m, "tau_series": len_m, "s_per_transition": t_m, "ess_per_s": ess_m,
-               "tv_path": tv_m, "tv_samples": chains * n_long, "accept_rate": acc_rate},
+                    % (name, info["n"], info["d"], h, chains, hidden, G),
+        "observables": "tau_int is the largest over: %s (constant ones skipped)" % ", ".join(names),
+        "gibbs": {"tau_int_sweeps": tau_g, "tau_per_observable": dict(zip(names, taus_g)), "tau_series": len_g,
+                  "s_per_sweep": t_g, "ess_per_s": ess_g, "tv_path": tv_g, "tv_samples": chains * n_long},
+        "mh": {"tau_int_transitions": tau_m, "tau_per_observable": dict(zip(names, taus_m)), "tau_series": len_m,
+               "s_per_transition": t_m, "ess_per_s": ess_m, "tv_path": tv_m, "tv_samples": chains * n_long,
+               "accept_rate": acc_rate},
         "train": {"samples": ntrain, "steps": cfg["train_steps"], "batch": cfg["batch"], "seconds": t_train,
                   "loss_first": float(losses[0]), "loss_last": float(losses[-20:].mean())},
         "ess_ratio_mh_over_gibbs": ess_m / ess_g,
         "tv_ok": bool(tv_g <= 0.01 and tv_m <= 0.01),
     }
+
+
+def mh_mode(args):
+    out = mh_compare(args, args.workload, args.hidden)
+    out["metric"] = "effective samples/s (TV<=0.01), Gibbs vs learned-proposal MH"
     print(json.dumps(out))
+
+
+def gibbs_ess(torch, pbit, s, info, c, chains, sweeps, step_s, hist_total, tau_chains=4096):
+    """tau_int of plain Gibbs on the timed workload (largest over the output
+    parities, cos/sin of the phase and ln|psi| of tau_chains chains after
+    the burn-in) and the effective samples per second of the timed run."""
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(0)
+    masks = sorted({int(m) for m in rng.integers(1, 1 << info["n"], size=16)}) if info["n"] > 1 else [1]
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    st = torch.zeros(tau_chains * info["W"], dtype=torch.int32, device="cuda")
+    burn = 200
+    s.gibbs_run([tau_chains], burn, 0, hist, st, seed=21, stream=stream)
+    tau, taus, L = adaptive_tau(
+        torch, lambda t: s.gibbs_run([tau_chains], 0, 1, hist, st, seed=21, sweep_offset=burn + t, resume=True,
+                                     stream=stream, specialize=1),
+        lambda: path_observables(torch, pbit, s, st, info, tau_chains, masks), min_len=256)
+    names = observable_names(masks)
+    out = {"tau_int_sweeps": tau, "tau_per_observable": dict(zip(names, taus)), "tau_series": L,
+           "tau_chains": tau_chains, "ess_per_s": chains * sweeps / tau / step_s,
+           "observables": "largest tau_int over %d output parities, cos and sin of the phase, ln|psi| "
+                          "(constant observables skipped)" % len(masks)}
+    if info["n"] <= 22:
+        out["tv_path"] = tv_path(hist_total, magnitude_marginal(c))
+    return out
 
 
 BF16_PEAK = 2.5e15  # MI355X dense bf16 MFMA FLOP/s
@@ -542,9 +613,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rct12")
+    ap.add_argument("--workload", default="brick20")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-chains", type=int, default=8192)
+    ap.add_argument("--cpu-chains", type=int, default=0,
+                    help="chains of the oracle's timed sample (0: about 10^10 updates, 10-20 s of host cores)")
+    ap.add_argument("--no-ess", action="store_true", help="gibbs mode: skip tau_int / ESS and the MH comparison")
+    ap.add_argument("--mh-workload", default="rhchain48_pi256",
+                    help="gibbs mode: workload of the learned-proposal comparison ('' to skip)")
     ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train", "shor"])
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--specialize", type=int, default=0, choices=[0, 1, 2])
@@ -571,7 +646,7 @@ def main():
         shor_mode(args)
         return
     if args.mode == "mh":
-        if args.workload == "rct12":
+        if args.workload not in MH_WORKLOADS:
             args.workload = "brick16"
         mh_mode(args)
         return
@@ -596,12 +671,14 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     # uint32 counts: a run whose chains x sweeps reaches 2^32 is cut into
-    # parts (the chain state carries over), each with its own histogram
+    # equal parts (the chain state carries over), each with its own
+    # histogram; the first part also runs the burn-in
     per_part = (2 ** 32 - 1) // chains
+    n_parts = -(-sweeps // per_part)
     parts = []
     done = 0
-    while done < sweeps:
-        n = min(per_part, sweeps - done)
+    for k in range(n_parts):
+        n = (sweeps - done) // (n_parts - k)
         parts.append((burn if done == 0 else 0, n, 0 if done == 0 else burn + done))
         done += n
     hists = [torch.zeros(info["hist_bins"], dtype=torch.int32, device=dev) for _ in parts]
@@ -641,6 +718,8 @@ def main():
     step()
     torch.cuda.synchronize()
     binned = float(sum(int(hh.to(torch.int64).sum().item()) & 0xFFFFFFFFFFFF for hh in hists))
+    hist_total = sum(hh.cpu().numpy().view(np.uint32).astype(np.uint64) for hh in hists).reshape(
+        1 << info["n"], 1 << info["K"])
     kms = [a.elapsed_time(b) for a, b in ev]
     kernel_s = float(np.mean(kms)) / 1e3
     ms_per_step = wall / args.steps * 1e3
@@ -681,14 +760,24 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
             "kernel": kname,
             "kernel_ms": kernel_s * 1e3,
+            "launches_per_step": len(parts),
+            "kernel_ms_per_launch": kernel_s * 1e3 / len(parts),
             "launch": {k: shape[k] for k in ("block", "lds_hist", "lanes_per_chain", "lds_bytes",
                                              "sweeps_per_launch")},
             "ops_per_update": per_sweep / max(h, 1),
             "ops_per_sample": per_sample,
         },
     }
+    if not args.no_ess:
+        out["ess"] = gibbs_ess(torch, pbit, s, info, c, chains, sweeps, ms_per_step / 1e3, hist_total)
+        if args.mh_workload:
+            # the learned proposal where it pays: a rotated-Hadamard chain whose
+            # path law is strongly correlated (every conditional of the
+            # uniform workloads is 1/2, so Gibbs is already i.i.d. there)
+            out["learned_proposal"] = mh_compare(args, args.mh_workload)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(c, h, burn, sweeps, min(args.cpu_chains, chains), soft_J or None)
+        cc = args.cpu_chains or max(64, min(chains, int(1e10 / ((burn + sweeps) * max(h, 1)))))
+        out["cpu_baseline"] = cpu_baseline(c, h, burn, sweeps, cc, soft_J or None)
     print(json.dumps(out))
 
 

@@ -314,6 +314,18 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
  * written to that JSON file, keyed by a hash of the compiled circuits, so a
  * second process skips the timing.  Uses temporary device buffers; blocks
  * until done. */
+/* Per-path observables of chain states, for autocorrelation estimates
+ * (Eq. (path): a path's output alpha, its phase, the sum of its gates'
+ * imaginary energies, and its magnitude exp(-Re E)).  For each of `chains`
+ * word-major lattices of circuit idx in d_state (W x chains u32, as
+ * pbit_gibbs_run leaves them): d_bin[c] = alpha * 2^K + phi, the histogram
+ * bin of the path, and d_logmag[c] = ln|psi_C| up to a constant of the
+ * circuit: the FP64 sum of ln|U_g| over the gates whose magnitude is not
+ * constant (0 for circuits without such gates).  Device buffers, owned by
+ * the caller; either output may be NULL.  Asynchronous on hip_stream. */
+pbit_status pbit_path_observables(pbit_circuit c, uint32_t idx, const uint32_t *d_state, uint32_t chains,
+                                  uint32_t *d_bin, double *d_logmag, void *hip_stream);
+
 pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char *cache_path, void *hip_stream);
 
 /* Launch shape that pbit_gibbs_run would use for circuit `index` under

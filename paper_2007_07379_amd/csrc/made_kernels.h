@@ -123,5 +123,9 @@ struct MhArgs {
     uint32_t hist_bins;       // 2^(n+K); privatised in LDS per workgroup when small
 };
 hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s);
+// Per-path bin and ln|psi| (non-constant-magnitude gates) of n word-major
+// lattices; bin or logmag may be NULL.
+hipError_t launch_observe(uint32_t Wk, const uint32_t *blob, const uint32_t *state, int n, uint32_t *bin,
+                          double *logmag, hipStream_t s);
 
 }  // namespace pbit

@@ -118,7 +118,42 @@ __global__ __launch_bounds__(256) void mh_accept_kernel(MhArgs a) {
     }
 }
 
+// Per-path observables of chain states (Eq. (path)): the bin alpha 2^K + phi
+// of each path and ln|psi| over the gates with non-constant magnitude (the
+// real-energy records; the other gates add one constant to every path).
+template <int W>
+__global__ __launch_bounds__(256) void observe_kernel(const uint32_t *__restrict__ B, const uint32_t *state, int n,
+                                                     uint32_t *bin, double *logmag) {
+    const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lc >= n) return;
+    const uint32_t Wc = B[H_W];
+    uint32_t x[W + 2];
+    x[W] = x[W + 1] = 0u;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = (uint32_t)w < Wc ? state[(int64_t)w * n + lc] : 0u;
+    if (bin) bin[lc] = phase_and_bin<W>(B, x, B[H_K], B[H_N]);
+    if (logmag) {
+        double s = 0.0, unused = 0.0;
+        if (B[H_NRE]) log_weights<W>(B + B[H_OFF_RE], B[H_NRE], x, x, s, unused);
+        logmag[lc] = s;
+    }
+}
+
 #define PBIT_FOR_EACH_W(X) X(1) X(2) X(3) X(4) X(6) X(8) X(10) X(12) X(13) X(14) X(16) X(17) X(20) X(24) X(28) X(32)
+
+hipError_t launch_observe(uint32_t Wk, const uint32_t *blob, const uint32_t *state, int n, uint32_t *bin,
+                          double *logmag, hipStream_t s) {
+    const int grid = (n + 255) / 256;
+    if (grid == 0) return hipSuccess;
+#define PBIT_LAUNCH(V)                                                                               \
+    if (Wk == V) {                                                                                   \
+        hipLaunchKernelGGL((observe_kernel<V>), dim3(grid), dim3(256), 0, s, blob, state, n, bin, logmag); \
+        return hipGetLastError();                                                                    \
+    }
+    PBIT_FOR_EACH_W(PBIT_LAUNCH)
+#undef PBIT_LAUNCH
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_mh_accept(uint32_t Wk, const MhArgs &a, hipStream_t s) {
     const int grid = (a.n + 255) / 256;

@@ -732,4 +732,23 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
     return PBIT_OK;
 }
 
+pbit_status pbit_path_observables(pbit_circuit c, uint32_t idx, const uint32_t *d_state, uint32_t chains,
+                                  uint32_t *d_bin, double *d_logmag, void *hip_stream) {
+    if (!c || !d_state) return set_error(PBIT_E_INVALID_ARG, "NULL handle or d_state");
+    if (idx >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
+    if (chains > 0x7FFFFFFFu) return set_error(PBIT_E_INVALID_ARG, "chains must be below 2^31");
+    if (chains == 0 || (!d_bin && !d_logmag)) return PBIT_OK;
+    const uint32_t *dblob = nullptr;
+    pbit_status st;
+    {
+        std::lock_guard<std::mutex> lock(c->mu);
+        if ((st = device_blobs(c, &dblob)) != PBIT_OK) return st;
+    }
+    const CompiledCircuit &k = c->circuits[idx];
+    hipError_t e = launch_observe(k.WS, dblob + c->blob_off[idx], d_state, (int)chains, d_bin, d_logmag,
+                                  (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_error(e, "path observables");
+    return PBIT_OK;
+}
+
 }  // extern "C"

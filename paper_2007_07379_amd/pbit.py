@@ -312,6 +312,7 @@ def _made_sigs(L):
     L.pbit_proposal_sample_score.argtypes = [V, C.c_uint32, C.c_uint32, P, C.c_uint32, V, V, V, V, V]
     L.pbit_proposal_score.argtypes = [V, V, C.c_uint32, V, V]
     L.pbit_mh_run.argtypes = [V, V, C.POINTER(MhCfg), V, V, V, V]
+    L.pbit_path_observables.argtypes = [V, C.c_uint32, V, C.c_uint32, V, V, V]
 
 
 class Proposal:
@@ -383,6 +384,15 @@ def mh_run(cset, proposal, chains, cycles, d_state, d_hist, d_accepts=None, gibb
     _made_sigs(L)
     _check(L.pbit_mh_run(cset.handle, proposal.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                          _ptr(d_accepts), _stream(stream)))
+
+
+def path_observables(cset, d_state, chains, d_bin=None, d_logmag=None, idx=0, stream=None):
+    """Per-chain histogram bin (alpha 2^K + phi, uint32) and ln|psi| over the
+    gates of non-constant magnitude (float64) of word-major lattices."""
+    L = lib()
+    _made_sigs(L)
+    _check(L.pbit_path_observables(cset.handle, idx, _ptr(d_state), chains, _ptr(d_bin), _ptr(d_logmag),
+                                   _stream(stream)))
 
 
 class ShorCfg(C.Structure):

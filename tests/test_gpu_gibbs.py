@@ -68,6 +68,10 @@ CASES = [
     ("hchain_odd", lambda: wc.hadamard_chain(33, K=1), 300, 5, 50, 0),
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 20, 0),
     ("rasym", lambda: wc.random_asymmetric(6, 10, 3, K=3), 777, 10, 40, 5),
+    # inputs beta != 0 (Eq. (U)): layer 0 clamped to beta
+    ("tiny_b5", lambda: dict(wc.tiny_ghz_t(), input=5), 1024, 200, 2000, 0),
+    ("rct5_b22", lambda: dict(wc.random_clifford_t(5, 7, 77, K=3), input=0b10110), 600, 10, 50, 3),
+    ("rbrick_b11", lambda: dict(wc.rotated_brickwork(5, 8, 3, math.pi / 7, K=3), input=0b01011), 640, 20, 100, 9),
 ]
 
 
@@ -90,9 +94,9 @@ MODES = {
 def test_bit_exact_vs_oracle(env, name, mk, chains, burn, sweeps, cb, mode):
     c = mk()
     say("case", name, chains, burn, sweeps, cb, "mode", mode)
-    st_g, h_g, _ = run_gpu(env, c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
+    st_g, h_g, _ = run_gpu(env, c, chains, burn, sweeps, seed=0x1234abcd5678 if not name.startswith("tiny") else 0,
                            chain_begin=cb, **MODES[mode])
-    st_o, h_o, comp = oracle_run(c, chains, burn, sweeps, seed=0x1234abcd5678 if name != "tiny" else 0,
+    st_o, h_o, comp = oracle_run(c, chains, burn, sweeps, seed=0x1234abcd5678 if not name.startswith("tiny") else 0,
                                  chain_begin=cb)
     assert np.array_equal(st_g, st_o)
     assert np.array_equal(h_g, h_o)
@@ -166,14 +170,31 @@ def _full_run(env, name, spl=0):
     return c, s, st, h, chains, burn, sweeps
 
 
-def test_full_rct12_sampled_chains_and_amplitudes(env):
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_full_rct12_bit_exact_and_amplitudes(env):
     """Full random Clifford+T workload (65,536 chains x 10,000 sweeps after
-    200 burn-in): sampled chains replayed by the oracle match bit for bit;
-    the histogram passes the 4-sigma rule against the 2^12 statevector and
-    the path-marginal TV is at the iid level and <= 0.01."""
+    200 burn-in) in the launch the benchmark times: every one of the 4096 x 8
+    uint64 counts equals the oracle's (tests/golden/rct12_full_hist.npz,
+    written by tests/golden/make_rct12_full.py from the oracle alone) and the
+    final lattice words of all chains hash to the oracle's SHA-256; sampled
+    chains replayed by the oracle match word for word; the histogram passes
+    the 4-sigma rule against the 2^12 statevector and the path-marginal TV is
+    at the iid level and <= 0.01."""
+    import hashlib
+    import json
     c, s, st, h, chains, burn, sweeps = _full_run(env, "rct12")
     T = chains * sweeps
     assert int(h.sum()) == T
+    gold_h = np.load(os.path.join(GOLD, "rct12_full_hist.npz"))["hist"]
+    gold_s = json.load(open(os.path.join(GOLD, "rct12_full_state.json")))
+    assert (gold_s["chains"], gold_s["burn_in"], gold_s["sweeps"]) == (chains, burn, sweeps)
+    diff = np.argwhere(h != gold_h)
+    say("rct12 full: counts differing from the oracle:", len(diff), diff[:5].tolist())
+    assert len(diff) == 0
+    assert np.array_equal(st[0], gold_s["first_chain"]) and np.array_equal(st[-1], gold_s["last_chain"])
+    assert hashlib.sha256(np.ascontiguousarray(st, dtype="<u4").tobytes()).hexdigest() == gold_s["sha256"]
     comp = ocomp.compile_circuit(oc.from_dict(c))
     rng = np.random.default_rng(0)
     picks = [0, 1, 63, 64, chains - 1] + [int(v) for v in rng.integers(0, chains, size=3)]
@@ -238,6 +259,42 @@ def test_full_brick20_sampled_chains_and_amplitudes(env):
     assert tv <= 0.01 and tv < 3 * oest.expected_iid_tv(pm, T)
 
 
+def test_brick20_chain_subset_bit_exact_in_the_benchmark_launch(env):
+    """The brickwork workload (n=20, d=24, K=4) on its first 4,096 chains for
+    the full 200 + 20,000 sweeps, in the benchmark's launch shape (the
+    circuit-specialised kernel, one lane per chain, counts by HBM atomics
+    into 2^24 bins) and cut at the benchmark's launch boundary (the sweeps
+    split in two halves, the second resumed from the first's state): every
+    count and every final lattice word equals the oracle's."""
+    torch, pbit = env
+    w = wc.WORKLOADS["brick20"]
+    c = wc.workload_circuit("brick20")
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    chains, burn, sweeps = 4096, w["burn_in"], w["sweeps"]
+    kw = dict(specialize=2, lanes_per_chain=1, hist_mode=2)
+    sh = s.launch_shape([w["chains"]], burn, sweeps // 2)
+    sh_sub = s.launch_shape([chains], burn, sweeps // 2, **kw)
+    say("benchmark shape", sh, "subset shape", sh_sub)
+    for k in ("kernel", "lanes_per_chain", "lds_hist", "block"):
+        assert sh[k] == sh_sub[k], k
+    state = torch.zeros(chains * info["W"], dtype=torch.int32, device="cuda")
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    half = sweeps // 2
+    s.gibbs_run([chains], burn, half, hist, state, seed=0, **kw)
+    s.gibbs_run([chains], 0, sweeps - half, hist, state, seed=0, sweep_offset=burn + half, resume=True, **kw)
+    torch.cuda.synchronize()
+    h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+    st = state.cpu().numpy().view(np.uint32).reshape(info["W"], chains).T
+    say("oracle: brick20 chains [0, %d) x %d sweeps" % (chains, burn + sweeps))
+    st_o, h_o, _ = oracle_run(c, chains, burn, sweeps)
+    assert int(h.sum()) == chains * sweeps
+    assert np.array_equal(st, st_o)
+    diff = np.argwhere(h != h_o)
+    say("counts differing:", len(diff))
+    assert len(diff) == 0
+
+
 def test_full_tiny_born_tv(env):
     c, s, st, h, chains, burn, sweeps = _full_run(env, "tiny")
     _, h_o, comp = oracle_run(c, chains, burn, sweeps)
@@ -295,3 +352,41 @@ def test_general_kernel_resume_across_kernels(env, first, second):
     h = hist.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(h_o.shape)
     assert np.array_equal(st, st_o)
     assert np.array_equal(h, h_o)
+
+
+@pytest.mark.parametrize("name,mk", [
+    ("rct5_b22", lambda: dict(wc.random_clifford_t(5, 7, 77, K=3), input=0b10110)),
+    ("rbrick", lambda: wc.rotated_brickwork(5, 8, 3, math.pi / 7, K=3)),
+    ("rhchain_b1", lambda: wc.rotated_hadamard_chain(10, math.pi / 8, K=1, input_state=1)),
+    ("rct12", lambda: wc.workload_circuit("rct12")),
+])
+def test_path_observables_match_oracle(env, name, mk):
+    """pbit_path_observables on the chains' final lattices: the bin equals
+    alpha 2^K + phi of the oracle's gate-by-gate path weight (Eq. (path)),
+    and ln|psi| differs from the oracle's ln of the product of gate
+    magnitudes by one constant for every path."""
+    torch, pbit = env
+    c = mk()
+    chains = 777
+    st, _, s = run_gpu(env, c, chains, 10, 3, seed=5)
+    info = s.info(0)
+    state = torch.from_numpy(st.T.copy().view(np.int32)).cuda().reshape(-1)
+    d_bin = torch.zeros(chains, dtype=torch.int32, device="cuda")
+    d_lm = torch.zeros(chains, dtype=torch.float64, device="cuda")
+    pbit.path_observables(s, state, chains, d_bin, d_lm)
+    torch.cuda.synchronize()
+    bins = d_bin.cpu().numpy().view(np.uint32)
+    lm = d_lm.cpu().numpy()
+    comp = ocomp.compile_circuit(oc.from_dict(c))
+    L = comp.n * (comp.d + 1)
+    offs = []
+    for ci in range(chains):
+        x = np.array([(int(st[ci, p >> 5]) >> (p & 31)) & 1 for p in range(L)], dtype=np.int64)
+        m, k = ocomp.path_weight(comp, x)
+        assert m > 0.0, ci
+        assert bins[ci] == (ocomp.alpha_of(comp, x) << comp.K) + k, ci
+        offs.append(lm[ci] - math.log(m))
+    offs = np.array(offs)
+    assert np.max(np.abs(offs - offs[0])) <= 1e-12 * max(1.0, float(np.max(np.abs(lm))) + abs(offs[0])) * 64
+    if info["uniform"]:
+        assert np.all(lm == 0.0)

@@ -43,6 +43,10 @@ CASES = [
     ("rct_w17", lambda: wc.random_clifford_t(16, 32, 1007, K=3), 257, 5, 21, 0),
     ("rasym", lambda: wc.random_asymmetric(6, 10, 3, K=3), 777, 10, 41, 5),
     ("rct_shallow", lambda: wc.random_clifford_t(16, 4, 24, K=3), 2000, 7, 300, 11),
+    # inputs beta != 0 (Eq. (U)): layer 0 clamped to beta
+    ("tiny_b5", lambda: dict(wc.tiny_ghz_t(), input=5), 1024, 200, 2000, 0),
+    ("rct5_b22", lambda: dict(wc.random_clifford_t(5, 7, 77, K=3), input=0b10110), 600, 10, 51, 3),
+    ("brick16_b", lambda: dict(wc.workload_circuit("brick16"), input=0xA5C3), 513, 10, 43, 77),
 ]
 
 _oracle_cache = {}

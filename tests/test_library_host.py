@@ -151,6 +151,12 @@ def _cases():
         ("rbrick", wc.rotated_brickwork(4, 6, 5, math.pi / 8, K=3)),
         ("hchain", wc.hadamard_chain(9, K=1)),
         ("rasym", wc.random_asymmetric(6, 10, 3, K=3)),
+        # inputs beta != 0 (Eq. (U)): layer 0 clamped to beta
+        ("tiny_b5", dict(wc.tiny_ghz_t(), input=5)),
+        ("rct_small_b22", dict(wc.random_clifford_t(5, 7, 77, K=3), input=0b10110)),
+        ("rhchain_b1", wc.rotated_hadamard_chain(10, math.pi / 8, K=1, input_state=1)),
+        ("rbrick_b11", dict(wc.rotated_brickwork(4, 6, 5, math.pi / 8, K=3), input=0b1011)),
+        ("rasym_b63", dict(wc.random_asymmetric(6, 10, 3, K=3), input=63)),
     ]
 
 

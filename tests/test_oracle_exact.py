@@ -69,6 +69,46 @@ def test_tiny_amplitudes_and_phase_bins():
         assert m == pytest.approx(0.5)
 
 
+@pytest.mark.parametrize("inp", ["1", "5"])
+def test_tiny_nonzero_inputs(inp):
+    """The tiny circuit on inputs beta = 1 and 5, worked by hand (golden
+    file): the statevector, the path sum, the dense column beta and every
+    path of the compiled lattice (clamped to beta on layer 0) agree with it."""
+    g = json.load(open(os.path.join(GOLD, "tiny_n3_d5_inputs.json")))
+    case = g["inputs"][inp]
+    c = _circ(dict(wc.tiny_ghz_t(), input=int(inp)))
+    want = np.zeros(8, dtype=complex)
+    for k, (re, im) in case["amplitudes"].items():
+        want[int(k)] = complex(re, im)
+    assert np.allclose(exact.statevector(c), want, atol=1e-12)
+    assert np.allclose(exact.path_sum(c), want, atol=1e-12)
+    assert np.allclose(exact.dense_unitary(c)[:, int(inp)], want, atol=1e-12)
+    comp = ocomp.compile_circuit(c)
+    assert comp.h == g["free_bits"] and comp.Z == pytest.approx(g["Z"], rel=1e-12)
+    seen = set()
+    for f, x, m, k, a in ocomp.enumerate_free(comp):
+        assert [x[q] for q in range(3)] == [(int(inp) >> q) & 1 for q in range(3)]
+        assert k == case["phase_bins"][str(a)]
+        assert m == pytest.approx(0.5)
+        seen.add(a)
+    assert seen == {int(a) for a in case["phase_bins"]}
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_nonzero_inputs_statevector_path_sum_dense_and_compile(seed):
+    """Inputs beta != 0 (1, 5 and all ones, reduced mod 2^n): Eq. (U) as a
+    matrix product, Eq. (path) as an explicit sum, the dense unitary's
+    column beta and the compiled lattice's path sum are the same vector."""
+    c = small_random(seed) if seed % 2 else small_asym(seed)
+    for beta in sorted({1 % 2 ** c.n, 5 % 2 ** c.n, 2 ** c.n - 1}):
+        cb = oc.Circuit(c.n, c.d, c.K, beta, c.gates, c.name)
+        sv = exact.statevector(cb)
+        assert np.allclose(sv, exact.path_sum(cb), atol=1e-12), beta
+        assert np.allclose(sv, exact.dense_unitary(cb)[:, beta], atol=1e-12), beta
+        comp = ocomp.compile_circuit(cb)
+        assert np.allclose(compiled_amplitudes(comp), sv, atol=1e-12), beta
+
+
 def test_hadamard_d2_worked_example():
     """Sec. 4, Fig. 3: four equal-magnitude paths, 0->1->1 has the opposite
     phase; output 0 collects 2, output 1 collects 0."""
