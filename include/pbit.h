@@ -240,7 +240,12 @@ typedef struct {
     float lr, beta1, beta2, eps;  /* 0 selects 1e-3, 0.9, 0.999, 1e-8 */
 } pbit_train_cfg;
 
-/* Creates a proposal for circuit idx of c (the handle must outlive it). */
+/* Creates a proposal for circuit idx of c (the handle must outlive it).
+ * Errors: PBIT_E_INVALID_ARG for a hidden width that is not a multiple of
+ * 64 in 64..4096, PBIT_E_MODE_UNAVAILABLE for circuits with three-qubit
+ * products or soft zeros, PBIT_E_TOO_LARGE when no sampler can hold the
+ * network's activations in 160 KiB of LDS (made_sample_kernel needs about
+ * 32 D + 64 H bytes: H <= 2,304 at D = 400). */
 pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_cfg *cfg, pbit_proposal *out);
 void pbit_proposal_free(pbit_proposal q);
 /* D (positions), H (hidden) and the number of parameters. */
@@ -314,6 +319,16 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
  * written to that JSON file, keyed by a hash of the compiled circuits, so a
  * second process skips the timing.  Uses temporary device buffers; blocks
  * until done. */
+/* The FP64 natural logarithm whose values the learned proposal's samplers
+ * and scorers sum into log q (the log of the threshold probability of each
+ * drawn or scored bit), evaluated on n device doubles: d_y[i] = ln(d_x[i])
+ * for positive normal d_x[i], within one ulp (2 atanh series on the
+ * mantissa reduced to [sqrt(2)/2, sqrt(2)) with the quotient's rounding
+ * error recovered, plus e ln 2).  Exported so its
+ * accuracy can be checked against a reference logarithm; device buffers,
+ * asynchronous on hip_stream. */
+pbit_status pbit_log_eval(const double *d_x, double *d_y, uint64_t n, void *hip_stream);
+
 /* Per-path observables of chain states, for autocorrelation estimates
  * (Eq. (path): a path's output alpha, its phase, the sum of its gates'
  * imaginary energies, and its magnitude exp(-Re E)).  For each of `chains`

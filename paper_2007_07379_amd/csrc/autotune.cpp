@@ -112,23 +112,29 @@ extern "C" pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, 
         if (d_state) (void)hipFree(d_state);
         return set_error(PBIT_E_OOM, "autotune buffers");
     }
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(d_state);
+        (void)hipFree(d_hist);
+        return hip_error(e, "autotune events");
+    }
     const uint32_t trial = (uint32_t)std::max<uint64_t>(8, std::min<uint64_t>(64, (uint64_t)cfg->burn_in + cfg->sweeps));
     pbit_status status = PBIT_OK;
     // time one configuration: one warm-up run, then the best of two
     auto time_cfg = [&](const pbit_gibbs_cfg &t, float *ms) -> pbit_status {
         float best = 1e30f;
         for (int r = 0; r < 3; ++r) {
-            (void)hipEventRecord(e0, s);
+            hipError_t ee = hipEventRecord(e0, s);
+            if (ee != hipSuccess) return hip_error(ee, "autotune event");
             pbit_status st = run_gibbs(c, &t, d_state, d_hist, s);
             if (st != PBIT_OK) return st;
-            (void)hipEventRecord(e1, s);
-            hipError_t ee = hipEventSynchronize(e1);
+            if ((ee = hipEventRecord(e1, s)) == hipSuccess) ee = hipEventSynchronize(e1);
             if (ee != hipSuccess) return hip_error(ee, "autotune sync");
             float v = 0;
-            (void)hipEventElapsedTime(&v, e0, e1);
+            if ((ee = hipEventElapsedTime(&v, e0, e1)) != hipSuccess) return hip_error(ee, "autotune timing");
             if (r > 0) best = std::min(best, v);
         }
         *ms = best;

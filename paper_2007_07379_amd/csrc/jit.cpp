@@ -517,19 +517,26 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
                           "-packed-fp32-ops"};
     const hiprtcResult rc = hiprtcCompileProgram(prog, 7, opts);
     size_t ls = 0;
-    (void)hiprtcGetProgramLogSize(prog, &ls);
+    if (hiprtcGetProgramLogSize(prog, &ls) != HIPRTC_SUCCESS) ls = 0;
     std::string lg(ls + 1, '\0');
-    if (ls) (void)hiprtcGetProgramLog(prog, &lg[0]);
+    if (ls && hiprtcGetProgramLog(prog, &lg[0]) != HIPRTC_SUCCESS) lg = "(log unavailable)";
     if (rc != HIPRTC_SUCCESS) {
         *log = "hipRTC compile failed: " + lg;
         (void)hiprtcDestroyProgram(&prog);
         return false;
     }
     size_t cs = 0;
-    (void)hiprtcGetCodeSize(prog, &cs);
-    std::vector<char> code(cs);
-    (void)hiprtcGetCode(prog, code.data());
+    std::vector<char> code;
+    bool got = hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs > 0;
+    if (got) {
+        code.resize(cs);
+        got = hiprtcGetCode(prog, code.data()) == HIPRTC_SUCCESS;
+    }
     (void)hiprtcDestroyProgram(&prog);
+    if (!got) {
+        *log = "hipRTC produced no code object";
+        return false;
+    }
     hipModule_t mod = nullptr;
     hipError_t e = hipModuleLoadData(&mod, code.data());
     if (e != hipSuccess) {
@@ -544,7 +551,12 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
         return false;
     }
     int scratch = 0;
-    (void)hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn);
+    e = hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn);
+    if (e != hipSuccess) {
+        (void)hipModuleUnload(mod);
+        *log = std::string("hipFuncGetAttribute: ") + hipGetErrorString(e);
+        return false;
+    }
     out->module = mod;
     out->fn = fn;
     out->lds_bytes = src.lds_bytes;

@@ -25,16 +25,15 @@ namespace pbit {
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Workgroup tile TT x TT, TT = 128 or 64 (four waves of TT/2 x TT/2, each
-// TT/32 x TT/32 MFMA tiles of 16 x 16).  K advances in stages of two 32-wide
-// chunks staged through double-buffered LDS; the global loads of a stage are
-// issued P stages ahead into registers, so their latency hides behind
-// the products of the stages in between.  The 128 tile reads half the LDS
-// bytes per product; the 64 tile gives a product four times the workgroups
-// (four per CU at 36 KiB of LDS each), which the small products of training
-// need to hide latency, and its own 64-column K range.
-// Prefetch depth, measured at 1, 2, 3 and 6 stages: 1 and 2 tie, 3 is 5 %
-// (64 tile) to 60 % (128 tile) slower, 6 a quarter slower on the 64 tile.
+// Workgroup tile TT x TT, TT = 64 (four waves of 32 x 32, each 2 x 2 MFMA
+// tiles of 16 x 16).  K advances in stages of two 32-wide chunks staged
+// through double-buffered LDS; the global loads of a stage are issued P
+// stages ahead into registers, so their latency hides behind the products
+// of the stages in between.  The 64 tile gives a product four workgroups per
+// CU (36 KiB of LDS each), which the small products of training need to
+// hide latency, and each tile has its own 64-column K range.  Prefetch
+// depth, measured at 1, 2, 3 and 6 stages: 1 and 2 tie, 3 is 5 % slower, 6
+// a quarter slower.
 constexpr int TK = 32, TKS = 2 * TK, LDSK = TKS + 8;
 constexpr int GEMM_P = 2;
 
@@ -168,13 +167,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int m0 = tile_m * TM, n0 = tile_n * TN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * (TT / 2), wc = (wave & 1) * (TT / 2);
-    // K range of the tile: the union of its 64-column ranges
-    const int t64 = tile_n * (TT / 64);
-    const int nt64 = (g.N + 63) / 64;
-    const bool two = TT == 128 && t64 + 1 < nt64;
+    static_assert(TT == 64, "the K ranges kbeg / kend are per 64-column tile");
+    // K range of the tile
     int kb = 0, ke = g.K;
-    if (g.kbeg) kb = two ? min(g.kbeg[t64], g.kbeg[t64 + 1]) : g.kbeg[t64];
-    if (g.kend) ke = two ? max(g.kend[t64], g.kend[t64 + 1]) : g.kend[t64];
+    if (g.kbeg) kb = g.kbeg[tile_n];
+    if (g.kend) ke = g.kend[tile_n];
     int c_lo = kb / TK, c_hi = (ke + TK - 1) / TK;  // 32-wide chunks [c_lo, c_hi)
     // split-K: slice blockIdx.z of the chunk range
     if (g.ksplit > 1) {
@@ -356,17 +353,18 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.ksplit > 1 && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part || (int64_t)g.M * g.N > INT32_MAX))
         return hipErrorInvalidValue;
     const int z = g.ksplit > 1 ? g.ksplit : 1;
-    // 128 x 128 tiles once a product has sixteen of them per CU, else 64 x 64
-    // (a 16,384 x 1,024 product: 49 us as 64 x 64 tiles, 52 us as 128 x 128)
-    const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
-    const int TT = t128 * z >= 4096 ? 128 : 64;
+    // 64 x 64 tiles: every product of the networks the proposal accepts
+    // (H <= 2,496, batches <= 16,384) has fewer than sixteen 128 x 128 tiles
+    // per CU, where four 64 x 64 workgroups per CU run faster (a 16,384 x
+    // 1,024 product: 49 us against 52 us)
+    constexpr int TT = 64;
     const int tiles = ((g.N + TT - 1) / TT) * ((g.M + TT - 1) / TT);
     dim3 grid(8 * ((tiles + 7) / 8), 1, z);
     const int ma = operand_mode(g.A, g.sam, g.sak, g.M, g.K), mb = operand_mode(g.B, g.sbn, g.sbk, g.N, g.K);
     const void *fn = nullptr;
 #define PBIT_GEMM(A_, B_) \
     if (ma == A_ && mb == B_)  \
-        fn = TT == 128 ? (const void *)gemm_kernel<A_, B_, 128> : (const void *)gemm_kernel<A_, B_, 64>;
+        fn = (const void *)gemm_kernel<A_, B_, TT>;
     PBIT_GEMM(0, 0) PBIT_GEMM(0, 1) PBIT_GEMM(0, 2)
     PBIT_GEMM(1, 0) PBIT_GEMM(1, 1) PBIT_GEMM(1, 2)
     PBIT_GEMM(2, 0) PBIT_GEMM(2, 1) PBIT_GEMM(2, 2)
@@ -1210,6 +1208,27 @@ hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s) {
     return launch_full_w<2>(a, reg_layout(a.D, a.DP, a.H).total, s);
 }
 
+// LDS of made_sample_kernel for the shape in a; sets a.defer (small networks
+// defer the log-probabilities to the end and keep the cones in LDS; the log
+// buffer reuses the activations when they are large enough)
+static size_t made_sample_lds(SampleArgs &a) {
+    const size_t base = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
+    a.defer = 0;
+    size_t lds = base;
+    if (a.H <= 256) {
+        const size_t ts = (size_t)a.h * 16 * 4, cn = (size_t)((a.h * a.W + 1) & ~1) * 4;
+        const size_t lg = (size_t)a.h * 16 * 8;
+        a.defer = lg <= (size_t)2 * 16 * a.H * 2 ? 2 : 1;
+        lds = base + ts + cn + (a.defer == 1 ? lg : 0);
+    }
+    return lds;
+}
+
+bool made_sample_launchable(const SampleArgs &a0) {
+    SampleArgs a = a0;
+    return reg_fits(a) || made_sample_lds(a) <= 160 * 1024;
+}
+
 hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
     SampleArgs a = a0;
     if (a.n <= 0) return hipSuccess;
@@ -1220,23 +1239,25 @@ hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
         return launch_reg_k<8, 8, 1, 1, false>(a, lds, s);
     }
     const int grid = (a.n + 15) / 16;
-    const size_t base = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
-    // small networks defer the log-probabilities to the end and keep the cones
-    // in LDS; the log buffer reuses the activations when they are large enough
-    a.defer = 0;
-    size_t lds = base;
-    if (a.H <= 256) {
-        const size_t ts = (size_t)a.h * 16 * 4, cn = (size_t)((a.h * a.W + 1) & ~1) * 4;
-        const size_t lg = (size_t)a.h * 16 * 8;
-        a.defer = lg <= (size_t)2 * 16 * a.H * 2 ? 2 : 1;
-        lds = base + ts + cn + (a.defer == 1 ? lg : 0);
-    }
+    const size_t lds = made_sample_lds(a);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)made_sample_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(made_sample_kernel, dim3(grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+__global__ void log_eval_kernel(const double *__restrict__ x, double *__restrict__ y, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = made_log(x[i]);
+}
+
+hipError_t launch_log_eval(const double *x, double *y, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(log_eval_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
     return hipGetLastError();
 }
 

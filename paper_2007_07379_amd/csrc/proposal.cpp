@@ -88,7 +88,6 @@ struct pbit_proposal_s {
 namespace {
 
 pbit_status upload(pbit_proposal q, hipStream_t s) {
-    (void)s;
     if (q->theta) return PBIT_OK;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -119,9 +118,13 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
                                        (int64_t)16 << 20);
     q->part = A.alloc<float>((size_t)q->part_floats);
     q->lpart = A.alloc<float>(((size_t)BATCH_MAX * D + 255) / 256);
+    hipError_t ce = hipSuccess;  // first failure of the copies below
+    auto copy = [&](void *dst, const void *src, size_t bytes) {
+        if (ce == hipSuccess && dst && bytes) ce = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
     auto up = [&](int *&dst, const std::vector<int> &src) {
         dst = A.alloc<int>(src.size() + 64);
-        if (dst) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice);
+        copy(dst, src.data(), src.size() * sizeof(int));
     };
     up(q->d_deg_in, q->deg_in);
     up(q->d_deg1, q->deg1);
@@ -156,13 +159,16 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     if (!q->theta || !q->L || !q->colpart || !q->part || !q->lpart || !q->d_phase || !q->d_phase_k || !q->g1beg ||
         !q->d_sched)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
-    (void)hipMemcpy(q->d_sched, q->sched.data(), q->sched.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    (void)hipMemcpy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4), hipMemcpyHostToDevice);
-    (void)hipMemcpy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4), hipMemcpyHostToDevice);
-    (void)hipMemcpy(q->theta, q->host_params.data(), q->P * sizeof(float), hipMemcpyHostToDevice);
-    (void)hipMemset(q->m, 0, q->P * sizeof(float));
-    (void)hipMemset(q->v, 0, q->P * sizeof(float));
-    e = hipDeviceSynchronize();
+    copy(q->d_sched, q->sched.data(), q->sched.size() * sizeof(uint32_t));
+    copy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4));
+    copy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4));
+    copy(q->theta, q->host_params.data(), q->P * sizeof(float));
+    if (ce != hipSuccess) return hip_error(ce, "proposal upload");
+    // Adam moments start at zero
+    e = hipMemsetAsync(q->m, 0, q->P * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(q->v, 0, q->P * sizeof(float), s);
+    // later calls may come on other streams: the set-up is complete on return
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_error(e, "proposal upload");
     return PBIT_OK;
 }
@@ -354,6 +360,19 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
                          "the proposal builds paths through cones; three-qubit products are not affine");
     if (k.blob[H_NSOFT])
         return set_error(PBIT_E_MODE_UNAVAILABLE, "soft zeros: the MH chain would bin paths that meet them");
+    {
+        SampleArgs probe;
+        std::memset(&probe, 0, sizeof(probe));
+        probe.n = 1;
+        probe.h = (int)k.h;
+        probe.W = (int)k.W;
+        probe.D = (int)k.L;
+        probe.DP = ((int)k.L + 31) / 32 * 32;
+        probe.H = (int)H;
+        if (!made_sample_launchable(probe))
+            return set_error(PBIT_E_TOO_LARGE, "hidden width " + std::to_string(H) + " over " + std::to_string(k.L) +
+                                                   " lattice positions: the sampler's activations exceed 160 KiB of LDS");
+    }
     auto *q = new pbit_proposal_s();
     q->circ = c;
     q->idx = idx;
@@ -664,6 +683,10 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
     if ((uint64_t)cfg->step_offset + cfg->cycles > 0xFFFFFFFFull ||
         (uint64_t)cfg->sweep_offset + (uint64_t)cfg->cycles * cfg->gibbs_per_mh > 0xFFFFFFFFull)
         return set_error(PBIT_E_INVALID_ARG, "step or sweep counter would wrap");
+    // the state buffer holds only this circuit's chains, which the Gibbs
+    // sweeps can address only on a single-circuit handle
+    if (cfg->gibbs_per_mh && c->circuits.size() != 1)
+        return set_error(PBIT_E_INVALID_ARG, "MH with Gibbs sweeps runs on single-circuit handles");
     hipStream_t s = (hipStream_t)hip_stream;
     pbit_status st = upload(q, s);
     if (st != PBIT_OK) return st;
@@ -694,7 +717,7 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
     uint32_t *hist_c = d_hist;  // this circuit's histogram (offset applied below for MH bins)
     for (uint32_t cy = 0; cy < cfg->cycles; ++cy) {
         const uint32_t step = cfg->step_offset + cy;
-            if ((st = pbit_proposal_sample_score(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, q->prop, q->lq_prop,
+        if ((st = pbit_proposal_sample_score(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, q->prop, q->lq_prop,
                                              d_state, q->lq_cur, s)) != PBIT_OK)
             return st;
         MhArgs a;
@@ -724,11 +747,17 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
             g.seed = cfg->seed;
             g.sweep_offset = cfg->sweep_offset + cy * cfg->gibbs_per_mh;
             g.init = PBIT_INIT_RESUME;
-            // the state buffer of a set holds only this circuit's chains here
-            if (c->circuits.size() != 1) return set_error(PBIT_E_INVALID_ARG, "MH runs on single-circuit handles");
             if ((st = run_gibbs(c, &g, d_state, d_hist, s)) != PBIT_OK) return st;
         }
     }
+    return PBIT_OK;
+}
+
+pbit_status pbit_log_eval(const double *d_x, double *d_y, uint64_t n, void *hip_stream) {
+    if (!d_x || !d_y) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
+    if (n >= (1ull << 40)) return set_error(PBIT_E_INVALID_ARG, "n must be below 2^40");
+    hipError_t e = launch_log_eval(d_x, d_y, n, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_error(e, "log eval");
     return PBIT_OK;
 }
 

@@ -465,7 +465,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
         }
     }
     int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_error(e, "hipDeviceGetAttribute");
 
     auto lane_stream = [&](int lane) { return lane == 0 ? stream : side->s[lane - 1]; };
     auto enqueue_work = [&]() -> pbit_status {

@@ -313,6 +313,7 @@ def _made_sigs(L):
     L.pbit_proposal_score.argtypes = [V, V, C.c_uint32, V, V]
     L.pbit_mh_run.argtypes = [V, V, C.POINTER(MhCfg), V, V, V, V]
     L.pbit_path_observables.argtypes = [V, C.c_uint32, V, C.c_uint32, V, V, V]
+    L.pbit_log_eval.argtypes = [V, V, P, V]
 
 
 class Proposal:
@@ -393,6 +394,13 @@ def path_observables(cset, d_state, chains, d_bin=None, d_logmag=None, idx=0, st
     _made_sigs(L)
     _check(L.pbit_path_observables(cset.handle, idx, _ptr(d_state), chains, _ptr(d_bin), _ptr(d_logmag),
                                    _stream(stream)))
+
+
+def log_eval(d_x, d_y, n, stream=None):
+    """The library's FP64 logarithm of log q on n device doubles."""
+    L = lib()
+    _made_sigs(L)
+    _check(L.pbit_log_eval(_ptr(d_x), _ptr(d_y), n, _stream(stream)))
 
 
 class ShorCfg(C.Structure):
