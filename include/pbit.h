@@ -311,6 +311,23 @@ typedef struct {
 pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state,
                         uint32_t *d_hist, uint64_t *d_accepts, void *hip_stream);
 
+/* pbit_mh_run for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, and the same states, counts and accept counters bit for
+ * bit, but nothing is allocated, freed or compiled: the proposals x' and
+ * both log q live in one static device array of 16 MiB per device (held
+ * until the process ends), which bounds chains x (4 W + 16) bytes (W =
+ * lattice words, each of the three parts rounded up to 256 bytes: about
+ * 246,700 chains at W = 13, 699,000 at W = 2; PBIT_E_TOO_LARGE beyond), and the gibbs_per_mh sweeps take the generic
+ * (not circuit-specialised) kernels.  Set-up happens in
+ * pbit_proposal_create, which places the network, the circuit images and
+ * the array's address on the current device; calling on another device is
+ * PBIT_E_INVALID_ARG.  Every call on a device shares its array (each call
+ * writes all of it that it reads, so nothing carries over), so calls that
+ * overlap on one device race: serialise them on one stream. */
+pbit_status pbit_mh_run_static(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state,
+                               uint32_t *d_hist, uint64_t *d_accepts, void *hip_stream);
+
 /* Autotuner.  Times candidate launch shapes (workgroup size, histogram
  * privatisation, toggle tables, sweeps per launch, persistent grid size) on
  * short runs of cfg's workload on hip_stream and keeps the fastest per

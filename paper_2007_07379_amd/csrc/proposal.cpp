@@ -34,6 +34,32 @@ struct DeviceArena {
     }
 };
 
+// Scratch of pbit_mh_run_static (the one allocation-free entry point): the
+// proposals x', log q(x') and log q(x) of every chain, 4 W + 16 bytes a
+// chain.  One array per device, held until the process ends; its device
+// address comes from hipGetSymbolAddress (the array's name in host code is
+// only a host-side stand-in).  Every call on a device shares it.
+constexpr size_t MH_STATIC_BYTES = (size_t)16 << 20;
+constexpr int MH_STATIC_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[MH_STATIC_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MH_STATIC_DEVICES] = {};
+
+// Device address of `scratch` on device dev, which must be current.
+pbit_status static_scratch(int dev, void **out) {
+    if (dev < 0 || dev >= MH_STATIC_DEVICES) return set_error(PBIT_E_INVALID_ARG, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress of the MH scratch");
+        if (!p) return set_error(PBIT_E_DEVICE, "hipGetSymbolAddress returned no address for the MH scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PBIT_OK;
+}
+
 int64_t splitmix(uint64_t &s) {
     uint64_t z = (s += 0x9E3779B97F4A7C15ull);
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -439,6 +465,20 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
     init(q->oW1, D, (int)H, q->deg_in, q->deg1);
     init(q->oW2, (int)H, (int)H, q->deg1, q->deg2);
     init(q->oV, (int)H, D, q->deg2, q->deg_out);
+    // set-up on the current device: the network and its work buffers, the
+    // circuit images, and the address of the allocation-free MH scratch
+    pbit_status ps = upload(q, nullptr);
+    const uint32_t *dblob = nullptr;
+    if (ps == PBIT_OK) {
+        std::lock_guard<std::mutex> lock(c->mu);
+        ps = device_blobs(c, &dblob);
+    }
+    void *scr = nullptr;
+    if (ps == PBIT_OK) ps = static_scratch(q->dev, &scr);
+    if (ps != PBIT_OK) {
+        delete q;
+        return ps;
+    }
     *out = q;
     return PBIT_OK;
 }
@@ -670,8 +710,15 @@ pbit_status pbit_proposal_sample_score(pbit_proposal q, uint32_t n, uint32_t cha
     return pbit_proposal_score(q, d_cur, n, d_logq_cur, s);
 }
 
-pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
-                        uint64_t *d_accepts, void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// pbit_mh_run; with no_alloc (pbit_mh_run_static) the proposals and their
+// log q live in the device's static scratch and the Gibbs sweeps take the
+// generic kernels, so nothing is allocated or compiled.
+pbit_status mh_run_impl(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
+                        uint64_t *d_accepts, void *hip_stream, bool no_alloc) {
     if (!c || !q || !cfg || !d_state || !d_hist) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
     if (q->circ != c) return set_error(PBIT_E_INVALID_ARG, "proposal belongs to another circuit handle");
     if (cfg->init != PBIT_INIT_ZERO && cfg->init != PBIT_INIT_RESUME) return set_error(PBIT_E_INVALID_ARG, "bad init");
@@ -688,20 +735,43 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
     if (cfg->gibbs_per_mh && c->circuits.size() != 1)
         return set_error(PBIT_E_INVALID_ARG, "MH with Gibbs sweeps runs on single-circuit handles");
     hipStream_t s = (hipStream_t)hip_stream;
-    pbit_status st = upload(q, s);
-    if (st != PBIT_OK) return st;
+    uint32_t *prop = nullptr;
+    double *lq_cur = nullptr, *lq_prop = nullptr;
+    pbit_status st;
+    if (no_alloc) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+        if (!q->theta || dev != q->dev)
+            return set_error(PBIT_E_INVALID_ARG, "the proposal was set up on another device");
+        const size_t b_prop = ((size_t)n * q->W * sizeof(uint32_t) + 255) & ~(size_t)255;
+        const size_t b_lq = ((size_t)n * sizeof(double) + 255) & ~(size_t)255;
+        if (b_prop + 2 * b_lq > MH_STATIC_BYTES)
+            return set_error(PBIT_E_TOO_LARGE, "chains x (4 W + 16) bytes exceed the 16 MiB static MH scratch");
+        void *base = nullptr;
+        if ((st = static_scratch(dev, &base)) != PBIT_OK) return st;
+        prop = (uint32_t *)base;
+        lq_cur = (double *)((unsigned char *)base + b_prop);
+        lq_prop = (double *)((unsigned char *)base + b_prop + b_lq);
+    }
+    if ((st = upload(q, s)) != PBIT_OK) return st;
     if ((st = refresh(q, s)) != PBIT_OK) return st;
-    if (q->mh_cap < n) {
-        q->prop = q->arena.alloc<uint32_t>((size_t)n * q->W);
-        q->lq_cur = q->arena.alloc<double>(n);
-        q->lq_prop = q->arena.alloc<double>(n);
-        if (!q->prop || !q->lq_cur || !q->lq_prop) return set_error(PBIT_E_OOM, "MH workspace");
-        q->mh_cap = (uint32_t)n;
+    if (!no_alloc) {
+        if (q->mh_cap < n) {
+            q->prop = q->arena.alloc<uint32_t>((size_t)n * q->W);
+            q->lq_cur = q->arena.alloc<double>(n);
+            q->lq_prop = q->arena.alloc<double>(n);
+            if (!q->prop || !q->lq_cur || !q->lq_prop) return set_error(PBIT_E_OOM, "MH workspace");
+            q->mh_cap = (uint32_t)n;
+        }
+        prop = q->prop;
+        lq_cur = q->lq_cur;
+        lq_prop = q->lq_prop;
     }
     const uint32_t *dblob = nullptr;
     {
         std::lock_guard<std::mutex> lock(c->mu);
-        if ((st = device_blobs(c, &dblob)) != PBIT_OK) return st;
+        if ((st = device_blobs(c, &dblob, no_alloc)) != PBIT_OK) return st;
     }
     const uint32_t *blob = dblob + c->blob_off[q->idx];
     const CompiledCircuit &k = c->circuits[q->idx];
@@ -714,21 +784,22 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
     }
     std::vector<uint32_t> chains(c->circuits.size(), 0u);
     chains[q->idx] = (uint32_t)n;
-    uint32_t *hist_c = d_hist;  // this circuit's histogram (offset applied below for MH bins)
     for (uint32_t cy = 0; cy < cfg->cycles; ++cy) {
         const uint32_t step = cfg->step_offset + cy;
-        if ((st = pbit_proposal_sample_score(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, q->prop, q->lq_prop,
-                                             d_state, q->lq_cur, s)) != PBIT_OK)
+        // every proposal and both log q are written before they are read:
+        // nothing of the scratch needs clearing
+        if ((st = pbit_proposal_sample_score(q, (uint32_t)n, cfg->chain_begin, cfg->seed, step, prop, lq_prop, d_state,
+                                             lq_cur, s)) != PBIT_OK)
             return st;
         MhArgs a;
         std::memset(&a, 0, sizeof(a));
         a.blob = blob;
         a.state = d_state;
-        a.prop = q->prop;
-        a.logq_cur = q->lq_cur;
-        a.logq_prop = q->lq_prop;
+        a.prop = prop;
+        a.logq_cur = lq_cur;
+        a.logq_prop = lq_prop;
         a.accepts = (unsigned long long *)d_accepts;
-        a.hist = hist_c + c->hist_off[q->idx];
+        a.hist = d_hist + c->hist_off[q->idx];
         a.n = (int)n;
         a.W = (int)k.W;
         a.chain_begin = cfg->chain_begin;
@@ -747,10 +818,24 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
             g.seed = cfg->seed;
             g.sweep_offset = cfg->sweep_offset + cy * cfg->gibbs_per_mh;
             g.init = PBIT_INIT_RESUME;
-            if ((st = run_gibbs(c, &g, d_state, d_hist, s)) != PBIT_OK) return st;
+            if ((st = run_gibbs(c, &g, d_state, d_hist, s, no_alloc)) != PBIT_OK) return st;
         }
     }
     return PBIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
+                        uint64_t *d_accepts, void *hip_stream) {
+    return mh_run_impl(c, q, cfg, d_state, d_hist, d_accepts, hip_stream, false);
+}
+
+pbit_status pbit_mh_run_static(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state,
+                               uint32_t *d_hist, uint64_t *d_accepts, void *hip_stream) {
+    return mh_run_impl(c, q, cfg, d_state, d_hist, d_accepts, hip_stream, true);
 }
 
 pbit_status pbit_log_eval(const double *d_x, double *d_y, uint64_t n, void *hip_stream) {

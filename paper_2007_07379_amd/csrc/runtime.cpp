@@ -74,12 +74,13 @@ pbit_status ensure_buf(std::map<int, DevBuf> &m, int dev, size_t bytes, void **o
 
 }  // namespace
 
-pbit_status device_blobs(pbit_circuit c, const uint32_t **base) {
+pbit_status device_blobs(pbit_circuit c, const uint32_t **base, bool no_alloc) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_error(e, "hipGetDevice");
     auto it = c->blobs.find(dev);
     if (it == c->blobs.end() || !it->second.ptr) {
+        if (no_alloc) return set_error(PBIT_E_INVALID_ARG, "circuit images are not resident on this device");
         std::vector<uint32_t> all;
         c->blob_off.clear();
         for (auto &k : c->circuits) {
@@ -134,9 +135,20 @@ bool runs_batched(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg, const s
     return batchable(c, i, cfg) && !spec[i];
 }
 
-pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
-                      hipStream_t stream) {
-    if (!c || !cfg || !cfg->chains) return set_error(PBIT_E_INVALID_ARG, "NULL handle, cfg or chains");
+pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_state, uint32_t *d_hist,
+                      hipStream_t stream, bool no_alloc) {
+    if (!c || !cfg_in || !cfg_in->chains) return set_error(PBIT_E_INVALID_ARG, "NULL handle, cfg or chains");
+    pbit_gibbs_cfg cfg_na;
+    const pbit_gibbs_cfg *cfg = cfg_in;
+    if (no_alloc) {
+        // the generic kernels only: a circuit-specialised kernel may need a
+        // run-time compile or a key buffer
+        cfg_na = *cfg_in;
+        cfg_na.specialize = 1;
+        cfg = &cfg_na;
+        if (!d_state) return set_error(PBIT_E_INVALID_ARG, "an allocation-free run needs d_state");
+        if (cfg->use_graph) return set_error(PBIT_E_INVALID_ARG, "an allocation-free run cannot capture a graph");
+    }
     if (!d_hist) return set_error(PBIT_E_INVALID_ARG, "d_hist is NULL");
     if (cfg->init != PBIT_INIT_ZERO && cfg->init != PBIT_INIT_RESUME)
         return set_error(PBIT_E_INVALID_ARG, "bad init mode");
@@ -176,7 +188,7 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_error(e, "hipGetDevice");
     const uint32_t *dblob = nullptr;
-    pbit_status st = device_blobs(c, &dblob);
+    pbit_status st = device_blobs(c, &dblob, no_alloc);
     if (st != PBIT_OK) return st;
 
     // ---- plan (every argument error before any enqueue) --------------------
@@ -399,6 +411,9 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_sta
             for (Plan &p : plans) p.lane = lane_of[p.circ];
         }
     }
+    if (no_alloc && (fork || keys_words || !bcirc.empty()))
+        return set_error(PBIT_E_INVALID_ARG,
+                         "an allocation-free run takes single-circuit launches of the generic kernels");
     SideStreams *side = nullptr;
     if (fork && (st = ensure_side(c->side, dev, &side)) != PBIT_OK) return st;
 

@@ -86,10 +86,14 @@ struct pbit_circuit_s {
 
 namespace pbit {
 
+// With no_alloc the run allocates no device memory and compiles nothing: it
+// takes the generic kernels, needs the images resident and d_state, and
+// refuses runs that would need library buffers, side streams or a graph.
 pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
-                      hipStream_t stream);
+                      hipStream_t stream, bool no_alloc = false);
 
-// Device image of every circuit of the handle on the current device.
-pbit_status device_blobs(pbit_circuit c, const uint32_t **base);
+// Device image of every circuit of the handle on the current device
+// (uploaded on first use; with no_alloc an error if it is not resident).
+pbit_status device_blobs(pbit_circuit c, const uint32_t **base, bool no_alloc = false);
 
 }  // namespace pbit

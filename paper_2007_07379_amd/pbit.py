@@ -312,6 +312,7 @@ def _made_sigs(L):
     L.pbit_proposal_sample_score.argtypes = [V, C.c_uint32, C.c_uint32, P, C.c_uint32, V, V, V, V, V]
     L.pbit_proposal_score.argtypes = [V, V, C.c_uint32, V, V]
     L.pbit_mh_run.argtypes = [V, V, C.POINTER(MhCfg), V, V, V, V]
+    L.pbit_mh_run_static.argtypes = [V, V, C.POINTER(MhCfg), V, V, V, V]
     L.pbit_path_observables.argtypes = [V, C.c_uint32, V, C.c_uint32, V, V, V]
     L.pbit_log_eval.argtypes = [V, V, P, V]
 
@@ -385,6 +386,18 @@ def mh_run(cset, proposal, chains, cycles, d_state, d_hist, d_accepts=None, gibb
     _made_sigs(L)
     _check(L.pbit_mh_run(cset.handle, proposal.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
                          _ptr(d_accepts), _stream(stream)))
+
+
+def mh_run_static(cset, proposal, chains, cycles, d_state, d_hist, d_accepts=None, gibbs_per_mh=4, seed=0,
+                  step_offset=0, sweep_offset=0, resume=False, chain_begin=0, stream=None):
+    """pbit_mh_run_static: mh_run with the proposals in the library's static
+    device array (no allocation; at most 16 MiB of chains x (4 W + 16) bytes)."""
+    cfg = MhCfg(chains, chain_begin, cycles, gibbs_per_mh, seed, step_offset, sweep_offset,
+                INIT_RESUME if resume else INIT_ZERO)
+    L = lib()
+    _made_sigs(L)
+    _check(L.pbit_mh_run_static(cset.handle, proposal.handle, C.byref(cfg), _ptr(d_state), _ptr(d_hist),
+                                _ptr(d_accepts), _stream(stream)))
 
 
 def path_observables(cset, d_state, chains, d_bin=None, d_logmag=None, idx=0, stream=None):
