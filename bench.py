@@ -355,6 +355,70 @@ def mh_mode(args):
     print(json.dumps(out))
 
 
+def masked_weight_counts(D, H):
+    """Unmasked weights of the three products of a D-position, H-wide MADE
+    (degrees as in the network definition)."""
+    din = np.arange(1, D + 1)
+    dh = 1 + (np.arange(H) * (D - 1)) // H
+    dout = np.arange(D)
+    return (int((din[:, None] <= dh[None, :]).sum()), int((dh[:, None] <= dh[None, :]).sum()),
+            int((dh[:, None] <= dout[None, :]).sum()))
+
+
+def sample_mode(args):
+    """The learned proposal's MH-step network work on its own: drawing
+    `chains` proposals (pbit_proposal_sample) and scoring the chains' current
+    paths (pbit_proposal_score), as one MH step of pbit_mh_run does, at the
+    workload's network shape.  The MFMA roofline counts one masked forward
+    (2 FLOP per unmasked weight) per path drawn or scored."""
+    import torch
+    from paper_2007_07379_amd import pbit
+    from workloads import circuits as wc
+    cfg = MH_WORKLOADS[args.workload]
+    c = cfg["circuit"](wc)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    H = args.hidden or cfg["hidden"]
+    n = cfg["chains"]
+    q = pbit.Proposal(s, hidden=H, seed=3)
+    D, W = q.D, info["W"]
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(n * W, dtype=torch.int32, device="cuda")
+    lq = torch.zeros(n, dtype=torch.float64, device="cuda")
+    cur = torch.zeros(n * W, dtype=torch.int32, device="cuda")
+    lqc = torch.zeros(n, dtype=torch.float64, device="cuda")
+    q.sample(n, cur, lqc, seed=1, step=0, stream=stream)  # valid current paths
+    for _ in range(max(args.warmup, 1)):
+        q.sample(n, out, lq, seed=2, step=1, stream=stream)
+        q.score(cur, n, lqc, stream=stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        q.sample(n, out, lq, seed=2, step=2 + i, stream=stream)
+        ev[i][1].record(stream)
+        q.score(cur, n, lqc, stream=stream)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    t_s = float(np.mean([e[0].elapsed_time(e[1]) for e in ev])) / 1e3
+    t_c = float(np.mean([e[1].elapsed_time(e[2]) for e in ev])) / 1e3
+    n1, n2, n3 = masked_weight_counts(D, H)
+    flops = 2.0 * (n1 + n2 + n3) * n
+    print(json.dumps({
+        "metric": "proposals/s (MADE sampler)", "value": n / t_s, "unit": "proposals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": (t_s + t_c) * 1e3, "higher_is_better": True,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "%s network: D=%d positions, two masked hidden layers of %d, %d chains (h=%d free)"
+                               % (args.workload, D, H, n, info["h"])},
+        "sample_ms": t_s * 1e3, "score_ms": t_c * 1e3,
+        "roofline_sample": {"bound": "mfma", "achieved": flops / t_s / 1e12, "peak": BF16_PEAK / 1e12,
+                            "unit": "TFLOP/s", "frac": flops / t_s / BF16_PEAK, "traffic": None,
+                            "flops_per_proposal": 2.0 * (n1 + n2 + n3)},
+        "roofline_score": {"bound": "mfma", "achieved": flops / t_c / 1e12, "peak": BF16_PEAK / 1e12,
+                           "unit": "TFLOP/s", "frac": flops / t_c / BF16_PEAK, "traffic": None},
+    }))
+
+
 def gibbs_ess(torch, pbit, s, info, c, chains, sweeps, step_s, hist_total, tau_chains=4096):
     """tau_int of plain Gibbs on the timed workload (largest over the output
     parities, cos/sin of the phase and ln|psi| of tau_chains chains after
@@ -411,12 +475,7 @@ def train_mode(args):
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) / 1e3
     # unmasked weights (degrees as in the network definition)
-    din = np.arange(1, D + 1)
-    dh = 1 + (np.arange(H) * (D - 1)) // H
-    dout = np.arange(D)
-    n1 = int((din[:, None] <= dh[None, :]).sum())
-    n2 = int((dh[:, None] <= dh[None, :]).sum())
-    n3 = int((dh[:, None] <= dout[None, :]).sum())
+    n1, n2, n3 = masked_weight_counts(D, H)
     # forward (3 products), weight gradients (3), input gradients of the two
     # hidden layers (2): 2 FLOP per multiply-add
     flops_step = 2 * batch * (3 * (n1 + n2 + n3) - n1)
@@ -535,6 +594,9 @@ MEASURED_TRAFFIC = {
     ("pbit_uniform_sweep (generated for the circuit, 4 lanes per chain)", "rct12"):
         ("2e84765c6595369e", ('jit.cpp', 'jit.h', 'compile.cpp', 'blob.h'), 132 * 1024 * 2, 36864 * 1024 * 1),
     ("gibbs_pair_kernel<16>", "rct12"): ("1cc1ef522bb50502", ('gibbs_pair.hip', 'philox.h', 'blob.h', 'gibbs.h'), 157.5 * 1024 * 2, 36864 * 1024 * 1),
+    # the 2^24-bin histogram's atomics, 32 bytes each (profiles/pbit_uniform_sweep_brick20_pmc.md)
+    ("pbit_uniform_sweep (generated for the circuit, 1 lanes per chain)", "brick20"):
+        ("80b38edd2421fbcf", ('jit.cpp', 'jit.h', 'compile.cpp', 'blob.h'), 170.797 * 1024 * 2, 8.19354e7 * 1024 * 1),
 }
 
 
@@ -620,7 +682,7 @@ def main():
     ap.add_argument("--no-ess", action="store_true", help="gibbs mode: skip tau_int / ESS and the MH comparison")
     ap.add_argument("--mh-workload", default="rhchain48_pi256",
                     help="gibbs mode: workload of the learned-proposal comparison ('' to skip)")
-    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train", "shor"])
+    ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train", "shor", "sample"])
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--specialize", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--hist-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
@@ -644,6 +706,11 @@ def main():
         if args.workload not in SHOR_WORKLOADS:
             args.workload = "shor27"
         shor_mode(args)
+        return
+    if args.mode == "sample":
+        if args.workload not in MH_WORKLOADS:
+            args.workload = "brick16"
+        sample_mode(args)
         return
     if args.mode == "mh":
         if args.workload not in MH_WORKLOADS:

@@ -478,3 +478,117 @@ def test_library_log_within_one_ulp(env):
     assert np.all(np.isfinite(y))
     assert float(err.max()) <= 2.0
     assert np.all(y[x == 1.0] == 0.0)
+
+
+def _tau_int(torch, series):
+    """tau_int of a [steps, chains] float tensor on the GPU: chain-pooled
+    autocovariance by FFT, Geyer's initial positive sequence; None for a
+    constant series."""
+    x = series - series.mean()
+    S = x.shape[0]
+    f = torch.fft.rfft(x, n=2 * S, dim=0)
+    acov = torch.fft.irfft((f * f.conj()).real.sum(dim=1), n=2 * S)[:S] / (
+        x.shape[1] * torch.arange(S, 0, -1, device=x.device, dtype=x.dtype))
+    if not float(acov[0]) > 1e-12:
+        return None
+    rho = (acov / acov[0]).cpu().numpy()
+    tau, k = -1.0, 0
+    while 2 * k + 1 < S // 2:
+        g = rho[2 * k] + rho[2 * k + 1]
+        if g <= 0:
+            break
+        tau += 2 * g
+        k += 1
+    return float(tau)
+
+
+def _observe(env, s, state, chains):
+    """[n_obs, chains]: the output alpha as +-1, cos of the phase, ln|psi|."""
+    torch, pbit = env
+    d_bin = torch.empty(chains, dtype=torch.int32, device="cuda")
+    d_lm = torch.empty(chains, dtype=torch.float64, device="cuda")
+    pbit.path_observables(s, state, chains, d_bin, d_lm)
+    b = d_bin.to(torch.int64)
+    K = s.info(0)["K"]
+    alpha, phi = b >> K, b & ((1 << K) - 1)
+    return torch.stack([(1 - 2 * alpha).double(), torch.cos(phi.double() * (2 * math.pi / (1 << K))), d_lm])
+
+
+def test_trained_proposal_beats_gibbs_and_the_untrained_proposal(env):
+    """What the trained network gains (the rotated-Hadamard chain of Eq.
+    (HadT), d = 48, theta = pi/128, whose path law makes single-site Gibbs
+    slow): trained on Gibbs samples on the GPU, MH (1 MH step : 4 Gibbs
+    sweeps) decorrelates at least 10 times faster per transition than plain
+    Gibbs per sweep and at least 5 times faster than the same MH with the
+    untrained (zero-weight, uniform) proposal, whose proposals are almost
+    never accepted; long runs of all three keep TV_path <= 0.01."""
+    torch, pbit = env
+    c = wc.rotated_hadamard_chain(48, math.pi / 128, K=1)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    W = info["W"]
+    tc, burn, G = 4096, 8192, 4
+    hist = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    pm, _ = exact.magnitude_marginal(oc.from_dict(c))
+
+    def series(advance, state, L):
+        out = []
+        for t in range(L):
+            advance(t)
+            out.append(_observe(env, s, state, tc).float())
+        a = torch.stack(out)  # [L, n_obs, chains] on the GPU
+        taus = [_tau_int(torch, a[:, o, :]) for o in range(a.shape[1])]
+        return max(t for t in taus if t is not None), taus
+
+    # plain Gibbs: one sweep per transition
+    st = torch.zeros(tc * W, dtype=torch.int32, device="cuda")
+    s.gibbs_run([tc], burn, 0, hist, st, seed=11)
+    tau_g, taus_g = series(lambda t: s.gibbs_run([tc], 0, 1, hist, st, seed=11, sweep_offset=burn + t, resume=True),
+                           st, 16384)
+    say("Gibbs tau_int per sweep", tau_g, taus_g)
+    # training set: independent chains after the burn-in
+    ntrain = 1 << 18
+    train = torch.zeros(ntrain * W, dtype=torch.int32, device="cuda")
+    s.gibbs_run([ntrain], burn, 1, torch.zeros_like(hist), train, seed=7)
+    trained = pbit.Proposal(s, hidden=128, seed=3)
+    losses = trained.train(train, ntrain, 4096, 1500)
+    say("loss", float(losses[:5].mean()), "->", float(losses[-20:].mean()))
+    untrained = pbit.Proposal(s, hidden=128, seed=3)
+    untrained.set_params(np.zeros(untrained.n_params, dtype=np.float32))
+
+    def mh_tau(q, seed, L):
+        st = torch.zeros(tc * W, dtype=torch.int32, device="cuda")
+        s.gibbs_run([tc], burn, 0, hist, st, seed=seed)
+        acc = torch.zeros(tc, dtype=torch.int64, device="cuda")
+
+        def adv(t):
+            cy, r = divmod(t, 1 + G)
+            if r == 0:
+                pbit.mh_run(s, q, tc, 1, st, hist, acc, gibbs_per_mh=0, seed=seed, step_offset=cy, resume=True)
+            else:
+                s.gibbs_run([tc], 0, 1, hist, st, seed=seed, sweep_offset=(1 << 30) + cy * G + r - 1, resume=True)
+        tau, taus = series(adv, st, L)
+        return tau, taus, float(acc.double().mean()) / ((L + G) // (1 + G))
+
+    tau_m, taus_m, acc_m = mh_tau(trained, 12, 2048)
+    tau_u, taus_u, acc_u = mh_tau(untrained, 13, 4096)
+    say("MH trained: tau_int per transition", tau_m, taus_m, "accept", acc_m)
+    say("MH untrained: tau_int per transition", tau_u, taus_u, "accept", acc_u)
+    assert tau_m * 10 <= tau_g
+    assert tau_m * 5 <= tau_u
+    assert acc_m > 0.3 and acc_m > 20 * acc_u
+    # long runs of 131,072 chains: TV of the output marginal
+    chains, cycles = 131072, 100
+    for name, run in [("gibbs", lambda h, st: s.gibbs_run([chains], 0, cycles * (1 + G), h, st, seed=1,
+                                                          sweep_offset=burn, resume=True)),
+                      ("mh", lambda h, st: pbit.mh_run(s, trained, chains, cycles, st, h, None, gibbs_per_mh=G,
+                                                       seed=2, resume=True))]:
+        st = torch.zeros(chains * W, dtype=torch.int32, device="cuda")
+        h = torch.zeros_like(hist)
+        s.gibbs_run([chains], burn, 0, h, st, seed=1)
+        run(h, st)
+        torch.cuda.synchronize()
+        hh = h.cpu().numpy().view(np.uint32).astype(np.uint64).reshape(1 << info["n"], 1 << info["K"])
+        tv = oest.tv_path(hh, pm)
+        say(name, "TV_path", tv, "samples", int(hh.sum()))
+        assert tv <= 0.01
