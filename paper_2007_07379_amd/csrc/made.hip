@@ -638,10 +638,14 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int CS = 16;
     const int DP = a.DP, H = a.H, W = a.W, h = a.h;
-    bf16 *Xs = reinterpret_cast<bf16 *>(smem);           // [CS][DP]
-    bf16 *H1s = Xs + CS * DP;                             // [CS][H]
-    bf16 *H2s = H1s + CS * H;                             // [CS][H]
-    float *logit = reinterpret_cast<float *>(H2s + CS * H);  // [CS]
+    // LDS rows padded by 8 elements (16 bytes): rows of 1,024 bf16 are a
+    // multiple of the 64 four-byte banks, and the 16 rows a half tile reads
+    // at once would otherwise sit on one bank
+    const int XS = DP + 8, HS = H + 8;
+    bf16 *Xs = reinterpret_cast<bf16 *>(smem);           // [CS][XS]
+    bf16 *H1s = Xs + CS * XS;                             // [CS][HS]
+    bf16 *H2s = H1s + CS * HS;                             // [CS][HS]
+    float *logit = reinterpret_cast<float *>(H2s + CS * HS);  // [CS]
     uint32_t *lat = reinterpret_cast<uint32_t *>(logit + CS);  // [CS][W]
     uint32_t *Ts = lat + CS * W;                          // deferred: [h][CS] thresholds
     uint32_t *cones = Ts + (a.defer ? h * CS : 0);        // deferred: [h][W] cone words
@@ -656,11 +660,11 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
     const uint32_t WS = B[H_WS];
     const uint32_t cid = B[H_CID];
 
-    for (int e = lane; e < CS * DP; e += 64) {
-        const int i = e % DP;
+    for (int e = lane; e < CS * XS; e += 64) {
+        const int i = e % XS;
         Xs[e] = (bf16)((i < a.D) ? (float)((cw[i >> 5] >> (i & 31)) & 1u) : 0.f);
     }
-    for (int e = lane; e < 2 * CS * H; e += 64) H1s[e] = (bf16)0.f;
+    for (int e = lane; e < 2 * CS * HS; e += 64) H1s[e] = (bf16)0.f;
     for (int e = lane; e < CS * W; e += 64) lat[e] = cw[e % W];
     if (a.defer)
         for (int e = lane; e < h * W; e += 64) cones[e] = cone_g[(int64_t)(e / W) * WS + e % W];
@@ -675,14 +679,14 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
         // (a) first-layer units whose degree became <= p
         for (int u0 = ph.x; u0 < ph.y; u0 += 16) {
             const int u = min(u0 + row, H - 1);
-            const f32x4 acc = mfma_chunks(Xs + row * DP + kq, a.W1T + (int64_t)u * DP + kq, (kk.x + 31) / 32);
+            const f32x4 acc = mfma_chunks(Xs + row * XS + kq, a.W1T + (int64_t)u * DP + kq, (kk.x + 31) / 32);
             const int un = u0 + row;
             if (un < ph.y) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float v = acc[e] + a.b1[un];
                     v = v > 0.f ? v : 0.f;
-                    H1s[((lane >> 4) * 4 + e) * H + un] = (bf16)v;
+                    H1s[((lane >> 4) * 4 + e) * HS + un] = (bf16)v;
                 }
             }
         }
@@ -690,21 +694,21 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
         // (b) second-layer units whose degree became <= p
         for (int u0 = ph.z; u0 < ph.w; u0 += 16) {
             const int u = min(u0 + row, H - 1);
-            const f32x4 acc = mfma_chunks(H1s + row * H + kq, a.W2T + (int64_t)u * H + kq, (kk.y + 31) / 32);
+            const f32x4 acc = mfma_chunks(H1s + row * HS + kq, a.W2T + (int64_t)u * H + kq, (kk.y + 31) / 32);
             const int un = u0 + row;
             if (un < ph.w) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float v = acc[e] + a.b2[un];
                     v = v > 0.f ? v : 0.f;
-                    H2s[((lane >> 4) * 4 + e) * H + un] = (bf16)v;
+                    H2s[((lane >> 4) * 4 + e) * HS + un] = (bf16)v;
                 }
             }
         }
         __syncthreads();
         // (c) logit of position p (every column of the tile computes it)
         {
-            const f32x4 acc = mfma_chunks(H2s + row * H + kq, a.VT + (int64_t)p * H + kq, (kk.z + 31) / 32);
+            const f32x4 acc = mfma_chunks(H2s + row * HS + kq, a.VT + (int64_t)p * H + kq, (kk.z + 31) / 32);
             if (row == 0) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) logit[(lane >> 4) * 4 + e] = acc[e] + a.c[p];
@@ -744,8 +748,8 @@ __global__ __launch_bounds__(64) void made_sample_kernel(SampleArgs a) {
                         while (mw) {
                             const int i = 32 * w + __builtin_ctz(mw);
                             mw &= mw - 1;
-                            const float xv = (float)Xs[lane * DP + i];
-                            Xs[lane * DP + i] = (bf16)(1.f - xv);
+                            const float xv = (float)Xs[lane * XS + i];
+                            Xs[lane * XS + i] = (bf16)(1.f - xv);
                         }
                     }
                 }
@@ -1212,7 +1216,7 @@ hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s) {
 // defer the log-probabilities to the end and keep the cones in LDS; the log
 // buffer reuses the activations when they are large enough)
 static size_t made_sample_lds(SampleArgs &a) {
-    const size_t base = (size_t)16 * a.DP * 2 + (size_t)2 * 16 * a.H * 2 + 16 * 4 + (size_t)16 * a.W * 4;
+    const size_t base = (size_t)16 * (a.DP + 8) * 2 + (size_t)2 * 16 * (a.H + 8) * 2 + 16 * 4 + (size_t)16 * a.W * 4;
     a.defer = 0;
     size_t lds = base;
     if (a.H <= 256) {
