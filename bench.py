@@ -627,15 +627,21 @@ def batch_mode(args):
     for i, ch in enumerate(chains):
         ps, pa, _ = algorithmic_ops(s.export(i))
         ops += ch * ((burn + sweeps) * ps + sweeps * pa)
-    stream = torch.cuda.current_stream()
+    # the run is captured once into a hipGraph (on a stream of its own: a
+    # graph needs a non-null stream) and replayed by the timed steps
+    stream = torch.cuda.Stream()
     hist = torch.zeros(s.hist_bins(), dtype=torch.int32, device="cuda")
     state = torch.zeros(s.state_words(chains), dtype=torch.int32, device="cuda")
-    kw = dict(persistent=1, specialize=args.specialize)
+    kw = dict(persistent=1, specialize=args.specialize, use_graph=not args.no_graph)
     kinds = [s.launch_shape(chains, burn, sweeps, idx=i, **kw)["kernel"] for i in range(len(circs))]
     n_spec = sum(1 for k in kinds if k == pbit.KERNEL_SPECIALISED)
     t0 = time.perf_counter()
-    for _ in range(max(args.warmup, 1)):  # the first run compiles any specialised kernels
-        hist.zero_()
+    # the first run compiles the specialised kernels (on host threads) and
+    # captures the graph
+    s.gibbs_run(chains, burn, sweeps, hist, state, seed=0, stream=stream, **kw)
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    for _ in range(max(args.warmup, 1) - 1):
         s.gibbs_run(chains, burn, sweeps, hist, state, seed=0, stream=stream, **kw)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
@@ -666,6 +672,9 @@ def batch_mode(args):
                                 "for the rest" % n_spec),
                      "kernel_ms": kernel_s * 1e3},
         "warmup_s": t_warm,
+        "first_run_s": t_first,
+        "specialised_circuits": n_spec,
+        "graph": bool(kw["use_graph"]),
     }
     print(json.dumps(out))
 
@@ -685,6 +694,7 @@ def main():
     ap.add_argument("--mode", default="gibbs", choices=["gibbs", "mh", "copy", "train", "shor", "sample"])
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--specialize", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--no-graph", action="store_true", help="batch256: enqueue each run instead of a graph replay")
     ap.add_argument("--hist-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="histogram placement (pbit_gibbs_cfg.hist_mode), gibbs mode")
     ap.add_argument("--gibbs-per-mh", type=int, default=4)

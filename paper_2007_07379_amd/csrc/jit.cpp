@@ -24,6 +24,8 @@
 
 #include <cstdio>
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <sstream>
 
 #include "blob.h"
@@ -499,12 +501,45 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     return out;
 }
 
-bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
+namespace {
+
+// Code objects by (target, source): the kernels generated for equal circuit
+// images are the same text, so a compile is done once per process whatever
+// handle asks for it.
+std::mutex g_code_mu;
+std::map<std::string, std::shared_ptr<const std::vector<char>>> g_code;
+
+uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull) {
+    for (unsigned char c : s) h = (h ^ c) * 1099511628211ull;
+    return h;
+}
+
+}  // namespace
+
+bool jit_arch(std::string *arch, std::string *log) {
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
         *log = "no device";
         return false;
+    }
+    *arch = prop.gcnArchName;
+    return true;
+}
+
+bool jit_compile(const JitSource &src, const std::string &arch, std::shared_ptr<const std::vector<char>> *code,
+                 std::string *log) {
+    // key: the target, the entry and the source text (with its length, so
+    // the FNV-1a digest alone never decides equality)
+    const std::string key = arch + "|" + src.entry + "|" + std::to_string(src.text.size()) + "|" +
+                            std::to_string(fnv1a(src.text));
+    {
+        std::lock_guard<std::mutex> lock(g_code_mu);
+        auto it = g_code.find(key);
+        if (it != g_code.end()) {
+            *code = it->second;
+            return true;
+        }
     }
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.text.c_str(), (src.entry + ".hip").c_str(), 0, nullptr, nullptr) !=
@@ -512,8 +547,8 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
         *log = "hiprtcCreateProgram failed";
         return false;
     }
-    const std::string arch = std::string("--gpu-architecture=") + prop.gcnArchName;
-    const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+    const std::string archopt = std::string("--gpu-architecture=") + arch;
+    const char *opts[] = {archopt.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
                           "-packed-fp32-ops"};
     const hiprtcResult rc = hiprtcCompileProgram(prog, 7, opts);
     size_t ls = 0;
@@ -526,17 +561,26 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
         return false;
     }
     size_t cs = 0;
-    std::vector<char> code;
+    auto out = std::make_shared<std::vector<char>>();
     bool got = hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs > 0;
     if (got) {
-        code.resize(cs);
-        got = hiprtcGetCode(prog, code.data()) == HIPRTC_SUCCESS;
+        out->resize(cs);
+        got = hiprtcGetCode(prog, out->data()) == HIPRTC_SUCCESS;
     }
     (void)hiprtcDestroyProgram(&prog);
     if (!got) {
         *log = "hipRTC produced no code object";
         return false;
     }
+    {
+        std::lock_guard<std::mutex> lock(g_code_mu);
+        auto it = g_code.emplace(key, out).first;  // a concurrent compile of the same text may have won
+        *code = it->second;
+    }
+    return true;
+}
+
+bool jit_load(const JitSource &src, const std::vector<char> &code, JitKernel *out, std::string *log) {
     hipModule_t mod = nullptr;
     hipError_t e = hipModuleLoadData(&mod, code.data());
     if (e != hipSuccess) {
@@ -562,6 +606,66 @@ bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
     out->lds_bytes = src.lds_bytes;
     out->max_block = src.max_block;
     out->scratch_bytes = scratch;
+    return true;
+}
+
+bool jit_build(const JitSource &src, JitKernel *out, std::string *log) {
+    std::string arch;
+    std::shared_ptr<const std::vector<char>> code;
+    return jit_arch(&arch, log) && jit_compile(src, arch, &code, log) && jit_load(src, *code, out, log);
+}
+
+bool jit_build_group(const std::vector<const JitSource *> &srcs, hipModule_t *module, std::vector<JitKernel> *out,
+                     std::string *log) {
+    *module = nullptr;
+    out->assign(srcs.size(), JitKernel());
+    if (srcs.empty()) return true;
+    std::string arch;
+    if (!jit_arch(&arch, log)) return false;
+    // kernel j: its source in a namespace of its own (helpers and tables keep
+    // their names), its extern "C" entry renamed to <entry>_g<j>
+    JitSource all;
+    all.entry = "pbit_group";
+    std::vector<std::string> names(srcs.size());
+    for (size_t j = 0; j < srcs.size(); ++j) {
+        std::string text = srcs[j]->text;
+        const std::string decl = " " + srcs[j]->entry + "(";
+        const size_t at = text.find(decl);
+        if (at == std::string::npos || text.find(decl, at + 1) != std::string::npos) {
+            *log = "generated source without a unique entry declaration";
+            return false;
+        }
+        names[j] = srcs[j]->entry + "_g" + std::to_string(j);
+        text.replace(at, decl.size(), " " + names[j] + "(");
+        all.text += "namespace pbit_k" + std::to_string(j) + " {\n" + text + "\n}\n";
+    }
+    std::shared_ptr<const std::vector<char>> code;
+    if (!jit_compile(all, arch, &code, log)) return false;
+    hipModule_t mod = nullptr;
+    hipError_t e = hipModuleLoadData(&mod, code->data());
+    if (e != hipSuccess) {
+        *log = std::string("hipModuleLoadData: ") + hipGetErrorString(e);
+        return false;
+    }
+    for (size_t j = 0; j < srcs.size(); ++j) {
+        hipFunction_t fn = nullptr;
+        int scratch = 0;
+        e = hipModuleGetFunction(&fn, mod, names[j].c_str());
+        if (e == hipSuccess) e = hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn);
+        if (e != hipSuccess) {
+            (void)hipModuleUnload(mod);
+            out->assign(srcs.size(), JitKernel());
+            *log = std::string("kernel of a group: ") + hipGetErrorString(e);
+            return false;
+        }
+        JitKernel &k = (*out)[j];
+        k.module = nullptr;  // the group's module, owned by the caller
+        k.fn = fn;
+        k.lds_bytes = srcs[j]->lds_bytes;
+        k.max_block = srcs[j]->max_block;
+        k.scratch_bytes = scratch;
+    }
+    *module = mod;
     return true;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -54,7 +55,7 @@ size_t jit_rows_bytes(const CompiledCircuit &k);
 
 // A compiled, loaded specialisation.
 struct JitKernel {
-    hipModule_t module = nullptr;
+    hipModule_t module = nullptr;  // NULL for a kernel of a shared group module
     hipFunction_t fn = nullptr;
     uint32_t hist_kind = JIT_HIST_GLOBAL;
     uint32_t lds_bytes = 0;
@@ -65,6 +66,24 @@ struct JitKernel {
 // Compiles `src` with hipRTC for the current device and loads it (and reads
 // back its per-lane scratch size).  On failure returns false and fills `log`.
 bool jit_build(const JitSource &src, JitKernel *out, std::string *log);
+
+// The pieces of jit_build.  jit_arch: the current device's target name.
+// jit_compile: hipRTC only (no device call); code objects are cached for the
+// process by target and source text.  jit_load: loads a code object on the
+// current device.
+bool jit_arch(std::string *arch, std::string *log);
+bool jit_compile(const JitSource &src, const std::string &arch, std::shared_ptr<const std::vector<char>> *code,
+                 std::string *log);
+bool jit_load(const JitSource &src, const std::vector<char> &code, JitKernel *out, std::string *log);
+
+// Compiles the kernels of srcs as one hipRTC program (each source in a
+// namespace of its own, entries renamed) and loads it as one module: hipRTC
+// compiles one program at a time per process, and one program of many
+// kernels takes about a quarter of the time of as many programs.  On success
+// *module is the shared module (the caller unloads it) and out[j] kernel j
+// (its own module field NULL).
+bool jit_build_group(const std::vector<const JitSource *> &srcs, hipModule_t *module, std::vector<JitKernel> *out,
+                     std::string *log);
 
 // Launches a loaded specialisation: lanes_log2 = log2(lanes per chain); lane
 // (chain c, residue r) runs the sweeps sweep_begin + r, + r + 2^lanes_log2, ...

@@ -22,6 +22,7 @@ pbit_circuit_s::~pbit_circuit_s() {
             if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     for (auto &kv : jit)
         if (kv.second.module) (void)hipModuleUnload(kv.second.module);
+    for (hipModule_t m : jit_groups) (void)hipModuleUnload(m);
     for (auto &kv : side) {
         for (int k = 0; k < pbit::SIDE_STREAMS; ++k) {
             if (kv.second.s[k]) (void)hipStreamDestroy(kv.second.s[k]);
@@ -110,8 +111,10 @@ bool batchable(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
 // circuit-specialised kernel (each costs a run-time compile, at most
 // BATCH_SPEC_MAX of them, the heaviest by chains x free bits first); the
 // persistent launch keeps the many small circuits.  With specialize == 0
-// (auto) only those whose run alone pays for the compile (2^33 updates or
-// more, the single-circuit rule) leave.
+// (auto) the same happens when the whole run is long (2^33 updates or more:
+// the compiles run on host threads at once, about a second for a hundred
+// kernels, and are kept in the handle); otherwise only a circuit whose run
+// alone pays for its compile (2^33 updates, the single-circuit rule) leaves.
 constexpr uint32_t BATCH_SPEC_CHAINS = 1024;
 constexpr size_t BATCH_SPEC_MAX = 256;
 std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
@@ -119,10 +122,14 @@ std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
     std::vector<bool> out(nc, false);
     if (cfg->specialize == 1 || (cfg->specialize == 0 && cfg->toggle_mode != 0)) return out;
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
+    uint64_t run_updates = 0;
+    for (uint32_t i = 0; i < nc; ++i) run_updates += (uint64_t)cfg->chains[i] * total * c->circuits[i].h;
+    const bool long_run = run_updates >= (1ull << 33);
     std::vector<std::pair<uint64_t, uint32_t>> cand;
     for (uint32_t i = 0; i < nc; ++i) {
         if (cfg->chains[i] < BATCH_SPEC_CHAINS || !batchable(c, i, cfg)) continue;
-        if (cfg->specialize == 0 && (uint64_t)cfg->chains[i] * total * c->circuits[i].h < (1ull << 33)) continue;
+        if (cfg->specialize == 0 && !long_run && (uint64_t)cfg->chains[i] * total * c->circuits[i].h < (1ull << 33))
+            continue;
         cand.push_back({(uint64_t)cfg->chains[i] * c->circuits[i].h, i});
     }
     std::stable_sort(cand.begin(), cand.end(), [](const std::pair<uint64_t, uint32_t> &a,
@@ -133,6 +140,111 @@ std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
 
 bool runs_batched(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg, const std::vector<bool> &spec) {
     return batchable(c, i, cfg) && !spec[i];
+}
+
+// Launch shape of circuit i outside the persistent launch: a circuit that
+// left a batch to be specialised (batch_specialised) takes its specialised
+// kernel under the automatic rule too.
+TuneChoice member_choice(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg, uint64_t total,
+                         const std::vector<bool> &spec) {
+    if (spec[i] && cfg->specialize == 0) {
+        pbit_gibbs_cfg g = *cfg;
+        g.specialize = 2;
+        return tune_choice(c, i, cfg->chains[i], total, &g);
+    }
+    return tune_choice(c, i, cfg->chains[i], total, cfg);
+}
+
+// Builds the circuit-specialised kernels a run needs that the handle does not
+// hold (nor has failed to build): one workgroup per CU holds an LDS histogram,
+// so such a kernel gets 1024 threads (four waves per SIMD) unless that spills
+// registers, then 512; without it, 256-thread workgroups.  Each round
+// compiles the current candidate of every pending kernel (equal sources are
+// compiled once per process) and loads them; a kernel that spills moves on
+// to its next candidate, keeping the spilling one if that fails.  Failures are recorded
+// in jit_failed (the run then takes the generic kernels, or reports them).
+// hipRTC compiles one program at a time per process, so a round's kernels
+// go into one program (about a quarter of the time of separate programs).
+void compile_jits(pbit_circuit c, int dev, const pbit_gibbs_cfg *cfg, const std::vector<TuneChoice> &choices,
+                  const std::vector<bool> &batched) {
+    struct Need {
+        uint32_t i, kind;
+        std::vector<uint32_t> mbs;
+        size_t cand = 0;
+        JitKernel best;  // a loaded kernel that spills, kept until a better one loads
+        JitSource src;
+        std::string log;
+    };
+    std::vector<Need> need;
+    const uint32_t nc = (uint32_t)c->circuits.size();
+    for (uint32_t i = 0; i < nc; ++i) {
+        if (!cfg->chains[i] || batched[i] || !choices[i].jit) continue;
+        const uint32_t kind = jit_hist_kind(choices[i]);
+        const auto key = std::make_tuple(dev, i, kind);
+        if (c->jit.count(key) || c->jit_failed.count(key)) continue;
+        bool dup = false;
+        for (const Need &n : need) dup |= n.i == i && n.kind == kind;
+        if (dup) continue;
+        Need n;
+        n.i = i;
+        n.kind = kind;
+        const bool lds = c->circuits[i].uniform && (kind == JIT_HIST_LDS || kind == JIT_HIST_PATHS);
+        n.mbs = lds ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256};
+        need.push_back(std::move(n));
+    }
+    if (need.empty()) return;
+    auto finish = [&](Need &n) {
+        const auto key = std::make_tuple(dev, n.i, n.kind);
+        if (n.best.fn) {
+            n.best.hist_kind = n.kind;
+            c->jit.emplace(key, n.best);
+        } else {
+            c->jit_failed[key] = n.log.empty() ? std::string("no kernel") : n.log;
+        }
+    };
+    std::vector<Need *> pending;
+    for (Need &n : need) pending.push_back(&n);
+    while (!pending.empty()) {
+        std::vector<Need *> round;
+        std::vector<const JitSource *> srcs;
+        for (Need *n : pending) {
+            n->src = jit_uniform_source(c->circuits[n->i], n->kind, n->mbs[n->cand]);
+            if (n->src.lds_bytes > JIT_LDS_LIMIT) {
+                n->log = "LDS of the specialised kernel exceeds 160 KiB";
+                finish(*n);
+                continue;
+            }
+            round.push_back(n);
+            srcs.push_back(&n->src);
+        }
+        // the round as one program; if that fails, each kernel on its own
+        // (so one failure costs only its own kernel)
+        std::vector<JitKernel> built(round.size());
+        std::vector<bool> ok(round.size(), false);
+        hipModule_t gm = nullptr;
+        std::string glog;
+        if (round.size() > 1 && jit_build_group(srcs, &gm, &built, &glog)) {
+            c->jit_groups.push_back(gm);
+            ok.assign(round.size(), true);
+        } else {
+            for (size_t j = 0; j < round.size(); ++j) ok[j] = jit_build(round[j]->src, &built[j], &round[j]->log);
+        }
+        pending.clear();
+        for (size_t j = 0; j < round.size(); ++j) {
+            Need &n = *round[j];
+            if (ok[j]) {
+                if (n.best.module) (void)hipModuleUnload(n.best.module);
+                n.best = built[j];
+            }
+            const bool spills = n.best.fn && n.best.scratch_bytes != 0;
+            if (spills && ok[j] && n.cand + 1 < n.mbs.size()) {
+                n.cand += 1;
+                pending.push_back(&n);
+            } else {
+                finish(n);
+            }
+        }
+    }
 }
 
 pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_state, uint32_t *d_hist,
@@ -197,44 +309,18 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_
     const std::vector<bool> spec = batch_specialised(c, cfg);
     for (uint32_t i = 0; i < nc; ++i) {
         if (!cfg->chains[i]) continue;
-        choices[i] = tune_choice(c, i, cfg->chains[i], total, cfg);
+        choices[i] = member_choice(c, i, cfg, total, spec);
         batched[i] = runs_batched(c, i, cfg, spec);
     }
     // circuit-specialised kernels are compiled here, before any enqueue (and
-    // outside a graph capture)
+    // outside a graph capture): every kernel the run needs and the handle
+    // does not hold yet, on host threads at once, then loaded in order
+    compile_jits(c, dev, cfg, choices, batched);
     std::vector<const JitKernel *> jits(nc, nullptr);
     for (uint32_t i = 0; i < nc; ++i) {
         if (!cfg->chains[i] || batched[i] || !choices[i].jit) continue;
-        const uint32_t kind = jit_hist_kind(choices[i]);
-        const auto key = std::make_tuple(dev, i, kind);
+        const auto key = std::make_tuple(dev, i, jit_hist_kind(choices[i]));
         auto it = c->jit.find(key);
-        if (it == c->jit.end() && !c->jit_failed.count(key)) {
-            // one workgroup per CU holds an LDS histogram, so it gets 1024
-            // threads (four waves per SIMD) unless that spills registers, then
-            // 512; without it, 256-thread workgroups
-            std::string log;
-            JitKernel jk;
-            bool ok = false;
-            const bool lds = c->circuits[i].uniform && (kind == JIT_HIST_LDS || kind == JIT_HIST_PATHS);
-            for (uint32_t mb : lds ? std::vector<uint32_t>{1024, 512} : std::vector<uint32_t>{256}) {
-                const JitSource src = jit_uniform_source(c->circuits[i], kind, mb);
-                if (src.lds_bytes > JIT_LDS_LIMIT) {
-                    log = "LDS of the specialised kernel exceeds 160 KiB";
-                    break;
-                }
-                if (jk.module) (void)hipModuleUnload(jk.module);
-                jk = JitKernel();
-                if (!jit_build(src, &jk, &log)) break;
-                ok = true;
-                if (jk.scratch_bytes == 0) break;
-            }
-            if (ok) {
-                jk.hist_kind = kind;
-                it = c->jit.emplace(key, jk).first;
-            } else {
-                c->jit_failed[key] = log;
-            }
-        }
         if (it != c->jit.end()) {
             jits[i] = &it->second;
         } else if (cfg->specialize == 2) {
@@ -593,7 +679,8 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     const uint64_t total = (uint64_t)cfg->burn_in + cfg->sweeps;
     std::memset(out, 0, sizeof(*out));
     out->kernel_words = k.WS;
-    if (runs_batched(c, index, cfg, batch_specialised(c, cfg))) {
+    const std::vector<bool> spec = batch_specialised(c, cfg);
+    if (runs_batched(c, index, cfg, spec)) {
         const BatchTuning bt = tune_batch(c, cfg);
         const size_t hb = ((size_t)1 << (k.n + k.K)) * 4;
         const bool lh = cfg->hist_mode == 1 || (cfg->hist_mode != 2 && hb <= bt.hist_lds_max);
@@ -605,7 +692,7 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
         out->sweeps_per_launch = cfg->sweeps_per_launch ? std::min<uint64_t>(cfg->sweeps_per_launch, total) : total;
         return PBIT_OK;
     }
-    TuneChoice tc = tune_choice(c, index, cfg->chains[index], total, cfg);
+    TuneChoice tc = member_choice(c, index, cfg, total, spec);
     if (tc.jit && cfg->specialize != 2) {
         // a specialisation that failed to build on this device is replaced
         // by the generic kernels

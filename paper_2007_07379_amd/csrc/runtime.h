@@ -81,6 +81,7 @@ struct pbit_circuit_s {
     // circuit-specialised kernels by (device, circuit, histogram kind JitHist)
     std::map<std::tuple<int, uint32_t, uint32_t>, pbit::JitKernel> jit;
     std::map<std::tuple<int, uint32_t, uint32_t>, std::string> jit_failed;
+    std::vector<hipModule_t> jit_groups;  // modules shared by the kernels of one group compile
     ~pbit_circuit_s();
 };
 

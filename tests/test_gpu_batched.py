@@ -158,10 +158,11 @@ def test_autotune_cache_and_identical_results(env):
 def test_full_batch256(env, specialize):
     """256 random Clifford+T circuits (n 4..16, d 4..32), 2^22 chains in
     total, 200 + 2000 sweeps: in one persistent launch per width class
-    (specialize=1), or with the circuits of 2^33 updates or more on their own
-    specialised launches (auto): pooled 4-sigma rule over every amplitude of
-    every circuit, TV_path per circuit, and sampled chains replayed by the
-    oracle."""
+    (specialize=1), or with every circuit of at least 1,024 chains on a
+    launch of its own specialised kernel, compiled on host threads (auto: the
+    run is long): pooled 4-sigma rule over every amplitude of every circuit,
+    TV_path per circuit, sampled chains replayed by the oracle, and the
+    cheapest members bit-exact in full."""
     torch, pbit = env
     data = json.load(open(os.path.join(wc.DATA_DIR, "batch256.json")))
     circs, chains = data["circuits"], data["chains"]
