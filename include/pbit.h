@@ -169,7 +169,10 @@ typedef struct {
                                    splits a chain's lattice words over two lanes (one lane for
                                    circuits with three-qubit products); with the
                                    specialised kernel L lanes split a chain's sweeps (lane r runs
-                                   sweeps r, r + L, ...).  4 and 8 need the specialised kernel. */
+                                   sweeps r, r + L, ...).  4 and 8 need the specialised kernel.
+                                   Other circuits with the specialised kernel: 1 runs one lane
+                                   per chain, 2 or more two waves per 64 chains that split each
+                                   colour's bits (auto: up to 32,768 chains). */
     uint32_t specialize;        /* 0 = auto (runs of 2^33 updates or more, and any run of a circuit
                                    whose kernel of the needed kind is already compiled in the
                                    handle), 1 = never, 2 = always
@@ -389,10 +392,12 @@ pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cfg *cfg, uin
 
 /* HIP source of the specialised sweep kernel of circuit `index`
  * (`pbit_uniform_sweep` when every conditional is 1/2, else
- * `pbit_general_sweep`: one lane per chain, the colour schedule unrolled,
- * lds_hist 0 or 1 only, else MODE_UNAVAILABLE), with the histogram
- * in global memory (lds_hist 0), its bins privatised in LDS (1), path counts
- * in LDS (2; h <= 16, else TOO_LARGE) or bins stored as keys (3), compiled
+ * `pbit_general_sweep`: the colour schedule unrolled, lds_hist 0 or 1 for
+ * one lane per chain, 4 or 5 (= 0 or 1 plus 4) for two waves per 64 chains
+ * that split each colour's bits; other values MODE_UNAVAILABLE), with the
+ * histogram in global memory (lds_hist 0), its bins privatised in LDS (1),
+ * path counts in LDS (2; h <= 16, else TOO_LARGE) or bins stored as keys
+ * (3), compiled
  * for workgroups of at most
  * max_block threads (256, 512 or 1024).  Copies at most cap bytes
  * (NUL-terminated) into buf; *len receives the full length + 1.  Host only,

@@ -188,7 +188,8 @@ size_t jit_rows_bytes(const CompiledCircuit &k) {
 }
 
 JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint32_t max_block) {
-    if (!k.uniform) return jit_general_source(k, hist_kind == JIT_HIST_LDS, max_block);
+    if (!k.uniform)
+        return jit_general_source(k, (hist_kind & 3u) == JIT_HIST_LDS, max_block, (hist_kind & JIT_PAIRED) != 0);
     const bool lds_hist = hist_kind == JIT_HIST_LDS, path_hist = hist_kind == JIT_HIST_PATHS;
     const bool keys = hist_kind == JIT_HIST_KEYS;
     const uint32_t *B = k.blob.data();
@@ -383,14 +384,60 @@ JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint3
     return out;
 }
 
-// Circuits with conditionals other than 1/2: one lane per chain (a chain's
-// sweeps depend on each other), the colour schedule unrolled.  Per colour,
-// every Philox block the colour needs is drawn first, then every bit's
+// Circuits with conditionals other than 1/2: a chain's sweeps depend on each
+// other, so lanes cannot split them; the colour schedule is unrolled.  One
+// lane per chain, or (paired) two waves per 64 chains that split each
+// colour's bits and exchange flip flags through LDS.  Per colour,
+// every Philox block the colour needs and no earlier colour drew is drawn
+// first (each block once a sweep), then every bit's
 // neighbourhood index (its scope bits at immediate positions), threshold
 // (from the LDS copy of the tables) and flip are computed, and then the
 // flipped bits' cones are XORed in: bits of one colour touch no scope of
 // another, so this equals flipping them one after the other.
-JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block) {
+namespace {
+
+// The free bits of each colour, in the image's colour-entry order.
+std::vector<std::vector<uint32_t>> colour_bits(const CompiledCircuit &k) {
+    const uint32_t *B = k.blob.data();
+    const uint32_t ncol = B[H_NCOL];
+    const uint32_t *colidx = B + B[H_OFF_COLIDX];
+    const uint32_t *colent = B + B[H_OFF_COLENT];
+    std::vector<std::vector<uint32_t>> colbits(ncol);
+    for (uint32_t c = 0; c < ncol; ++c)
+        for (uint32_t kk = 0; kk < (uint32_t)MAX_FW; ++kk) {
+            const uint32_t off = colidx[(c * MAX_FW + kk) * 2], cnt = colidx[(c * MAX_FW + kk) * 2 + 1];
+            for (uint32_t e = 0; e < cnt; ++e) {
+                const uint32_t blk = colent[off + e] >> 4, msk = colent[off + e] & 15u;
+                for (uint32_t t = 0; t < 4; ++t)
+                    if ((msk >> t) & 1u) colbits[c].push_back(4 * blk + t);
+            }
+        }
+    return colbits;
+}
+
+// Flip-mask words one half of the paired kernel exchanges per colour.
+uint32_t flip_mask_words(const std::vector<std::vector<uint32_t>> &colbits) {
+    uint32_t fw = 1;
+    for (const auto &bits : colbits)
+        for (uint32_t hf = 0; hf < 2; ++hf) {
+            uint32_t nb = 0;
+            for (uint32_t b : bits) nb += ((b >> 2) & 1u) == hf;
+            fw = std::max(fw, (nb + 31) / 32);
+        }
+    return fw;
+}
+
+}  // namespace
+
+size_t jit_general_lds_bytes(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool paired) {
+    const uint32_t *B = k.blob.data();
+    const size_t thr = (size_t)B[H_THR_TOTAL] * 4, hist = lds_hist ? ((size_t)4 << B[H_HBITS]) : 0;
+    const size_t rows = thr + hist <= JIT_LDS_LIMIT ? thr : 0;
+    const size_t flips = paired ? (size_t)2 * max_block * flip_mask_words(colour_bits(k)) * 4 : 0;
+    return rows + hist + flips;
+}
+
+JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool paired) {
     const uint32_t *B = k.blob.data();
     const uint32_t W = B[H_W], WS = B[H_WS], h = B[H_H], ncol = B[H_NCOL];
     const uint32_t *cw = B + B[H_OFF_CONST];
@@ -399,8 +446,6 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     const uint32_t *thrinfo = B + B[H_OFF_THRINFO];
     const uint32_t *thrtab = B + B[H_OFF_THRTAB];
     const uint32_t total = B[H_THR_TOTAL];
-    const uint32_t *colidx = B + B[H_OFF_COLIDX];
-    const uint32_t *colent = B + B[H_OFF_COLENT];
     const uint32_t nbins = 1u << B[H_HBITS];
     const uint32_t ctag = B[H_CID];
     JitSource out;
@@ -408,12 +453,19 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     out.max_block = max_block;
     const bool thr_lds = (size_t)total * 4 + (lds_hist ? (size_t)nbins * 4 : 0) <= JIT_LDS_LIMIT;
     out.rows_words = thr_lds ? total : 0;
-    out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0);
+
+    // the colours' free bits, and (paired) which half handles each: the bits
+    // of Philox block j go to half j & 1, so every block is drawn by one half
+    const std::vector<std::vector<uint32_t>> colbits = colour_bits(k);
+    const uint32_t fw = flip_mask_words(colbits);
+    const uint32_t waves = max_block / 64;
+    const uint32_t flip_words = paired ? 2 * waves * 64 * fw : 0;
+    out.lds_bytes = out.rows_words * 4 + (lds_hist ? nbins * 4 : 0) + flip_words * 4;
 
     std::ostringstream o;
     o << PRELUDE;
     o << "\n// circuit: n=" << B[H_N] << " d=" << B[H_D] << " K=" << B[H_K] << " W=" << W << " h=" << h
-      << " colours=" << ncol << " id=" << B[H_CID] << "\n";
+      << " colours=" << ncol << " id=" << B[H_CID] << (paired ? " (two waves per 64 chains)" : "") << "\n";
     o << "static __device__ const u32 thr_init[" << std::max<uint32_t>(total, 1) << "] = {";
     for (uint32_t i = 0; i < std::max<uint32_t>(total, 1); ++i)
         o << (i % 8 ? " " : "\n    ") << hx(i < total ? thrtab[i] : 0u) << ",";
@@ -424,58 +476,118 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
          "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from, u32 resume) {\n";
     if (thr_lds) o << "    __shared__ u32 lds_t[" << std::max<uint32_t>(total, 1) << "];\n";
     if (lds_hist) o << "    __shared__ u32 lds_h[" << nbins << "];\n";
+    if (paired) o << "    __shared__ u32 lds_f[" << flip_words << "];  // [buffer][wave][word][lane]\n";
     if (thr_lds) o << "    for (u32 e = threadIdx.x; e < " << total << "u; e += blockDim.x) lds_t[e] = thr_init[e];\n";
     if (lds_hist) o << "    for (u32 e = threadIdx.x; e < " << nbins << "u; e += blockDim.x) lds_h[e] = 0u;\n";
     o << "    __syncthreads();\n";
     o << "    const u32 *tab = " << (thr_lds ? "lds_t" : "thr_init") << ";\n";
-    o << "    const u32 lc = blockIdx.x * blockDim.x + threadIdx.x;\n"
-         "    if (lc < n_chains) {\n"
-         "        const u32 chain = chain_begin + lc;\n"
+    if (paired) {
+        // waves 2g and 2g + 1 of a workgroup run the same 64 chains; every
+        // wave runs every sweep (the colours end in workgroup barriers)
+        o << "    const u32 wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
+             "    const u32 half = wv & 1u, lane = threadIdx.x & 63u;\n"
+             "    const u32 lc = blockIdx.x * (blockDim.x >> 1) + (wv >> 1) * 64u + lane;\n"
+             "    const bool valid = lc < n_chains;\n"
+             "    {\n";
+    } else {
+        o << "    const u32 lc = blockIdx.x * blockDim.x + threadIdx.x;\n"
+             "    if (lc < n_chains) {\n";
+    }
+    o << "        const u32 chain = chain_begin + lc;\n"
          "        u32 x[" << W << "];\n"
-         "        if (resume) {\n";
+         "        if (resume" << (paired ? " && valid" : "") << ") {\n";
     for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = state[(u64)" << w << " * n_chains + lc];\n";
     o << "        } else {\n";
     for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = " << hx(cw[w]) << ";\n";
     o << "        }\n"
          "        for (u32 it = 0; it < n_sweeps; ++it) {\n"
          "            const u32 s = sweep_begin + it;\n";
+    if (paired)
+        for (uint32_t j = 0; j < (h + 3) / 4; ++j)
+            o << "            u32 u" << j << "_0 = 0u, u" << j << "_1 = 0u, u" << j << "_2 = 0u, u" << j << "_3 = 0u;\n";
+    // a Philox block serves the free bits 4j..4j+3, which may belong to
+    // several colours: it is drawn once per sweep, before the first colour
+    // that needs it, and its words stay in registers until the last
+    std::vector<bool> drawn((h + 3) / 4, false);
+    auto draw = [&](const char *ind, uint32_t j) {
+        if (drawn[j]) return;
+        drawn[j] = true;
+        if (paired)
+            o << ind << "philox(s, " << j << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u" << j << "_0, u" << j
+              << "_1, u" << j << "_2, u" << j << "_3);\n";
+        else
+            o << ind << "u32 u" << j << "_0, u" << j << "_1, u" << j << "_2, u" << j << "_3;\n"
+              << ind << "philox(s, " << j << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u" << j << "_0, u" << j
+              << "_1, u" << j << "_2, u" << j << "_3);\n";
+    };
+    // index, threshold and flip flag of free bit b
+    auto flip = [&](const char *ind, uint32_t b) {
+        const uint32_t *rec = thrinfo + b * THR_STRIDE;
+        const uint32_t toff = rec[0], ns = rec[1];
+        o << ind << "const u32 i" << b << " = 0u";
+        for (uint32_t j = 0; j < ns; ++j)
+            o << " | (((x[" << (rec[2 + j] >> 5) << "] >> " << (rec[2 + j] & 31) << "u) & 1u) << " << j << ")";
+        o << ";\n";
+        const uint32_t p = fpos[b];
+        o << ind << "const u32 f" << b << " = (u" << (b >> 2) << "_" << (b & 3) << " < tab[" << toff << "u + i" << b
+          << "] ? 1u : 0u) ^ ((x[" << (p >> 5) << "] >> " << (p & 31) << "u) & 1u);\n";
+    };
+    // XOR of free bit b's cone, under the all-ones-or-zero mask expression m
+    auto apply = [&](const char *ind, uint32_t b, const std::string &m) {
+        o << ind << "{\n" << ind << "    const u32 m = " << m << ";\n";
+        for (uint32_t w = 0; w < W; ++w) {
+            const uint32_t mk = cone[(size_t)b * WS + w];
+            if (mk) o << ind << "    x[" << w << "] ^= m & " << hx(mk) << ";\n";
+        }
+        o << ind << "}\n";
+    };
     for (uint32_t c = 0; c < ncol; ++c) {
-        std::vector<std::pair<uint32_t, uint32_t>> ents;  // (block, mask)
-        for (uint32_t kk = 0; kk < (uint32_t)MAX_FW; ++kk) {
-            const uint32_t off = colidx[(c * MAX_FW + kk) * 2], cnt = colidx[(c * MAX_FW + kk) * 2 + 1];
-            for (uint32_t e = 0; e < cnt; ++e) ents.push_back({colent[off + e] >> 4, colent[off + e] & 15u});
+        const std::vector<uint32_t> &bits = colbits[c];
+        if (!paired) {
+            for (uint32_t b : bits) draw("            ", b >> 2);
+            o << "            {  // colour " << c << "\n";
+            for (uint32_t b : bits) flip("                ", b);
+            for (uint32_t b : bits) apply("                ", b, "0u - f" + std::to_string(b));
+            o << "            }\n";
+            continue;
         }
-        o << "            {  // colour " << c << "\n";
-        for (auto &en : ents)
-            o << "                u32 u" << en.first << "_0, u" << en.first << "_1, u" << en.first << "_2, u" << en.first
-              << "_3;\n                philox(s, " << en.first << "u, chain, " << hx(ctag) << ", seed_lo, seed_hi, u"
-              << en.first << "_0, u" << en.first << "_1, u" << en.first << "_2, u" << en.first << "_3);\n";
-        std::vector<uint32_t> bits;
-        for (auto &en : ents)
-            for (uint32_t t = 0; t < 4; ++t)
-                if ((en.second >> t) & 1u) bits.push_back(4 * en.first + t);
-        for (uint32_t b : bits) {
-            const uint32_t *rec = thrinfo + b * THR_STRIDE;
-            const uint32_t toff = rec[0], ns = rec[1];
-            o << "                const u32 i" << b << " = 0u";
-            for (uint32_t j = 0; j < ns; ++j)
-                o << " | (((x[" << (rec[2 + j] >> 5) << "] >> " << (rec[2 + j] & 31) << "u) & 1u) << " << j << ")";
-            o << ";\n";
-            const uint32_t p = fpos[b];
-            o << "                const u32 f" << b << " = (u" << (b >> 2) << "_" << (b & 3) << " < tab[" << toff << "u + i"
-              << b << "] ? 1u : 0u) ^ ((x[" << (p >> 5) << "] >> " << (p & 31) << "u) & 1u);\n";
-        }
-        for (uint32_t b : bits) {
-            o << "                {\n                    const u32 m = 0u - f" << b << ";\n";
-            for (uint32_t w = 0; w < W; ++w) {
-                const uint32_t mk = cone[(size_t)b * WS + w];
-                if (mk) o << "                    x[" << w << "] ^= m & " << hx(mk) << ";\n";
+        // paired: each half draws its blocks and takes its bits' flips, the
+        // flags cross through LDS, and both halves apply every flip
+        std::vector<uint32_t> sub[2];
+        for (uint32_t b : bits) sub[(b >> 2) & 1u].push_back(b);
+        const uint32_t buf = c & 1u;
+        o << "            {  // colour " << c << "\n"
+             "                u32 mine[" << fw << "] = {";
+        for (uint32_t q = 0; q < fw; ++q) o << (q ? ", " : "") << "0u";
+        o << "};\n";
+        for (uint32_t hf = 0; hf < 2; ++hf) {
+            o << "                " << (hf ? "} else {\n" : "if (half == 0u) {\n");
+            for (uint32_t b : sub[hf]) draw("                    ", b >> 2);
+            for (size_t q = 0; q < sub[hf].size(); ++q) {
+                flip("                    ", sub[hf][q]);
+                o << "                    mine[" << q / 32 << "] |= f" << sub[hf][q] << " << " << q % 32 << ";\n";
             }
-            o << "                }\n";
         }
+        o << "                }\n";
+        for (uint32_t q = 0; q < fw; ++q)
+            o << "                lds_f[((" << buf << "u * " << waves << "u + wv) * " << fw << "u + " << q
+              << "u) * 64u + lane] = mine[" << q << "];\n";
+        o << "                __syncthreads();\n";
+        for (uint32_t q = 0; q < fw; ++q)
+            o << "                const u32 other" << q << " = lds_f[((" << buf << "u * " << waves << "u + (wv ^ 1u)) * "
+              << fw << "u + " << q << "u) * 64u + lane];\n"
+              << "                const u32 fa" << q << " = half == 0u ? mine[" << q << "] : other" << q << ";\n"
+              << "                const u32 fb" << q << " = half == 0u ? other" << q << " : mine[" << q << "];\n";
+        for (uint32_t hf = 0; hf < 2; ++hf)
+            for (size_t q = 0; q < sub[hf].size(); ++q)
+                apply("                ", sub[hf][q],
+                      std::string("0u - ((") + (hf ? "fb" : "fa") + std::to_string(q / 32) + " >> " +
+                          std::to_string(q % 32) + ") & 1u)");
         o << "            }\n";
     }
-    o << "            if (s >= bin_from) {\n";
+    // the sample of sweep s: every lattice is the same in both halves, which
+    // bin the sweeps of their parity
+    o << "            if (s >= bin_from" << (paired ? " && (s & 1u) == half && valid" : "") << ") {\n";
     emit_soft_code(o, "                ", B);
     o << "                if (!soft_hit) {\n";
     emit_bin_code(o, "                    ", B);
@@ -486,7 +598,7 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     o << "                }\n"
          "            }\n"
          "        }\n"
-         "        if (state && n_sweeps) {\n";
+         "        if (state && n_sweeps" << (paired ? " && half == 0u && valid" : "") << ") {\n";
     for (uint32_t w = 0; w < W; ++w) o << "            state[(u64)" << w << " * n_chains + lc] = x[" << w << "];\n";
     o << "        }\n"
          "    }\n";

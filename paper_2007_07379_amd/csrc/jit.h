@@ -44,11 +44,19 @@ enum JitHist : uint32_t {
     // the key buffer, key (s - bin_from) * n_chains + chain for sweep s, with
     // bin_from no earlier than the launch's first sweep (keyhist.h bins them)
     JIT_HIST_KEYS = 3,
+    // flag on the kind of pbit_general_sweep: two waves per 64 chains (the
+    // bits of Philox block j to wave j & 1, flip flags crossed through LDS
+    // once per colour, sweeps of each parity binned by one wave), for runs
+    // with too few chains to give each SIMD two waves of one chain a lane
+    JIT_PAIRED = 4,
 };
 // Circuits with other conditionals get the kernel of jit_general_source
 // (`pbit_general_sweep`: one lane per chain, LDS or HBM histogram only).
 JitSource jit_uniform_source(const CompiledCircuit &k, uint32_t hist_kind, uint32_t max_block);
-JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block);
+JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool paired);
+// Static LDS of that kernel (threshold tables when they fit, histogram, flip
+// masks of the paired form), without generating it.
+size_t jit_general_lds_bytes(const CompiledCircuit &k, bool lds_hist, uint32_t max_block, bool paired);
 
 // LDS bytes of the compacted toggle rows (without the histogram).
 size_t jit_rows_bytes(const CompiledCircuit &k);

@@ -707,12 +707,11 @@ extern "C" pbit_status pbit_launch_shape_get(pbit_circuit c, const pbit_gibbs_cf
     }
     out->kernel = tc.jit ? PBIT_KERNEL_SPECIALISED : (tc.pair ? PBIT_KERNEL_TWO_LANE : PBIT_KERNEL_ONE_LANE);
     out->block = tc.block;
-    out->lds_hist = tc.jit ? jit_hist_kind(tc) : (tc.lds_hist ? 1u : 0u);
+    out->lds_hist = tc.jit ? (jit_hist_kind(tc) & 3u) : (tc.lds_hist ? 1u : 0u);
     out->toggle_tables = tc.tog ? 1u : 0u;
     out->lanes_per_chain = tc.jit ? (1u << tc.lanes_log2) : (tc.pair ? 2u : 1u);
-    const size_t thr_b = (size_t)k.blob[H_THR_TOTAL] * 4;
     const size_t hist_lb = tc.lds_hist ? ((size_t)4 << (k.n + k.K)) : 0;
-    out->lds_bytes = (uint32_t)(tc.jit && !k.uniform ? (thr_b + hist_lb <= JIT_LDS_LIMIT ? thr_b : 0) + hist_lb
+    out->lds_bytes = (uint32_t)(tc.jit && !k.uniform ? jit_general_lds_bytes(k, tc.lds_hist, 256, tc.lanes_log2 != 0)
                                 : tc.jit ? jit_rows_bytes(k) + hist_lb + (tc.path_hist ? ((size_t)4 << k.h) : 0)
                                 : tc.pair ? gibbs_pair_lds_bytes(k.blob.data(), tc.lds_hist)
                                           : gibbs_lds_bytes(k.blob.data(), tc.tog, tc.lds_hist));
@@ -727,9 +726,12 @@ extern "C" pbit_status pbit_specialised_source(pbit_circuit c, uint32_t index, u
         return set_error(PBIT_E_INVALID_ARG, "max_block must be 256, 512 or 1024");
     if (index >= c->circuits.size()) return set_error(PBIT_E_INVALID_ARG, "circuit index out of range");
     const CompiledCircuit &k = c->circuits[index];
-    if (lds_hist > 3) return set_error(PBIT_E_INVALID_ARG, "lds_hist must be 0, 1, 2 or 3");
-    if (!k.uniform && lds_hist > 1)
+    if (lds_hist > 3 && lds_hist != 4 && lds_hist != 5)
+        return set_error(PBIT_E_INVALID_ARG, "lds_hist must be 0, 1, 2, 3, 4 or 5");
+    if (!k.uniform && (lds_hist & 3u) > 1)
         return set_error(PBIT_E_MODE_UNAVAILABLE, "path counts and keys need every conditional 1/2");
+    if (k.uniform && lds_hist > 3)
+        return set_error(PBIT_E_MODE_UNAVAILABLE, "the two-wave form is pbit_general_sweep's");
     if (lds_hist == JIT_HIST_PATHS && k.h > 16) return set_error(PBIT_E_TOO_LARGE, "path counts need h <= 16");
     const JitSource src = jit_uniform_source(k, lds_hist, max_block);
     *len = src.text.size() + 1;

@@ -78,16 +78,28 @@ TuneChoice tune_choice(pbit_circuit c, uint32_t i, uint32_t chains, uint64_t tot
     const bool short_run = work < (1ull << 33);
     t.jit = cfg->specialize == 2 || (auto_rule && (!short_run || jit_compiled_any(c, i)));
     if (t.jit && !k.uniform) {
-        // other conditionals: one lane per chain (sweeps depend on each
-        // other), threshold tables and the histogram in LDS when they fit
-        t.lanes_log2 = 0;
+        // other conditionals: sweeps depend on each other, so one lane per
+        // chain, or two waves per 64 chains (splitting each colour's bits)
+        // for runs of at most 32,768 chains, which leave most SIMDs without
+        // a wave (measured on rctch12: 10 % faster there, 27 % slower at
+        // 65,536 chains, where the barriers and the doubled cone XORs cost
+        // more than the second wave per SIMD gains), or when lanes_per_chain
+        // asks for more than one; threshold tables and the histogram in LDS
+        // when they fit
+        const uint32_t L = cfg->lanes_per_chain;
+        t.general = true;
+        t.lanes_log2 = (L >= 2 || (L == 0 && chains <= 32768u)) ? 1u : 0u;
         t.pair = false;
         t.tog = true;
         t.path_hist = t.keys = false;
         const size_t thr_b = (size_t)k.blob[H_THR_TOTAL] * 4;
         const size_t hist_b = ((size_t)1 << (k.n + k.K)) * 4;
-        t.lds_hist = cfg->hist_mode == 1 || (cfg->hist_mode != 2 && thr_b + hist_b <= LDS_MAX);
+        const size_t flips_b = t.lanes_log2 ? jit_general_lds_bytes(k, false, 256, true) -
+                                                  jit_general_lds_bytes(k, false, 256, false)
+                                            : 0;
+        t.lds_hist = cfg->hist_mode == 1 || (cfg->hist_mode != 2 && thr_b + hist_b + flips_b <= LDS_MAX);
         t.block = cfg->block_size ? cfg->block_size : 256;
+        if (t.lanes_log2 && t.block % 128) t.block = t.block < 128 ? 128 : 256;  // pairs of waves
     } else if (t.jit) {
         uint32_t L = cfg->lanes_per_chain;
         if (!L) {

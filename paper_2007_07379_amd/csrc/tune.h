@@ -18,11 +18,13 @@ struct TuneChoice {
     uint32_t lanes_log2 = 0;  // specialised kernel: log2(lanes per chain)
     bool path_hist = false;   // specialised kernel: LDS counts per path, binned at the end
     bool keys = false;        // specialised kernel: bins stored as keys, counted by the key histogram
+    bool general = false;     // specialised kernel of a circuit with other conditionals (pbit_general_sweep)
 };
 
-// Histogram kind of the specialised kernel (JitHist in jit.h).
+// Kind of the specialised kernel (JitHist in jit.h): the histogram placement,
+// with JIT_PAIRED (4) for the two-wave form of pbit_general_sweep.
 inline uint32_t jit_hist_kind(const TuneChoice &t) {
-    return t.path_hist ? 2u : (t.keys ? 3u : (t.lds_hist ? 1u : 0u));
+    return (t.path_hist ? 2u : (t.keys ? 3u : (t.lds_hist ? 1u : 0u))) | (t.general && t.lanes_log2 ? 4u : 0u);
 }
 
 // Is a circuit-specialised kernel of this histogram kind (any kind) for

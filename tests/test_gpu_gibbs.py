@@ -86,6 +86,11 @@ MODES = {
     # with other conditionals), histogram in LDS or HBM, sweep groups
     "spec": dict(specialize=2, lanes_per_chain=1),
     "spec_ghist_groups": dict(specialize=2, lanes_per_chain=1, hist_mode=2, sweeps_per_launch=7),
+    # two lanes per chain: sweeps split for uniform circuits; for the others
+    # pbit_general_sweep in its two-wave form (each colour's bits split, flip
+    # flags crossed through LDS)
+    "spec_pair": dict(specialize=2, lanes_per_chain=2),
+    "spec_pair_ghist_groups": dict(specialize=2, lanes_per_chain=2, hist_mode=2, sweeps_per_launch=7),
 }
 
 

@@ -50,7 +50,9 @@ CASES = [
 
 MODES = [dict(toggle_mode=1, specialize=1), dict(toggle_mode=2), dict(toggle_mode=1, hist_mode=2, specialize=1),
          dict(toggle_mode=1, sweeps_per_launch=7, specialize=1), dict(toggle_mode=1, block_size=64, specialize=1),
-         dict(specialize=2), dict(specialize=2, hist_mode=2, sweeps_per_launch=9)]
+         dict(specialize=2), dict(specialize=2, hist_mode=2, sweeps_per_launch=9),
+         # the general kernel with one lane per chain and in its two-wave form
+         dict(specialize=2, lanes_per_chain=1), dict(specialize=2, lanes_per_chain=2, block_size=128)]
 
 
 def run(env, s, chains, burn, sweeps, seed, cb, **kw):

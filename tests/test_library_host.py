@@ -367,8 +367,17 @@ def test_launch_shape_rules(pb):
     assert sh["kernel"] == pb.KERNEL_TWO_LANE and sh["block"] == 128 and sh["sweeps_per_launch"] == 7
     r = pb.CircuitSet(wc.rotated_hadamard_chain(10, math.pi / 8, K=1))
     assert r.launch_shape([1000], 0, 10, lanes_per_chain=2)["kernel"] == pb.KERNEL_ONE_LANE
+    # the general kernel: two waves per 64 chains up to 32,768 chains (auto),
+    # one lane per chain above or when asked
     sh = r.launch_shape([1000], 0, 10, specialize=2)
-    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lanes_per_chain"] == 1 and sh["lds_hist"] in (0, 1)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lanes_per_chain"] == 2 and sh["lds_hist"] in (0, 1)
+    assert sh["block"] % 128 == 0
+    sh = r.launch_shape([1000], 0, 10, specialize=2, lanes_per_chain=1)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lanes_per_chain"] == 1
+    sh = r.launch_shape([65536], 0, 10, specialize=2)
+    assert sh["kernel"] == pb.KERNEL_SPECIALISED and sh["lanes_per_chain"] == 1
+    sh = r.launch_shape([1000], 0, 10, specialize=2, lanes_per_chain=2, block_size=64)
+    assert sh["lanes_per_chain"] == 2 and sh["block"] == 128
     assert r.launch_shape([1000], 0, 10, specialize=1)["kernel"] == pb.KERNEL_ONE_LANE
     m = pb.CircuitSet([wc.tiny_ghz_t(), wc.rotated_hadamard_chain(6, math.pi / 8, K=1)])
     assert m.launch_shape([100, 100], 0, 10, idx=0)["kernel"] == pb.KERNEL_PERSISTENT
@@ -481,10 +490,10 @@ def test_general_source_compiles_for_gfx950(pb, name, mk, J, tmp_path):
     without register spills, with the histogram in LDS or HBM; path counts
     and keys are refused."""
     s = pb.CircuitSet(mk(), soft_zero_J=J)
-    for lds in (False, True):
+    for lds in (0, 1, 4, 5):  # one lane per chain, or two waves per 64 chains (+ 4)
         src = s.specialised_source(0, lds_hist=lds, max_block=256)
         assert "pbit_general_sweep" in src
-        f = tmp_path / ("%s_%d.hip" % (name, int(lds)))
+        f = tmp_path / ("%s_%d.hip" % (name, lds))
         f.write_text(src)
         cmd = ["/opt/rocm/bin/hipcc", "-include", "hip/hip_runtime.h", "--offload-arch=gfx950", "-O3",
                "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
