@@ -279,7 +279,10 @@ pbit_status pbit_proposal_sample(pbit_proposal q, uint32_t n, uint32_t chain_beg
  * states or proposals); equal bit for bit to the value the sampler reports
  * for a path it drew.  Networks of width <= 256 are scored by the fused
  * autoregressive kernel with its bits read from d_states, wider ones by the
- * batched forward GEMMs. */
+ * batched forward GEMMs: for widths up to 1,024 on lattices of <= 512 bits
+ * with <= 128 free bits (the wide sampler's networks) the logits are then
+ * added up in that sampler's order by a replay kernel, for the others by
+ * one more GEMM. */
 pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint32_t n, double *d_logq,
                                 void *hip_stream);
 /* pbit_proposal_sample (n proposals into d_out, d_logq) and

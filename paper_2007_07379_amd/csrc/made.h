@@ -38,6 +38,11 @@ struct GemmArgs {
     int accumulate;          // fp32 output: C += result
     int ksplit;              // > 1: K split in that many slices (fp32 out, no bias / relu / gate)
     float *part;             // split-K workspace, ksplit x M x N floats
+    // K runs over hidden units and both operands take the k-slot order of the
+    // samplers inside each 32-wide chunk (k-slot 8 g + 4 t + e holds unit
+    // 16 t + 4 g + e), so each output sums its products as the wide sampler
+    // does; needs both operands in mode 0 (k contiguous)
+    int kperm;
 };
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);

@@ -120,13 +120,26 @@ __device__ __forceinline__ void stage_load(StageRegs &st, const bf16 *__restrict
 }
 
 template <int MODE, int ROWS>
-__device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]) {
+__device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK], bool kperm) {
     const int t = threadIdx.x;
     constexpr int NS = ROWS / 32, RB = ROWS / 8;
     u32x4v v[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) v[j] = st.interior ? st.v[j] : st.v[j] & seg_mask(st.rem[j]);
-    if (MODE != 1) {
+    if (MODE != 1 && kperm) {
+        // the segment's two 4-unit pieces w, w + 1 of their 32-wide chunk go
+        // to k-slots 8 (w & 3) + 4 (w >> 2)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int seg = t + 256 * j, r = seg >> 3, kk = (seg & 7) * 8;
+            const int base = kk & 32, w = (kk & 31) >> 2;
+#pragma unroll
+            for (int hpc = 0; hpc < 2; ++hpc) {
+                const int wp = w + hpc, slot = base + 8 * (wp & 3) + 4 * (wp >> 2);
+                *reinterpret_cast<uint2 *>(&T[r][lds_col(r, slot)]) = uint2{v[j][2 * hpc], v[j][2 * hpc + 1]};
+            }
+        }
+    } else if (MODE != 1) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             const int seg = t + 256 * j, r = seg >> 3;
@@ -201,8 +214,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 stage_load<MB, TN>(rb[i], g.B, g.sbn, g.sbk, n0, g.N, (c_lo + 2 * i) * TK, kst);
             }
         }
-        stage_store<MA, TM>(ra[0], As[0]);
-        stage_store<MB, TN>(rb[0], Bs[0]);
+        stage_store<MA, TM>(ra[0], As[0], g.kperm);
+        stage_store<MB, TN>(rb[0], Bs[0], g.kperm);
         __syncthreads();
         for (int sb = 0; sb < S; sb += P) {
 #pragma unroll
@@ -241,8 +254,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         }
                     }
                     if (st + 1 < S) {
-                        stage_store<MA, TM>(ra[(i + 1) % P], As[buf ^ 1]);
-                        stage_store<MB, TN>(rb[(i + 1) % P], Bs[buf ^ 1]);
+                        stage_store<MA, TM>(ra[(i + 1) % P], As[buf ^ 1], g.kperm);
+                        stage_store<MB, TN>(rb[(i + 1) % P], Bs[buf ^ 1], g.kperm);
                     }
                     __syncthreads();
                 }
@@ -361,6 +374,7 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     const int tiles = ((g.N + TT - 1) / TT) * ((g.M + TT - 1) / TT);
     dim3 grid(8 * ((tiles + 7) / 8), 1, z);
     const int ma = operand_mode(g.A, g.sam, g.sak, g.M, g.K), mb = operand_mode(g.B, g.sbn, g.sbk, g.N, g.K);
+    if (g.kperm && (ma != 0 || mb != 0)) return hipErrorInvalidValue;
     const void *fn = nullptr;
 #define PBIT_GEMM(A_, B_) \
     if (ma == A_ && mb == B_)  \
@@ -1144,6 +1158,471 @@ __global__ __launch_bounds__(512) void made_sample_reg_kernel(SampleArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// wide register-resident sampler (256 < H <= 1024, lattices of <= 512 bits,
+// at most 128 free bits)
+// ---------------------------------------------------------------------------
+// The procedure of made_sample_reg_kernel for networks whose weights do not
+// fit in LDS.  Each wave serves 16 chains and keeps in registers their
+// first-layer activations (32 chunks of four dwords) and the logits of every
+// free bit (8 blocks of 16 free bits, one MFMA accumulator each); the
+// second-layer activations are never stored.  The network is streamed step
+// by step.  A step is one half tile of a phase (16 hidden units): layer 1
+// (weight rows of W1 against the chains' inputs) or layer 2 (rows of W2
+// against the first-layer activations).  A layer-2 half tile's outputs that
+// belong to the phase are final once computed, so their terms of every
+// logit, V[p][u] a_u for the free positions p, are added to the logit
+// accumulators right away (a 16 x 16 x 16 product per block of free bits,
+// units outside the phase masked to zero so each unit is added once); V's
+// mask makes the terms of positions that come before the unit's degree
+// zero.  When a free bit is drawn its logit is therefore complete.  The four
+// waves of a workgroup run the same steps: the 256 threads copy the next
+// step's rows from global memory into one of two LDS buffers while every
+// wave computes the current step from the other (rows whose K runs over
+// hidden units stored in the k-slot order of stage_rows_k), and one barrier
+// a step hands the buffers over.  64 chains are in flight per CU (one wave
+// per SIMD), twice made_sample_kernel's 32.  Every activation is computed as
+// the batched GEMMs compute it (one MFMA chain over the K chunks from zero,
+// bias, ReLU, bf16), so the scorer of these networks is the GEMMs for both
+// layers followed by wd_replay_kernel, which adds the logit terms in this
+// kernel's order: sampler and scorer give the same log q bit for bit.
+constexpr int WD_NH = 32;               // hidden chunks (H <= 1024)
+constexpr int WD_NX = 16;               // lattice words = input chunks (<= 512 bits)
+constexpr int WD_NB = 8;                // blocks of 16 free bits (h <= 128)
+constexpr int WD_RS = 32 * WD_NH + 8;   // LDS row stride of a staged half tile (elements)
+constexpr int WD_VS = 16;               // LDS row stride of a staged V block (elements)
+constexpr int WD_BUF = 16 * WD_RS + 16 * WD_NB * WD_VS;  // elements of one step buffer
+
+struct WdLayout {
+    size_t lut, b1, b2, c, fp, buf, total;
+};
+
+__host__ __device__ inline WdLayout wd_layout(int D, int H) {
+    WdLayout L;
+    L.lut = 0;
+    L.b1 = 256 * 16;
+    L.b2 = L.b1 + (size_t)H * 4;
+    L.c = L.b2 + (size_t)H * 4;
+    L.fp = L.c + (size_t)D * 4;
+    L.buf = (L.fp + 16 * WD_NB * 4 + 15) & ~(size_t)15;
+    L.total = L.buf + (size_t)2 * WD_BUF * 2;
+    return L;
+}
+
+bool made_sample_wide_ok(const SampleArgs &a) {
+    return a.H > 256 && a.H <= 32 * WD_NH && a.W <= WD_NX && a.DP <= 32 * WD_NX && a.h <= 16 * WD_NB &&
+           wd_layout(a.D, a.H).total <= 160 * 1024;
+}
+
+// A staged step: thread t holds piece t (elements 4t .. 4t + 3) of the 16
+// weight rows where the rows have it, and for a layer-2 step pieces t and
+// t + 256 of the V block (free bit f = piece / 4, units 16 ht + 4 (piece % 4)
+// .. + 3 of position fp[f]).
+struct WdStage {
+    uint2 w[16];
+    uint2 v[2];
+};
+
+__device__ __forceinline__ void wd_fetch(const SampleArgs &a, const int *fp, int4 st, WdStage &x) {
+    const int t = threadIdx.x;
+    const int np = 8 * st.z;  // pieces a row
+    const bf16 *src = (st.x == 0 ? a.W1T + (int64_t)st.y * a.DP : a.W2T + (int64_t)st.y * a.H);
+    const int64_t rs = st.x == 0 ? a.DP : a.H;
+    if (t < np) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x.w[r] = *reinterpret_cast<const uint2 *>(src + (int64_t)r * rs + 4 * t);
+    }
+    if (st.x == 1) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int pc = t + 256 * j, f = pc >> 2;
+            x.v[j] = f < a.h ? *reinterpret_cast<const uint2 *>(a.VT + (int64_t)fp[f] * a.H + st.y + 4 * (pc & 3))
+                             : uint2{0u, 0u};
+        }
+    }
+}
+
+__device__ __forceinline__ void wd_store(bf16 *buf, int4 st, const WdStage &x) {
+    const int t = threadIdx.x;
+    const int np = 8 * st.z;
+    // inputs keep their order; hidden units take the k-slot 8 g + 4 t' + e
+    // of unit 16 t' + 4 g + e inside each 32-unit chunk
+    const int slot = st.x == 0 ? 4 * t : 32 * (t >> 3) + 8 * (t & 3) + 4 * ((t >> 2) & 1);
+    if (t < np) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) *reinterpret_cast<uint2 *>(buf + r * WD_RS + slot) = x.w[r];
+    }
+    if (st.x == 1) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int pc = t + 256 * j;
+            *reinterpret_cast<uint2 *>(buf + 16 * WD_RS + (pc >> 2) * WD_VS + 4 * (pc & 3)) = x.v[j];
+        }
+    }
+}
+
+// A lane's first-layer activations: chunk k (hidden units 32 k .. 32 k + 31
+// in k-slot order) is dwords 4 k .. 4 k + 3; vectors of 32 dwords, so that a
+// write at a wave-uniform index is an indexed register move.
+typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
+typedef uint32_t u32x4w __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+struct WdAct {
+    u32x32 q0, q1, q2, q3;
+};
+static_assert(WD_NH == 32, "four activation vectors");
+
+__device__ __forceinline__ bf16x8 wd_chunk(const WdAct &a, int k) {
+    const u32x32 &v = (k >> 3) == 0 ? a.q0 : ((k >> 3) == 1 ? a.q1 : ((k >> 3) == 2 ? a.q2 : a.q3));
+    const int b = 4 * (k & 7);
+    const u32x4w r = {v[b], v[b + 1], v[b + 2], v[b + 3]};
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+// half tile ht (units 16 ht + 4 g + e of the lane's chain) = dwords 2 ht, 2 ht + 1
+__device__ __forceinline__ void wd_put(WdAct &a, int ht, uint32_t lo, uint32_t hi) {
+    const int e = 2 * (ht & 15);
+    switch (ht >> 4) {
+    case 0:
+        a.q0[e] = lo;
+        a.q0[e + 1] = hi;
+        break;
+    case 1:
+        a.q1[e] = lo;
+        a.q1[e + 1] = hi;
+        break;
+    case 2:
+        a.q2[e] = lo;
+        a.q2[e + 1] = hi;
+        break;
+    default:
+        a.q3[e] = lo;
+        a.q3[e + 1] = hi;
+        break;
+    }
+}
+
+// One step on the staged rows `cur` (see made_sample_wide_kernel).  The K
+// chunks run in groups of eight whose A (and layer-1 B) operands are read
+// from LDS together; nk is a multiple of 8 except at the end of a row, so
+// only a row's last group selects zero operands past nk.
+__device__ __forceinline__ void wd_step(const bf16 *cur, int4 st, int c, int g, const uint32_t (&lat)[WD_NX],
+                                        WdAct &act1, f32x4 (&lacc)[WD_NB], const bf16x8 *lut, const float *b1s,
+                                        const float *b2s) {
+    const int nk = st.z, ht = st.y >> 4;
+    // units 16 ht + r (A row r = c) against the lane's chain: outputs unit
+    // 16 ht + 4 g + e of chain c
+    const bf16 *arow = cur + c * WD_RS + 8 * g;
+    const bf16x8 zero = {};
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (st.x == 0) {
+#pragma unroll
+        for (int q = 0; q < WD_NX / 8; ++q) {
+            if (8 * q >= nk) break;
+            bf16x8 av[8], bv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                av[j] = *reinterpret_cast<const bf16x8 *>(arow + 32 * (8 * q + j));
+                bv[j] = lut[(lat[8 * q + j] >> (8 * g)) & 0xffu];
+            }
+            if (8 * q + 8 <= nk) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[j], bv[j], acc, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(8 * q + j < nk ? av[j] : zero, bv[j], acc, 0, 0, 0);
+            }
+        }
+        const float *bias = b1s + st.y + 4 * g;
+        wd_put(act1, ht, pack_bf16(relu(acc[0] + bias[0]), relu(acc[1] + bias[1])),
+               pack_bf16(relu(acc[2] + bias[2]), relu(acc[3] + bias[3])));
+    } else {
+#pragma unroll
+        for (int q = 0; q < WD_NH / 8; ++q) {
+            if (8 * q >= nk) break;
+            bf16x8 av[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) av[j] = *reinterpret_cast<const bf16x8 *>(arow + 32 * (8 * q + j));
+            if (8 * q + 8 <= nk) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[j], wd_chunk(act1, 8 * q + j), acc, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(8 * q + j < nk ? av[j] : zero,
+                                                                  wd_chunk(act1, 8 * q + j), acc, 0, 0, 0);
+            }
+        }
+        // the phase's units of the half tile, as the B operand (K = unit
+        // 16 ht + 4 g + e) of the logit blocks' products
+        const int lo = st.w & 0xff, hi = st.w >> 8;
+        const float *bias = b2s + st.y + 4 * g;
+        float y[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int u = 4 * g + e;
+            y[e] = (u >= lo && u < hi) ? relu(acc[e] + bias[e]) : 0.f;
+        }
+        const s16x4 bv = __builtin_bit_cast(s16x4, uint2{pack_bf16(y[0], y[1]), pack_bf16(y[2], y[3])});
+        const bf16 *vrow = cur + 16 * WD_RS + c * WD_VS + 4 * g;
+        s16x4 va[WD_NB];
+#pragma unroll
+        for (int b = 0; b < WD_NB; ++b) va[b] = *reinterpret_cast<const s16x4 *>(vrow + 16 * b * WD_VS);
+#pragma unroll
+        for (int b = 0; b < WD_NB; ++b) lacc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(va[b], bv, lacc[b], 0, 0, 0);
+    }
+}
+
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void
+made_sample_wide_kernel(SampleArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const WdLayout L = wd_layout(a.D, a.H);
+    bf16x8 *lut = reinterpret_cast<bf16x8 *>(smem + L.lut);
+    float *b1s = reinterpret_cast<float *>(smem + L.b1);
+    float *b2s = reinterpret_cast<float *>(smem + L.b2);
+    float *cs = reinterpret_cast<float *>(smem + L.c);
+    int *fp = reinterpret_cast<int *>(smem + L.fp);
+    bf16 *buf = reinterpret_cast<bf16 *>(smem + L.buf);
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) lut[i] = bits_to_bf16x8((uint32_t)i);
+    for (int i = threadIdx.x; i < a.H; i += blockDim.x) {
+        b1s[i] = a.b1[i];
+        b2s[i] = a.b2[i];
+    }
+    for (int i = threadIdx.x; i < a.D; i += blockDim.x) cs[i] = a.c[i];
+    for (int i = threadIdx.x; i < a.h; i += blockDim.x) fp[i] = a.wphase[i].z;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    const int wave = threadIdx.x >> 6;
+    const int my_chain = (blockIdx.x * 4 + wave) * 16 + c;
+    const bool valid = my_chain < a.n;
+    const uint32_t *B = a.blob;
+    const uint32_t *cw = B + B[H_OFF_CONST];
+    const uint32_t cid = B[H_CID];
+    const int W = a.W;
+
+    uint32_t lat[WD_NX];
+    WdAct act1;
+    f32x4 lacc[WD_NB];
+#pragma unroll
+    for (int w = 0; w < WD_NX; ++w) lat[w] = w < W ? cw[w] : 0u;
+    act1.q0 = act1.q1 = act1.q2 = act1.q3 = u32x32{};
+#pragma unroll
+    for (int b = 0; b < WD_NB; ++b) lacc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    WdStage x;
+    if (a.nsteps > 0) {
+        const int4 st0 = a.wstep[0];
+        wd_fetch(a, fp, st0, x);
+        wd_store(buf, st0, x);
+    }
+    __syncthreads();
+    double lq = 0.0;
+    U4 u4 = {0u, 0u, 0u, 0u};
+    for (int f = 0; f < a.h; ++f) {
+        const int4 ph = a.wphase[f];  // {first step, end step, p, 0}
+        const int p = ph.z;
+        // score mode: the scored path's word holding bit p, loaded now and
+        // used after the phase's steps
+        const uint32_t pw = (a.score && valid) ? a.score[(int64_t)(p >> 5) * a.n + my_chain] : 0u;
+        for (int sidx = ph.x; sidx < ph.y; ++sidx) {
+            // {layer (0, 1), first unit 16 ht, K chunks, units of the phase
+            // in the half tile: [lo, hi) as lo | hi << 8}
+            const int4 st = a.wstep[sidx];
+            const bf16 *cur = buf + (sidx & 1) * WD_BUF;
+            const bool more = sidx + 1 < a.nsteps;
+            int4 nx = st;
+            if (more) {
+                nx = a.wstep[sidx + 1];
+                wd_fetch(a, fp, nx, x);  // in flight during this step's products
+            }
+            wd_step(cur, st, c, g, lat, act1, lacc, lut, b1s, b2s);
+            if (more) wd_store(buf + ((sidx + 1) & 1) * WD_BUF, nx, x);
+            __syncthreads();
+        }
+        // the logit of free bit f: element f & 3 of block f >> 4 on the lanes
+        // of group (f & 15) >> 2, passed to the chain's four lane groups
+        float mine = 0.f;
+#pragma unroll
+        for (int b = 0; b < WD_NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if ((f >> 4) == b && (f & 3) == e) mine = lacc[b][e];
+        const float lg = __shfl(mine, c + 16 * ((f & 15) >> 2), 64);
+        // the bit of free bit f: drawn against the threshold of the logit,
+        // or read from the scored path; every lane group does its chain's
+        const uint32_t T = made_threshold(lg + cs[p]);
+        uint32_t bit;
+        if (!a.score) {
+            if ((f & 3) == 0)
+                u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + (uint32_t)my_chain, cid | (1u << 16),
+                                   a.seed_lo, a.seed_hi);
+            const uint32_t u = (f & 3) == 0 ? u4.x : ((f & 3) == 1 ? u4.y : ((f & 3) == 2 ? u4.z : u4.w));
+            bit = u < T ? 1u : 0u;
+        } else {
+            bit = (pw >> (p & 31)) & 1u;
+        }
+        // log q in free-bit order
+        lq += made_log_prob(T, bit);
+        // the lattice bit at p is the free bit itself: flip its cone when
+        // the new value differs from the current one
+        const uint32_t m = 0u - (((pick_word(lat, p >> 5) >> (p & 31)) & 1u) ^ bit);
+        const uint32_t *cone = a.wcone + (size_t)f * a.cone_stride;  // wave-uniform
+#pragma unroll
+        for (int w = 0; w < WD_NX; ++w)
+            if (w < W) lat[w] ^= m & cone[w];
+    }
+    if (g == 0 && valid) {
+        if (a.out && !a.score)
+            for (int w = 0; w < W; ++w) a.out[(int64_t)w * a.n + my_chain] = pick_word(lat, w);
+        a.logq[my_chain] = lq;
+    }
+}
+
+hipError_t launch_wide(const SampleArgs &a, hipStream_t s) {
+    const size_t lds = wd_layout(a.D, a.H).total;
+    const int grid = (a.n + 63) / 64;
+    hipError_t e = hipFuncSetAttribute((const void *)made_sample_wide_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(made_sample_wide_kernel, dim3(grid), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+// The scorer's last stage for the networks of made_sample_wide_kernel: the
+// logits of the scored paths from their second-layer activations H2 (the
+// GEMMs' bf16 output, row per path), added in the sampler's order (each
+// layer-2 step in turn: the phase's units of the half tile against the rows
+// of V of every free bit, one 16 x 16 x 16 product per block of 16 free
+// bits), and log q as the sampler sums it.  The sampler reads the logit of a
+// free bit after the steps of its phase; the later steps add to it only
+// products with weights V's mask keeps at zero (+0 each), so reading every
+// logit after the last step gives the same bits.
+// A workgroup scores 64 paths, a wave 16 of them (lane (c, g): path c,
+// units 4 g .. 4 g + 3 of a half tile) over all blocks.  The steps come in
+// 64-unit panels (the step list's half tiles never decrease): the panel's
+// columns of V for every free bit and of H2 for the 64 paths are staged in
+// LDS with whole-row loads, the next panel's loads in flight while the
+// current one's steps run.
+constexpr int WD_MAXL2 = 2 * WD_NH + 2 * 16 * WD_NB;  // layer-2 steps of a schedule, at most
+constexpr int RP_PS = 64 + 4;                          // LDS row stride of a panel (elements)
+constexpr int RP_V = 16 * WD_NB * RP_PS;               // elements of a V panel
+constexpr int RP_H = 64 * RP_PS;                       // elements of an H2 panel
+constexpr int RP_STAGE = (RP_V + RP_H) * 2;            // bytes of one stage
+constexpr int RP_LC = 32;                              // free bits of a chunk of log q terms
+constexpr int RP_END = 16 * WD_NB * 64 * 4 + RP_LC * 64 * 8;  // bytes of the logits and log q terms
+
+__global__ __launch_bounds__(256) void wd_replay_kernel(ReplayArgs a) {
+    __shared__ __align__(16) unsigned char sm[2 * RP_STAGE > RP_END ? 2 * RP_STAGE : RP_END];
+    __shared__ int2 l2s[WD_MAXL2];
+    __shared__ int fps[16 * WD_NB];
+    for (int i = threadIdx.x; i < a.n2; i += blockDim.x) l2s[i] = a.l2[i];
+    for (int i = threadIdx.x; i < 16 * WD_NB; i += blockDim.x) fps[i] = i < a.h ? a.fpos[i] : 0;
+    __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, c = lane & 15, g = lane >> 4, wave = t >> 6;
+    const int pbase = blockIdx.x * 64;  // first path of the workgroup in the batch
+    // panel k's pieces of 16 bytes: V row f = i >> 3 (the row of free bit f,
+    // zero past the last), H2 row r (path pbase + r, clamped)
+    uint4 pv[4], ph[2];
+    auto fetch = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int id = t + 256 * i, f = id >> 3;
+            pv[i] = *reinterpret_cast<const uint4 *>(a.VT + (int64_t)fps[f] * a.H + 64 * k + 8 * (id & 7));
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int id = t + 256 * i, r = id >> 3, j = pbase + r < a.nb ? pbase + r : 0;
+            ph[i] = *reinterpret_cast<const uint4 *>(a.H2 + (int64_t)j * a.H + 64 * k + 8 * (id & 7));
+        }
+    };
+    auto stage = [&](int buf) __attribute__((always_inline)) {
+        bf16 *V = reinterpret_cast<bf16 *>(sm + buf * RP_STAGE), *Hs = V + RP_V;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int id = t + 256 * i, f = id >> 3;
+            *reinterpret_cast<uint4 *>(V + f * RP_PS + 8 * (id & 7)) = f < a.h ? pv[i] : uint4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int id = t + 256 * i;
+            *reinterpret_cast<uint4 *>(Hs + (id >> 3) * RP_PS + 8 * (id & 7)) = ph[i];
+        }
+    };
+    f32x4 lacc[WD_NB];
+#pragma unroll
+    for (int b = 0; b < WD_NB; ++b) lacc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int np = a.H / 64;
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int si = 0;
+    for (int k = 0; k < np; ++k) {
+        if (k + 1 < np) fetch(k + 1);
+        const bf16 *V = reinterpret_cast<const bf16 *>(sm + (k & 1) * RP_STAGE), *Hs = V + RP_V;
+        for (; si < a.n2 && (l2s[si].x >> 6) == k; ++si) {
+            const int2 st = l2s[si];
+            const int lo = st.y & 0xff, hi = (st.y >> 8) & 0xff, u0 = (st.x & 63) + 4 * g;
+            uint2 h = *reinterpret_cast<const uint2 *>(Hs + (16 * wave + c) * RP_PS + u0);
+            // units of the half tile outside the phase: zero
+            const int v0 = 4 * g;
+            if (!(v0 >= lo && v0 < hi)) h.x &= 0xffff0000u;
+            if (!(v0 + 1 >= lo && v0 + 1 < hi)) h.x &= 0x0000ffffu;
+            if (!(v0 + 2 >= lo && v0 + 2 < hi)) h.y &= 0xffff0000u;
+            if (!(v0 + 3 >= lo && v0 + 3 < hi)) h.y &= 0x0000ffffu;
+            const s16x4 bv = __builtin_bit_cast(s16x4, h);
+            s16x4 va[WD_NB];
+#pragma unroll
+            for (int b = 0; b < WD_NB; ++b)
+                va[b] = *reinterpret_cast<const s16x4 *>(V + (16 * b + c) * RP_PS + u0);
+#pragma unroll
+            for (int b = 0; b < WD_NB; ++b)
+                lacc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(va[b], bv, lacc[b], 0, 0, 0);
+        }
+        __syncthreads();
+        if (k + 1 < np) stage((k + 1) & 1);
+        __syncthreads();
+    }
+    // lane (c, g) holds free bits 16 b + 4 g + e of path 16 wave + c; the
+    // stages' LDS now takes the logits and the log q terms
+    float *lgt = reinterpret_cast<float *>(sm);                         // [free bit][path]
+    double *lp = reinterpret_cast<double *>(sm + 16 * WD_NB * 64 * 4);  // [free bit of the chunk][path]
+#pragma unroll
+    for (int b = 0; b < WD_NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lgt[(16 * b + 4 * g + e) * 64 + 16 * wave + c] = lacc[b][e];
+    __syncthreads();
+    // the log q terms of RP_LC free bits at a time in parallel, then each
+    // path adds them to its sum in free-bit order
+    double lq = 0.0;
+    for (int f0 = 0; f0 < a.h; f0 += RP_LC) {
+        for (int idx = t; idx < 64 * RP_LC; idx += blockDim.x) {
+            const int f = f0 + (idx >> 6), r = idx & 63, j = pbase + r;
+            if (f < a.h && j < a.nb) {
+                const int p = fps[f];
+                const uint32_t T = made_threshold(lgt[f * 64 + r] + a.c[p]);
+                const uint32_t w = a.states[(int64_t)(p >> 5) * a.n + a.b0 + j];
+                lp[idx] = made_log_prob(T, (w >> (p & 31)) & 1u);
+            }
+        }
+        __syncthreads();
+        if (t < 64) {
+            const int fe = f0 + RP_LC < a.h ? f0 + RP_LC : a.h;
+            for (int f = f0; f < fe; ++f) lq += lp[(f - f0) * 64 + t];
+        }
+        __syncthreads();
+    }
+    if (t < 64 && pbase + t < a.nb) a.logq[pbase + t] = lq;
+}
+
+hipError_t launch_wide_replay(const ReplayArgs &a, hipStream_t s) {
+    if (a.nb <= 0) return hipSuccess;
+    if (a.h > 16 * WD_NB || a.H % 64 || a.n2 < 0 || a.n2 > WD_MAXL2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(wd_replay_kernel, dim3((a.nb + 63) / 64), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int NX, int NH, int NB, int NP, bool FULL>
 hipError_t launch_reg_k(const SampleArgs &a, size_t lds, hipStream_t s) {
     // enough waves per workgroup to share the staged network, few enough to
@@ -1230,7 +1709,7 @@ static size_t made_sample_lds(SampleArgs &a) {
 
 bool made_sample_launchable(const SampleArgs &a0) {
     SampleArgs a = a0;
-    return reg_fits(a) || made_sample_lds(a) <= 160 * 1024;
+    return reg_fits(a) || made_sample_wide_ok(a) || made_sample_lds(a) <= 160 * 1024;
 }
 
 hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
@@ -1242,6 +1721,8 @@ hipError_t launch_made_sample(const SampleArgs &a0, hipStream_t s) {
         if (reg_chunks(a.DP) && (a.H == 64 || a.H == 128)) return launch_full_w<1>(a, lds, s);
         return launch_reg_k<8, 8, 1, 1, false>(a, lds, s);
     }
+    // wider networks on lattices of at most 512 bits: the wide one
+    if (made_sample_wide_ok(a) && a.wstep) return launch_wide(a, s);
     const int grid = (a.n + 15) / 16;
     const size_t lds = made_sample_lds(a);
     if (lds > 160 * 1024) return hipErrorInvalidValue;

@@ -83,12 +83,40 @@ struct SampleArgs {
     double *logq_cur;     // dual mode: log q of the scored current paths
     const uint32_t *score;  // score mode: word-major paths whose bits are read instead of drawn
     int defer;            // set by the launcher: 0 logs in the loop, 1/2 deferred (2: over the activations)
+    // the wide register-resident sampler's schedule: per free bit {first
+    // step, end step, lattice position p, 0}; per step {layer (0 or 1),
+    // first unit of the half tile, K chunks, for layer 2 the phase's units
+    // [lo, hi) of the half tile as lo | hi << 8}; per free bit its cone
+    // words (cone_stride apart)
+    const int4 *wphase, *wstep;
+    const uint32_t *wcone;
+    int cone_stride, nsteps;
 };
 
 hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s);
 // True if one of the samplers can run the shape of a (n, h, W, D, DP, H set):
 // the register-resident kernel, or made_sample_kernel within 160 KiB of LDS.
 bool made_sample_launchable(const SampleArgs &a);
+// True if the wide register-resident sampler takes the shape of a (networks
+// of 256 < H <= 1024, lattices of at most 512 bits, at most 128 free bits);
+// its scorer is then the GEMMs and launch_wide_replay.
+bool made_sample_wide_ok(const SampleArgs &a);
+// The scorer's logits and log q for the networks of the wide sampler
+// (made_sample_wide_ok), from the batch's second-layer activations: paths
+// b0 .. b0 + nb - 1 of `states` (word-major, n paths a word), H2 row i =
+// path b0 + i, log q into logq[0 .. nb).  l2: the sampler's layer-2 steps
+// in order, {first unit of the half tile, lo | hi << 8}; fpos: the lattice
+// position of each free bit.
+struct ReplayArgs {
+    const bf16 *H2, *VT;
+    const float *c;
+    const int2 *l2;
+    const int *fpos;
+    const uint32_t *states;
+    int n, b0, nb, h, H, n2;
+    double *logq;
+};
+hipError_t launch_wide_replay(const ReplayArgs &a, hipStream_t s);
 // One pass that draws proposals (out, logq) and scores the paths in `score`
 // (logq_cur) with the arithmetic of the two separate calls; only for the
 // networks made_sample_dual_ok accepts (H <= 256, lattices <= 256 bits).

@@ -87,6 +87,10 @@ struct pbit_proposal_s {
     // count in the high half, the logit's K chunk count, the lattice
     // position, then the free bit's cone words (W <= 8)
     std::vector<uint32_t> sched;
+    // the wide sampler's schedule (SampleArgs::wphase, wstep, wcone)
+    std::vector<int4> wphase, wstep;
+    std::vector<uint32_t> wcone;
+    std::vector<int2> l2;  // its layer-2 steps, {first unit, lo | hi << 8} (the scorer's replay)
     int dev = -1;
     DeviceArena arena;
     // device
@@ -97,6 +101,9 @@ struct pbit_proposal_s {
     int *k1end = nullptr, *k2end = nullptr, *k3end = nullptr, *g2beg = nullptr, *g1beg = nullptr;
     int4 *d_phase = nullptr, *d_phase_k = nullptr;
     uint32_t *d_sched = nullptr;
+    int4 *d_wphase = nullptr, *d_wstep = nullptr;
+    uint32_t *d_wcone = nullptr;
+    int2 *d_l2 = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
     float *L = nullptr;
     float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / COLSUM_ROWS) x max(D, H)
@@ -182,10 +189,18 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->d_phase = A.alloc<int4>(q->phase.size() + 1);
     q->d_phase_k = A.alloc<int4>(q->phase_k.size() + 1);
     q->d_sched = A.alloc<uint32_t>(q->sched.size() + 16);
+    q->d_wphase = A.alloc<int4>(q->wphase.size() + 1);
+    q->d_wstep = A.alloc<int4>(q->wstep.size() + 1);
+    q->d_wcone = A.alloc<uint32_t>(q->wcone.size() + 1);
+    q->d_l2 = A.alloc<int2>(q->l2.size() + 1);
     if (!q->theta || !q->L || !q->colpart || !q->part || !q->lpart || !q->d_phase || !q->d_phase_k || !q->g1beg ||
-        !q->d_sched)
+        !q->d_sched || !q->d_wphase || !q->d_wstep || !q->d_wcone || !q->d_l2)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
     copy(q->d_sched, q->sched.data(), q->sched.size() * sizeof(uint32_t));
+    copy(q->d_wphase, q->wphase.data(), q->wphase.size() * sizeof(int4));
+    copy(q->d_wstep, q->wstep.data(), q->wstep.size() * sizeof(int4));
+    copy(q->d_wcone, q->wcone.data(), q->wcone.size() * sizeof(uint32_t));
+    copy(q->d_l2, q->l2.data(), q->l2.size() * sizeof(int2));
     copy(q->d_phase, q->phase.data(), q->phase.size() * sizeof(int4));
     copy(q->d_phase_k, q->phase_k.data(), q->phase_k.size() * sizeof(int4));
     copy(q->theta, q->host_params.data(), q->P * sizeof(float));
@@ -235,7 +250,10 @@ void splitk(pbit_proposal q, GemmArgs &g) {
 }
 
 // Forward of n <= BATCH_MAX paths (X already unpacked): H1, H2, L.
-pbit_status forward(pbit_proposal q, int n, hipStream_t s) {
+// The network on the batch in q->X.  For the wide sampler's scorer (wide):
+// layer 2 in the sampler's k-slot order, and no logits (the replay adds
+// them in the sampler's order).
+pbit_status forward(pbit_proposal q, int n, hipStream_t s, bool wide = false) {
     const int D = q->D, DP = q->DP, H = q->H;
     GemmArgs g = gemm0();
     g.A = q->X; g.sam = DP; g.sak = 1;
@@ -251,7 +269,9 @@ pbit_status forward(pbit_proposal q, int n, hipStream_t s) {
     g.C = q->H2; g.scm = H; g.scn = 1;
     g.M = n; g.N = H; g.K = H;
     g.kend = q->k2end; g.bias = q->theta + q->ob2; g.relu = 1; g.out_bf16 = 1;
+    g.kperm = wide ? 1 : 0;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm2");
+    if (wide) return PBIT_OK;
     g = gemm0();
     g.A = q->H2; g.sam = H; g.sak = 1;
     g.B = q->VT; g.sbk = 1; g.sbn = H;
@@ -448,8 +468,25 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
                                  (m2 & 0xffffu) | ((uint32_t)((k2 + 31) / 32) << 16), (uint32_t)((k3 + 31) / 32),
                                  (uint32_t)p};
         for (uint32_t r : rec) q->sched.push_back(r);
+        // the wide sampler's steps: the layer-1 half tiles holding a unit of
+        // the phase, then the layer-2 ones with the phase's units among their
+        // 16 ([lo, hi) as lo | hi << 8), whose logit terms are added then
+        const int s0 = (int)q->wstep.size();
+        // (K chunks rounded up to a multiple of 8 within the row: the extra
+        // chunks meet weights the degree masks keep at zero)
+        const int nk1 = std::min((k1 + 255) / 256 * 8, q->DP / 32), nk2 = std::min((k2 + 255) / 256 * 8, (int)H / 32);
+        if (u1b > u1a)
+            for (int ht = u1a / 16; ht <= (u1b - 1) / 16; ++ht) q->wstep.push_back(int4{0, 16 * ht, nk1, 0});
+        if (u2b > u2a)
+            for (int ht = u2a / 16; ht <= (u2b - 1) / 16; ++ht) {
+                const int lo = std::max(u2a - 16 * ht, 0), hi = std::min(u2b - 16 * ht, 16);
+                q->wstep.push_back(int4{1, 16 * ht, nk2, lo | hi << 8});
+                q->l2.push_back(int2{16 * ht, lo | hi << 8});
+            }
+        q->wphase.push_back(int4{s0, (int)q->wstep.size(), p, 0});
         const uint32_t *cn = k.blob.data() + k.blob[H_OFF_CONE] + (size_t)b * k.WS;
         for (uint32_t w = 0; w < 8; ++w) q->sched.push_back(w < k.W ? cn[w] : 0u);
+        for (uint32_t w = 0; w < k.W; ++w) q->wcone.push_back(cn[w]);
     }
     // initial parameters
     q->host_params.assign(q->P, 0.f);
@@ -657,6 +694,11 @@ pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, u
     a.logq = d_logq;
     a.score = score;
     a.logq_cur = d_logq_cur;
+    a.wphase = q->d_wphase;
+    a.wstep = q->d_wstep;
+    a.wcone = q->d_wcone;
+    a.cone_stride = q->W;
+    a.nsteps = (int)q->wstep.size();
     if (d_logq_cur) {
         hipError_t e = launch_made_sample_dual(a, s);
         if (e != hipSuccess) return hip_error(e, "made sampler (sample and score)");
@@ -675,18 +717,48 @@ pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint3
                                 void *hip_stream) {
     if (!q || !d_states || !d_logq) return set_error(PBIT_E_INVALID_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)hip_stream;
-    // small networks: the fused kernel in score mode (one launch); large ones:
-    // the batched GEMMs.  Both give the same bits.
+    // small networks: the sampler's own kernel in score mode.  Else the
+    // batched GEMMs, whose activations carry the samplers' bits, then the
+    // logits in the order of the sampler that serves the shape: the wide
+    // sampler's replay, or one more GEMM (made_sample_kernel's order).  The
+    // scorer gives the sampler's bits either way.
     if (q->H <= SCORE_FUSED_MAX_H) return sample_or_score(q, n, 0, 0, 0, nullptr, d_logq, d_states, s);
+    SampleArgs probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.H = q->H;
+    probe.h = q->h;
+    probe.W = q->W;
+    probe.D = q->D;
+    probe.DP = q->DP;
+    const bool wide = made_sample_wide_ok(probe);
     pbit_status st = upload(q, s);
     if (st != PBIT_OK) return st;
     if ((st = refresh(q, s)) != PBIT_OK) return st;
     for (uint32_t b0 = 0; b0 < n; b0 += BATCH_MAX) {
         const int nb = (int)std::min<uint32_t>(BATCH_MAX, n - b0);
         if ((st = unpack_range(q, d_states, n, b0, nb, s)) != PBIT_OK) return st;
-        if ((st = forward(q, nb, s)) != PBIT_OK) return st;
-        hipError_t e = launch_logq(q->L, d_states, n, b0, q->d_fpos, q->h, nb, q->D, d_logq + b0, s);
-        if (e != hipSuccess) return hip_error(e, "logq");
+        if ((st = forward(q, nb, s, wide)) != PBIT_OK) return st;
+        hipError_t e;
+        if (wide) {
+            ReplayArgs r;
+            r.H2 = q->H2;
+            r.VT = q->VT;
+            r.c = q->theta + q->oc;
+            r.l2 = q->d_l2;
+            r.fpos = q->d_fpos;
+            r.n2 = (int)q->l2.size();
+            r.states = d_states;
+            r.n = (int)n;
+            r.b0 = (int)b0;
+            r.nb = nb;
+            r.h = q->h;
+            r.H = q->H;
+            r.logq = d_logq + b0;
+            e = launch_wide_replay(r, s);
+        } else {
+            e = launch_logq(q->L, d_states, n, b0, q->d_fpos, q->h, nb, q->D, d_logq + b0, s);
+        }
+        if (e != hipSuccess) return hip_error(e, wide ? "logit replay" : "logq");
     }
     return PBIT_OK;
 }
@@ -700,6 +772,7 @@ pbit_status pbit_proposal_sample_score(pbit_proposal q, uint32_t n, uint32_t cha
     SampleArgs probe;
     std::memset(&probe, 0, sizeof(probe));
     probe.H = q->H;
+    probe.h = q->h;
     probe.W = q->W;
     probe.D = q->D;
     probe.DP = q->DP;

@@ -251,11 +251,12 @@ def _sample(env, q, n, seed=3, step=0):
     return d_out, d_lq
 
 
-@pytest.mark.parametrize("which,H", [("small", 64), ("small", 512), ("brick16", 1024)])
+@pytest.mark.parametrize("which,H", [("small", 64), ("small", 512), ("brick16", 1024), ("small", 1152)])
 def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
     """Sampled paths are valid lattices; scoring them gives the sampler's log q
-    bit for bit (H = 64: the fused kernel in score mode; 512, 1024: the
-    batched GEMM forward)."""
+    bit for bit (H = 64: the fused kernel in score mode; 512, 1024: the wide
+    sampler against the batched GEMMs and the logit replay; 1,152:
+    made_sample_kernel against the batched GEMM forward)."""
     torch, pbit = env
     c = SMALL() if which == "small" else wc.workload_circuit("brick16")
     s = pbit.CircuitSet(c)
@@ -278,7 +279,8 @@ def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
 
 
 @pytest.mark.parametrize("which,H,n", [("small", 64, 3001), ("rh48", 128, 4099), ("small", 256, 2000),
-                                        ("w4", 128, 2000), ("w8", 64, 1500), ("brick16", 1024, 1000)])
+                                        ("w4", 128, 2000), ("w8", 64, 1500), ("brick16", 1024, 1000),
+                                        ("small", 1152, 1000)])
 def test_sample_score_equals_separate_calls(env, which, H, n):
     """The MH step's fused pass (proposals drawn and the current paths scored
     in one kernel for small networks; the two calls in sequence otherwise)
@@ -314,13 +316,13 @@ def test_sample_score_equals_separate_calls(env, which, H, n):
 
 
 @pytest.mark.parametrize("which,H,n", [("small", 64, 4096), ("rh48", 128, 4099), ("small", 512, 2000),
-                                        ("brick16", 1024, 1024)])
+                                        ("brick16", 1024, 1024), ("small", 1152, 2000)])
 def test_sampler_logq_matches_oracle(env, which, H, n):
     """log q of sampled paths against the FP64 oracle's log q on the same
     bf16 weights, within the bound carried from the logits (|d log
     sigma(z) / dz| <= 1) plus the FP32 sigmoid and the 2^-32 quantisation of
     the threshold; H <= 256 runs the register-resident sampler, H = 512 and
-    1,024 made_sample_kernel."""
+    1,024 the wide sampler, H = 1,152 made_sample_kernel."""
     torch, pbit = env
     if which == "small":
         c = SMALL()
@@ -351,11 +353,11 @@ def test_sampler_logq_matches_oracle(env, which, H, n):
     assert np.all(err <= 1.5 * bound)
 
 
-@pytest.mark.parametrize("H", [64, 512])
+@pytest.mark.parametrize("H", [64, 512, 1152])
 def test_sampler_distribution_is_q(env, H):
     """The sampled path law is q: chi-square over all 2^h paths of a small
-    circuit (H = 64: the register-resident sampler; H = 512:
-    made_sample_kernel)."""
+    circuit (H = 64: the register-resident sampler; H = 512: the wide
+    sampler; H = 1,152: made_sample_kernel)."""
     torch, pbit = env
     c = wc.rotated_hadamard_chain(7, math.pi / 5, K=1)
     s = pbit.CircuitSet(c)
