@@ -43,6 +43,21 @@ struct GemmArgs {
     // 16 t + 4 g + e), so each output sums its products as the wide sampler
     // does; needs both operands in mode 0 (k contiguous)
     int kperm;
+    // split-K partial sums stay in `part` (ksplit slices, or one with
+    // ksplit <= 1) for a later reduction; no epilogue
+    int keep_parts;
+    // per 64-row tile column sums of the stored output, in a fixed order:
+    // colpart[(m / 64) N + n] (fp32; bf16 outputs are summed as stored)
+    float *colpart;
+    // logits to loss gradient: C(m, n) becomes (sigmoid(v) - x) inv_n on the
+    // columns with lossfree[n] (0 elsewhere), x = lossx[m slx + n], and each
+    // tile's share of the batch-mean binary cross-entropy goes to
+    // losspart[tile] (tiles numbered row-major over the 64 x 64 grid)
+    const bf16 *lossx;
+    int64_t slx;
+    const int *lossfree;
+    float inv_n;
+    float *losspart;
 };
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             }
         }
     }
-    if (g.ksplit > 1) {
+    if (g.ksplit > 1 || g.keep_parts) {
         // raw partial sums of this slice; the reduction applies the epilogue
         float *part = g.part + (int64_t)blockIdx.z * g.M * g.N;
 #pragma unroll
@@ -281,14 +281,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // branches (clamped addresses), so the loads overlap; only the stores
     // are guarded
     float bias_j[F];
-    int dcol[F];
+    int dcol[F], lfree[F];
 #pragma unroll
     for (int j = 0; j < F; ++j) {
         const int n = n0 + wc + j * 16 + (lane & 15);
         const int nc = n < g.N ? n : g.N - 1;
         bias_j[j] = g.bias ? g.bias[nc] : 0.f;
         dcol[j] = g.deg_col ? g.deg_col[nc] : 0;
+        lfree[j] = g.lossx ? g.lossfree[nc] : 0;
     }
+    float csum[F];  // this lane's share of its columns' tile sums
+#pragma unroll
+    for (int j = 0; j < F; ++j) csum[j] = 0.f;
+    float nll = 0.f;
     int drow[F][4];
 #pragma unroll
     for (int i = 0; i < F; ++i)
@@ -322,16 +327,71 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 if (g.relu) v = v > 0.f ? v : 0.f;
                 if (g.gate && !((float)gv[j][e] > 0.f)) v = 0.f;
                 if (masked && drow[i][e] > dcol[j]) v = 0.f;
-                if (m < g.M && n < g.N) {
-                    const int64_t o = (int64_t)m * g.scm + (int64_t)n * g.scn;
-                    if (g.out_bf16)
-                        reinterpret_cast<bf16 *>(g.C)[o] = (bf16)v;
-                    else if (g.accumulate)
-                        reinterpret_cast<float *>(g.C)[o] += v;
-                    else
-                        reinterpret_cast<float *>(g.C)[o] = v;
+                const bool inside = m < g.M && n < g.N;
+                if (g.lossx) {
+                    // v is the logit z: one exponential t = e^-|z| gives
+                    // sigmoid(z) (1 / (1 + t) for z >= 0, t / (1 + t)
+                    // below) and the loss, softplus(-z) for x = 1 and
+                    // softplus(z) for x = 0, softplus(y) = max(y, 0) + log1p(t)
+                    float gval = 0.f;
+                    if (inside && lfree[j]) {
+                        const float x = (float)g.lossx[(int64_t)m * g.slx + n];
+                        const float t = expf(-fabsf(v));
+                        const float r = __builtin_amdgcn_rcpf(1.f + t);  // 1 + t in [1, 2]
+                        const float sg = v >= 0.f ? r : t * r;
+                        gval = (sg - x) * g.inv_n;
+                        const float zz = x > 0.5f ? -v : v;
+                        nll += (fmaxf(zz, 0.f) + log1pf(t)) * g.inv_n;
+                    }
+                    v = gval;
                 }
+                float stored = 0.f;
+                if (inside) {
+                    const int64_t o = (int64_t)m * g.scm + (int64_t)n * g.scn;
+                    if (g.out_bf16) {
+                        const bf16 b = (bf16)v;
+                        reinterpret_cast<bf16 *>(g.C)[o] = b;
+                        stored = (float)b;
+                    } else if (g.accumulate) {
+                        reinterpret_cast<float *>(g.C)[o] += v;
+                    } else {
+                        reinterpret_cast<float *>(g.C)[o] = v;
+                        stored = v;
+                    }
+                }
+                csum[j] += stored;
             }
+    }
+    if (g.colpart) {
+        // column sums over the tile's 64 rows: the four lane groups of a wave
+        // (a fixed butterfly), then rows 0..31 plus rows 32..63
+        __shared__ float cred[64];
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            csum[j] += __shfl_xor(csum[j], 16);
+            csum[j] += __shfl_xor(csum[j], 32);
+        }
+        if (wr != 0 && lane < 16) {
+#pragma unroll
+            for (int j = 0; j < F; ++j) cred[wc + j * 16 + lane] = csum[j];
+        }
+        __syncthreads();
+        if (wr == 0 && lane < 16) {
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                const int n = n0 + wc + j * 16 + lane;
+                if (n < g.N) g.colpart[(int64_t)tile_m * g.N + n] = csum[j] + cred[wc + j * 16 + lane];
+            }
+        }
+    }
+    if (g.lossx) {
+        // the tile's loss share: a butterfly within each wave, then the
+        // four waves in order
+        __shared__ float lred[4];
+        for (int o = 32; o > 0; o >>= 1) nll += __shfl_xor(nll, o);
+        if (lane == 0) lred[wave] = nll;
+        __syncthreads();
+        if (threadIdx.x == 0) g.losspart[tile] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
     }
 }
 
@@ -363,8 +423,12 @@ static int operand_mode(const bf16 *p, int64_t sr, int64_t sk, int R, int K) {
 }
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
-    if (g.ksplit > 1 && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part || (int64_t)g.M * g.N > INT32_MAX))
+    const bool parts = g.ksplit > 1 || g.keep_parts;
+    if (parts && (g.bias || g.relu || g.gate || g.out_bf16 || !g.part || g.colpart || g.lossx ||
+                  (int64_t)g.M * g.N > INT32_MAX))
         return hipErrorInvalidValue;
+    if (g.lossx && (!g.lossfree || !g.losspart || g.relu || g.gate || g.accumulate)) return hipErrorInvalidValue;
+    if (g.colpart && g.accumulate) return hipErrorInvalidValue;
     const int z = g.ksplit > 1 ? g.ksplit : 1;
     // 64 x 64 tiles: every product of the networks the proposal accepts
     // (H <= 2,496, batches <= 16,384) has fewer than sixteen 128 x 128 tiles
@@ -386,7 +450,7 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     void *args[] = {const_cast<GemmArgs *>(&g)};
     hipError_t e = hipLaunchKernel(fn, grid, dim3(256), args, 0, s);
     if (e == hipSuccess) e = hipGetLastError();
-    if (e != hipSuccess || g.ksplit <= 1) return e;
+    if (e != hipSuccess || g.ksplit <= 1 || g.keep_parts) return e;
     const int64_t tot = (int64_t)g.M * g.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g);
     return hipGetLastError();
@@ -406,137 +470,67 @@ __global__ void unpack_kernel(const uint32_t *__restrict__ states, int n, int D,
     X[e] = (bf16)v;
 }
 
-// dLoss/dL = (sigmoid(L) - x) / n on free positions; each workgroup writes
-// its share of the batch-mean binary cross-entropy to loss[blockIdx.x].
-// Grid-stride over the n D elements (a thread's elements in ascending order),
-// so a few thousand workgroups cover any batch.
-__global__ __launch_bounds__(256) void loss_grad_kernel(const float *__restrict__ L, const bf16 *__restrict__ X,
-                                                        const int *__restrict__ freem, int n, int D, int DP,
-                                                        float inv_n, bf16 *__restrict__ G, float *__restrict__ loss) {
-    __shared__ float red[4];
-    // n D < 2^31 (checked at launch): 32-bit index arithmetic
-    const uint32_t tot = (uint32_t)n * (uint32_t)D, stride = gridDim.x * 256u;
-    float nll = 0.f;
-    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < tot; e += stride) {
-        const uint32_t b = e / (uint32_t)D, i = e - b * (uint32_t)D;
-        const float z = L[e];
-        const float x = (float)X[(int64_t)b * DP + i];
-        float gval = 0.f;
-        if (freem[i]) {
-            // one exponential t = e^-|z|: sigmoid(z) = 1 / (1 + t) for z >= 0,
-            // t / (1 + t) below; the loss is softplus(-z) for x = 1 and
-            // softplus(z) for x = 0, softplus(y) = max(y, 0) + log1p(t)
-            const float t = expf(-fabsf(z));
-            const float r = __builtin_amdgcn_rcpf(1.f + t);  // 1 + t in [1, 2]
-            const float s = z >= 0.f ? r : t * r;
-            gval = (s - x) * inv_n;
-            const float zz = x > 0.5f ? -z : z;
-            nll += (fmaxf(zz, 0.f) + log1pf(t)) * inv_n;
-        }
-        G[e] = (bf16)gval;
-    }
-    // fixed-order reduction: butterfly within each wave, then the four waves
-    for (int o = 32; o > 0; o >>= 1) nll += __shfl_xor(nll, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nll;
-    __syncthreads();
-    if (threadIdx.x == 0) loss[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];  // per-block partial
-}
-
-// Sums the per-block partial losses in a fixed order into *out.
-__global__ __launch_bounds__(256) void loss_sum_kernel(const float *__restrict__ part, int nb, float *__restrict__ out) {
-    __shared__ float red[256];
-    float v = 0.f;
-#pragma unroll 8
-    for (int i = threadIdx.x; i < nb; i += 256) v += part[i];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+// The gradient of every parameter from what the training GEMMs left (the
+// weight gradients' split-K slices, added in ascending order and masked by
+// degree, the bias gradients' 64-row column partials, added in ascending
+// order), then either stored (adam == 0) or taken by one Adam step; block 0
+// also adds the loss shares in a fixed order.
+__global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
+    if (blockIdx.x == 0 && a.loss) {
+        __shared__ float red[256];
+        float v = 0.f;
+        for (int i = threadIdx.x; i < a.nloss; i += 256) v += a.losspart[i];
+        red[threadIdx.x] = v;
         __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = red[0];
-}
-
-// Column sums of a row-major n x N bf16 matrix in two deterministic passes:
-// workgroup (column tile, chunk of COLSUM_ROWS rows) sums its rows for 64
-// columns (four row groups, combined in a fixed order), then each column adds
-// its chunk partials (four interleaved sets in ascending chunk order,
-// combined in a fixed order).
-__global__ __launch_bounds__(256) void colsum_part_kernel(const bf16 *__restrict__ G, int n, int N,
-                                                          float *__restrict__ part) {
-    __shared__ float red[4][64];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + tx;
-    const int r0 = blockIdx.y * COLSUM_ROWS + ty * (COLSUM_ROWS / 4);
-    float s = 0.f;
-    if (j < N) {
-        const int r1 = min(r0 + COLSUM_ROWS / 4, n);
-        for (int b = r0; b < r1; ++b) s += (float)G[(int64_t)b * N + j];
-    }
-    red[ty][tx] = s;
-    __syncthreads();
-    if (ty == 0 && j < N) part[(int64_t)blockIdx.y * N + j] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
-}
-
-// Vector variant for N % 8 == 0 and a 16-byte aligned G: thread (column
-// group of 8, row group of 8) adds COLSUM_ROWS / 8 rows with one 16-byte load
-// per row; the eight row groups are combined in a fixed order.
-__global__ __launch_bounds__(256) void colsum_part8_kernel(const bf16 *__restrict__ G, int n, int N,
-                                                           float *__restrict__ part) {
-    __shared__ float red[8][256];
-    const int cg = threadIdx.x & 31, rg = threadIdx.x >> 5;
-    const int c0 = blockIdx.x * 256 + cg * 8;
-    const int rbase = blockIdx.y * COLSUM_ROWS;
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (c0 < N) {
-#pragma unroll
-        for (int q = 0; q < COLSUM_ROWS / 8; ++q) {
-            const int r = rbase + rg + 8 * q;
-            if (r < n) {
-                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(G + (int64_t)r * N + c0);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) acc[i] += (float)v[i];
-            }
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
         }
+        if (threadIdx.x == 0) *a.loss = red[0];
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) red[rg][cg * 8 + i] = acc[i];
-    __syncthreads();
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c < N) {
-        float s = 0.f;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s += red[q][threadIdx.x];
-        part[(int64_t)blockIdx.y * N + c] = s;
-    }
-}
-
-__global__ __launch_bounds__(256) void colsum_final_kernel(const float *__restrict__ part, int chunks, int N,
-                                                           float *__restrict__ out) {
-    __shared__ float red[4][64];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + tx;
-    float s = 0.f;
-    if (j < N) {
-#pragma unroll 4
-        for (int c = ty; c < chunks; c += 4) s += part[(int64_t)c * N + j];
-    }
-    red[ty][tx] = s;
-    __syncthreads();
-    if (ty == 0 && j < N) out[j] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
-}
-
-__global__ void adam_kernel(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
-                            const float *__restrict__ g, int64_t P, float lr, float b1, float b2, float eps, float c1,
-                            float c2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    th[i] = th[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    if (i >= a.P) return;
+    const int D = a.D, H = a.H;
+    auto slices = [&](const float *part, int z, int64_t MN, int64_t e) {
+        float v = 0.f;
+#pragma unroll 4
+        for (int k = 0; k < z; ++k) v += part[(int64_t)k * MN + e];
+        return v;
+    };
+    auto cols = [&](const float *part, int N, int j) {
+        float v = 0.f;
+        for (int k = 0; k < a.chunks; ++k) v += part[(int64_t)k * N + j];
+        return v;
+    };
+    float gi;
+    if (i < a.ob1) {  // W1 [D][H]
+        const int64_t e = i - a.oW1;
+        const int m = (int)(e / H), n = (int)(e - (int64_t)m * H);
+        gi = a.deg_in[m] > a.deg1[n] ? 0.f : slices(a.pW1, a.zW1, (int64_t)D * H, e);
+    } else if (i < a.oW2) {  // b1
+        gi = cols(a.cb1, H, (int)(i - a.ob1));
+    } else if (i < a.ob2) {  // W2 [H][H]
+        const int64_t e = i - a.oW2;
+        const int m = (int)(e / H), n = (int)(e - (int64_t)m * H);
+        gi = a.deg1[m] > a.deg2[n] ? 0.f : slices(a.pW2, a.zW2, (int64_t)H * H, e);
+    } else if (i < a.oV) {  // b2
+        gi = cols(a.cb2, H, (int)(i - a.ob2));
+    } else if (i < a.oc) {  // V [H][D]
+        const int64_t e = i - a.oV;
+        const int m = (int)(e / D), n = (int)(e - (int64_t)m * D);
+        gi = a.deg2[m] > a.deg_out[n] ? 0.f : slices(a.pV, a.zV, (int64_t)H * D, e);
+    } else {  // c
+        gi = cols(a.cc, D, (int)(i - a.oc));
+    }
+    if (!a.adam) {
+        a.grad[i] = gi;
+        return;
+    }
+    const float mi = a.b1 * a.m[i] + (1.f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    a.th[i] = a.th[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
 }
 
 // bf16 shadows of up to three K x N weights (row-major) and their transposes
@@ -1752,36 +1746,12 @@ hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, 
     return hipGetLastError();
 }
 
-hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
-                            float *part, float *loss, hipStream_t s) {
-    const int64_t tot = (int64_t)n * D;
-    if (tot > INT32_MAX) return hipErrorInvalidValue;
-    const int nb = (int)std::min<int64_t>((tot + 255) / 256, 2048);
-    hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)nb), dim3(256), 0, s, L, X, freem, n, D, DP, 1.f / (float)n, G,
-                       part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, part, nb, loss);
-    return hipGetLastError();
-}
-
-hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s) {
-    const int chunks = (n + COLSUM_ROWS - 1) / COLSUM_ROWS;
-    if (chunks == 0 || N == 0) return hipSuccess;
-    if (N % 8 == 0 && (((uintptr_t)G) & 15) == 0)
-        hipLaunchKernelGGL(colsum_part8_kernel, dim3((N + 255) / 256, chunks), dim3(256), 0, s, G, n, N, part);
-    else
-        hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0, s, G, n, N, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 63) / 64), dim3(256), 0, s, part, chunks, N, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t P, float lr, float b1, float b2,
-                       float eps, float c1, float c2, hipStream_t s) {
-    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, th, m, v, g, P, lr, b1, b2,
-                       eps, c1, c2);
+hipError_t launch_grad_final(const GradFinal &a, hipStream_t s) {
+    if (a.P <= 0) return hipSuccess;
+    if (a.zW1 < 1 || a.zW2 < 1 || a.zV < 1 || a.chunks < 1 || (a.adam && (!a.th || !a.m || !a.v)) ||
+        (!a.adam && !a.grad))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(grad_final_kernel, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

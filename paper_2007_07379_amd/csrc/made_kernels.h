@@ -125,17 +125,26 @@ hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s);
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
 // y[i] = made_log(x[i]) for i < n (n < 2^40)
 hipError_t launch_log_eval(const double *x, double *y, uint64_t n, hipStream_t s);
-// G and the batch-mean loss, written to *loss (per-workgroup partials in
-// `part`, min(ceil(n D / 256), 2048) floats, summed in a fixed order).
-hipError_t launch_loss_grad(const float *L, const bf16 *X, const int *freem, int n, int D, int DP, bf16 *G,
-                            float *part, float *loss, hipStream_t s);
-// out[j] = sum_b G[b][j]: partial sums over COLSUM_ROWS-row chunks into
-// `part` (ceil(n / COLSUM_ROWS) x N floats), then over the chunks in a fixed
-// order.
-constexpr int COLSUM_ROWS = 64;
-hipError_t launch_colsum(const bf16 *G, int n, int N, float *part, float *out, hipStream_t s);
-hipError_t launch_adam(float *th, float *m, float *v, const float *g, int64_t P, float lr, float b1, float b2,
-                       float eps, float c1, float c2, hipStream_t s);
+// The parameter gradient from the training GEMMs' leftovers and, with adam,
+// one Adam step (see grad_final_kernel).  Flat parameter order W1 [D][H],
+// b1, W2 [H][H], b2, V [H][D], c at the given offsets.
+struct GradFinal {
+    int adam;
+    float *th, *m, *v;  // Adam state (adam)
+    float *grad;        // gradient out (!adam)
+    float lr, b1, b2, eps, c1, c2;
+    int64_t P, oW1, ob1, oW2, ob2, oV, oc;
+    int D, H;
+    const float *pW1, *pW2, *pV;  // split-K slices of the weight gradients
+    int zW1, zW2, zV;             // their slice counts (>= 1)
+    const float *cb1, *cb2, *cc;  // 64-row column partials of G1, G2, G3
+    int chunks;                   // their row-chunk count
+    const int *deg_in, *deg1, *deg2, *deg_out;
+    const float *losspart;        // loss shares, nloss of them, summed into *loss (may be NULL)
+    int nloss;
+    float *loss;
+};
+hipError_t launch_grad_final(const GradFinal &a, hipStream_t s);
 // bf16 shadow Wb (K x N, row-major) and transpose WT (N x KP, zero-padded)
 // of an fp32 K x N weight W; one launch for `count` (1 to 3) weights.
 struct ShadowJob {

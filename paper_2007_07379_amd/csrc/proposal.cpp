@@ -94,7 +94,7 @@ struct pbit_proposal_s {
     int dev = -1;
     DeviceArena arena;
     // device
-    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *loss = nullptr;
     bf16 *W1b = nullptr, *W1T = nullptr, *W2b = nullptr, *W2T = nullptr, *Vb = nullptr, *VT = nullptr;
     int *d_deg_in = nullptr, *d_deg1 = nullptr, *d_deg2 = nullptr, *d_deg_out = nullptr, *d_free = nullptr,
         *d_fpos = nullptr;
@@ -106,10 +106,13 @@ struct pbit_proposal_s {
     int2 *d_l2 = nullptr;
     bf16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *G3 = nullptr, *G2 = nullptr, *G1 = nullptr;
     float *L = nullptr;
-    float *colpart = nullptr;  // column-sum partials, (BATCH_MAX / COLSUM_ROWS) x max(D, H)
-    float *part = nullptr;     // split-K partial sums of the weight gradients
-    float *lpart = nullptr;    // per-workgroup partial losses
-    int64_t part_floats = 0;
+    // what the training GEMMs leave for grad_final_kernel: 64-row column
+    // partials of G1, G2, G3 (BATCH_MAX / 64 x H, H, D), split-K slices of
+    // dW1, dW2, dV (up to zcap[] slices each), the logits tiles' loss shares
+    float *cb1 = nullptr, *cb2 = nullptr, *cc = nullptr;
+    float *pW1 = nullptr, *pW2 = nullptr, *pV = nullptr;
+    int zcap[3] = {0, 0, 0};
+    float *losspart = nullptr;
     uint32_t *prop = nullptr;
     double *lq_cur = nullptr, *lq_prop = nullptr;
     uint32_t mh_cap = 0;
@@ -119,6 +122,18 @@ struct pbit_proposal_s {
 };
 
 namespace {
+
+// Weight gradients reduce over the batch (K = n) into few output tiles:
+// split K so the launch has about 256 workgroups of 128 x 128 (which the GEMM
+// launch then runs as about 1,024 of 64 x 64, four per CU), at most 16
+// slices, each of at least four 32-wide chunks.  On the 1,024-wide training
+// step, half or twice the slices are 2 % and 5 % slower.
+int splitk_slices(int M, int N, int K) {
+    const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+    const int chunks = (K + 31) / 32;
+    const int ks = (int)std::min<int64_t>(16, (256 + tiles - 1) / tiles);
+    return std::max(1, std::min(ks, chunks / 4));
+}
 
 pbit_status upload(pbit_proposal q, hipStream_t s) {
     if (q->theta) return PBIT_OK;
@@ -131,7 +146,6 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->theta = A.alloc<float>(q->P);
     q->m = A.alloc<float>(q->P);
     q->v = A.alloc<float>(q->P);
-    q->grad = A.alloc<float>(q->P);
     q->loss = A.alloc<float>(1 << 16);
     q->W1b = A.alloc<bf16>((size_t)D * H);
     q->W1T = A.alloc<bf16>((size_t)H * DP);
@@ -146,11 +160,17 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->G2 = A.alloc<bf16>((size_t)BATCH_MAX * H);
     q->G3 = A.alloc<bf16>((size_t)BATCH_MAX * D);
     q->L = A.alloc<float>((size_t)BATCH_MAX * D);
-    q->colpart = A.alloc<float>((size_t)(BATCH_MAX / COLSUM_ROWS) * std::max(D, H));
-    q->part_floats = std::min<int64_t>((int64_t)16 * std::max<int64_t>((int64_t)H * H, (int64_t)D * H),
-                                       (int64_t)16 << 20);
-    q->part = A.alloc<float>((size_t)q->part_floats);
-    q->lpart = A.alloc<float>(((size_t)BATCH_MAX * D + 255) / 256);
+    q->cb1 = A.alloc<float>((size_t)(BATCH_MAX / 64) * H);
+    q->cb2 = A.alloc<float>((size_t)(BATCH_MAX / 64) * H);
+    q->cc = A.alloc<float>((size_t)(BATCH_MAX / 64) * D);
+    // slices for the largest batch (the split only grows with K)
+    q->zcap[0] = splitk_slices(D, H, BATCH_MAX);
+    q->zcap[1] = splitk_slices(H, H, BATCH_MAX);
+    q->zcap[2] = splitk_slices(H, D, BATCH_MAX);
+    q->pW1 = A.alloc<float>((size_t)q->zcap[0] * D * H);
+    q->pW2 = A.alloc<float>((size_t)q->zcap[1] * H * H);
+    q->pV = A.alloc<float>((size_t)q->zcap[2] * H * D);
+    q->losspart = A.alloc<float>((size_t)(BATCH_MAX / 64) * ((D + 63) / 64));
     hipError_t ce = hipSuccess;  // first failure of the copies below
     auto copy = [&](void *dst, const void *src, size_t bytes) {
         if (ce == hipSuccess && dst && bytes) ce = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -193,7 +213,8 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->d_wstep = A.alloc<int4>(q->wstep.size() + 1);
     q->d_wcone = A.alloc<uint32_t>(q->wcone.size() + 1);
     q->d_l2 = A.alloc<int2>(q->l2.size() + 1);
-    if (!q->theta || !q->L || !q->colpart || !q->part || !q->lpart || !q->d_phase || !q->d_phase_k || !q->g1beg ||
+    if (!q->theta || !q->L || !q->cb1 || !q->cb2 || !q->cc || !q->pW1 || !q->pW2 || !q->pV || !q->losspart ||
+        !q->d_phase || !q->d_phase_k || !q->g1beg ||
         !q->d_sched || !q->d_wphase || !q->d_wstep || !q->d_wcone || !q->d_l2)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
     copy(q->d_sched, q->sched.data(), q->sched.size() * sizeof(uint32_t));
@@ -232,28 +253,23 @@ GemmArgs gemm0() {
     return g;
 }
 
-// Weight gradients reduce over the batch (K = n) into few output tiles:
-// split K so the launch has about 256 workgroups of 128 x 128 (which the GEMM
-// launch then runs as about 1,024 of 64 x 64, four per CU), within the
-// workspace.  On the 1,024-wide training step, half or twice the slices are
-// 2 % and 5 % slower.
-void splitk(pbit_proposal q, GemmArgs &g) {
-    const int64_t tiles = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
-    const int chunks = (g.K + 31) / 32;
-    int ks = (int)std::min<int64_t>(16, (256 + tiles - 1) / tiles);
-    ks = std::min(ks, std::max(1, chunks / 4));
-    ks = (int)std::min<int64_t>(ks, (int64_t)(q->part_floats / ((int64_t)g.M * g.N)));
-    if (ks > 1) {
-        g.ksplit = ks;
-        g.part = q->part;
-    }
+// A weight gradient's GEMM leaves its split-K slices in `part` (up to cap
+// of them); returns the slice count.
+int splitk(GemmArgs &g, float *part, int cap) {
+    const int ks = std::min(splitk_slices(g.M, g.N, g.K), cap);
+    g.ksplit = ks;
+    g.keep_parts = 1;
+    g.part = part;
+    return ks;
 }
 
 // Forward of n <= BATCH_MAX paths (X already unpacked): H1, H2, L.
 // The network on the batch in q->X.  For the wide sampler's scorer (wide):
 // layer 2 in the sampler's k-slot order, and no logits (the replay adds
-// them in the sampler's order).
-pbit_status forward(pbit_proposal q, int n, hipStream_t s, bool wide = false) {
+// them in the sampler's order).  For training (train): the logits GEMM
+// writes the loss gradient G3 (bf16), its column partials and the loss
+// shares instead of the logits.
+pbit_status forward(pbit_proposal q, int n, hipStream_t s, bool wide = false, bool train = false) {
     const int D = q->D, DP = q->DP, H = q->H;
     GemmArgs g = gemm0();
     g.A = q->X; g.sam = DP; g.sak = 1;
@@ -278,62 +294,116 @@ pbit_status forward(pbit_proposal q, int n, hipStream_t s, bool wide = false) {
     g.C = q->L; g.scm = D; g.scn = 1;
     g.M = n; g.N = D; g.K = H;
     g.kend = q->k3end; g.bias = q->theta + q->oc; g.out_bf16 = 0;
+    if (train) {
+        g.C = q->G3;
+        g.out_bf16 = 1;
+        g.lossx = q->X;
+        g.slx = DP;
+        g.lossfree = q->d_free;
+        g.inv_n = 1.f / (float)n;
+        g.losspart = q->losspart;
+        g.colpart = q->cc;
+    }
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm3");
     return PBIT_OK;
 }
 
-// Gradient of the batch in q->X / q->L into q->grad; the batch-mean loss is written to *loss_dev.
-pbit_status backward(pbit_proposal q, int n, float *loss_dev, hipStream_t s) {
+// The backward GEMMs of the batch after forward(train): the weight
+// gradients' split-K slices into pW1, pW2, pV (slice counts into z[]) and
+// the column partials of G2, G1 into cb2, cb1; grad_final finishes them.
+pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
     const int D = q->D, DP = q->DP, H = q->H;
     hipError_t e;
-    if ((e = launch_loss_grad(q->L, q->X, q->d_free, n, D, DP, q->G3, q->lpart, loss_dev, s)) != hipSuccess)
-        return hip_error(e, "loss_grad");
     // dV = H2^T G3 (masked)
     GemmArgs g = gemm0();
     g.A = q->H2; g.sam = 1; g.sak = H;
     g.B = q->G3; g.sbk = D; g.sbn = 1;
-    g.C = q->grad + q->oV; g.scm = D; g.scn = 1;
     g.M = H; g.N = D; g.K = n;
     g.deg_row = q->d_deg2; g.deg_col = q->d_deg_out;
-    splitk(q, g);
+    z[2] = splitk(g, q->pV, q->zcap[2]);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dV");
-    if ((e = launch_colsum(q->G3, n, D, q->colpart, q->grad + q->oc, s)) != hipSuccess) return hip_error(e, "dc");
-    // G2 = (G3 V^T) * (H2 > 0)
+    // G2 = (G3 V^T) * (H2 > 0); db2 partials
     g = gemm0();
     g.A = q->G3; g.sam = D; g.sak = 1;
     g.B = q->Vb; g.sbk = 1; g.sbn = D;
     g.C = q->G2; g.scm = H; g.scn = 1;
     g.M = n; g.N = H; g.K = D;
     g.kbeg = q->g2beg; g.gate = q->H2; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
+    g.colpart = q->cb2;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G2");
-    // dW2 = H1^T G2 (masked); db2
+    // dW2 = H1^T G2 (masked)
     g = gemm0();
     g.A = q->H1; g.sam = 1; g.sak = H;
     g.B = q->G2; g.sbk = H; g.sbn = 1;
-    g.C = q->grad + q->oW2; g.scm = H; g.scn = 1;
     g.M = H; g.N = H; g.K = n;
     g.deg_row = q->d_deg1; g.deg_col = q->d_deg2;
-    splitk(q, g);
+    z[1] = splitk(g, q->pW2, q->zcap[1]);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW2");
-    if ((e = launch_colsum(q->G2, n, H, q->colpart, q->grad + q->ob2, s)) != hipSuccess) return hip_error(e, "db2");
-    // G1 = (G2 W2^T) * (H1 > 0)
+    // G1 = (G2 W2^T) * (H1 > 0); db1 partials
     g = gemm0();
     g.A = q->G2; g.sam = H; g.sak = 1;
     g.B = q->W2b; g.sbk = 1; g.sbn = H;
     g.C = q->G1; g.scm = H; g.scn = 1;
     g.M = n; g.N = H; g.K = H;
     g.kbeg = q->g1beg; g.gate = q->H1; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
+    g.colpart = q->cb1;
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G1");
-    // dW1 = X^T G1 (masked); db1
+    // dW1 = X^T G1 (masked)
     g = gemm0();
     g.A = q->X; g.sam = 1; g.sak = DP;
     g.B = q->G1; g.sbk = H; g.sbn = 1;
-    g.C = q->grad + q->oW1; g.scm = H; g.scn = 1;
     g.M = D; g.N = H; g.K = n;
     g.deg_row = q->d_deg_in; g.deg_col = q->d_deg1;
-    splitk(q, g);
+    z[0] = splitk(g, q->pW1, q->zcap[0]);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW1");
-    if ((e = launch_colsum(q->G1, n, H, q->colpart, q->grad + q->ob1, s)) != hipSuccess) return hip_error(e, "db1");
+    return PBIT_OK;
+}
+
+// The gradient of the batch of n into `grad` (adam_step == false), or one
+// Adam step on it; the batch-mean loss into *loss_dev.
+pbit_status grad_final(pbit_proposal q, int n, const int z[3], float *loss_dev, bool adam_step, float *grad, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
+    GradFinal a;
+    std::memset(&a, 0, sizeof(a));
+    a.adam = adam_step ? 1 : 0;
+    a.th = q->theta;
+    a.m = q->m;
+    a.v = q->v;
+    a.grad = grad;
+    a.lr = lr;
+    a.b1 = b1;
+    a.b2 = b2;
+    a.eps = eps;
+    a.c1 = c1;
+    a.c2 = c2;
+    a.P = (int64_t)q->P;
+    a.oW1 = (int64_t)q->oW1;
+    a.ob1 = (int64_t)q->ob1;
+    a.oW2 = (int64_t)q->oW2;
+    a.ob2 = (int64_t)q->ob2;
+    a.oV = (int64_t)q->oV;
+    a.oc = (int64_t)q->oc;
+    a.D = q->D;
+    a.H = q->H;
+    a.pW1 = q->pW1;
+    a.pW2 = q->pW2;
+    a.pV = q->pV;
+    a.zW1 = z[0];
+    a.zW2 = z[1];
+    a.zV = z[2];
+    a.cb1 = q->cb1;
+    a.cb2 = q->cb2;
+    a.cc = q->cc;
+    a.chunks = (n + 63) / 64;
+    a.deg_in = q->d_deg_in;
+    a.deg1 = q->d_deg1;
+    a.deg2 = q->d_deg2;
+    a.deg_out = q->d_deg_out;
+    a.losspart = q->losspart;
+    a.nloss = ((n + 63) / 64) * ((q->D + 63) / 64);
+    a.loss = loss_dev;
+    hipError_t e = launch_grad_final(a, s);
+    if (e != hipSuccess) return hip_error(e, adam_step ? "adam" : "gradient");
     return PBIT_OK;
 }
 
@@ -590,14 +660,13 @@ pbit_status pbit_proposal_grad(pbit_proposal q, const uint32_t *d_states, uint32
     pbit_status st = upload(q, s);
     if (st != PBIT_OK) return st;
     if ((st = refresh(q, s)) != PBIT_OK) return st;
-    hipError_t e = hipMemsetAsync(q->loss, 0, sizeof(float), s);
-    if (e != hipSuccess) return hip_error(e, "memset");
     if ((st = unpack_range(q, d_states, n, 0, (int)n, s)) != PBIT_OK) return st;
-    if ((st = forward(q, (int)n, s)) != PBIT_OK) return st;
-    if ((st = backward(q, (int)n, q->loss, s)) != PBIT_OK) return st;
-    e = hipMemcpyAsync(d_grad, q->grad, q->P * sizeof(float), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_error(e, "grad copy");
+    if ((st = forward(q, (int)n, s, false, true)) != PBIT_OK) return st;
+    int z[3];
+    if ((st = backward(q, (int)n, s, z)) != PBIT_OK) return st;
+    if ((st = grad_final(q, (int)n, z, q->loss, false, d_grad, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, s)) != PBIT_OK) return st;
     float l = 0.f;
+    hipError_t e;
     e = hipMemcpyAsync(&l, q->loss, sizeof(float), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_error(e, "loss copy");
@@ -624,14 +693,15 @@ pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint6
         if (cursor + cfg->batch > n_samples) cursor = 0;
         if ((st = unpack_range(q, d_states, n_samples, cursor, (int)cfg->batch, s)) != PBIT_OK) return st;
         cursor += cfg->batch;
-        if ((st = forward(q, (int)cfg->batch, s)) != PBIT_OK) return st;
-        if ((st = backward(q, (int)cfg->batch, q->loss + it, s)) != PBIT_OK) return st;
+        if ((st = forward(q, (int)cfg->batch, s, false, true)) != PBIT_OK) return st;
+        int z[3];
+        if ((st = backward(q, (int)cfg->batch, s, z)) != PBIT_OK) return st;
         q->t += 1;
         const double c1 = 1.0 / (1.0 - std::pow((double)b1, q->t));
         const double c2 = 1.0 / (1.0 - std::pow((double)b2, q->t));
-        if ((e = launch_adam(q->theta, q->m, q->v, q->grad, (int64_t)q->P, lr, b1, b2, eps, (float)c1, (float)c2, s)) !=
-            hipSuccess)
-            return hip_error(e, "adam");
+        if ((st = grad_final(q, (int)cfg->batch, z, q->loss + it, true, nullptr, lr, b1, b2, eps, (float)c1,
+                             (float)c2, s)) != PBIT_OK)
+            return st;
         q->dirty = true;
         if ((st = refresh(q, s)) != PBIT_OK) return st;
     }
