@@ -164,7 +164,8 @@ bool jit_compiled(pbit_circuit c, uint32_t i, uint32_t kind) {
 bool jit_compiled_any(pbit_circuit c, uint32_t i) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
-    for (uint32_t kind = 0; kind < 4; ++kind)
+    // histogram kinds 0..3, each also with JIT_PAIRED
+    for (uint32_t kind = 0; kind < 8; ++kind)
         if (c->jit.count(std::make_tuple(dev, i, kind))) return true;
     return false;
 }
