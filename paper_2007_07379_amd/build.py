@@ -34,6 +34,7 @@ SOURCES = [
     ("tune.cpp", "hip-host"),
     ("jit.cpp", "hip-host"),
     ("proposal.cpp", "hip"),
+    ("blaslt.cpp", "hip-host"),
     ("autotune.cpp", "hip-host"),
     ("gibbs.hip", "hip"),
     ("gibbs_pair.hip", "hip"),
@@ -77,7 +78,7 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(run, jobs))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc", "-lhipblaslt"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stdout + r.stderr))

@@ -533,6 +533,48 @@ __global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
     a.th[i] = a.th[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
 }
 
+// The ReLU-derivative gate of a library product's bf16 output and its column
+// partials: G[m][j] = 0 where A[m][j] <= 0, then per 64-row chunk c the column
+// sums of the gated G into colpart[c N + j].  A workgroup takes 64 rows x 128
+// columns; thread (column group of 8, row group of 4) adds its 4 rows in
+// ascending order, and the 16 row groups are added in order.  N % 8 == 0 and
+// 16-byte aligned rows.
+__global__ __launch_bounds__(256) void gate_colsum_kernel(bf16 *__restrict__ G, const bf16 *__restrict__ A, int n,
+                                                          int N, float *__restrict__ colpart) {
+    __shared__ float red[16][128];
+    const int cg = threadIdx.x & 15, rg = threadIdx.x >> 4;
+    const int c0 = blockIdx.x * 128 + cg * 8;
+    const int r0 = blockIdx.y * 64 + rg * 4;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (c0 < N) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + q;
+            if (r < n) {
+                const int64_t o = (int64_t)r * N + c0;
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + o);
+                bf16x8 g = *reinterpret_cast<const bf16x8 *>(G + o);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (!((float)a[i] > 0.f)) g[i] = (bf16)0.f;
+                    acc[i] += (float)g[i];
+                }
+                *reinterpret_cast<bf16x8 *>(G + o) = g;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[rg][cg * 8 + i] = acc[i];
+    __syncthreads();
+    const int j = blockIdx.x * 128 + (int)threadIdx.x;
+    if (threadIdx.x < 128 && j < N) {
+        float v = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v += red[q][threadIdx.x];
+        colpart[(int64_t)blockIdx.y * N + j] = v;
+    }
+}
+
 // bf16 shadows of up to three K x N weights (row-major) and their transposes
 // N x KP (row n holds the K inputs of unit n, zero-padded to KP), one weight
 // per blockIdx.z.  Workgroup (blockIdx.x, blockIdx.y) takes the 32 x 32 tile
@@ -1743,6 +1785,14 @@ hipError_t launch_log_eval(const double *x, double *y, uint64_t n, hipStream_t s
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s) {
     const int64_t tot = (int64_t)n * DP;
     hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, states, n, D, DP, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_colsum(bf16 *G, const bf16 *A, int n, int N, float *colpart, hipStream_t s) {
+    if (n <= 0 || N <= 0) return hipSuccess;
+    if (N % 8 || (((uintptr_t)G) & 15) || (((uintptr_t)A) & 15)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gate_colsum_kernel, dim3((unsigned)((N + 127) / 128), (unsigned)((n + 63) / 64)), dim3(256), 0,
+                       s, G, A, n, N, colpart);
     return hipGetLastError();
 }
 

@@ -145,6 +145,9 @@ struct GradFinal {
     float *loss;
 };
 hipError_t launch_grad_final(const GradFinal &a, hipStream_t s);
+// G[m][j] = 0 where A[m][j] <= 0 (n x N bf16, row-major, N % 8 == 0), and
+// the 64-row column partials of the gated G into colpart (ceil(n / 64) x N).
+hipError_t launch_gate_colsum(bf16 *G, const bf16 *A, int n, int N, float *colpart, hipStream_t s);
 // bf16 shadow Wb (K x N, row-major) and transpose WT (N x KP, zero-padded)
 // of an fp32 K x N weight W; one launch for `count` (1 to 3) weights.
 struct ShadowJob {

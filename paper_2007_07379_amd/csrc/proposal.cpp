@@ -4,12 +4,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/pbit.h"
 #include "blob.h"
 #include "made.h"
+#include "blaslt.h"
 #include "made_kernels.h"
 #include "runtime.h"
 
@@ -113,6 +115,11 @@ struct pbit_proposal_s {
     float *pW1 = nullptr, *pW2 = nullptr, *pV = nullptr;
     int zcap[3] = {0, 0, 0};
     float *losspart = nullptr;
+    // the library products of a training step (made on first use; NULL if
+    // the library has none for this device) and their workspace
+    std::unique_ptr<LtState, void (*)(LtState *)> lt{nullptr, lt_destroy};
+    bool lt_tried = false;
+    void *lt_ws = nullptr;
     uint32_t *prop = nullptr;
     double *lq_cur = nullptr, *lq_prop = nullptr;
     uint32_t mh_cap = 0;
@@ -171,6 +178,7 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->pW2 = A.alloc<float>((size_t)q->zcap[1] * H * H);
     q->pV = A.alloc<float>((size_t)q->zcap[2] * H * D);
     q->losspart = A.alloc<float>((size_t)(BATCH_MAX / 64) * ((D + 63) / 64));
+    q->lt_ws = A.alloc<unsigned char>(LT_WORKSPACE);
     hipError_t ce = hipSuccess;  // first failure of the copies below
     auto copy = [&](void *dst, const void *src, size_t bytes) {
         if (ce == hipSuccess && dst && bytes) ce = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -214,6 +222,7 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->d_wcone = A.alloc<uint32_t>(q->wcone.size() + 1);
     q->d_l2 = A.alloc<int2>(q->l2.size() + 1);
     if (!q->theta || !q->L || !q->cb1 || !q->cb2 || !q->cc || !q->pW1 || !q->pW2 || !q->pV || !q->losspart ||
+        !q->lt_ws ||
         !q->d_phase || !q->d_phase_k || !q->g1beg ||
         !q->d_sched || !q->d_wphase || !q->d_wstep || !q->d_wcone || !q->d_l2)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
@@ -264,6 +273,15 @@ int splitk(GemmArgs &g, float *part, int cap) {
 }
 
 // Forward of n <= BATCH_MAX paths (X already unpacked): H1, H2, L.
+// The library handle of a training step's products (NULL when there is none).
+LtState *lt_of(pbit_proposal q) {
+    if (!q->lt_tried) {
+        q->lt_tried = true;
+        q->lt.reset(lt_create());
+    }
+    return q->lt.get();
+}
+
 // The network on the batch in q->X.  For the wide sampler's scorer (wide):
 // layer 2 in the sampler's k-slot order, and no logits (the replay adds
 // them in the sampler's order).  For training (train): the logits GEMM
@@ -271,22 +289,31 @@ int splitk(GemmArgs &g, float *part, int cap) {
 // shares instead of the logits.
 pbit_status forward(pbit_proposal q, int n, hipStream_t s, bool wide = false, bool train = false) {
     const int D = q->D, DP = q->DP, H = q->H;
-    GemmArgs g = gemm0();
-    g.A = q->X; g.sam = DP; g.sak = 1;
-    g.B = q->W1T; g.sbk = 1; g.sbn = DP;
-    g.C = q->H1; g.scm = H; g.scn = 1;
-    g.M = n; g.N = H; g.K = D;
-    g.kend = q->k1end; g.bias = q->theta + q->ob1; g.relu = 1; g.out_bf16 = 1;
-    hipError_t e = launch_gemm(g, s);
-    if (e != hipSuccess) return hip_error(e, "gemm1");
-    g = gemm0();
-    g.A = q->H1; g.sam = H; g.sak = 1;
-    g.B = q->W2T; g.sbk = 1; g.sbn = H;
-    g.C = q->H2; g.scm = H; g.scn = 1;
-    g.M = n; g.N = H; g.K = H;
-    g.kend = q->k2end; g.bias = q->theta + q->ob2; g.relu = 1; g.out_bf16 = 1;
-    g.kperm = wide ? 1 : 0;
-    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm2");
+    // a training step's hidden layers: the library products when they run
+    LtState *lt = train ? lt_of(q) : nullptr;
+    const bool lt_hidden =
+        lt &&
+        lt_gemm_nt(lt, n, H, DP, q->X, DP, q->W1T, DP, q->theta + q->ob1, true, q->H1, H, q->lt_ws, LT_WORKSPACE, s) &&
+        lt_gemm_nt(lt, n, H, H, q->H1, H, q->W2T, H, q->theta + q->ob2, true, q->H2, H, q->lt_ws, LT_WORKSPACE, s);
+    GemmArgs g;
+    hipError_t e;
+    if (!lt_hidden) {
+        g = gemm0();
+        g.A = q->X; g.sam = DP; g.sak = 1;
+        g.B = q->W1T; g.sbk = 1; g.sbn = DP;
+        g.C = q->H1; g.scm = H; g.scn = 1;
+        g.M = n; g.N = H; g.K = D;
+        g.kend = q->k1end; g.bias = q->theta + q->ob1; g.relu = 1; g.out_bf16 = 1;
+        if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm1");
+        g = gemm0();
+        g.A = q->H1; g.sam = H; g.sak = 1;
+        g.B = q->W2T; g.sbk = 1; g.sbn = H;
+        g.C = q->H2; g.scm = H; g.scn = 1;
+        g.M = n; g.N = H; g.K = H;
+        g.kend = q->k2end; g.bias = q->theta + q->ob2; g.relu = 1; g.out_bf16 = 1;
+        g.kperm = wide ? 1 : 0;
+        if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "gemm2");
+    }
     if (wide) return PBIT_OK;
     g = gemm0();
     g.A = q->H2; g.sam = H; g.sak = 1;
@@ -322,15 +349,21 @@ pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
     g.deg_row = q->d_deg2; g.deg_col = q->d_deg_out;
     z[2] = splitk(g, q->pV, q->zcap[2]);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dV");
-    // G2 = (G3 V^T) * (H2 > 0); db2 partials
-    g = gemm0();
-    g.A = q->G3; g.sam = D; g.sak = 1;
-    g.B = q->Vb; g.sbk = 1; g.sbn = D;
-    g.C = q->G2; g.scm = H; g.scn = 1;
-    g.M = n; g.N = H; g.K = D;
-    g.kbeg = q->g2beg; g.gate = q->H2; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
-    g.colpart = q->cb2;
-    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G2");
+    // G2 = (G3 V^T) * (H2 > 0); db2 partials (the library product, then the
+    // gate and the column partials, when it runs)
+    LtState *lt = lt_of(q);
+    if (lt && lt_gemm_nt(lt, n, H, D, q->G3, D, q->Vb, D, nullptr, false, q->G2, H, q->lt_ws, LT_WORKSPACE, s)) {
+        if ((e = launch_gate_colsum(q->G2, q->H2, n, H, q->cb2, s)) != hipSuccess) return hip_error(e, "G2 gate");
+    } else {
+        g = gemm0();
+        g.A = q->G3; g.sam = D; g.sak = 1;
+        g.B = q->Vb; g.sbk = 1; g.sbn = D;
+        g.C = q->G2; g.scm = H; g.scn = 1;
+        g.M = n; g.N = H; g.K = D;
+        g.kbeg = q->g2beg; g.gate = q->H2; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
+        g.colpart = q->cb2;
+        if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G2");
+    }
     // dW2 = H1^T G2 (masked)
     g = gemm0();
     g.A = q->H1; g.sam = 1; g.sak = H;
@@ -340,14 +373,18 @@ pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
     z[1] = splitk(g, q->pW2, q->zcap[1]);
     if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW2");
     // G1 = (G2 W2^T) * (H1 > 0); db1 partials
-    g = gemm0();
-    g.A = q->G2; g.sam = H; g.sak = 1;
-    g.B = q->W2b; g.sbk = 1; g.sbn = H;
-    g.C = q->G1; g.scm = H; g.scn = 1;
-    g.M = n; g.N = H; g.K = H;
-    g.kbeg = q->g1beg; g.gate = q->H1; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
-    g.colpart = q->cb1;
-    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G1");
+    if (lt && lt_gemm_nt(lt, n, H, H, q->G2, H, q->W2b, H, nullptr, false, q->G1, H, q->lt_ws, LT_WORKSPACE, s)) {
+        if ((e = launch_gate_colsum(q->G1, q->H1, n, H, q->cb1, s)) != hipSuccess) return hip_error(e, "G1 gate");
+    } else {
+        g = gemm0();
+        g.A = q->G2; g.sam = H; g.sak = 1;
+        g.B = q->W2b; g.sbk = 1; g.sbn = H;
+        g.C = q->G1; g.scm = H; g.scn = 1;
+        g.M = n; g.N = H; g.K = H;
+        g.kbeg = q->g1beg; g.gate = q->H1; g.sgm = H; g.sgn = 1; g.out_bf16 = 1;
+        g.colpart = q->cb1;
+        if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G1");
+    }
     // dW1 = X^T G1 (masked)
     g = gemm0();
     g.A = q->X; g.sam = 1; g.sak = DP;
