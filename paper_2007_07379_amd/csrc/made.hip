@@ -497,8 +497,11 @@ __global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
         for (int k = 0; k < z; ++k) v += part[(int64_t)k * MN + e];
         return v;
     };
+    // (unrolled so a thread's chunk loads are in flight together: the bias
+    // entries' threads would otherwise wait one memory latency per chunk)
     auto cols = [&](const float *part, int N, int j) {
         float v = 0.f;
+#pragma unroll 16
         for (int k = 0; k < a.chunks; ++k) v += part[(int64_t)k * N + j];
         return v;
     };
