@@ -241,6 +241,38 @@ def test_adam_step_matches_closed_form(env):
     assert np.allclose(after, want, rtol=1e-5, atol=1e-7)
 
 
+def test_training_is_deterministic(env):
+    """On the learned proposal's training shape (D = 400, H = 1,024, batch
+    4,096) a proposal's gradient is the same bits on every call, and so are
+    the parameters after the same Adam steps from the same start (set_params
+    resets the moments): the library products keep the kernel chosen on first
+    use and every reduction has a fixed order."""
+    torch, pbit = env
+    c = wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    H = 1024
+    q = pbit.Proposal(s, hidden=H)
+    flat = random_params(q.D, H, 5)
+    q.set_params(flat)
+    n = 4096
+    _, _, words = valid_paths(c, n, 8)
+    d_states = to_dev(torch, words)
+    grads = []
+    for _ in range(2):
+        d_grad = torch.zeros(q.n_params, dtype=torch.float32, device="cuda")
+        q.grad(d_states, n, d_grad)
+        torch.cuda.synchronize()
+        grads.append(d_grad.cpu().numpy().copy())
+    assert np.array_equal(grads[0].view(np.uint32), grads[1].view(np.uint32))
+    after = []
+    for _ in range(2):
+        q.set_params(flat)
+        losses = q.train(d_states, n, n, 3)
+        after.append((q.get_params().copy(), losses.copy()))
+    assert np.array_equal(after[0][0].view(np.uint32), after[1][0].view(np.uint32))
+    assert np.array_equal(after[0][1].view(np.uint32), after[1][1].view(np.uint32))
+
+
 def _sample(env, q, n, seed=3, step=0):
     torch, pbit = env
     W = q.cset.info(0)["W"]
