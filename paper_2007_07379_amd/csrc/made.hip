@@ -1231,9 +1231,10 @@ constexpr int WD_NB = 8;                // blocks of 16 free bits (h <= 128)
 constexpr int WD_RS = 32 * WD_NH + 8;   // LDS row stride of a staged half tile (elements)
 constexpr int WD_VS = 16;               // LDS row stride of a staged V block (elements)
 constexpr int WD_BUF = 16 * WD_RS + 16 * WD_NB * WD_VS;  // elements of one step buffer
+static_assert(2 * WD_BUF * 2 >= 16 * WD_NB * 64 * 8, "the log terms of a pass fit in the step buffers");
 
 struct WdLayout {
-    size_t lut, b1, b2, c, fp, buf, total;
+    size_t lut, b1, b2, c, fp, rnd, buf, total;
 };
 
 __host__ __device__ inline WdLayout wd_layout(int D, int H) {
@@ -1243,7 +1244,8 @@ __host__ __device__ inline WdLayout wd_layout(int D, int H) {
     L.b2 = L.b1 + (size_t)H * 4;
     L.c = L.b2 + (size_t)H * 4;
     L.fp = L.c + (size_t)D * 4;
-    L.buf = (L.fp + 16 * WD_NB * 4 + 15) & ~(size_t)15;
+    L.rnd = (L.fp + 16 * WD_NB * 4 + 15) & ~(size_t)15;
+    L.buf = L.rnd + (size_t)16 * WD_NB * 64 * 4;
     L.total = L.buf + (size_t)2 * WD_BUF * 2;
     return L;
 }
@@ -1256,13 +1258,14 @@ bool made_sample_wide_ok(const SampleArgs &a) {
 // A staged step: thread t holds piece t (elements 4t .. 4t + 3) of the 16
 // weight rows where the rows have it, and for a layer-2 step pieces t and
 // t + 256 of the V block (free bit f = piece / 4, units 16 ht + 4 (piece % 4)
-// .. + 3 of position fp[f]).
+// .. + 3 of position fp[f]; voff[j] is the offset of piece t + 256 j in VT
+// without the 16 ht, for f >= h that of an existing row).
 struct WdStage {
     uint2 w[16];
     uint2 v[2];
 };
 
-__device__ __forceinline__ void wd_fetch(const SampleArgs &a, const int *fp, int4 st, WdStage &x) {
+__device__ __forceinline__ void wd_fetch(const SampleArgs &a, const uint32_t (&voff)[2], int4 st, WdStage &x) {
     const int t = threadIdx.x;
     const int np = 8 * st.z;  // pieces a row
     const bf16 *src = (st.x == 0 ? a.W1T + (int64_t)st.y * a.DP : a.W2T + (int64_t)st.y * a.H);
@@ -1273,15 +1276,12 @@ __device__ __forceinline__ void wd_fetch(const SampleArgs &a, const int *fp, int
     }
     if (st.x == 1) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int pc = t + 256 * j, f = pc >> 2;
-            x.v[j] = f < a.h ? *reinterpret_cast<const uint2 *>(a.VT + (int64_t)fp[f] * a.H + st.y + 4 * (pc & 3))
-                             : uint2{0u, 0u};
-        }
+        for (int j = 0; j < 2; ++j) x.v[j] = *reinterpret_cast<const uint2 *>(a.VT + voff[j] + st.y);
     }
 }
 
-__device__ __forceinline__ void wd_store(bf16 *buf, int4 st, const WdStage &x) {
+// V pieces of free bits at or past h are stored as zeros.
+__device__ __forceinline__ void wd_store(bf16 *buf, int4 st, const WdStage &x, int h) {
     const int t = threadIdx.x;
     const int np = 8 * st.z;
     // inputs keep their order; hidden units take the k-slot 8 g + 4 t' + e
@@ -1295,7 +1295,8 @@ __device__ __forceinline__ void wd_store(bf16 *buf, int4 st, const WdStage &x) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int pc = t + 256 * j;
-            *reinterpret_cast<uint2 *>(buf + 16 * WD_RS + (pc >> 2) * WD_VS + 4 * (pc & 3)) = x.v[j];
+            *reinterpret_cast<uint2 *>(buf + 16 * WD_RS + (pc >> 2) * WD_VS + 4 * (pc & 3)) =
+                (pc >> 2) < h ? x.v[j] : uint2{0u, 0u};
         }
     }
 }
@@ -1414,6 +1415,16 @@ __device__ __forceinline__ void wd_step(const bf16 *cur, int4 st, int c, int g, 
     }
 }
 
+// The schedule and the cones are read-only for the whole launch and read at
+// wave-uniform addresses: through the constant address space they become
+// scalar loads, batched where consecutive.
+typedef const __attribute__((address_space(4))) int *wd_cint;
+typedef const __attribute__((address_space(4))) uint32_t *wd_cu32;
+
+__device__ __forceinline__ int4 wd_sched(wd_cint p, int i) {
+    return int4{p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]};
+}
+
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1))) void
 made_sample_wide_kernel(SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1423,6 +1434,9 @@ made_sample_wide_kernel(SampleArgs a) {
     float *b2s = reinterpret_cast<float *>(smem + L.b2);
     float *cs = reinterpret_cast<float *>(smem + L.c);
     int *fp = reinterpret_cast<int *>(smem + L.fp);
+    // [free bit][chain of the workgroup]: the Philox word of the draw, then
+    // the probability word of the chosen bit (see below)
+    uint32_t *rnd = reinterpret_cast<uint32_t *>(smem + L.rnd);
     bf16 *buf = reinterpret_cast<bf16 *>(smem + L.buf);
     for (int i = threadIdx.x; i < 256; i += blockDim.x) lut[i] = bits_to_bf16x8((uint32_t)i);
     for (int i = threadIdx.x; i < a.H; i += blockDim.x) {
@@ -1432,15 +1446,31 @@ made_sample_wide_kernel(SampleArgs a) {
     for (int i = threadIdx.x; i < a.D; i += blockDim.x) cs[i] = a.c[i];
     for (int i = threadIdx.x; i < a.h; i += blockDim.x) fp[i] = a.wphase[i].z;
     __syncthreads();
+    const wd_cint wph = (wd_cint)(const int *)a.wphase, wst = (wd_cint)(const int *)a.wstep;
+    const wd_cu32 wcn = (wd_cu32)a.wcone;
 
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     const int wave = threadIdx.x >> 6;
+    const int wc = 16 * wave + c;  // the chain's column of rnd
     const int my_chain = (blockIdx.x * 4 + wave) * 16 + c;
     const bool valid = my_chain < a.n;
     const uint32_t *B = a.blob;
     const uint32_t *cw = B + B[H_OFF_CONST];
     const uint32_t cid = B[H_CID];
     const int W = a.W;
+    // the chain's Philox words of the whole pass (one call per four free
+    // bits), computed up front with the calls spread over its four lane
+    // groups instead of one dependent call every fourth draw
+    if (!a.score) {
+        for (int i = g; 4 * i < a.h; i += 4) {
+            const U4 u4 = philox4x32_10(a.step, (uint32_t)i, a.chain_begin + (uint32_t)my_chain, cid | (1u << 16),
+                                        a.seed_lo, a.seed_hi);
+            rnd[(4 * i + 0) * 64 + wc] = u4.x;
+            rnd[(4 * i + 1) * 64 + wc] = u4.y;
+            rnd[(4 * i + 2) * 64 + wc] = u4.z;
+            rnd[(4 * i + 3) * 64 + wc] = u4.w;
+        }
+    }
 
     uint32_t lat[WD_NX];
     WdAct act1;
@@ -1451,34 +1481,50 @@ made_sample_wide_kernel(SampleArgs a) {
 #pragma unroll
     for (int b = 0; b < WD_NB; ++b) lacc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
     WdStage x;
+    // The phases' steps are consecutive from step 0.  The schedule records
+    // are read one step (one phase) ahead of their use, so that their
+    // scalar loads are in flight while a step computes: st is the record of
+    // step sidx, s_next that of step sidx + 1, ph_next that of the next phase.
+    const int4 zero4 = {0, 0, 0, 0};
+    int4 st = a.nsteps > 0 ? wd_sched(wst, 0) : zero4;
+    int4 s_next = a.nsteps > 1 ? wd_sched(wst, 1) : zero4;
+    int4 ph_next = a.h > 0 ? wd_sched(wph, 0) : zero4;
+    uint32_t voff[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int pc = threadIdx.x + 256 * j, f = min(pc >> 2, max(a.h - 1, 0));
+        voff[j] = (uint32_t)(a.h > 0 ? fp[f] : 0) * (uint32_t)a.H + 4u * (uint32_t)(pc & 3);
+    }
     if (a.nsteps > 0) {
-        const int4 st0 = a.wstep[0];
-        wd_fetch(a, fp, st0, x);
-        wd_store(buf, st0, x);
+        wd_fetch(a, voff, st, x);
+        wd_store(buf, st, x, a.h);
     }
     __syncthreads();
-    double lq = 0.0;
-    U4 u4 = {0u, 0u, 0u, 0u};
+    int sidx = 0;
     for (int f = 0; f < a.h; ++f) {
-        const int4 ph = a.wphase[f];  // {first step, end step, p, 0}
+        const int4 ph = ph_next;  // {first step, end step, p, 0}
+        if (f + 1 < a.h) ph_next = wd_sched(wph, f + 1);
         const int p = ph.z;
+        // the cone of free bit f (16 words, zero past W), loaded now and
+        // applied after the phase's steps
+        uint32_t cone[WD_NX];
+#pragma unroll
+        for (int w = 0; w < WD_NX; ++w) cone[w] = wcn[(size_t)f * a.cone_stride + w];
         // score mode: the scored path's word holding bit p, loaded now and
         // used after the phase's steps
         const uint32_t pw = (a.score && valid) ? a.score[(int64_t)(p >> 5) * a.n + my_chain] : 0u;
-        for (int sidx = ph.x; sidx < ph.y; ++sidx) {
+        for (; sidx < ph.y; ++sidx) {
             // {layer (0, 1), first unit 16 ht, K chunks, units of the phase
             // in the half tile: [lo, hi) as lo | hi << 8}
-            const int4 st = a.wstep[sidx];
             const bf16 *cur = buf + (sidx & 1) * WD_BUF;
             const bool more = sidx + 1 < a.nsteps;
-            int4 nx = st;
-            if (more) {
-                nx = a.wstep[sidx + 1];
-                wd_fetch(a, fp, nx, x);  // in flight during this step's products
-            }
+            const int4 nx = s_next;
+            if (sidx + 2 < a.nsteps) s_next = wd_sched(wst, sidx + 2);
+            if (more) wd_fetch(a, voff, nx, x);  // in flight during this step's products
             wd_step(cur, st, c, g, lat, act1, lacc, lut, b1s, b2s);
-            if (more) wd_store(buf + ((sidx + 1) & 1) * WD_BUF, nx, x);
+            if (more) wd_store(buf + ((sidx + 1) & 1) * WD_BUF, nx, x, a.h);
             __syncthreads();
+            st = nx;
         }
         // the logit of free bit f: element f & 3 of block f >> 4 on the lanes
         // of group (f & 15) >> 2, passed to the chain's four lane groups
@@ -1492,27 +1538,26 @@ made_sample_wide_kernel(SampleArgs a) {
         // the bit of free bit f: drawn against the threshold of the logit,
         // or read from the scored path; every lane group does its chain's
         const uint32_t T = made_threshold(lg + cs[p]);
-        uint32_t bit;
-        if (!a.score) {
-            if ((f & 3) == 0)
-                u4 = philox4x32_10(a.step, (uint32_t)f >> 2, a.chain_begin + (uint32_t)my_chain, cid | (1u << 16),
-                                   a.seed_lo, a.seed_hi);
-            const uint32_t u = (f & 3) == 0 ? u4.x : ((f & 3) == 1 ? u4.y : ((f & 3) == 2 ? u4.z : u4.w));
-            bit = u < T ? 1u : 0u;
-        } else {
-            bit = (pw >> (p & 31)) & 1u;
-        }
-        // log q in free-bit order
-        lq += made_log_prob(T, bit);
+        const uint32_t bit = !a.score ? (rnd[f * 64 + wc] < T ? 1u : 0u) : (pw >> (p & 31)) & 1u;
+        // the bit's probability times 2^32, T for a 1 and 2^32 - T for a 0
+        // (both in [1, 2^32 - 1]); its logarithm is taken after the pass
+        if (g == 0) rnd[f * 64 + wc] = bit ? T : 0u - T;
         // the lattice bit at p is the free bit itself: flip its cone when
         // the new value differs from the current one
         const uint32_t m = 0u - (((pick_word(lat, p >> 5) >> (p & 31)) & 1u) ^ bit);
-        const uint32_t *cone = a.wcone + (size_t)f * a.cone_stride;  // wave-uniform
 #pragma unroll
-        for (int w = 0; w < WD_NX; ++w)
-            if (w < W) lat[w] ^= m & cone[w];
+        for (int w = 0; w < WD_NX; ++w) lat[w] ^= m & cone[w];
     }
+    // log q: the logarithms of the probability words, spread over the
+    // chain's lane groups (the step buffers are free now), then added in
+    // free-bit order by one lane, as made_log_prob terms are added everywhere
+    __syncthreads();
+    double *lt = reinterpret_cast<double *>(buf);  // [free bit][chain of the workgroup]
+    for (int f = g; f < a.h; f += 4) lt[f * 64 + wc] = made_log((double)rnd[f * 64 + wc] * 0x1p-32);
+    __syncthreads();
     if (g == 0 && valid) {
+        double lq = 0.0;
+        for (int f = 0; f < a.h; ++f) lq += lt[f * 64 + wc];
         if (a.out && !a.score)
             for (int w = 0; w < W; ++w) a.out[(int64_t)w * a.n + my_chain] = pick_word(lat, w);
         a.logq[my_chain] = lq;
@@ -1522,6 +1567,7 @@ made_sample_wide_kernel(SampleArgs a) {
 hipError_t launch_wide(const SampleArgs &a, hipStream_t s) {
     const size_t lds = wd_layout(a.D, a.H).total;
     const int grid = (a.n + 63) / 64;
+    if (a.cone_stride < WD_NX) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)made_sample_wide_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -87,11 +87,15 @@ struct SampleArgs {
     // step, end step, lattice position p, 0}; per step {layer (0 or 1),
     // first unit of the half tile, K chunks, for layer 2 the phase's units
     // [lo, hi) of the half tile as lo | hi << 8}; per free bit its cone
-    // words (cone_stride apart)
+    // words (cone_stride apart, at least 16 of them, zero past W)
     const int4 *wphase, *wstep;
     const uint32_t *wcone;
     int cone_stride, nsteps;
 };
+
+// The distance between consecutive free bits' cones in SampleArgs::wcone
+// for W lattice words.
+inline uint32_t wd_cone_stride(uint32_t W) { return W < 16 ? 16 : W; }
 
 hipError_t launch_made_sample(const SampleArgs &a, hipStream_t s);
 // True if one of the samplers can run the shape of a (n, h, W, D, DP, H set):

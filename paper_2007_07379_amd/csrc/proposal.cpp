@@ -593,7 +593,9 @@ pbit_status pbit_proposal_create(pbit_circuit c, uint32_t idx, const pbit_made_c
         q->wphase.push_back(int4{s0, (int)q->wstep.size(), p, 0});
         const uint32_t *cn = k.blob.data() + k.blob[H_OFF_CONE] + (size_t)b * k.WS;
         for (uint32_t w = 0; w < 8; ++w) q->sched.push_back(w < k.W ? cn[w] : 0u);
-        for (uint32_t w = 0; w < k.W; ++w) q->wcone.push_back(cn[w]);
+        // at least 16 words a free bit, zero past W, so the wide sampler
+        // reads a fixed-length block
+        for (uint32_t w = 0; w < wd_cone_stride(k.W); ++w) q->wcone.push_back(w < k.W ? cn[w] : 0u);
     }
     // initial parameters
     q->host_params.assign(q->P, 0.f);
@@ -804,7 +806,7 @@ pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, u
     a.wphase = q->d_wphase;
     a.wstep = q->d_wstep;
     a.wcone = q->d_wcone;
-    a.cone_stride = q->W;
+    a.cone_stride = wd_cone_stride(q->W);
     a.nsteps = (int)q->wstep.size();
     if (d_logq_cur) {
         hipError_t e = launch_made_sample_dual(a, s);
