@@ -222,7 +222,8 @@ pbit_status upload(pbit_proposal q, hipStream_t s) {
     q->d_wcone = A.alloc<uint32_t>(q->wcone.size() + 1);
     q->d_l2 = A.alloc<int2>(q->l2.size() + 1);
     if (!q->theta || !q->L || !q->cb1 || !q->cb2 || !q->cc || !q->pW1 || !q->pW2 || !q->pV || !q->losspart ||
-        !q->lt_ws ||
+        !q->lt_ws || !q->m || !q->v || !q->loss || !q->W1b || !q->W1T || !q->W2b || !q->W2T || !q->Vb || !q->VT ||
+        !q->X || !q->H1 || !q->H2 || !q->G1 || !q->G2 || !q->G3 ||
         !q->d_phase || !q->d_phase_k || !q->g1beg ||
         !q->d_sched || !q->d_wphase || !q->d_wstep || !q->d_wcone || !q->d_l2)
         return set_error(PBIT_E_OOM, "device allocation for the proposal failed");
