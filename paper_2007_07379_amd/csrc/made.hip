@@ -430,10 +430,11 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.lossx && (!g.lossfree || !g.losspart || g.relu || g.gate || g.accumulate)) return hipErrorInvalidValue;
     if (g.colpart && g.accumulate) return hipErrorInvalidValue;
     const int z = g.ksplit > 1 ? g.ksplit : 1;
-    // 64 x 64 tiles: every product of the networks the proposal accepts
-    // (H <= 2,496, batches <= 16,384) has fewer than sixteen 128 x 128 tiles
-    // per CU, where four 64 x 64 workgroups per CU run faster (a 16,384 x
-    // 1,024 product: 49 us against 52 us)
+    // 64 x 64 tiles: the products of the networks the proposal accepts
+    // (H <= 2,496, training batches <= 16,384, scored batches <= 65,536)
+    // have at most sixteen 128 x 128 tiles per CU, where four 64 x 64
+    // workgroups per CU ran faster (a 16,384 x 1,024 product: 49 us against
+    // 52 us)
     constexpr int TT = 64;
     const int tiles = ((g.N + TT - 1) / TT) * ((g.M + TT - 1) / TT);
     dim3 grid(8 * ((tiles + 7) / 8), 1, z);
