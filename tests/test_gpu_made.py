@@ -283,18 +283,19 @@ def _sample(env, q, n, seed=3, step=0):
     return d_out, d_lq
 
 
-@pytest.mark.parametrize("which,H", [("small", 64), ("small", 512), ("brick16", 1024), ("small", 1152)])
-def test_sampler_paths_valid_and_logq_bitwise(env, which, H):
+@pytest.mark.parametrize("which,H,n", [("small", 64, 4096), ("small", 512, 4096), ("brick16", 1024, 1024),
+                                       ("small", 1152, 4096), ("brick16", 1024, 66536)])
+def test_sampler_paths_valid_and_logq_bitwise(env, which, H, n):
     """Sampled paths are valid lattices; scoring them gives the sampler's log q
     bit for bit (H = 64: the fused kernel in score mode; 512, 1024: the wide
     sampler against the batched GEMMs and the logit replay; 1,152:
-    made_sample_kernel against the batched GEMM forward)."""
+    made_sample_kernel against the batched GEMM forward).  66,536 paths: a
+    full forward batch of 65,536 and a ragged one of 1,000."""
     torch, pbit = env
     c = SMALL() if which == "small" else wc.workload_circuit("brick16")
     s = pbit.CircuitSet(c)
     q = pbit.Proposal(s, hidden=H)
     q.set_params(random_params(q.D, H, 11, scale=2.0))
-    n = 4096 if which == "small" else 1024
     d_out, d_lq = _sample(env, q, n)
     comp = ocomp.compile_circuit(oc.from_dict(c))
     words = d_out.cpu().numpy().view(np.uint32).reshape(comp.W, n)
