@@ -16,8 +16,7 @@ typedef __bf16 bf16;
 // so transposed products need no copies.  The reduction of output column
 // tile nt (64 columns) runs over [kbeg[nt], kend[nt]) in ascending 32-wide
 // chunks, so every output is a fixed sequence of v_mfma_f32_16x16x32_bf16
-// accumulations (a workgroup of 128 columns runs the union of its two ranges:
-// the extra chunks multiply exact-zero masked weights).  Products that feed
+// accumulations.  Products that feed
 // the sampler's arithmetic never split K; the weight gradients may
 // (ksplit slices summed in a fixed order by a second kernel).
 struct GemmArgs {
@@ -61,5 +60,18 @@ struct GemmArgs {
 };
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+
+// Up to GEMM_GROUP_MAX split-K products whose slices stay for a later
+// finalize (keep_parts, no epilogue), with one operand layout, in a single
+// launch: their workgroups share the machine and one tail (products of
+// different layouts get a launch each).  The slices are those launch_gemm
+// would write, bit for bit.
+constexpr int GEMM_GROUP_MAX = 3;
+struct GemmGroup {
+    GemmArgs g[GEMM_GROUP_MAX];
+    int bx[GEMM_GROUP_MAX], z[GEMM_GROUP_MAX];  // blocks of a tile order (multiple of 8), slices
+    int count;
+};
+hipError_t launch_gemm_group(const GemmArgs *gs, int count, hipStream_t s);
 
 }  // namespace pbit

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "blob.h"
 #include "made.h"
@@ -162,8 +163,9 @@ __device__ __forceinline__ void stage_store(const StageRegs &st, bf16 (*T)[LDSK]
     }
 }
 
+// One workgroup's tile (block bx of the tile order, split-K slice bz).
 template <int MA, int MB, int TT>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_body(const GemmArgs &g, int bx, int bz) {
     constexpr int TM = TT, TN = TT, F = TT / 32;  // F x F MFMA tiles per wave
     constexpr int P = GEMM_P;
     __shared__ __align__(16) bf16 As[2][TM][LDSK];
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // share their A rows in that XCD's L2
     const int tn = (g.N + TN - 1) / TN, tm = (g.M + TM - 1) / TM;
     const int T = tn * tm, per = (T + 7) / 8;
-    const int tile = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+    const int tile = (bx % 8) * per + bx / 8;
     if (tile >= T) return;
     const int tile_m = tile / tn, tile_n = tile % tn;
     const int m0 = tile_m * TM, n0 = tile_n * TN;
@@ -186,10 +188,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     if (g.kbeg) kb = g.kbeg[tile_n];
     if (g.kend) ke = g.kend[tile_n];
     int c_lo = kb / TK, c_hi = (ke + TK - 1) / TK;  // 32-wide chunks [c_lo, c_hi)
-    // split-K: slice blockIdx.z of the chunk range
+    // split-K: slice bz of the chunk range
     if (g.ksplit > 1) {
         const int nc = c_hi - c_lo, per = (nc + g.ksplit - 1) / g.ksplit;
-        c_lo = c_lo + (int)blockIdx.z * per;
+        c_lo = c_lo + bz * per;
         c_hi = min(c_hi, c_lo + per);
     }
     // a tile whose every output is masked needs no reduction
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
     if (g.ksplit > 1 || g.keep_parts) {
         // raw partial sums of this slice; the reduction applies the epilogue
-        float *part = g.part + (int64_t)blockIdx.z * g.M * g.N;
+        float *part = g.part + (int64_t)bz * g.M * g.N;
 #pragma unroll
         for (int i = 0; i < F; ++i)
 #pragma unroll
@@ -395,6 +397,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
 }
 
+template <int MA, int MB, int TT>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    gemm_body<MA, MB, TT>(g, (int)blockIdx.x, (int)blockIdx.z);
+}
+
+// Several products of one operand layout in one launch: problem p takes
+// blocks [start_p, start_p + nb_p), nb_p = bx_p z_p (bx_p, a multiple of 8,
+// blocks of its tile order, z_p its slices), so the workgroups of all of them
+// share the machine and one tail.  Block offsets stay multiples of 8, so a
+// problem's tile order keeps its XCD mapping.
+template <int MA, int MB>
+__global__ __launch_bounds__(256) void gemm_group_kernel(GemmGroup gg) {
+    int id = (int)blockIdx.x, p = 0;
+    while (p + 1 < gg.count && id >= gg.bx[p] * gg.z[p]) {
+        id -= gg.bx[p] * gg.z[p];
+        ++p;
+    }
+    gemm_body<MA, MB, 64>(gg.g[p], id % gg.bx[p], id / gg.bx[p]);
+}
+
 // Split-K reduction: slices added in ascending order, degree mask, fp32 out.
 // M N < 2^31 (checked at launch): 32-bit index arithmetic.
 __global__ void splitk_reduce_kernel(GemmArgs g) {
@@ -462,6 +484,52 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Lattice words (word-major, word w of sample b at states[w n + b]) -> bf16
 // 0/1 rows X[b][i], zero for i >= D.
+hipError_t launch_gemm_group(const GemmArgs *gs, int count, hipStream_t s) {
+    if (count < 1 || count > GEMM_GROUP_MAX) return hipErrorInvalidValue;
+    GemmGroup gg;
+    std::memset(&gg, 0, sizeof(gg));
+    gg.count = count;
+    int ma = -1, mb = -1;
+    int64_t blocks = 0;
+    for (int i = 0; i < count; ++i) {
+        const GemmArgs &g = gs[i];
+        // slices kept for a later finalize: no epilogue, no reduction launch
+        if (!g.keep_parts || !g.part || g.bias || g.relu || g.gate || g.out_bf16 || g.colpart || g.lossx || g.kperm ||
+            (int64_t)g.M * g.N > INT32_MAX)
+            return hipErrorInvalidValue;
+        const int a = operand_mode(g.A, g.sam, g.sak, g.M, g.K), b = operand_mode(g.B, g.sbn, g.sbk, g.N, g.K);
+        if (i == 0) {
+            ma = a;
+            mb = b;
+        } else if (a != ma || b != mb) {
+            // operand layouts differ: a launch each, same slices
+            for (int j = 0; j < count; ++j) {
+                const hipError_t e = launch_gemm(gs[j], s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }
+        const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64);
+        gg.g[i] = g;
+        gg.bx[i] = 8 * ((tiles + 7) / 8);
+        gg.z[i] = g.ksplit > 1 ? g.ksplit : 1;
+        blocks += (int64_t)gg.bx[i] * gg.z[i];
+    }
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    const void *fn = nullptr;
+#define PBIT_GEMM(A_, B_) \
+    if (ma == A_ && mb == B_) \
+        fn = (const void *)gemm_group_kernel<A_, B_>;
+    PBIT_GEMM(0, 0) PBIT_GEMM(0, 1) PBIT_GEMM(0, 2)
+    PBIT_GEMM(1, 0) PBIT_GEMM(1, 1) PBIT_GEMM(1, 2)
+    PBIT_GEMM(2, 0) PBIT_GEMM(2, 1) PBIT_GEMM(2, 2)
+#undef PBIT_GEMM
+    void *args[] = {&gg};
+    hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(256), args, 0, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    return e;
+}
+
 __global__ void unpack_kernel(const uint32_t *__restrict__ states, int n, int D, int DP, bf16 *__restrict__ X) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)n * DP) return;

@@ -350,14 +350,7 @@ pbit_status forward(pbit_proposal q, int n, hipStream_t s, bool wide = false, bo
 pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
     const int D = q->D, DP = q->DP, H = q->H;
     hipError_t e;
-    // dV = H2^T G3 (masked)
-    GemmArgs g = gemm0();
-    g.A = q->H2; g.sam = 1; g.sak = H;
-    g.B = q->G3; g.sbk = D; g.sbn = 1;
-    g.M = H; g.N = D; g.K = n;
-    g.deg_row = q->d_deg2; g.deg_col = q->d_deg_out;
-    z[2] = splitk(g, q->pV, q->zcap[2]);
-    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dV");
+    GemmArgs g;
     // G2 = (G3 V^T) * (H2 > 0); db2 partials (the library product, then the
     // gate and the column partials, when it runs)
     LtState *lt = lt_of(q);
@@ -373,14 +366,6 @@ pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
         g.colpart = q->cb2;
         if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G2");
     }
-    // dW2 = H1^T G2 (masked)
-    g = gemm0();
-    g.A = q->H1; g.sam = 1; g.sak = H;
-    g.B = q->G2; g.sbk = H; g.sbn = 1;
-    g.M = H; g.N = H; g.K = n;
-    g.deg_row = q->d_deg1; g.deg_col = q->d_deg2;
-    z[1] = splitk(g, q->pW2, q->zcap[1]);
-    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW2");
     // G1 = (G2 W2^T) * (H1 > 0); db1 partials
     if (lt && lt_gemm_nt(lt, n, H, H, q->G2, H, q->W2b, H, nullptr, false, q->G1, H, q->lt_ws, LT_WORKSPACE, s)) {
         if ((e = launch_gate_colsum(q->G1, q->H1, n, H, q->cb1, s)) != hipSuccess) return hip_error(e, "G1 gate");
@@ -394,14 +379,29 @@ pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
         g.colpart = q->cb1;
         if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "G1");
     }
-    // dW1 = X^T G1 (masked)
-    g = gemm0();
-    g.A = q->X; g.sam = 1; g.sak = DP;
-    g.B = q->G1; g.sbk = H; g.sbn = 1;
-    g.M = D; g.N = H; g.K = n;
-    g.deg_row = q->d_deg_in; g.deg_col = q->d_deg1;
-    z[0] = splitk(g, q->pW1, q->zcap[0]);
-    if ((e = launch_gemm(g, s)) != hipSuccess) return hip_error(e, "dW1");
+    // the weight gradients, split-K slices kept for grad_final: dW2 = H1^T G2,
+    // dV = H2^T G3, dW1 = X^T G1 (masked), in one launch (dW2, whose slices
+    // are the longest, first)
+    GemmArgs w[3];
+    w[0] = gemm0();
+    w[0].A = q->H1; w[0].sam = 1; w[0].sak = H;
+    w[0].B = q->G2; w[0].sbk = H; w[0].sbn = 1;
+    w[0].M = H; w[0].N = H; w[0].K = n;
+    w[0].deg_row = q->d_deg1; w[0].deg_col = q->d_deg2;
+    z[1] = splitk(w[0], q->pW2, q->zcap[1]);
+    w[1] = gemm0();
+    w[1].A = q->H2; w[1].sam = 1; w[1].sak = H;
+    w[1].B = q->G3; w[1].sbk = D; w[1].sbn = 1;
+    w[1].M = H; w[1].N = D; w[1].K = n;
+    w[1].deg_row = q->d_deg2; w[1].deg_col = q->d_deg_out;
+    z[2] = splitk(w[1], q->pV, q->zcap[2]);
+    w[2] = gemm0();
+    w[2].A = q->X; w[2].sam = 1; w[2].sak = DP;
+    w[2].B = q->G1; w[2].sbk = H; w[2].sbn = 1;
+    w[2].M = D; w[2].N = H; w[2].K = n;
+    w[2].deg_row = q->d_deg_in; w[2].deg_col = q->d_deg1;
+    z[0] = splitk(w[2], q->pW1, q->zcap[0]);
+    if ((e = launch_gemm_group(w, 3, s)) != hipSuccess) return hip_error(e, "weight gradients");
     return PBIT_OK;
 }
 
