@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "made.h"
+#include "made_log_table.h"
 
 namespace pbit {
 
@@ -22,41 +23,37 @@ __device__ __forceinline__ uint32_t made_threshold(float logit) {
     return t >= 4294967296.0f ? 0xFFFFFFFFu : (t >= 1.0f ? (uint32_t)t : 1u);
 }
 
-// Natural logarithm of a positive normal double, within one ulp (0.75 ulp
-// at worst over 10^5 sampled arguments, emulated exactly on the host):
-// x = 2^e m with m in [sqrt(2)/2, sqrt(2)), log m = 2 atanh(s) with
-// s = f / (m + 1), f = m - 1 (exact), |s| <= 0.1716.  The part of f / (m + 1)
-// that the rounded quotient s misses, s_lo, is recovered with one fma and
-// the exact rounding error of m + 1, so log m = 2 (s + s_lo) + 2 s z Q(z),
-// z = s^2, Q = sum_{k=1..10} z^(k-1) / (2k + 1) (the next term is below
-// 1e-18 of the sum); e ln 2 is added with ln 2 split into a double and its
-// remainder.  About 35 FP64 operations.
+// Natural logarithm of a positive normal double, within one ulp (0.74 ulp
+// at worst over 3.3e4 arguments, the 2^32 grid of the thresholds and edge
+// cases, emulated exactly on the host; the GPU test bounds it against numpy
+// over 10^6).  x = 2^e m, m in [1, 2); the top 8 fraction bits j select an
+// inverse G_j of 9 significant bits with |m G_j - 1| <= 2^-8, so that
+// r = m G_j - 1 is exact in one fma, and log x = (e + k_j) log 2 + T_j +
+// log1p(r) with T_j = -log G_j - k_j log 2 (k_j = 1 above sqrt(2), so that
+// the bins next to 1 have T = 0 and results near 0 keep their relative
+// accuracy).  log 2 and T_j are split so that (e + k_j) log2_hi + T_hi is
+// exact; log1p(r) - r is r^2 times a degree-6 polynomial (the next term is
+// below 2^-67 |r|).  About 13 FP64 operations and three table reads
+// (made_log_table.h, written by gen_log_table.py).
 __device__ __forceinline__ double made_log(double x) {
-    int e;
-    double m = frexp(x, &e);  // m in [0.5, 1)
-    if (m < 0x1.6a09e667f3bcdp-1) {
-        m += m;
-        e -= 1;
-    }
-    const double f = m - 1.0;          // exact
-    const double d = m + 1.0;          // rounded
-    const double ed = m - (d - 1.0);   // (m + 1) - d, exact
-    const double s = f / d;
-    const double slo = (fma(-s, d, f) - s * ed) / d;
-    const double z = s * s;
-    double Q = 1.0 / 21.0;
-    Q = fma(Q, z, 1.0 / 19.0);
-    Q = fma(Q, z, 1.0 / 17.0);
-    Q = fma(Q, z, 1.0 / 15.0);
-    Q = fma(Q, z, 1.0 / 13.0);
-    Q = fma(Q, z, 1.0 / 11.0);
-    Q = fma(Q, z, 1.0 / 9.0);
-    Q = fma(Q, z, 1.0 / 7.0);
-    Q = fma(Q, z, 1.0 / 5.0);
-    Q = fma(Q, z, 1.0 / 3.0);
-    const double de = (double)e;
-    const double tail = fma(2.0 * s * z, Q, fma(de, 0x1.abc9e3b39803fp-56, 2.0 * slo));
-    return fma(de, 0x1.62e42fefa39efp-1, 2.0 * s + tail);
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t hw = (uint32_t)(b >> 32);
+    const int e = (int)(hw >> 20) - 1023;
+    const int j = (int)((hw >> 12) & 255u);
+    const double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    const double r = fma(m, MADE_LOG_G[j], -1.0);  // exact
+    const double E = (double)(e + MADE_LOG_K[j]);
+    double q = -0.125;
+    q = fma(q, r, 1.0 / 7.0);
+    q = fma(q, r, -1.0 / 6.0);
+    q = fma(q, r, 0.2);
+    q = fma(q, r, -0.25);
+    q = fma(q, r, 1.0 / 3.0);
+    q = fma(q, r, -0.5);
+    const double r2 = r * r;
+    const double lo = fma(r2, q, fma(E, MADE_LOG_LN2_LO, MADE_LOG_TL[j]));
+    const double hi = fma(E, MADE_LOG_LN2_HI, MADE_LOG_TH[j]);  // exact
+    return hi + (r + lo);
 }
 
 // log of the probability of `bit` under threshold T: log(T / 2^32) for a 1,
