@@ -712,19 +712,24 @@ def main():
     if args.mode == "train":
         train_mode(args)
         return
+    # the modes with workloads of their own take their default when
+    # --workload was left at the Gibbs default, and refuse unknown names
+    def mode_workload(table, default):
+        if args.workload == ap.get_default("workload"):
+            args.workload = default
+        elif args.workload not in table:
+            ap.error("--mode %s: unknown workload %r (one of: %s)" % (args.mode, args.workload, ", ".join(table)))
+
     if args.mode == "shor":
-        if args.workload not in SHOR_WORKLOADS:
-            args.workload = "shor27"
+        mode_workload(SHOR_WORKLOADS, "shor27")
         shor_mode(args)
         return
     if args.mode == "sample":
-        if args.workload not in MH_WORKLOADS:
-            args.workload = "brick16"
+        mode_workload(MH_WORKLOADS, "brick16")
         sample_mode(args)
         return
     if args.mode == "mh":
-        if args.workload not in MH_WORKLOADS:
-            args.workload = "brick16"
+        mode_workload(MH_WORKLOADS, "brick16")
         mh_mode(args)
         return
     if args.workload == "batch256":
