@@ -115,7 +115,9 @@ bool batchable(pbit_circuit c, uint32_t i, const pbit_gibbs_cfg *cfg) {
 // the compiles run on host threads at once, about a second for a hundred
 // kernels, and are kept in the handle); otherwise only a circuit whose run
 // alone pays for its compile (2^33 updates, the single-circuit rule) leaves.
-constexpr uint32_t BATCH_SPEC_CHAINS = 1024;
+// (The 256-circuit batch of 2^22 chains: 0.736 of the VALU peak with a
+// threshold of 1,024 chains, 0.754 with 512, 0.73 with 256.)
+constexpr uint32_t BATCH_SPEC_CHAINS = 512;
 constexpr size_t BATCH_SPEC_MAX = 256;
 std::vector<bool> batch_specialised(pbit_circuit c, const pbit_gibbs_cfg *cfg) {
     const uint32_t nc = (uint32_t)c->circuits.size();

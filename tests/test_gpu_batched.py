@@ -108,7 +108,7 @@ def test_persistent_groups_graph_and_grid_shapes(env):
 
 
 def test_specialised_members_of_a_batch(env):
-    """specialize=2 takes the circuits with at least 1,024 chains out of the
+    """specialize=2 takes the circuits with at least 512 chains out of the
     persistent launch into their own circuit-specialised launches (the
     non-uniform circuit, which never rides in the persistent launch, gets its
     specialised kernel too); states and counts are those of the plain
@@ -123,7 +123,7 @@ def test_specialised_members_of_a_batch(env):
     say("kernels", kinds)
     assert pbit.KERNEL_SPECIALISED in kinds and pbit.KERNEL_PERSISTENT in kinds
     for i, k in enumerate(kinds):
-        assert (k == pbit.KERNEL_SPECIALISED) == (chains[i] >= 1024 or i == 14), (i, k, chains[i])
+        assert (k == pbit.KERNEL_SPECIALISED) == (chains[i] >= 512 or i == 14), (i, k, chains[i])
     for kw in [dict(persistent=1, specialize=2), dict(persistent=1, specialize=2, sweeps_per_launch=5),
                dict(persistent=1, specialize=2, hist_mode=3), dict(persistent=1, specialize=2, hist_mode=4)]:
         say("batch", kw)
