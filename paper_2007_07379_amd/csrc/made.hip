@@ -539,26 +539,24 @@ __global__ void unpack_kernel(const uint32_t *__restrict__ states, int n, int D,
     X[e] = (bf16)v;
 }
 
-// The gradient of every parameter from what the training GEMMs left (the
-// weight gradients' split-K slices, added in ascending order and masked by
-// degree, the bias gradients' 64-row column partials, added in ascending
-// order), then either stored (adam == 0) or taken by one Adam step; block 0
-// also adds the loss shares in a fixed order.
-__global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
-    if (blockIdx.x == 0 && a.loss) {
-        __shared__ float red[256];
-        float v = 0.f;
-        for (int i = threadIdx.x; i < a.nloss; i += 256) v += a.losspart[i];
-        red[threadIdx.x] = v;
+// Block 0 of a finalize launch adds the loss shares in a fixed order.
+__device__ __forceinline__ void gf_loss(const GradFinal &a) {
+    __shared__ float red[256];
+    float v = 0.f;
+    for (int i = threadIdx.x; i < a.nloss; i += 256) v += a.losspart[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) *a.loss = red[0];
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.P) return;
+    if (threadIdx.x == 0) *a.loss = red[0];
+}
+
+// The gradient of flat parameter i < P: a weight's split-K slices added in
+// ascending order and masked by degree, a bias's 64-row column partials
+// added in ascending order.
+__device__ __forceinline__ float gf_grad(const GradFinal &a, int64_t i) {
     const int D = a.D, H = a.H;
     auto slices = [&](const float *part, int z, int64_t MN, int64_t e) {
         float v = 0.f;
@@ -574,35 +572,138 @@ __global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
         for (int k = 0; k < a.chunks; ++k) v += part[(int64_t)k * N + j];
         return v;
     };
-    float gi;
     if (i < a.ob1) {  // W1 [D][H]
         const int64_t e = i - a.oW1;
         const int m = (int)(e / H), n = (int)(e - (int64_t)m * H);
-        gi = a.deg_in[m] > a.deg1[n] ? 0.f : slices(a.pW1, a.zW1, (int64_t)D * H, e);
+        return a.deg_in[m] > a.deg1[n] ? 0.f : slices(a.pW1, a.zW1, (int64_t)D * H, e);
     } else if (i < a.oW2) {  // b1
-        gi = cols(a.cb1, H, (int)(i - a.ob1));
+        return cols(a.cb1, H, (int)(i - a.ob1));
     } else if (i < a.ob2) {  // W2 [H][H]
         const int64_t e = i - a.oW2;
         const int m = (int)(e / H), n = (int)(e - (int64_t)m * H);
-        gi = a.deg1[m] > a.deg2[n] ? 0.f : slices(a.pW2, a.zW2, (int64_t)H * H, e);
+        return a.deg1[m] > a.deg2[n] ? 0.f : slices(a.pW2, a.zW2, (int64_t)H * H, e);
     } else if (i < a.oV) {  // b2
-        gi = cols(a.cb2, H, (int)(i - a.ob2));
+        return cols(a.cb2, H, (int)(i - a.ob2));
     } else if (i < a.oc) {  // V [H][D]
         const int64_t e = i - a.oV;
         const int m = (int)(e / D), n = (int)(e - (int64_t)m * D);
-        gi = a.deg2[m] > a.deg_out[n] ? 0.f : slices(a.pV, a.zV, (int64_t)H * D, e);
-    } else {  // c
-        gi = cols(a.cc, D, (int)(i - a.oc));
+        return a.deg2[m] > a.deg_out[n] ? 0.f : slices(a.pV, a.zV, (int64_t)H * D, e);
     }
-    if (!a.adam) {
+    return cols(a.cc, D, (int)(i - a.oc));  // c
+}
+
+// One Adam step from gradient gi, moments m, v and value th (updated in
+// place).
+__device__ __forceinline__ void gf_adam_math(const GradFinal &a, float gi, float &m, float &v, float &th) {
+    m = a.b1 * m + (1.f - a.b1) * gi;
+    v = a.b2 * v + (1.f - a.b2) * gi * gi;
+    th = th - a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+}
+
+// One Adam step of parameter i on gradient gi; returns the new value.
+__device__ __forceinline__ float gf_adam(const GradFinal &a, int64_t i, float gi) {
+    float m = a.m[i], v = a.v[i], th = a.th[i];
+    gf_adam_math(a, gi, m, v, th);
+    a.m[i] = m;
+    a.v[i] = v;
+    a.th[i] = th;
+    return th;
+}
+
+// The gradient of every parameter from what the training GEMMs left, then
+// either stored (adam == 0) or taken by one Adam step; block 0 also adds the
+// loss shares.  One thread per flat parameter.
+__global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
+    if (blockIdx.x == 0 && a.loss) gf_loss(a);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.P) return;
+    const float gi = gf_grad(a, i);
+    if (!a.adam)
         a.grad[i] = gi;
-        return;
+    else
+        (void)gf_adam(a, i, gi);
+}
+
+// The Adam step with the bf16 shadows of the updated weights written in the
+// same pass (the arithmetic of grad_final_kernel, element for element).  The
+// first a.tiles[0] + a.tiles[1] + a.tiles[2] workgroups take 32 x 32 tiles of
+// W1, W2 and V (rows k0.. of the KP rows of WT, columns n0..): thread
+// (column tx, row group ty) updates rows ty, ty + 8, ... and writes Wb along
+// n; the tile is transposed through LDS and WT written along k, zero past K.
+// The rest take the biases b1, b2, c, one thread each.  Workgroup 0 adds the
+// loss shares.
+constexpr int AS_ROWS = 32, AS_COLS = 32;
+__global__ __launch_bounds__(256) void adam_shadow_kernel(GradFinal a, int4 tiles) {
+    if (blockIdx.x == 0 && a.loss) gf_loss(a);
+    int id = (int)blockIdx.x;
+    const int tcount[3] = {tiles.x, tiles.y, tiles.z};
+    const int64_t off[3] = {a.oW1, a.oW2, a.oV};
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        if (id < tcount[w]) {
+            __shared__ float t[AS_ROWS][AS_COLS + 1];
+            const ShadowJob &J = a.sh[w];
+            const int gx = (J.N + AS_COLS - 1) / AS_COLS;
+            const int n0 = (id % gx) * AS_COLS, k0 = (id / gx) * AS_ROWS;
+            const int tx = threadIdx.x & (AS_COLS - 1), ty = threadIdx.x / AS_COLS;
+            constexpr int RG = 256 / AS_COLS, Q = AS_ROWS / RG;
+            // every load of the thread's elements first, then the arithmetic
+            // and the stores (the stores could alias the loads, so
+            // interleaved they would wait one memory latency apiece)
+            float g[Q], m[Q], v[Q], th[Q];
+            const int n = n0 + tx;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int k = k0 + ty + RG * q;
+                g[q] = m[q] = v[q] = th[q] = 0.f;
+                if (k < J.K && n < J.N) {
+                    const int64_t i = off[w] + (int64_t)k * J.N + n;
+                    g[q] = gf_grad(a, i);
+                    m[q] = a.m[i];
+                    v[q] = a.v[i];
+                    th[q] = a.th[i];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int k = k0 + ty + RG * q;
+                float x = 0.f;
+                if (k < J.K && n < J.N) {
+                    const int64_t e = (int64_t)k * J.N + n, i = off[w] + e;
+                    gf_adam_math(a, g[q], m[q], v[q], th[q]);
+                    a.m[i] = m[q];
+                    a.v[i] = v[q];
+                    a.th[i] = th[q];
+                    J.Wb[e] = (bf16)th[q];
+                    x = th[q];
+                }
+                t[ty + RG * q][tx] = x;
+            }
+            __syncthreads();
+            // transposed: thread (k offset kx, column group ny) writes
+            // WT[n0 + ny + 8 r][k0 + kx]
+            const int kx = threadIdx.x & (AS_ROWS - 1), ny = threadIdx.x / AS_ROWS;
+#pragma unroll
+            for (int r = 0; r < AS_COLS / 8; ++r) {
+                const int nn = n0 + ny + 8 * r, k = k0 + kx;
+                if (nn < J.N && k < J.KP) J.WT[(int64_t)nn * J.KP + k] = (bf16)t[kx][ny + 8 * r];
+            }
+            return;
+        }
+        id -= tcount[w];
     }
-    const float mi = a.b1 * a.m[i] + (1.f - a.b1) * gi;
-    const float vi = a.b2 * a.v[i] + (1.f - a.b2) * gi * gi;
-    a.m[i] = mi;
-    a.v[i] = vi;
-    a.th[i] = a.th[i] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+    // biases: b1 [H], b2 [H], c [D] in that order
+    const int j = id * 256 + (int)threadIdx.x;
+    int64_t i;
+    if (j < a.H)
+        i = a.ob1 + j;
+    else if (j < 2 * a.H)
+        i = a.ob2 + (j - a.H);
+    else if (j < 2 * a.H + a.D)
+        i = a.oc + (j - 2 * a.H);
+    else
+        return;
+    (void)gf_adam(a, i, gf_grad(a, i));
 }
 
 // The ReLU-derivative gate of a library product's bf16 output and its column
@@ -1919,6 +2020,26 @@ hipError_t launch_grad_final(const GradFinal &a, hipStream_t s) {
     if (a.zW1 < 1 || a.zW2 < 1 || a.zV < 1 || a.chunks < 1 || (a.adam && (!a.th || !a.m || !a.v)) ||
         (!a.adam && !a.grad))
         return hipErrorInvalidValue;
+    if (a.adam && a.sh[0].Wb) {
+        // the three weights' shapes and offsets must be the flat layout's
+        const int64_t D = a.D, H = a.H;
+        const ShadowJob *J = a.sh;
+        const bool shapes = J[0].K == a.D && J[0].N == a.H && J[1].K == a.H && J[1].N == a.H && J[2].K == a.H &&
+                            J[2].N == a.D && a.ob1 == a.oW1 + D * H && a.ob2 == a.oW2 + H * H &&
+                            a.oc == a.oV + H * D && a.oW2 == a.ob1 + H && a.oV == a.ob2 + H && a.P == a.oc + D;
+        int tc[3];
+        int64_t blocks = 0;
+        for (int w = 0; w < 3; ++w) {
+            if (!J[w].Wb || !J[w].WT || J[w].KP < J[w].K || J[w].K <= 0 || J[w].N <= 0) return hipErrorInvalidValue;
+            tc[w] = ((J[w].N + AS_COLS - 1) / AS_COLS) * ((J[w].KP + AS_ROWS - 1) / AS_ROWS);
+            blocks += tc[w];
+        }
+        if (!shapes) return hipErrorInvalidValue;
+        blocks += (2 * H + D + 255) / 256;
+        if (blocks > INT32_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(adam_shadow_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, int4{tc[0], tc[1], tc[2], 0});
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(grad_final_kernel, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

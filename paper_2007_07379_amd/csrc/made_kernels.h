@@ -126,9 +126,18 @@ hipError_t launch_made_sample_dual(const SampleArgs &a, hipStream_t s);
 hipError_t launch_unpack(const uint32_t *states, int n, int D, int DP, bf16 *X, hipStream_t s);
 // y[i] = made_log(x[i]) for i < n (n < 2^40)
 hipError_t launch_log_eval(const double *x, double *y, uint64_t n, hipStream_t s);
+// bf16 shadow Wb (K x N, row-major) and transpose WT (N x KP, zero-padded)
+// of an fp32 K x N weight W; one launch for `count` (1 to 3) weights.
+struct ShadowJob {
+    const float *W;
+    int K, N, KP;
+    bf16 *Wb, *WT;
+};
 // The parameter gradient from the training GEMMs' leftovers and, with adam,
 // one Adam step (see grad_final_kernel).  Flat parameter order W1 [D][H],
-// b1, W2 [H][H], b2, V [H][D], c at the given offsets.
+// b1, W2 [H][H], b2, V [H][D], c at the given offsets.  With adam and
+// sh[0].Wb set, the step also writes the bf16 shadows of the updated W1, W2
+// and V (sh[0..2], W unused), in place of a separate shadow launch.
 struct GradFinal {
     int adam;
     float *th, *m, *v;  // Adam state (adam)
@@ -144,18 +153,12 @@ struct GradFinal {
     const float *losspart;        // loss shares, nloss of them, summed into *loss (may be NULL)
     int nloss;
     float *loss;
+    ShadowJob sh[3];              // shadows of W1, W2, V written by the Adam step (sh[0].Wb NULL: none)
 };
 hipError_t launch_grad_final(const GradFinal &a, hipStream_t s);
 // G[m][j] = 0 where A[m][j] <= 0 (n x N bf16, row-major, N % 8 == 0), and
 // the 64-row column partials of the gated G into colpart (ceil(n / 64) x N).
 hipError_t launch_gate_colsum(bf16 *G, const bf16 *A, int n, int N, float *colpart, hipStream_t s);
-// bf16 shadow Wb (K x N, row-major) and transpose WT (N x KP, zero-padded)
-// of an fp32 K x N weight W; one launch for `count` (1 to 3) weights.
-struct ShadowJob {
-    const float *W;
-    int K, N, KP;
-    bf16 *Wb, *WT;
-};
 struct ShadowJobs {
     ShadowJob j[3];
 };

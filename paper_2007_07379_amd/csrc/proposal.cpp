@@ -406,7 +406,8 @@ pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
 }
 
 // The gradient of the batch of n into `grad` (adam_step == false), or one
-// Adam step on it; the batch-mean loss into *loss_dev.
+// Adam step on it that also writes the weights' bf16 shadows; the batch-mean
+// loss into *loss_dev.
 pbit_status grad_final(pbit_proposal q, int n, const int z[3], float *loss_dev, bool adam_step, float *grad, float lr,
                        float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
     GradFinal a;
@@ -448,6 +449,11 @@ pbit_status grad_final(pbit_proposal q, int n, const int z[3], float *loss_dev, 
     a.losspart = q->losspart;
     a.nloss = ((n + 63) / 64) * ((q->D + 63) / 64);
     a.loss = loss_dev;
+    if (adam_step) {  // the step writes the shadows of the updated weights
+        a.sh[0] = {nullptr, q->D, q->H, q->DP, q->W1b, q->W1T};
+        a.sh[1] = {nullptr, q->H, q->H, q->H, q->W2b, q->W2T};
+        a.sh[2] = {nullptr, q->H, q->D, q->H, q->Vb, q->VT};
+    }
     hipError_t e = launch_grad_final(a, s);
     if (e != hipSuccess) return hip_error(e, adam_step ? "adam" : "gradient");
     return PBIT_OK;
@@ -750,8 +756,7 @@ pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint6
         if ((st = grad_final(q, (int)cfg->batch, z, q->loss + it, true, nullptr, lr, b1, b2, eps, (float)c1,
                              (float)c2, s)) != PBIT_OK)
             return st;
-        q->dirty = true;
-        if ((st = refresh(q, s)) != PBIT_OK) return st;
+        q->dirty = false;  // the Adam step refreshed the shadows
     }
     if (losses_out) {
         e = hipMemcpyAsync(losses_out, q->loss, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost, s);

@@ -273,6 +273,37 @@ def test_training_is_deterministic(env):
     assert np.array_equal(after[0][1].view(np.uint32), after[1][1].view(np.uint32))
 
 
+@pytest.mark.parametrize("which,H", [("small", 64), ("small", 512), ("brick16", 1024)])
+def test_adam_step_shadows_equal_a_refresh(env, which, H):
+    """The Adam step writes the bf16 shadows (row-major and transposed) of the
+    weights it updates; a second proposal given the same parameters builds
+    its shadows with the separate shadow pass.  Logits, samples, their log q
+    and the scores must agree bit for bit (D = 28 and 400: transposed rows
+    padded past D)."""
+    torch, pbit = env
+    c = SMALL() if which == "small" else wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    q = pbit.Proposal(s, hidden=H, seed=4)
+    D = q.D
+    n = 1024
+    _, _, words = valid_paths(c, n, 12)
+    d_states = to_dev(torch, words)
+    q.train(d_states, n, 512, 3, lr=3e-3)
+    r = pbit.Proposal(s, hidden=H, seed=9)
+    r.set_params(q.get_params())
+    outs = []
+    for p in (q, r):
+        d_logits = torch.zeros(n * D, dtype=torch.float32, device="cuda")
+        p.logits(d_states, n, d_logits)
+        d_out, d_lq = _sample(env, p, 2048, seed=5)
+        d_sc = torch.zeros(n, dtype=torch.float64, device="cuda")
+        p.score(d_states, n, d_sc)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().view(np.uint8) for t in (d_logits, d_out, d_lq, d_sc)])
+    for a, b, name in zip(outs[0], outs[1], ("logits", "samples", "log q", "scores")):
+        assert np.array_equal(a, b), name
+
+
 def _sample(env, q, n, seed=3, step=0):
     torch, pbit = env
     W = q.cset.info(0)["W"]
