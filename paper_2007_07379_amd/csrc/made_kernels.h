@@ -134,7 +134,7 @@ struct ShadowJob {
     bf16 *Wb, *WT;
 };
 // The parameter gradient from the training GEMMs' leftovers and, with adam,
-// one Adam step (see grad_final_kernel).  Flat parameter order W1 [D][H],
+// one Adam step (grad_final_kernel, adam_shadow_kernel).  Flat parameter order W1 [D][H],
 // b1, W2 [H][H], b2, V [H][D], c at the given offsets.  With adam and
 // sh[0].Wb set, the step also writes the bf16 shadows of the updated W1, W2
 // and V (sh[0..2], W unused), in place of a separate shadow launch.
