@@ -448,7 +448,7 @@ BF16_PEAK = 2.5e15  # MI355X dense bf16 MFMA FLOP/s
 
 
 def train_mode(args):
-    """MADE training throughput on the config-5 network (D = 400 lattice
+    """MADE training throughput on the brick16 network (D = 400 lattice
     positions of the n=16, d=24 brickwork circuit, two masked hidden layers
     of 1024, batch 4096): Adam steps per second and the MFMA roofline of the
     masked products (forward, weight gradients, input gradients of the
