@@ -288,7 +288,8 @@ pbit_status pbit_proposal_score(pbit_proposal q, const uint32_t *d_states, uint3
 /* pbit_proposal_sample (n proposals into d_out, d_logq) and
  * pbit_proposal_score of the n word-major paths d_cur (into d_logq_cur) in
  * one call: the MH step's two passes over the network.  For networks of
- * width <= 256 on lattices of <= 256 bits it is one kernel that carries both
+ * width 64 or 128 whose padded lattice row is 64 or 128 positions (within
+ * the register sampler's LDS limit) it is one kernel that carries both
  * paths of a chain through the same weight tiles; otherwise the two calls
  * run in sequence.  Outputs are bit-identical to the two separate calls.
  * d_cur must not overlap d_out. */
@@ -345,11 +346,12 @@ pbit_status pbit_mh_run_static(pbit_circuit c, pbit_proposal q, const pbit_mh_cf
 /* The FP64 natural logarithm whose values the learned proposal's samplers
  * and scorers sum into log q (the log of the threshold probability of each
  * drawn or scored bit), evaluated on n device doubles: d_y[i] = ln(d_x[i])
- * for positive normal d_x[i], within one ulp (2 atanh series on the
- * mantissa reduced to [sqrt(2)/2, sqrt(2)) with the quotient's rounding
- * error recovered, plus e ln 2).  Exported so its
- * accuracy can be checked against a reference logarithm; device buffers,
- * asynchronous on hip_stream. */
+ * for positive normal d_x[i], within one ulp (x = 2^e m; the top 8 fraction
+ * bits of m select a 9-bit inverse G of m's bin, so r = m G - 1 is exact and
+ * |r| <= 2^-8; ln x = e ln 2 - ln G + log1p(r), with a table for -ln G split
+ * so that its high part and e's share add exactly, and a degree-8 series for
+ * log1p).  Exported so its accuracy can be checked against a reference
+ * logarithm; device buffers, asynchronous on hip_stream. */
 pbit_status pbit_log_eval(const double *d_x, double *d_y, uint64_t n, void *hip_stream);
 
 /* Per-path observables of chain states, for autocorrelation estimates
