@@ -22,7 +22,8 @@
  *    diagonal copies its input p-bits, a gate whose matrix is a permutation
  *    (times phases) fixes its outputs as an affine GF(2) function of its
  *    inputs (NOT, CNOT = XOR), and only gates with no zero entry create new
- *    independent ("free") p-bits.  Other zero patterns are rejected.
+ *    independent ("free") p-bits.  Other zero patterns are rejected unless
+ *    the circuit enables soft zeros (soft_zero_J of pbit_circuit_desc).
  *  - Every nonzero entry must have a phase on the grid 2 pi k / 2^K; the
  *    sample phase is then an integer bin k in [0, 2^K).
  *  - Histograms are uint32[2^n][2^K] (index alpha * 2^K + k), owned and
@@ -180,10 +181,11 @@ typedef struct {
                                    generated for the circuit and compiled with hipRTC on first use
                                    (cached in the handle); circuits with conditionals other than
                                    1/2 get one lane per chain and the colour schedule unrolled.
-                                   In a persistent batch, 2 takes the circuits with at least 1,024
+                                   In a persistent batch, 2 takes the circuits with at least 512
                                    chains (at most 256, heaviest by chains x free bits first) out
                                    of the batch into launches of their own specialised kernels;
-                                   0 takes those among them with 2^33 updates or more. */
+                                   0 does the same when the whole run has 2^33 updates or more,
+                                   else takes only members whose own run has that many. */
 } pbit_gibbs_cfg;
 
 /* Gibbs sampling of Feynman paths (Fig. 2 steps 1-3): every chain sweeps its
@@ -335,14 +337,6 @@ pbit_status pbit_mh_run(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
 pbit_status pbit_mh_run_static(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg, uint32_t *d_state,
                                uint32_t *d_hist, uint64_t *d_accepts, void *hip_stream);
 
-/* Autotuner.  Times candidate launch shapes (workgroup size, histogram
- * privatisation, toggle tables, sweeps per launch, persistent grid size) on
- * short runs of cfg's workload on hip_stream and keeps the fastest per
- * circuit (and per batched class) in the handle; later runs whose cfg
- * leaves those fields 0 use it.  With cache_path the choices are read from /
- * written to that JSON file, keyed by a hash of the compiled circuits, so a
- * second process skips the timing.  Uses temporary device buffers; blocks
- * until done. */
 /* The FP64 natural logarithm whose values the learned proposal's samplers
  * and scorers sum into log q (the log of the threshold probability of each
  * drawn or scored bit), evaluated on n device doubles: d_y[i] = ln(d_x[i])
@@ -366,6 +360,14 @@ pbit_status pbit_log_eval(const double *d_x, double *d_y, uint64_t n, void *hip_
 pbit_status pbit_path_observables(pbit_circuit c, uint32_t idx, const uint32_t *d_state, uint32_t chains,
                                   uint32_t *d_bin, double *d_logmag, void *hip_stream);
 
+/* Autotuner.  Times candidate launch shapes (workgroup size, lanes per chain, histogram
+ * privatisation, toggle tables, sweeps per launch, persistent grid size) on
+ * short runs of cfg's workload on hip_stream and keeps the fastest per
+ * circuit (and per batched class) in the handle; later runs whose cfg
+ * leaves those fields 0 use it.  With cache_path the choices are read from /
+ * written to that JSON file, keyed by a hash of the compiled circuits, so a
+ * second process skips the timing.  Uses temporary device buffers; blocks
+ * until done. */
 pbit_status pbit_autotune(pbit_circuit c, const pbit_gibbs_cfg *cfg, const char *cache_path, void *hip_stream);
 
 /* Launch shape that pbit_gibbs_run would use for circuit `index` under
