@@ -18,6 +18,17 @@ struct GibbsArgs {
     uint32_t lds_hist;
 };
 
+// A Metropolis-Hastings accept of independence proposals that a launch takes
+// for each chain before its sweeps (the circuit-specialised kernel for
+// circuits with non-constant magnitudes, one lane per chain): the same
+// arithmetic as mh_accept_kernel, and the post-transition path binned.
+struct MhFuse {
+    const uint32_t *prop;                  // word-major proposals
+    const double *logq_cur, *logq_prop;    // log q of the current paths and of the proposals
+    unsigned long long *accepts;           // per-chain accept counters (may be NULL)
+    uint32_t step;                         // MH step counter (Philox counter word 0)
+};
+
 struct GibbsLaunch {
     const uint32_t *blob;   // device image of the circuit (blob.h)
     uint32_t *state;        // word-major lattice words, n_chains per word; may be NULL
@@ -30,6 +41,7 @@ struct GibbsLaunch {
     uint32_t bin_from;      // sweeps with counter >= bin_from are binned
     uint32_t resume;        // 1: read the lattice from state; 0: start from all-zero free bits
     uint32_t lds_hist;      // 1: histogram privatised in LDS
+    const MhFuse *mh;       // an MH accept before the sweeps (NULL: none; resume must be 1)
 };
 
 // LDS bytes a launch needs (toggle tables when `tog`, thresholds, and the

@@ -23,6 +23,7 @@
 #include <hip/hiprtc.h>
 
 #include <cstdio>
+#include <cstring>
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -36,6 +37,13 @@ namespace {
 std::string hx(uint32_t v) {
     char b[16];
     std::snprintf(b, sizeof b, "0x%08xu", v);
+    return b;
+}
+
+// an exact FP64 literal (hexadecimal significand)
+std::string hf(double v) {
+    char b[40];
+    std::snprintf(b, sizeof b, "(%a)", v);
     return b;
 }
 
@@ -450,6 +458,7 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     const uint32_t ctag = B[H_CID];
     JitSource out;
     out.entry = "pbit_general_sweep";
+    out.general = true;
     out.max_block = max_block;
     const bool thr_lds = (size_t)total * 4 + (lds_hist ? (size_t)nbins * 4 : 0) <= JIT_LDS_LIMIT;
     out.rows_words = thr_lds ? total : 0;
@@ -470,10 +479,31 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     for (uint32_t i = 0; i < std::max<uint32_t>(total, 1); ++i)
         o << (i % 8 ? " " : "\n    ") << hx(i < total ? thrtab[i] : 0u) << ",";
     o << "\n};\n\n";
+    // ln|U| tables of the gates with non-constant magnitude (the real-energy
+    // records, in gate order) for the MH accept: 4-entry tables become
+    // selects, 16-entry ones arrays
+    const uint32_t nre = B[H_NRE];
+    const uint32_t *re = B + B[H_OFF_RE];
+    auto re_val = [&](uint32_t r, uint32_t t) {
+        const uint32_t *rec = re + (size_t)r * RE_STRIDE;
+        const uint64_t bits = (uint64_t)rec[8 + 2 * t] | ((uint64_t)rec[9 + 2 * t] << 32);
+        double v;
+        std::memcpy(&v, &bits, sizeof v);
+        return v;
+    };
+    for (uint32_t r = 0; r < nre; ++r) {
+        const uint32_t a = re[(size_t)r * RE_STRIDE];
+        if (a != 2) continue;
+        o << "static __device__ const double mh_re" << r << "[16] = {";
+        for (uint32_t t = 0; t < 16; ++t) o << (t % 4 ? " " : "\n    ") << hf(re_val(r, t)) << ",";
+        o << "\n};\n";
+    }
     o << "extern \"C\" __global__ void __attribute__((amdgpu_flat_work_group_size(1, " << max_block
       << "))) pbit_general_sweep(\n"
          "    u32 *__restrict__ state, u32 *__restrict__ hist, u32 n_chains, u32 lanes_log2, u32 chain_begin,\n"
-         "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from, u32 resume) {\n";
+         "    u32 seed_lo, u32 seed_hi, u32 sweep_begin, u32 n_sweeps, u32 bin_from, u32 resume,\n"
+         "    const u32 *__restrict__ mh_prop, const double *__restrict__ mh_lq_cur,\n"
+         "    const double *__restrict__ mh_lq_prop, u64 *__restrict__ mh_acc, u32 mh_step) {\n";
     if (thr_lds) o << "    __shared__ u32 lds_t[" << std::max<uint32_t>(total, 1) << "];\n";
     if (lds_hist) o << "    __shared__ u32 lds_h[" << nbins << "];\n";
     if (paired) o << "    __shared__ u32 lds_f[" << flip_words << "];  // [buffer][wave][word][lane]\n";
@@ -499,8 +529,58 @@ JitSource jit_general_source(const CompiledCircuit &k, bool lds_hist, uint32_t m
     for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = state[(u64)" << w << " * n_chains + lc];\n";
     o << "        } else {\n";
     for (uint32_t w = 0; w < W; ++w) o << "            x[" << w << "] = " << hx(cw[w]) << ";\n";
-    o << "        }\n"
-         "        for (u32 it = 0; it < n_sweeps; ++it) {\n"
+    o << "        }\n";
+    if (!paired) {
+        // the MH accept of the proposal (one lane per chain only): log r =
+        // [ln|psi(y)| - ln|psi(x)|] + [log q(x) - log q(y)], the ln|U| terms
+        // added in gate order from zero; accept iff Philox word 0 at
+        // (step, 0, chain, id | 2 << 16) < min(1, e^(log r)) 2^32; the
+        // post-transition path is binned
+        auto bitx = [&](const char *v, uint32_t p) {
+            return std::string("((") + v + "[" + std::to_string(p >> 5) + "] >> " + std::to_string(p & 31) + "u) & 1u)";
+        };
+        o << "        if (mh_prop) {\n"
+             "            u32 y[" << W << "];\n";
+        for (uint32_t w = 0; w < W; ++w) o << "            y[" << w << "] = mh_prop[(u64)" << w << " * n_chains + lc];\n";
+        o << "            double lr = mh_lq_cur[lc] - mh_lq_prop[lc];\n";
+        if (nre) {
+            o << "            double wx = 0.0, wy = 0.0;\n";
+            for (uint32_t r = 0; r < nre; ++r) {
+                const uint32_t *rec = re + (size_t)r * RE_STRIDE;
+                const uint32_t a = rec[0];
+                for (int side = 0; side < 2; ++side) {
+                    const char *v = side ? "y" : "x";
+                    std::string in = "0u", out = "0u";
+                    for (uint32_t j = 0; j < a; ++j) {
+                        in += " | (" + bitx(v, rec[1 + j]) + " << " + std::to_string(j) + ")";
+                        out += " | (" + bitx(v, rec[3 + j]) + " << " + std::to_string(j) + ")";
+                    }
+                    const std::string t = std::string("t") + v + std::to_string(r);
+                    o << "            const u32 " << t << " = (" << out << ") * " << (1u << a) << "u + (" << in << ");\n";
+                    o << "            w" << v << " += ";
+                    if (a == 1)
+                        o << "(" << t << " & 2u) ? ((" << t << " & 1u) ? " << hf(re_val(r, 3)) << " : " << hf(re_val(r, 2))
+                          << ") : ((" << t << " & 1u) ? " << hf(re_val(r, 1)) << " : " << hf(re_val(r, 0)) << ");\n";
+                    else
+                        o << "mh_re" << r << "[" << t << "];\n";
+                }
+            }
+            o << "            lr += wy - wx;\n";
+        }
+        o << "            const double acc = lr >= 0.0 ? 1.0 : exp(lr);\n"
+             "            u32 m0, m1, m2, m3;\n"
+             "            philox(mh_step, 0u, chain, " << hx(ctag | (2u << 16)) << ", seed_lo, seed_hi, m0, m1, m2, m3);\n"
+             "            if ((double)m0 < acc * 4294967296.0) {\n";
+        for (uint32_t w = 0; w < W; ++w) o << "                x[" << w << "] = y[" << w << "];\n";
+        o << "                if (mh_acc) mh_acc[lc] += 1ull;\n"
+             "            }\n"
+             "            {\n";
+        emit_bin_code(o, "                ", B);
+        o << (lds_hist ? "                atomicAdd(&lds_h[bin], 1u);\n" : "                atomicAdd(&hist[bin], 1u);\n");
+        o << "            }\n"
+             "        }\n";
+    }
+    o << "        for (u32 it = 0; it < n_sweeps; ++it) {\n"
          "            const u32 s = sweep_begin + it;\n";
     if (paired)
         for (uint32_t j = 0; j < (h + 3) / 4; ++j)
@@ -717,6 +797,7 @@ bool jit_load(const JitSource &src, const std::vector<char> &code, JitKernel *ou
     out->fn = fn;
     out->lds_bytes = src.lds_bytes;
     out->max_block = src.max_block;
+    out->general = src.general;
     out->scratch_bytes = scratch;
     return true;
 }
@@ -775,6 +856,7 @@ bool jit_build_group(const std::vector<const JitSource *> &srcs, hipModule_t *mo
         k.fn = fn;
         k.lds_bytes = srcs[j]->lds_bytes;
         k.max_block = srcs[j]->max_block;
+        k.general = srcs[j]->general;
         k.scratch_bytes = scratch;
     }
     *module = mod;
@@ -793,7 +875,19 @@ hipError_t jit_launch(const JitKernel &k, const GibbsLaunch &a, uint32_t lanes_l
     uint32_t *state = a.state, *hist = a.hist;
     uint32_t n_chains = a.n_chains, ll = lanes_log2, cb = a.chain_begin, slo = a.seed_lo, shi = a.seed_hi;
     uint32_t sb = a.sweep_begin, ns = a.n_sweeps, bf = a.bin_from, rs = a.resume;
-    void *args[] = {&state, &hist, &n_chains, &ll, &cb, &slo, &shi, &sb, &ns, &bf, &rs};
+    if (!k.general) {
+        if (a.mh) return hipErrorInvalidValue;
+        void *args[] = {&state, &hist, &n_chains, &ll, &cb, &slo, &shi, &sb, &ns, &bf, &rs};
+        return hipModuleLaunchKernel(k.fn, (uint32_t)grid, 1, 1, block, 1, 1, 0, stream, args, nullptr);
+    }
+    // the MH accept needs one lane per chain, the chains' states and sweeps
+    // after it (its path is written back with the last sweep's)
+    if (a.mh && (lanes_log2 != 0 || !a.resume || !state || a.n_sweeps == 0)) return hipErrorInvalidValue;
+    const uint32_t *mp = a.mh ? a.mh->prop : nullptr;
+    const double *mc = a.mh ? a.mh->logq_cur : nullptr, *mq = a.mh ? a.mh->logq_prop : nullptr;
+    unsigned long long *macc = a.mh ? a.mh->accepts : nullptr;
+    uint32_t mstep = a.mh ? a.mh->step : 0u;
+    void *args[] = {&state, &hist, &n_chains, &ll, &cb, &slo, &shi, &sb, &ns, &bf, &rs, &mp, &mc, &mq, &macc, &mstep};
     return hipModuleLaunchKernel(k.fn, (uint32_t)grid, 1, 1, block, 1, 1, 0, stream, args, nullptr);
 }
 

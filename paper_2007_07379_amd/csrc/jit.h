@@ -25,6 +25,7 @@ struct JitSource {
     uint32_t lds_bytes = 0;  // static LDS of the kernel
     uint32_t xor_words = 0;  // lattice words XORed per sweep (sum of block supports)
     uint32_t max_block = 256;
+    bool general = false;     // pbit_general_sweep (takes the MH accept arguments)
 };
 
 // Generates the kernel for `k` (k.uniform must hold).  With lds_hist the
@@ -69,6 +70,7 @@ struct JitKernel {
     uint32_t lds_bytes = 0;
     uint32_t max_block = 256;
     int scratch_bytes = 0;  // per-lane scratch of the compiled kernel (register spills)
+    bool general = false;   // pbit_general_sweep: takes the MH accept arguments
 };
 
 // Compiles `src` with hipRTC for the current device and loads it (and reads

@@ -1003,8 +1003,11 @@ pbit_status mh_run_impl(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
         a.seed_lo = (uint32_t)cfg->seed;
         a.seed_hi = (uint32_t)(cfg->seed >> 32);
         a.hist_bins = 1u << (k.n + k.K);
-        if ((e = launch_mh_accept(k.WS, a, s)) != hipSuccess) return hip_error(e, "mh accept");
-        if (cfg->gibbs_per_mh) {
+        if (!cfg->gibbs_per_mh) {
+            if ((e = launch_mh_accept(k.WS, a, s)) != hipSuccess) return hip_error(e, "mh accept");
+        } else {
+            // the sweeps' run takes the accept first (inside the first sweep
+            // launch when that is the specialised kernel, else on its own)
             pbit_gibbs_cfg g;
             std::memset(&g, 0, sizeof(g));
             g.chains = chains.data();
@@ -1014,7 +1017,7 @@ pbit_status mh_run_impl(pbit_circuit c, pbit_proposal q, const pbit_mh_cfg *cfg,
             g.seed = cfg->seed;
             g.sweep_offset = cfg->sweep_offset + cy * cfg->gibbs_per_mh;
             g.init = PBIT_INIT_RESUME;
-            if ((st = run_gibbs(c, &g, d_state, d_hist, s, no_alloc)) != PBIT_OK) return st;
+            if ((st = run_gibbs(c, &g, d_state, d_hist, s, no_alloc, &a, q->idx)) != PBIT_OK) return st;
         }
     }
     return PBIT_OK;

@@ -10,6 +10,7 @@
 #include "blob.h"
 #include "gibbs.h"
 #include "keyhist.h"
+#include "made_kernels.h"
 #include "tune.h"
 
 pbit_circuit_s::~pbit_circuit_s() {
@@ -250,7 +251,7 @@ void compile_jits(pbit_circuit c, int dev, const pbit_gibbs_cfg *cfg, const std:
 }
 
 pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_state, uint32_t *d_hist,
-                      hipStream_t stream, bool no_alloc) {
+                      hipStream_t stream, bool no_alloc, const MhArgs *mh, uint32_t mh_circ) {
     if (!c || !cfg_in || !cfg_in->chains) return set_error(PBIT_E_INVALID_ARG, "NULL handle, cfg or chains");
     pbit_gibbs_cfg cfg_na;
     const pbit_gibbs_cfg *cfg = cfg_in;
@@ -282,6 +283,8 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_
         return set_error(PBIT_E_INVALID_ARG, "sweep counter would wrap");
     if (cfg->use_graph && !stream) return set_error(PBIT_E_INVALID_ARG, "graph replay needs a non-null stream");
     const uint32_t nc = (uint32_t)c->circuits.size();
+    if (mh && (mh_circ >= nc || cfg->init != PBIT_INIT_RESUME || cfg->use_graph || total == 0))
+        return set_error(PBIT_E_INVALID_ARG, "an MH accept needs a resumed run of some sweeps without a graph");
     for (uint32_t i = 0; i < nc; ++i)
         if (cfg->chains[i] && c->circuits[i].ny && cfg->toggle_mode == 2)
             return set_error(PBIT_E_MODE_UNAVAILABLE,
@@ -571,6 +574,26 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_error(e, "hipDeviceGetAttribute");
 
+    // the MH accept: inside the circuit's first sweep launch when that is the
+    // specialised kernel for non-constant magnitudes with one lane per chain
+    MhFuse mh_fuse;
+    bool mh_fused = false;
+    if (mh) {
+        for (Plan &p : plans) {
+            if (p.circ != mh_circ) continue;
+            if (p.jit && p.jit->general && p.lanes_log2 == 0 && p.a.resume && p.a.state && p.a.n_sweeps > 0 &&
+                !p.hist_out) {
+                mh_fuse.prop = mh->prop;
+                mh_fuse.logq_cur = mh->logq_cur;
+                mh_fuse.logq_prop = mh->logq_prop;
+                mh_fuse.accepts = mh->accepts;
+                mh_fuse.step = mh->step;
+                p.a.mh = &mh_fuse;
+                mh_fused = true;
+            }
+            break;
+        }
+    }
     auto lane_stream = [&](int lane) { return lane == 0 ? stream : side->s[lane - 1]; };
     auto enqueue_work = [&]() -> pbit_status {
         for (const Plan &p : plans) {
@@ -614,6 +637,10 @@ pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg_in, uint32_t *d_
     // fork the side streams from the caller's stream, enqueue, join them back
     // (also after an error, so no side stream is left behind a capture)
     auto enqueue = [&]() -> pbit_status {
+        if (mh && !mh_fused) {  // before the fork: every stream's sweeps follow it
+            const hipError_t me = launch_mh_accept(c->circuits[mh_circ].WS, *mh, stream);
+            if (me != hipSuccess) return hip_error(me, "mh accept");
+        }
         if (!fork) return enqueue_work();
         hipError_t fe = hipEventRecord(side->fork, stream);
         for (int k = 0; k < SIDE_STREAMS && fe == hipSuccess; ++k) fe = hipStreamWaitEvent(side->s[k], side->fork, 0);

@@ -87,11 +87,19 @@ struct pbit_circuit_s {
 
 namespace pbit {
 
+struct MhArgs;
+
 // With no_alloc the run allocates no device memory and compiles nothing: it
 // takes the generic kernels, needs the images resident and d_state, and
 // refuses runs that would need library buffers, side streams or a graph.
+// With mh (circuit mh_circ, the run resumed from d_state) the run first
+// takes that MH accept for every chain: inside the first sweep launch of
+// the circuit when it is the circuit-specialised kernel for non-constant
+// magnitudes with one lane per chain, else as a launch of its own before
+// the sweeps (the same states, counts and accept counters either way).
 pbit_status run_gibbs(pbit_circuit c, const pbit_gibbs_cfg *cfg, uint32_t *d_state, uint32_t *d_hist,
-                      hipStream_t stream, bool no_alloc = false);
+                      hipStream_t stream, bool no_alloc = false, const MhArgs *mh = nullptr,
+                      uint32_t mh_circ = 0);
 
 // Device image of every circuit of the handle on the current device
 // (uploaded on first use; with no_alloc an error if it is not resident).

@@ -304,6 +304,51 @@ def test_adam_step_shadows_equal_a_refresh(env, which, H):
         assert np.array_equal(a, b), name
 
 
+def test_mh_accept_inside_the_sweep_kernel_equals_the_separate_accept(env):
+    """Once the handle holds the circuit-specialised sweep kernel of a
+    circuit with non-constant magnitudes (one lane per chain: more than
+    32,768 chains), an MH cycle's accept runs inside its first sweep launch;
+    the allocation-free run takes the separate accept kernel and the generic
+    sweeps.  States, phase-bin counts and accept counters agree bit for bit
+    over three cycles from the all-zero paths and two resumed ones."""
+    torch, pbit = env
+    # theta = pi / 5: every gate's magnitude varies (cos against sin), and a
+    # near-uniform proposal still gets accepted often
+    c = wc.rotated_hadamard_chain(48, math.pi / 5, K=1)
+    s = pbit.CircuitSet(c)
+    info = s.info(0)
+    W = info["W"]
+    q = pbit.Proposal(s, hidden=128, seed=2)
+    q.set_params(random_params(q.D, 128, 7, scale=0.05))
+    n = 40000
+    # compile the specialised kernel into the handle (a run of its own)
+    h0 = torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda")
+    s.gibbs_run([n], 0, 2, h0, torch.zeros(n * W, dtype=torch.int32, device="cuda"), seed=1, specialize=2)
+    shape = s.launch_shape([n], 0, 4, init=1)
+    assert shape["kernel"] == 3 and shape["lanes_per_chain"] == 1, shape
+
+    def fresh():
+        return (torch.zeros(n * W, dtype=torch.int32, device="cuda"),
+                torch.zeros(info["hist_bins"], dtype=torch.int32, device="cuda"),
+                torch.zeros(n, dtype=torch.int64, device="cuda"))
+
+    st_a, h_a, acc_a = fresh()
+    st_b, h_b, acc_b = fresh()
+    pbit.mh_run(s, q, n, 3, st_a, h_a, acc_a, gibbs_per_mh=4, seed=11, chain_begin=5)
+    pbit.mh_run_static(s, q, n, 3, st_b, h_b, acc_b, gibbs_per_mh=4, seed=11, chain_begin=5)
+    pbit.mh_run(s, q, n, 2, st_a, h_a, acc_a, gibbs_per_mh=3, seed=11, chain_begin=5, step_offset=3,
+                sweep_offset=12, resume=True)
+    pbit.mh_run_static(s, q, n, 2, st_b, h_b, acc_b, gibbs_per_mh=3, seed=11, chain_begin=5, step_offset=3,
+                       sweep_offset=12, resume=True)
+    torch.cuda.synchronize()
+    say("accepted", int(acc_a.sum()), "and", int(acc_b.sum()), "of", n * 5)
+    assert torch.equal(acc_a, acc_b)
+    assert torch.equal(h_a, h_b)
+    assert torch.equal(st_a, st_b)
+    assert int(acc_a.sum()) > 0
+    assert int(h_a.to(torch.int64).sum()) == n * (3 * 5 + 2 * 4)
+
+
 def _sample(env, q, n, seed=3, step=0):
     torch, pbit = env
     W = q.cset.info(0)["W"]
