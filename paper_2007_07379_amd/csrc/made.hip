@@ -693,17 +693,24 @@ __global__ __launch_bounds__(256) void adam_shadow_kernel(GradFinal a, int4 tile
         id -= tcount[w];
     }
     // biases: b1 [H], b2 [H], c [D] in that order
-    const int j = id * 256 + (int)threadIdx.x;
-    int64_t i;
-    if (j < a.H)
-        i = a.ob1 + j;
-    else if (j < 2 * a.H)
-        i = a.ob2 + (j - a.H);
-    else if (j < 2 * a.H + a.D)
-        i = a.oc + (j - 2 * a.H);
-    else
+    const int nbias = (2 * a.H + a.D + 255) / 256;
+    if (id < nbias) {
+        const int j = id * 256 + (int)threadIdx.x;
+        int64_t i;
+        if (j < a.H)
+            i = a.ob1 + j;
+        else if (j < 2 * a.H)
+            i = a.ob2 + (j - a.H);
+        else if (j < 2 * a.H + a.D)
+            i = a.oc + (j - 2 * a.H);
+        else
+            return;
+        (void)gf_adam(a, i, gf_grad(a, i));
         return;
-    (void)gf_adam(a, i, gf_grad(a, i));
+    }
+    // the next batch's unpack
+    const uint32_t e = (uint32_t)(id - nbias) * 256u + threadIdx.x;
+    if (e < (uint32_t)a.ux_n * ((uint32_t)a.ux_DP >> 3)) unpack_row8(a.ux_states, a.ux_stride, a.ux_b0, a.D, a.ux_DP, a.ux_X, e);
 }
 
 // The ReLU-derivative gate of a library product's bf16 output and its column
@@ -2036,6 +2043,12 @@ hipError_t launch_grad_final(const GradFinal &a, hipStream_t s) {
         }
         if (!shapes) return hipErrorInvalidValue;
         blocks += (2 * H + D + 255) / 256;
+        if (a.ux_n > 0) {
+            const int64_t ue = (int64_t)a.ux_n * (a.ux_DP / 8);
+            if (!a.ux_states || !a.ux_X || a.ux_DP % 32 || a.ux_DP < a.D || ue > (int64_t)UINT32_MAX)
+                return hipErrorInvalidValue;
+            blocks += (ue + 255) / 256;
+        }
         if (blocks > INT32_MAX) return hipErrorInvalidValue;
         hipLaunchKernelGGL(adam_shadow_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, int4{tc[0], tc[1], tc[2], 0});
         return hipGetLastError();

@@ -154,7 +154,37 @@ struct GradFinal {
     int nloss;
     float *loss;
     ShadowJob sh[3];              // shadows of W1, W2, V written by the Adam step (sh[0].Wb NULL: none)
+    // With the shadows: rows [ux_b0, ux_b0 + ux_n) of a word-major state
+    // array (row stride ux_stride) unpacked into ux_X [ux_n][ux_DP] bf16 in
+    // the same launch (the next training batch; ux_n = 0: none)
+    const uint32_t *ux_states;
+    uint64_t ux_stride, ux_b0;
+    int ux_n, ux_DP;
+    bf16 *ux_X;
 };
+// Thread e < n DP / 8 of an unpack of rows [b0, b0 + n) of a word-major
+// state array (row stride `stride`): X[b][8g .. 8g + 7] = the path's bits
+// 8g .. 8g + 7 as bf16 0 / 1 (positions >= D as 0), one 16-byte store, so a
+// wave's stores run along the rows (b = e / (DP / 8), g = e % (DP / 8); DP a
+// multiple of 32).
+__device__ __forceinline__ void unpack_row8(const uint32_t *__restrict__ states, uint64_t stride, uint64_t b0,
+                                            int D, int DP, bf16 *__restrict__ X, uint32_t e) {
+    const uint32_t G = (uint32_t)DP >> 3;
+    const uint32_t b = e / G, g = e - b * G;
+    const int i0 = (int)g * 8, left = D - i0;
+    uint32_t bits = 0;
+    if (left > 0) {
+        bits = (states[(uint64_t)(i0 >> 5) * stride + b0 + b] >> (i0 & 31)) & 0xFFu;
+        if (left < 8) bits &= (1u << left) - 1u;
+    }
+    constexpr uint32_t ONE = 0x3F80u;  // bf16 1.0
+    uint4 w;
+    w.x = ((bits & 1u) ? ONE : 0u) | ((bits & 2u) ? ONE << 16 : 0u);
+    w.y = ((bits & 4u) ? ONE : 0u) | ((bits & 8u) ? ONE << 16 : 0u);
+    w.z = ((bits & 16u) ? ONE : 0u) | ((bits & 32u) ? ONE << 16 : 0u);
+    w.w = ((bits & 64u) ? ONE : 0u) | ((bits & 128u) ? ONE << 16 : 0u);
+    *reinterpret_cast<uint4 *>(X + (uint64_t)b * DP + i0) = w;
+}
 hipError_t launch_grad_final(const GradFinal &a, hipStream_t s);
 // G[m][j] = 0 where A[m][j] <= 0 (n x N bf16, row-major, N % 8 == 0), and
 // the 64-row column partials of the gated G into colpart (ceil(n / 64) x N).

@@ -409,7 +409,9 @@ pbit_status backward(pbit_proposal q, int n, hipStream_t s, int z[3]) {
 // Adam step on it that also writes the weights' bf16 shadows; the batch-mean
 // loss into *loss_dev.
 pbit_status grad_final(pbit_proposal q, int n, const int z[3], float *loss_dev, bool adam_step, float *grad, float lr,
-                       float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s,
+                       const uint32_t *next_states = nullptr, uint64_t next_stride = 0, uint64_t next_b0 = 0,
+                       int next_n = 0) {
     GradFinal a;
     std::memset(&a, 0, sizeof(a));
     a.adam = adam_step ? 1 : 0;
@@ -453,6 +455,14 @@ pbit_status grad_final(pbit_proposal q, int n, const int z[3], float *loss_dev, 
         a.sh[0] = {nullptr, q->D, q->H, q->DP, q->W1b, q->W1T};
         a.sh[1] = {nullptr, q->H, q->H, q->H, q->W2b, q->W2T};
         a.sh[2] = {nullptr, q->H, q->D, q->H, q->Vb, q->VT};
+        if (next_n > 0) {  // the next batch's inputs, unpacked in the same launch
+            a.ux_states = next_states;
+            a.ux_stride = next_stride;
+            a.ux_b0 = next_b0;
+            a.ux_n = next_n;
+            a.ux_DP = q->DP;
+            a.ux_X = q->X;
+        }
     }
     hipError_t e = launch_grad_final(a, s);
     if (e != hipSuccess) return hip_error(e, adam_step ? "adam" : "gradient");
@@ -468,28 +478,13 @@ pbit_status sample_or_score(pbit_proposal q, uint32_t n, uint32_t chain_begin, u
 }  // namespace
 
 // unpack of a column range of a word-major state array with row stride
-// `stride`: thread (b, g) writes X[b][8g .. 8g + 7] (positions >= D as zero)
-// with one 16-byte store, so a wave's stores run along the rows.  DP is a
-// multiple of 32 and n DP / 8 < 2^32 (checked at launch).
+// `stride` (unpack_row8 per thread).  DP is a multiple of 32 and n DP / 8 <
+// 2^32 (checked at launch).
 __global__ void unpack_strided_kernel(const uint32_t *__restrict__ states, uint64_t stride, uint64_t b0, int n,
                                       int D, int DP, bf16 *__restrict__ X) {
-    const uint32_t G = (uint32_t)DP >> 3;
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (uint32_t)n * G) return;
-    const uint32_t b = e / G, g = e - b * G;
-    const int i0 = (int)g * 8, left = D - i0;
-    uint32_t bits = 0;
-    if (left > 0) {
-        bits = (states[(uint64_t)(i0 >> 5) * stride + b0 + b] >> (i0 & 31)) & 0xFFu;
-        if (left < 8) bits &= (1u << left) - 1u;
-    }
-    constexpr uint32_t ONE = 0x3F80u;  // bf16 1.0
-    uint4 w;
-    w.x = ((bits & 1u) ? ONE : 0u) | ((bits & 2u) ? ONE << 16 : 0u);
-    w.y = ((bits & 4u) ? ONE : 0u) | ((bits & 8u) ? ONE << 16 : 0u);
-    w.z = ((bits & 16u) ? ONE : 0u) | ((bits & 32u) ? ONE << 16 : 0u);
-    w.w = ((bits & 64u) ? ONE : 0u) | ((bits & 128u) ? ONE << 16 : 0u);
-    *reinterpret_cast<uint4 *>(X + (uint64_t)b * DP + i0) = w;
+    if (e >= (uint32_t)n * ((uint32_t)DP >> 3)) return;
+    unpack_row8(states, stride, b0, D, DP, X, e);
 }
 
 __global__ void fill_const_kernel(const uint32_t *__restrict__ blob, uint32_t *__restrict__ state, int n, int W) {
@@ -742,20 +737,26 @@ pbit_status pbit_proposal_train(pbit_proposal q, const uint32_t *d_states, uint6
     if ((st = refresh(q, s)) != PBIT_OK) return st;
     hipError_t e = hipMemsetAsync(q->loss, 0, sizeof(float) * cfg->steps, s);
     if (e != hipSuccess) return hip_error(e, "memset");
-    uint64_t cursor = 0;
+    // consecutive batches, wrapping to the start when one would run past the
+    // samples; each step's finalize unpacks the next step's batch (X is last
+    // read by that step's weight gradients), the first is unpacked here
+    auto wrap = [&](uint64_t c) { return c + cfg->batch > n_samples ? (uint64_t)0 : c; };
+    uint64_t cursor = wrap(0);
+    if (cfg->steps && (st = unpack_range(q, d_states, n_samples, cursor, (int)cfg->batch, s)) != PBIT_OK) return st;
     for (uint32_t it = 0; it < cfg->steps; ++it) {
-        if (cursor + cfg->batch > n_samples) cursor = 0;
-        if ((st = unpack_range(q, d_states, n_samples, cursor, (int)cfg->batch, s)) != PBIT_OK) return st;
-        cursor += cfg->batch;
         if ((st = forward(q, (int)cfg->batch, s, false, true)) != PBIT_OK) return st;
         int z[3];
         if ((st = backward(q, (int)cfg->batch, s, z)) != PBIT_OK) return st;
         q->t += 1;
         const double c1 = 1.0 / (1.0 - std::pow((double)b1, q->t));
         const double c2 = 1.0 / (1.0 - std::pow((double)b2, q->t));
+        const uint64_t next = wrap(cursor + cfg->batch);
+        const bool more = it + 1 < cfg->steps;
         if ((st = grad_final(q, (int)cfg->batch, z, q->loss + it, true, nullptr, lr, b1, b2, eps, (float)c1,
-                             (float)c2, s)) != PBIT_OK)
+                             (float)c2, s, more ? d_states : nullptr, n_samples, next, more ? (int)cfg->batch : 0)) !=
+            PBIT_OK)
             return st;
+        cursor = next;
         q->dirty = false;  // the Adam step refreshed the shadows
     }
     if (losses_out) {

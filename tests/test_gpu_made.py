@@ -273,6 +273,40 @@ def test_training_is_deterministic(env):
     assert np.array_equal(after[0][1].view(np.uint32), after[1][1].view(np.uint32))
 
 
+@pytest.mark.parametrize("which,H", [("small", 64), ("brick16", 1024)])
+def test_training_batches_unpacked_in_the_finalize(env, which, H):
+    """A multi-step train call unpacks each later batch inside the previous
+    step's finalize; one-step calls on the same batches (each a contiguous
+    copy of the word-major columns) unpack on their own.  Parameters and
+    losses agree bit for bit over batches that wrap past the end of the
+    samples (1,000 samples, batches of 384 at 0, 384, 0, 384)."""
+    torch, pbit = env
+    c = SMALL() if which == "small" else wc.workload_circuit("brick16")
+    s = pbit.CircuitSet(c)
+    W = s.info(0)["W"]
+    n, B, steps = 1000, 384, 4
+    _, _, words = valid_paths(c, n, 21)
+    d_states = to_dev(torch, words)
+    flat = random_params(pbit.Proposal(s, hidden=H).D, H, 3)
+    q = pbit.Proposal(s, hidden=H)
+    q.set_params(flat)
+    la = q.train(d_states, n, B, steps, lr=2e-3)
+    r = pbit.Proposal(s, hidden=H)
+    r.set_params(flat)
+    lb = []
+    cur = 0
+    for _ in range(steps):
+        if cur + B > n:
+            cur = 0
+        part = d_states.view(W, n)[:, cur:cur + B].contiguous().view(-1)
+        lb.append(r.train(part, B, B, 1, lr=2e-3)[0])
+        cur += B
+    torch.cuda.synchronize()
+    assert np.array_equal(np.asarray(la, dtype=np.float32).view(np.uint32),
+                          np.asarray(lb, dtype=np.float32).view(np.uint32))
+    assert np.array_equal(q.get_params().view(np.uint32), r.get_params().view(np.uint32))
+
+
 @pytest.mark.parametrize("which,H", [("small", 64), ("small", 512), ("brick16", 1024)])
 def test_adam_step_shadows_equal_a_refresh(env, which, H):
     """The Adam step writes the bf16 shadows (row-major and transposed) of the
