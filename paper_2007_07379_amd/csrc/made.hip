@@ -626,12 +626,13 @@ __global__ __launch_bounds__(256) void grad_final_kernel(GradFinal a) {
 
 // The Adam step with the bf16 shadows of the updated weights written in the
 // same pass (the arithmetic of grad_final_kernel, element for element).  The
-// first a.tiles[0] + a.tiles[1] + a.tiles[2] workgroups take 32 x 32 tiles of
-// W1, W2 and V (rows k0.. of the KP rows of WT, columns n0..): thread
-// (column tx, row group ty) updates rows ty, ty + 8, ... and writes Wb along
-// n; the tile is transposed through LDS and WT written along k, zero past K.
-// The rest take the biases b1, b2, c, one thread each.  Workgroup 0 adds the
-// loss shares.
+// first tiles.x + tiles.y + tiles.z workgroups take 32 x 32 tiles of W1, W2
+// and V (rows k0.. of the KP rows of WT, columns n0..): thread (column tx,
+// row group ty) updates rows ty, ty + 8, ... and writes Wb along n; the tile
+// is transposed through LDS and WT written along k, zero past K.  The next
+// ceil((2H + D) / 256) take the biases b1, b2, c, one thread each, and the
+// rest, when a.ux_n > 0, unpack the next batch (unpack_row8).  Workgroup 0
+// adds the loss shares.
 constexpr int AS_ROWS = 32, AS_COLS = 32;
 __global__ __launch_bounds__(256) void adam_shadow_kernel(GradFinal a, int4 tiles) {
     if (blockIdx.x == 0 && a.loss) gf_loss(a);
