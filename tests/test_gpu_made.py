@@ -338,17 +338,34 @@ def test_adam_step_shadows_equal_a_refresh(env, which, H):
         assert np.array_equal(a, b), name
 
 
-def test_mh_accept_inside_the_sweep_kernel_equals_the_separate_accept(env):
+def _rr_chain(d):
+    """Two qubits driven by d two-qubit gates, each the Kronecker product of
+    two rotated Hadamards (Eq. (HadT)) at different angles: zero-free, with
+    three magnitudes, so every gate is a 16-entry real-energy record."""
+    ra, _ = wc.mat_rh(math.pi / 5)
+    rb, _ = wc.mat_rh(math.pi / 7)
+    A = np.array(ra).reshape(2, 2)
+    Bm = np.array(rb).reshape(2, 2)
+    M = np.kron(Bm, A)  # row o0 + 2 o1, column i0 + 2 i1
+    re = [float(v) for v in M.ravel()]
+    gates = [{"layer": l, "qubits": [0, 1], "kind": "RR", "re": re, "im": [0.0] * 16} for l in range(1, d + 1)]
+    return wc.circuit("rr_chain_d%d" % d, 2, d, 1, gates)
+
+
+@pytest.mark.parametrize("which", ["rh48_pi5", "rr2_d12"])
+def test_mh_accept_inside_the_sweep_kernel_equals_the_separate_accept(env, which):
     """Once the handle holds the circuit-specialised sweep kernel of a
     circuit with non-constant magnitudes (one lane per chain: more than
     32,768 chains), an MH cycle's accept runs inside its first sweep launch;
     the allocation-free run takes the separate accept kernel and the generic
     sweeps.  States, phase-bin counts and accept counters agree bit for bit
-    over three cycles from the all-zero paths and two resumed ones."""
+    over three cycles from the all-zero paths and two resumed ones (one-qubit
+    records, whose tables the kernel selects from, and two-qubit ones, which
+    it reads from arrays)."""
     torch, pbit = env
     # theta = pi / 5: every gate's magnitude varies (cos against sin), and a
     # near-uniform proposal still gets accepted often
-    c = wc.rotated_hadamard_chain(48, math.pi / 5, K=1)
+    c = wc.rotated_hadamard_chain(48, math.pi / 5, K=1) if which == "rh48_pi5" else _rr_chain(12)
     s = pbit.CircuitSet(c)
     info = s.info(0)
     W = info["W"]
